@@ -1,0 +1,249 @@
+/*
+ * lbib.h - C ABI of the MI355X (gfx950) lattice-Boltzmann / immersed-boundary
+ * capillary solver.
+ *
+ * The library advances the 2D hybrid kinematic/dynamic immersed-boundary
+ * lattice-Boltzmann method of Coclite, "Vascular journey and adhesion
+ * mechanics of micro-sized carriers in narrow capillaries" (arXiv 1907.00080):
+ *   - D2Q9 BGK collide-and-stream with Guo body forcing (Sec. 2.1, Eqs. BGK,
+ *     feq, GaussHermite; Sec. 2.2, Eqs. forcedBGK, ForcingTerm), x periodic,
+ *     no-slip walls at y = -1/2 and y = ny - 1/2 (halfway bounce-back);
+ *   - mass-spring membranes with strain, bending and enclosed-area forces
+ *     (Sec. 2.2, Eqs. strainFor, bendFor, areaFor);
+ *   - ligand-receptor bonds: stochastic formation/rupture and linear springs
+ *     (Sec. 2.2, Eq. adhFor; Sec. 3 parameters);
+ *   - red cells moved by the kinematic IB (Sec. 2.3, Eq. kinematicPos);
+ *     rigid and soft particles by the dynamic IB with probe-based pressure
+ *     and viscous loads (Sec. 2.2, Eqs. hydroForP, hydroForNu; Sec. 2.3,
+ *     Eqs. newtonSoft, verletPos, verletVel, linearVelRig, angularVelRig).
+ *
+ * Units: lattice units throughout (dx = dt = 1, rho0 = 1, cs^2 = 1/3).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an lbib_status; LBIB_OK == 0.  On any other value
+ *     the call had no effect on the context's state, and lbib_last_error()
+ *     describes the cause.  No C++ exception crosses this boundary.
+ *   - Host arrays passed in are owned by the caller and copied during the
+ *     call.  Readback calls write into caller-owned host buffers of the
+ *     stated sizes.  NULL where an array is required -> LBIB_EINVAL.
+ *   - Device memory: the library allocates none of its state.  The caller
+ *     queries the workspace size, allocates that many bytes of device
+ *     memory (any allocator; 256-byte alignment required) and binds it
+ *     together with a HIP stream.  The workspace must outlive the context.
+ *     All kernels are enqueued on the bound stream; lbib_step returns once
+ *     the work is enqueued.  Readback calls synchronise that stream.
+ *   - Lifecycle: create -> add_body / set_receptors / set_adhesion /
+ *     init_fields (setup) -> workspace_query -> bind -> finalize_setup
+ *     (running) -> step / readback ... -> destroy.  A call made in the wrong
+ *     phase returns LBIB_ESTATE.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Lagrangian data crosses the boundary in float64; marker x coordinates
+ *     are unwrapped (the lattice is periodic in x, bodies are not cut).
+ */
+#ifndef LBIB_H
+#define LBIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBIB_ABI_VERSION 1u
+
+typedef struct lbib_ctx lbib_ctx;
+
+typedef enum {
+  LBIB_OK = 0,
+  LBIB_EINVAL = 1,     /* bad argument: NULL, size or value out of range      */
+  LBIB_ESTATE = 2,     /* call not allowed in the context's current phase      */
+  LBIB_EHIP = 3,       /* a HIP runtime call failed (message has the HIP error) */
+  LBIB_ENOSPACE = 4,   /* workspace smaller than lbib_workspace_query's value  */
+  LBIB_EUNSTABLE = 5   /* watchdog: non-finite or non-positive density found   */
+} lbib_status;
+
+typedef enum { LBIB_F32 = 0, LBIB_F64 = 1 } lbib_dtype;
+
+typedef enum {
+  LBIB_RBC_KINEMATIC = 0,   /* red cell: kinematic IB, forces spread to the fluid */
+  LBIB_PARTICLE_SOFT = 1,   /* deformable particle: dynamic IB, Verlet + BDF2     */
+  LBIB_PARTICLE_RIGID = 2   /* rigid particle: dynamic IB, BDF2 on U and Omega    */
+} lbib_body_kind;
+
+/* Lattice of nx * ny nodes at x = 0..nx-1, y = 0..ny-1 (Sec. 3: periodic in x,
+ * walls in y).  tau: BGK relaxation time (> 1/2), nu = (tau - 1/2)/3.
+ * (gx, gy): uniform body force driving the flow (the pressure drop of the
+ * Poiseuille set-up).  periodic_y = 1 replaces the walls by periodicity
+ * (used by conservation tests).  dtype: precision of the populations and of
+ * the collision arithmetic; populations are stored shifted by their rest
+ * weights (f_i - w_i).  seed and instance key the Philox4x32-10 stream of
+ * the bond kinetics.  tile_x, tile_y: lattice tile of the fused kernel and
+ * of the marker bins, one of (64,4), (128,2), (32,8), (256,1); 0,0 = default. */
+typedef struct {
+  int32_t nx, ny;
+  int32_t periodic_y;
+  int32_t dtype;
+  double tau;
+  double gx, gy;
+  uint64_t seed;
+  int32_t instance;
+  int32_t tile_x, tile_y;
+} lbib_lattice_desc;
+
+/* One closed membrane (Sec. 2.2): nv vertices, counter-clockwise, given in
+ * their stress-free configuration (rest lengths, rest angles and rest area
+ * are taken from them).  ks, kb, ka: strain, bending and area constants;
+ * p_ref: reference pressure of the area penalty.  density_ratio: rho_P/rho
+ * (particle mass = ratio * rest area, Sec. 3).  sigma: bond spring constant.
+ * ligand_stride: 0 = no ligands; s > 0: a ligand on every element l with
+ * l % s == 0 (s = 2 is the density rho_L = 0.5 of Sec. 3).  Ligands are
+ * only meaningful on particles. */
+typedef struct {
+  int32_t kind;
+  int32_t nv;
+  double ks, kb, ka, p_ref;
+  double density_ratio;
+  double sigma;
+  int32_t ligand_stride;
+} lbib_body_desc;
+
+/* Bond kinetics (Sec. 2.2 Wall-Particle Interaction, Sec. 3): bonds form only
+ * when an element centroid is closer than y_cr to a wall; y_eq is the
+ * force-free bond length.  Formation/rupture probabilities per step:
+ * P = 1 - exp(-k dt) with k_f = kf0_dt exp(-s_ts (y - y_eq)^2 / (2 kbt)) and
+ * k_r = kr0_dt exp((sigma - s_ts)(y - y_eq)^2 / (2 kbt)), s_ts =
+ * sigma_ts_frac * sigma.  freeze_topology = 1 keeps the bond table fixed. */
+typedef struct {
+  double y_cr, y_eq;
+  double kf0_dt, kr0_dt;
+  double sigma_ts_frac;
+  double kbt;
+  int32_t freeze_topology;
+} lbib_adhesion_desc;
+
+/* Whole-lattice diagnostics of the last completed step. */
+typedef struct {
+  int64_t step;          /* number of completed time steps                     */
+  double mass;           /* sum of rho                                         */
+  double mom_x, mom_y;   /* sum of rho u (physical, half-force velocity)      */
+  double rho_min;
+  double u_max;          /* max |u|                                            */
+  int64_t nonfinite;     /* nodes with a non-finite population                 */
+  int32_t nbonds;
+} lbib_diag;
+
+uint32_t lbib_abi_version(void);
+
+/* Status name for an lbib_status value (static string). */
+const char* lbib_status_string(int32_t status);
+
+/* Message of the last failed call on ctx (owned by ctx, valid until the next
+ * call on it).  ctx may be NULL: then the last lbib_create failure. */
+const char* lbib_last_error(const lbib_ctx* ctx);
+
+/* Create a context in the setup phase.  nx, ny >= 1, tau > 1/2. */
+lbib_status lbib_create(const lbib_lattice_desc* desc, lbib_ctx** out);
+
+/* Add a body (setup phase).  xy: nv*2 doubles (x0, y0, x1, y1, ...).
+ * nv >= 3.  *id receives the body index (bodies are numbered in call order). */
+lbib_status lbib_add_body(lbib_ctx* ctx, const lbib_body_desc* desc, const double* xy,
+                          int32_t* id);
+
+/* Receptor positions on one wall (setup phase): wall 0 is y = -1/2, wall 1 is
+ * y = ny - 1/2.  x: n strictly increasing values in [0, nx).  Replaces any
+ * earlier set.  n = 0 clears the wall. */
+lbib_status lbib_set_receptors(lbib_ctx* ctx, int32_t wall, const double* x, int32_t n);
+
+/* Bond kinetics parameters (setup phase; defaults: no bonds form). */
+lbib_status lbib_set_adhesion(lbib_ctx* ctx, const lbib_adhesion_desc* desc);
+
+/* Initial fluid state (setup phase): populations at equilibrium with
+ * density rho and velocity (ux, uy), host arrays of ny*nx doubles, row-major
+ * [y][x].  rho may be NULL (1 everywhere); ux/uy NULL = 0.  Default: rest. */
+lbib_status lbib_init_fields(lbib_ctx* ctx, const double* rho, const double* ux,
+                             const double* uy);
+
+/* Bytes of device workspace the context needs (setup phase, after all
+ * add_body / set_receptors calls). */
+lbib_status lbib_workspace_query(const lbib_ctx* ctx, size_t* bytes);
+
+/* Attach caller-owned device memory (>= the queried size, 256-byte aligned)
+ * and the HIP stream (hipStream_t, NULL = default stream) all work goes to. */
+lbib_status lbib_bind(lbib_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_stream);
+
+/* Upload the set-up, compute the stress-free state, enter the running phase. */
+lbib_status lbib_finalize_setup(lbib_ctx* ctx);
+
+/* Advance nsteps >= 0 time steps (running phase).  Asynchronous on the
+ * bound stream.  If a watchdog interval is set (lbib_set_watchdog), the call
+ * synchronises at its end and returns LBIB_EUNSTABLE when the state holds a
+ * non-finite population or a non-positive density (state left in place). */
+lbib_status lbib_step(lbib_ctx* ctx, int64_t nsteps);
+
+/* Watchdog after every lbib_step call when on != 0 (default off). */
+lbib_status lbib_set_watchdog(lbib_ctx* ctx, int32_t on);
+
+/* Steps per captured HIP graph used by lbib_step (even, 0 = no graphs;
+ * default 0).  Graph replays and plain launches give bitwise-identical
+ * results. */
+lbib_status lbib_set_graph_steps(lbib_ctx* ctx, int32_t steps);
+
+/* Fields of the last completed step (synchronises): rho and the physical
+ * half-force velocity u = (sum f e + F/2)/rho, ny*nx doubles each, [y][x].
+ * Any pointer may be NULL to skip it.  Before the first step: initial state. */
+lbib_status lbib_get_fields(lbib_ctx* ctx, double* rho, double* ux, double* uy);
+
+/* Current vertex positions of body `body` (synchronises): nv*2 doubles. */
+lbib_status lbib_get_markers(lbib_ctx* ctx, int32_t body, double* xy);
+
+/* Overwrite current and previous vertex positions of a body (running phase);
+ * xy_prev may be NULL (= xy).  Rest state is unchanged.  Synchronises. */
+lbib_status lbib_set_markers(lbib_ctx* ctx, int32_t body, const double* xy,
+                             const double* xy_prev);
+
+/* Force each marker of `body` handed to the fluid in the last step
+ * (synchronises), nv*2 doubles: for a red cell the membrane force; for a
+ * particle the weak-coupling force times the marker's arc weight. */
+lbib_status lbib_get_marker_forces(lbib_ctx* ctx, int32_t body, double* fxy);
+
+/* Ligand count over all bodies (global ligand ids are numbered body by body,
+ * element ascending). */
+lbib_status lbib_num_ligands(const lbib_ctx* ctx, int32_t* n);
+
+/* Bond table (synchronises): lig_to_rec[n_ligands], -1 = free, else receptor
+ * index (wall 0 receptors first, then wall 1).  *nbonds may be NULL. */
+lbib_status lbib_get_bonds(lbib_ctx* ctx, int32_t* lig_to_rec, int32_t* nbonds);
+
+/* Overwrite the bond table (running phase).  Entries must be -1 or a valid
+ * receptor index, with no receptor used twice. */
+lbib_status lbib_set_bonds(lbib_ctx* ctx, const int32_t* lig_to_rec);
+
+/* Checkpoint of the complete dynamic state (populations, marker positions
+ * and history, rigid-body state, bond table, step counter).  Call with
+ * blob = NULL to get the size.  set_state restores it bitwise. */
+lbib_status lbib_get_state(lbib_ctx* ctx, void* blob, size_t* bytes);
+lbib_status lbib_set_state(lbib_ctx* ctx, const void* blob, size_t bytes);
+
+/* Whole-lattice diagnostics (synchronises). */
+lbib_status lbib_diagnostics(lbib_ctx* ctx, lbib_diag* out);
+
+/* Measurement: launch the fused lattice kernel (streaming, collision and
+ * gathered spreading) `reps` times on the bound stream with the current
+ * state, bracketed by HIP events, and return the mean duration per launch
+ * in milliseconds (synchronises).  The kernel reads the current populations
+ * and writes the spare buffer only, so the dynamic state is unchanged.
+ * Requires at least one completed step (the marker bins of that step). */
+lbib_status lbib_time_lattice_kernel(lbib_ctx* ctx, int32_t reps, double* avg_ms);
+
+/* Completed step count. */
+lbib_status lbib_get_step(const lbib_ctx* ctx, int64_t* step);
+
+/* Free the context (not the caller's workspace).  NULL is allowed. */
+lbib_status lbib_destroy(lbib_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBIB_H */

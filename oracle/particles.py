@@ -7,7 +7,7 @@ F^p = -p_l n_l l_l (Eq. hydroForP) and viscous load F^tau = (tau_l . n_l) l_l
 to the centroid; element loads are shared equally by the two vertices.
 Sec. 2.3: soft particles integrate Newton's law per vertex (Eq. newtonSoft)
 with the Verlet position update seeded by the interpolated fluid velocity
-(Eq. verletPos) and a BDF2 velocity (Eq. verletVel); rigid particles sum
+(Eq. verletPos); rigid particles sum
 loads into a force and a moment and advance U and Omega with BDF2
 (Eqs. linearVelRig, angularVelRig).  No-slip is imposed weakly.
 
@@ -26,7 +26,14 @@ Readings for what the text leaves open:
   * weak coupling: the marker velocity U_k^{n+1} of the particle is
     imposed through the Eulerian force F_k = 2 rho0 (U_k^{n+1} - u*(X_k^n)),
     spread at X_k^n with weight ds_k = (l_{k-1} + l_k)/2; the internal
-    forces of a particle reach the fluid only through this term.
+    forces of a particle reach the fluid only through this term;
+  * the imposed velocity of a soft-particle vertex is its displacement over
+    the step, (X^{n+1} - X^n)/dt.  The second-order velocity of Eq.
+    (verletVel), 3/2 X^{n+1} - 2 X^n + 1/2 X^{n-1}, reduces the coupling
+    force to a difference of successive interpolated fluid velocities, a
+    feedback with a unit eigenvalue that grows (about x1.2 per step) once a
+    vertex sits in the half cell next to a wall; the displacement velocity
+    is the first-order form of the same quantity and is stable there.
 """
 from __future__ import annotations
 

@@ -10,7 +10,8 @@ the reading used everywhere in this project):
   2. membrane forces at X^n (Eqs. strainFor, bendFor, areaFor) and
      adhesion springs (Eq. adhFor);
   3. particles: probe loads from the pre-forcing fluid state, new
-     positions X^{n+1} and velocities, weak-coupling forces (Sec. 2.3);
+     positions X^{n+1} and velocities, weak-coupling forces (Sec. 2.3;
+     soft vertices impose their displacement velocity, see particles.py);
   4. spreading: Eulerian force = uniform drive g + RBC forces at X^n +
      particle coupling forces at X^n;
   5. lattice Boltzmann collide-and-stream with that force (Sec. 2.1, 2.2);
@@ -155,10 +156,8 @@ class Sim:
                 Fv = (membrane.internal_force(b.X, b.l0, b.theta0, b.A0, b.ks, b.kb, b.ka, b.p_ref)
                       + membrane.share_to_vertices(fel))
                 Xn1 = b.X + U0 + 0.5 * Fv / b.mv
-                if first:
-                    Un1 = Xn1 - b.X
-                else:
-                    Un1 = 1.5 * Xn1 - 2.0 * b.X + 0.5 * b.Xm
+                # velocity imposed by the weak coupling: displacement of the step
+                Un1 = Xn1 - b.X
             else:
                 Ftot = fel.sum(axis=0)
                 c = membrane.centroids(b.X)

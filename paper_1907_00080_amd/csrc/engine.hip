@@ -1,0 +1,948 @@
+// engine.hip - host side of the LB-IB library: set-up, workspace layout,
+// step scheduling (plain launches or captured HIP graphs), readback, C ABI.
+//
+// One Engine holds one or more independent lattice instances that advance in
+// lock-step with the same kernels (a single instance is the plain solver; a
+// batch of uneven instances is a parameter sweep).  All device state lives in
+// the caller-provided workspace; the engine never allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbib.h"
+#include "../../include/lbib_batch.h"
+#include "lbib_dev.h"
+
+using namespace lbib;
+
+namespace {
+
+struct BodyHost {
+  lbib_body_desc d;
+  std::vector<double> xy;
+};
+
+struct InstHost {
+  lbib_lattice_desc lat{};
+  std::vector<BodyHost> bodies;
+  std::vector<double> rec[2];
+  lbib_adhesion_desc adh{};
+  std::vector<double> rho0, ux0, uy0;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool valid_tile(int tx, int ty) {
+  return (tx == 64 && ty == 4) || (tx == 128 && ty == 2) || (tx == 32 && ty == 8) ||
+         (tx == 256 && ty == 1);
+}
+
+struct Layout {
+  size_t lat, body, A, B, U;
+  size_t x, y, xm, ym, xn, yn, fx, fy, l0, th0, r0x, r0y;
+  size_t mbody, cx, cy, wx, wy;
+  size_t s[9];
+  size_t bin_off, bin_cnt, bin_tmp, bin_idx, tile_inst;
+  size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x;
+  size_t step_next, step_cur, ties, red;
+  size_t total;
+};
+
+}  // namespace
+
+struct lbib_ctx {
+  std::vector<InstHost> inst;
+  int dtype = LBIB_F32;
+  int TX = 64, TY = 4;
+  int phase = 0;  // 0 setup, 1 bound, 2 running
+  // sizes
+  int ninst = 0, nm = 0, nbody = 0, nlig = 0, nrec = 0, ntiles = 0;
+  long long nodes = 0;
+  std::vector<int> marker_base, body_base, lig_base, rec_base, tile_base;
+  std::vector<long long> node_base;
+  Layout L{};
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  long long step = 0;
+  int parity = 0;  // 0: A holds the state; 1: B holds it
+  bool watchdog = false;
+  int graph_steps = 0;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::string err;
+  bool is_batch = false;
+};
+
+static std::string g_create_err;
+
+namespace {
+
+lbib_status fail(lbib_ctx* c, lbib_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ctx, LBIB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+int elem_size(int dtype) { return dtype == LBIB_F64 ? 8 : 4; }
+
+void compute_sizes(lbib_ctx* c) {
+  c->ninst = (int)c->inst.size();
+  c->nm = c->nbody = c->nlig = c->nrec = c->ntiles = 0;
+  c->nodes = 0;
+  c->marker_base.clear(); c->body_base.clear(); c->lig_base.clear();
+  c->rec_base.clear(); c->tile_base.clear(); c->node_base.clear();
+  for (auto& I : c->inst) {
+    c->marker_base.push_back(c->nm);
+    c->body_base.push_back(c->nbody);
+    c->lig_base.push_back(c->nlig);
+    c->rec_base.push_back(c->nrec);
+    c->tile_base.push_back(c->ntiles);
+    c->node_base.push_back(c->nodes);
+    for (auto& b : I.bodies) {
+      c->nm += b.d.nv;
+      c->nbody += 1;
+      if (b.d.ligand_stride > 0) c->nlig += (b.d.nv + b.d.ligand_stride - 1) / b.d.ligand_stride;
+    }
+    c->nrec += (int)(I.rec[0].size() + I.rec[1].size());
+    const int ntx = (I.lat.nx + c->TX - 1) / c->TX, nty = (I.lat.ny + c->TY - 1) / c->TY;
+    c->ntiles += ntx * nty;
+    c->nodes += (long long)I.lat.nx * I.lat.ny;
+  }
+}
+
+void compute_layout(lbib_ctx* c) {
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = cur;
+    cur = align256(cur + std::max<size_t>(bytes, 8));
+    return o;
+  };
+  Layout& L = c->L;
+  const size_t es = elem_size(c->dtype);
+  const size_t nm = std::max(c->nm, 1), nl = std::max(c->nlig, 1), nr = std::max(c->nrec, 1);
+  L.lat = take(sizeof(LatDev) * c->ninst);
+  L.body = take(sizeof(BodyDev) * std::max(c->nbody, 1));
+  L.A = take(es * 9 * c->nodes);
+  L.B = take(es * 9 * c->nodes);
+  L.U = take(es * 2 * c->nodes);
+  size_t* dbl[] = {&L.x, &L.y, &L.xm, &L.ym, &L.xn, &L.yn, &L.fx, &L.fy,
+                   &L.l0, &L.th0, &L.r0x, &L.r0y};
+  for (auto* o : dbl) *o = take(8 * nm);
+  L.mbody = take(4 * nm);
+  L.cx = take(4 * nm);
+  L.cy = take(4 * nm);
+  L.wx = take(8 * 3 * nm);
+  L.wy = take(8 * 3 * nm);
+  for (auto& s : L.s) s = take(8 * nm);
+  L.bin_off = take(4 * (c->ntiles + c->ninst));
+  L.bin_cnt = take(4 * c->ntiles);
+  L.bin_tmp = take(4 * nm);
+  L.bin_idx = take(4 * nm);
+  L.tile_inst = take(4 * c->ntiles);
+  L.lig_body = take(4 * nl);
+  L.lig_elem = take(4 * nl);
+  L.l2r = take(4 * nl);
+  L.lig_flag = take(4 * nl);
+  L.r2l = take(4 * nr);
+  L.rec_x = take(8 * nr);
+  L.step_next = take(8 * c->ninst);
+  L.step_cur = take(8 * c->ninst);
+  L.ties = take(8 * c->ninst);
+  L.red = take(8 * (6 * 1024 + 64));
+  L.total = cur;
+}
+
+template <typename T>
+Ptrs<T> make_ptrs(const lbib_ctx* c) {
+  const Layout& L = c->L;
+  char* w = c->ws;
+  Ptrs<T> p{};
+  p.lat = (LatDev*)(w + L.lat);
+  p.body = (BodyDev*)(w + L.body);
+  T* a = (T*)(w + L.A);
+  T* b = (T*)(w + L.B);
+  p.A = c->parity == 0 ? a : b;
+  p.B = c->parity == 0 ? b : a;
+  p.U = (T*)(w + L.U);
+  p.x = (double*)(w + L.x); p.y = (double*)(w + L.y);
+  p.xm = (double*)(w + L.xm); p.ym = (double*)(w + L.ym);
+  p.xn = (double*)(w + L.xn); p.yn = (double*)(w + L.yn);
+  p.fx = (double*)(w + L.fx); p.fy = (double*)(w + L.fy);
+  p.l0 = (double*)(w + L.l0); p.th0 = (double*)(w + L.th0);
+  p.r0x = (double*)(w + L.r0x); p.r0y = (double*)(w + L.r0y);
+  p.mbody = (int*)(w + L.mbody);
+  p.cx = (int*)(w + L.cx); p.cy = (int*)(w + L.cy);
+  p.wx = (double*)(w + L.wx); p.wy = (double*)(w + L.wy);
+  double** sp[] = {&p.s_len, &p.s_nx, &p.s_ny, &p.s_bc, &p.s_bnx, &p.s_bny, &p.s_bfl, &p.s_fex, &p.s_fey};
+  for (int k = 0; k < 9; ++k) *sp[k] = (double*)(w + L.s[k]);
+  p.bin_off = (int*)(w + L.bin_off);
+  p.bin_cnt = (int*)(w + L.bin_cnt);
+  p.bin_tmp = (int*)(w + L.bin_tmp);
+  p.bin_idx = (int*)(w + L.bin_idx);
+  p.tile_inst = (int*)(w + L.tile_inst);
+  p.lig_body = (int*)(w + L.lig_body);
+  p.lig_elem = (int*)(w + L.lig_elem);
+  p.l2r = (int*)(w + L.l2r);
+  p.lig_flag = (int*)(w + L.lig_flag);
+  p.r2l = (int*)(w + L.r2l);
+  p.rec_x = (double*)(w + L.rec_x);
+  p.step_next = (long long*)(w + L.step_next);
+  p.step_cur = (long long*)(w + L.step_cur);
+  p.ties = (unsigned long long*)(w + L.ties);
+  p.red = (double*)(w + L.red);
+  p.nm_total = c->nm;
+  p.nbody_total = c->nbody;
+  p.ntile_total = c->ntiles;
+  p.ninst = c->ninst;
+  p.nlig_total = c->nlig;
+  return p;
+}
+
+StepArgs step_args(const lbib_ctx* c) {
+  StepArgs a;
+  a.tile_x = c->TX;
+  a.tile_y = c->TY;
+  a.ntiles_total = c->ntiles;
+  return a;
+}
+
+// Stress-free state of a closed chain (host, float64).
+void rest_state(const std::vector<double>& xy, int nv, std::vector<double>& l0,
+                std::vector<double>& th0, double& A) {
+  l0.resize(nv);
+  th0.resize(nv);
+  A = 0.0;
+  for (int v = 0; v < nv; ++v) {
+    const int vp = (v + 1) % nv, vm = (v + nv - 1) % nv;
+    const double dxr = xy[2 * vp] - xy[2 * v], dyr = xy[2 * vp + 1] - xy[2 * v + 1];
+    const double lr = std::sqrt(dxr * dxr + dyr * dyr);
+    const double dxl = xy[2 * v] - xy[2 * vm], dyl = xy[2 * v + 1] - xy[2 * vm + 1];
+    const double ll = std::sqrt(dxl * dxl + dyl * dyl);
+    const double txr = dxr / lr, tyr = dyr / lr, txl = dxl / ll, tyl = dyl / ll;
+    l0[v] = lr;
+    th0[v] = std::atan2(txl * tyr - tyl * txr, txl * txr + tyl * tyr);
+    A += xy[2 * v] * xy[2 * vp + 1] - xy[2 * vp] * xy[2 * v + 1];
+  }
+  A *= 0.5;
+}
+
+template <typename T>
+lbib_status upload_all(lbib_ctx* c) {
+  const Layout& L = c->L;
+  hipStream_t s = c->stream;
+  std::vector<LatDev> lat(c->ninst);
+  std::vector<BodyDev> bodies(std::max(c->nbody, 1));
+  const size_t nm = std::max(c->nm, 1);
+  std::vector<double> x(nm), y(nm), l0(nm), th0(nm), r0x(nm, 0.0), r0y(nm, 0.0);
+  std::vector<int> mbody(nm, 0);
+  std::vector<int> tile_inst(std::max(c->ntiles, 1));
+  std::vector<int> lig_body(std::max(c->nlig, 1)), lig_elem(std::max(c->nlig, 1));
+  std::vector<double> rec_x(std::max(c->nrec, 1));
+  int bi = 0, li = 0;
+  for (int i = 0; i < c->ninst; ++i) {
+    InstHost& I = c->inst[i];
+    LatDev& D = lat[i];
+    std::memset(&D, 0, sizeof(D));
+    D.nx = I.lat.nx; D.ny = I.lat.ny; D.periodic_y = I.lat.periodic_y;
+    D.ntx = (D.nx + c->TX - 1) / c->TX;
+    D.nty = (D.ny + c->TY - 1) / c->TY;
+    D.tile_base = c->tile_base[i];
+    D.bin_base = c->tile_base[i] + i;
+    D.marker_base = c->marker_base[i];
+    D.body_base = c->body_base[i];
+    D.n_bodies = (int)I.bodies.size();
+    D.lig_base = c->lig_base[i];
+    D.rec_base = c->rec_base[i];
+    D.n_rec0 = (int)I.rec[0].size();
+    D.n_rec1 = (int)I.rec[1].size();
+    D.instance = I.lat.instance;
+    D.node_base = c->node_base[i];
+    D.tau = I.lat.tau; D.gx = I.lat.gx; D.gy = I.lat.gy;
+    D.seed = I.lat.seed;
+    D.y_cr = I.adh.y_cr; D.y_eq = I.adh.y_eq; D.kf0_dt = I.adh.kf0_dt; D.kr0_dt = I.adh.kr0_dt;
+    D.sigma_ts_frac = I.adh.sigma_ts_frac; D.kbt = I.adh.kbt; D.freeze = I.adh.freeze_topology;
+    for (int t = 0; t < D.ntx * D.nty; ++t) tile_inst[D.tile_base + t] = i;
+    int m = D.marker_base, nl = 0;
+    for (auto& b : I.bodies) {
+      BodyDev& B = bodies[bi];
+      std::memset(&B, 0, sizeof(B));
+      B.kind = b.d.kind; B.nv = b.d.nv; B.v0 = m; B.inst = i;
+      B.ks = b.d.ks; B.kb = b.d.kb; B.ka = b.d.ka; B.p_ref = b.d.p_ref; B.sigma = b.d.sigma;
+      B.lig_stride = b.d.ligand_stride;
+      B.lig_base = D.lig_base + nl;
+      std::vector<double> bl0, bth0;
+      double A0;
+      rest_state(b.xy, b.d.nv, bl0, bth0, A0);
+      B.A0 = A0;
+      B.mass = b.d.density_ratio * 1.0 * A0;
+      B.mv = B.mass / b.d.nv;
+      double xc = 0, yc = 0;
+      for (int v = 0; v < b.d.nv; ++v) { xc += b.xy[2 * v]; yc += b.xy[2 * v + 1]; }
+      xc /= b.d.nv; yc /= b.d.nv;
+      double r2 = 0;
+      for (int v = 0; v < b.d.nv; ++v) {
+        x[m + v] = b.xy[2 * v];
+        y[m + v] = b.xy[2 * v + 1];
+        l0[m + v] = bl0[v];
+        th0[m + v] = bth0[v];
+        mbody[m + v] = bi;
+        if (b.d.kind == LBIB_PARTICLE_RIGID) {
+          r0x[m + v] = b.xy[2 * v] - xc;
+          r0y[m + v] = b.xy[2 * v + 1] - yc;
+          r2 += r0x[m + v] * r0x[m + v] + r0y[m + v] * r0y[m + v];
+        }
+      }
+      B.xc = xc; B.yc = yc; B.theta = 0.0;
+      B.inertia = 0.5 * B.mass * (r2 / b.d.nv);
+      if (b.d.ligand_stride > 0) {
+        int k = 0;
+        for (int e = 0; e < b.d.nv; e += b.d.ligand_stride, ++k) {
+          lig_body[li] = bi;
+          lig_elem[li] = e;
+          ++li;
+        }
+        B.n_lig = k;
+        nl += k;
+      }
+      m += b.d.nv;
+      ++bi;
+    }
+    D.n_markers = m - D.marker_base;
+    D.n_lig = nl;
+    for (int w = 0; w < 2; ++w)
+      for (size_t k = 0; k < I.rec[w].size(); ++k)
+        rec_x[D.rec_base + (w == 0 ? 0 : D.n_rec0) + k] = I.rec[w][k];
+  }
+  char* w = c->ws;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  HIPCHK(c, up(L.lat, lat.data(), sizeof(LatDev) * c->ninst));
+  HIPCHK(c, up(L.body, bodies.data(), sizeof(BodyDev) * bodies.size()));
+  HIPCHK(c, up(L.x, x.data(), 8 * nm));
+  HIPCHK(c, up(L.y, y.data(), 8 * nm));
+  HIPCHK(c, up(L.xm, x.data(), 8 * nm));
+  HIPCHK(c, up(L.ym, y.data(), 8 * nm));
+  HIPCHK(c, up(L.xn, x.data(), 8 * nm));
+  HIPCHK(c, up(L.yn, y.data(), 8 * nm));
+  HIPCHK(c, hipMemsetAsync(w + L.fx, 0, 8 * nm, s));
+  HIPCHK(c, hipMemsetAsync(w + L.fy, 0, 8 * nm, s));
+  HIPCHK(c, up(L.l0, l0.data(), 8 * nm));
+  HIPCHK(c, up(L.th0, th0.data(), 8 * nm));
+  HIPCHK(c, up(L.r0x, r0x.data(), 8 * nm));
+  HIPCHK(c, up(L.r0y, r0y.data(), 8 * nm));
+  HIPCHK(c, up(L.mbody, mbody.data(), 4 * nm));
+  HIPCHK(c, up(L.tile_inst, tile_inst.data(), 4 * tile_inst.size()));
+  HIPCHK(c, up(L.lig_body, lig_body.data(), 4 * lig_body.size()));
+  HIPCHK(c, up(L.lig_elem, lig_elem.data(), 4 * lig_elem.size()));
+  HIPCHK(c, hipMemsetAsync(w + L.l2r, 0xff, 4 * std::max(c->nlig, 1), s));
+  HIPCHK(c, hipMemsetAsync(w + L.r2l, 0xff, 4 * std::max(c->nrec, 1), s));
+  HIPCHK(c, up(L.rec_x, rec_x.data(), 8 * rec_x.size()));
+  HIPCHK(c, hipMemsetAsync(w + L.step_next, 0, 8 * c->ninst, s));
+  HIPCHK(c, hipMemsetAsync(w + L.step_cur, 0, 8 * c->ninst, s));
+  HIPCHK(c, hipMemsetAsync(w + L.ties, 0, 8 * c->ninst, s));
+  // bins: empty until the first step
+  {
+    std::vector<int> off(c->ntiles + c->ninst);
+    for (int i = 0; i < c->ninst; ++i) {
+      const int nt = lat[i].ntx * lat[i].nty;
+      for (int t = 0; t <= nt; ++t) off[lat[i].bin_base + t] = lat[i].marker_base;
+    }
+    HIPCHK(c, up(L.bin_off, off.data(), 4 * off.size()));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  // populations: equilibrium of the initial fields, shifted by the weights
+  for (int i = 0; i < c->ninst; ++i) {
+    InstHost& I = c->inst[i];
+    const long long N = (long long)I.lat.nx * I.lat.ny;
+    std::vector<T> h(9 * N);
+    for (long long k = 0; k < N; ++k) {
+      const double rho = I.rho0.empty() ? 1.0 : I.rho0[k];
+      const double ux = I.ux0.empty() ? 0.0 : I.ux0[k];
+      const double uy = I.uy0.empty() ? 0.0 : I.uy0[k];
+      const double uu = ux * ux + uy * uy;
+      for (int q = 0; q < 9; ++q) {
+        const double eu = ex(q) * ux + ey(q) * uy;
+        const double w8 = wq<double>(q);
+        h[q * N + k] = T(w8 * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
+      }
+    }
+    HIPCHK(c, hipMemcpyAsync(w + L.A + 9 * c->node_base[i] * sizeof(T), h.data(), sizeof(T) * h.size(),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  HIPCHK(c, hipMemsetAsync(w + L.B, 0, sizeof(T) * 9 * c->nodes, s));
+  HIPCHK(c, hipMemsetAsync(w + L.U, 0, sizeof(T) * 2 * c->nodes, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->parity = 0;
+  c->step = 0;
+  return LBIB_OK;
+}
+
+template <typename T>
+void enqueue_steps(lbib_ctx* c, long long n) {
+  const StepArgs a = step_args(c);
+  for (long long k = 0; k < n; ++k) {
+    Ptrs<T> p = make_ptrs<T>(c);
+    launch_lagrangian<T>(p, a, c->stream);
+    launch_lb_fused<T>(p, a, c->stream);
+    launch_advance<T>(p, c->stream);
+    c->parity ^= 1;
+  }
+}
+
+void drop_graphs(lbib_ctx* c) {
+  for (auto& g : c->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+template <typename T>
+lbib_status run_steps(lbib_ctx* c, long long n) {
+  const int G = c->graph_steps;
+  if (G > 0) {
+    while (n >= G) {
+      int par = c->parity;
+      if (!c->gexec[par]) {
+        hipGraph_t graph;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_steps<T>(c, G);
+        HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+        c->parity = par;  // capture did not execute anything
+        hipGraphExec_t ex_;
+        hipError_t e = hipGraphInstantiate(&ex_, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(c, LBIB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        c->gexec[par] = ex_;
+      }
+      HIPCHK(c, hipGraphLaunch(c->gexec[par], c->stream));
+      c->parity = par ^ (G & 1);
+      c->step += G;
+      n -= G;
+    }
+  }
+  enqueue_steps<T>(c, n);
+  c->step += n;
+  HIPCHK(c, hipGetLastError());
+  return LBIB_OK;
+}
+
+template <typename T>
+lbib_status diag_impl(lbib_ctx* c, double out[6]) {
+  Ptrs<T> p = make_ptrs<T>(c);
+  double* dout = p.red + 6 * 1024;
+  launch_diag<T>(p, step_args(c), c->nodes, dout, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(out, dout, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBIB_OK;
+}
+
+template <typename T>
+lbib_status fields_impl(lbib_ctx* c, int inst, double* rho, double* ux, double* uy) {
+  const InstHost& I = c->inst[inst];
+  const long long N = (long long)I.lat.nx * I.lat.ny;
+  Ptrs<T> p = make_ptrs<T>(c);
+  // stage in the non-current population buffer (rewritten in full by the next step)
+  double* stage = (double*)p.B;
+  launch_fields<T>(p, step_args(c), inst, stage, stage + N, stage + 2 * N, I.lat.nx, I.lat.ny,
+                   c->node_base[inst], c->stream);
+  HIPCHK(c, hipGetLastError());
+  std::vector<double> tmp(3 * N);
+  HIPCHK(c, hipMemcpyAsync(tmp.data(), stage, 3 * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (rho) std::memcpy(rho, tmp.data(), N * sizeof(double));
+  if (ux) std::memcpy(ux, tmp.data() + N, N * sizeof(double));
+  if (uy) std::memcpy(uy, tmp.data() + 2 * N, N * sizeof(double));
+  return LBIB_OK;
+}
+
+lbib_status check_body(lbib_ctx* c, int inst, int body) {
+  if (inst < 0 || inst >= c->ninst) return fail(c, LBIB_EINVAL, "instance out of range");
+  if (body < 0 || body >= (int)c->inst[inst].bodies.size()) return fail(c, LBIB_EINVAL, "body out of range");
+  return LBIB_OK;
+}
+
+int body_v0(const lbib_ctx* c, int inst, int body) {
+  int v = c->marker_base[inst];
+  for (int k = 0; k < body; ++k) v += c->inst[inst].bodies[k].d.nv;
+  return v;
+}
+
+// Dynamic-state regions saved by get_state.
+std::vector<std::pair<size_t, size_t>> state_regions(const lbib_ctx* c) {
+  const Layout& L = c->L;
+  const size_t es = elem_size(c->dtype);
+  const size_t nm = std::max(c->nm, 1), nl = std::max(c->nlig, 1), nr = std::max(c->nrec, 1);
+  const size_t Aoff = c->parity == 0 ? L.A : L.B;
+  std::vector<std::pair<size_t, size_t>> r = {
+      {Aoff, es * 9 * c->nodes}, {L.U, es * 2 * c->nodes},
+      {L.body, sizeof(BodyDev) * std::max(c->nbody, 1)},
+      {L.x, 8 * nm}, {L.y, 8 * nm}, {L.xm, 8 * nm}, {L.ym, 8 * nm}, {L.xn, 8 * nm}, {L.yn, 8 * nm},
+      {L.fx, 8 * nm}, {L.fy, 8 * nm}, {L.cx, 4 * nm}, {L.cy, 4 * nm}, {L.wx, 24 * nm}, {L.wy, 24 * nm},
+      {L.bin_off, 4 * (size_t)(c->ntiles + c->ninst)}, {L.bin_idx, 4 * nm},
+      {L.l2r, 4 * nl}, {L.r2l, 4 * nr}, {L.step_next, 8 * (size_t)c->ninst},
+      {L.step_cur, 8 * (size_t)c->ninst}, {L.ties, 8 * (size_t)c->ninst}};
+  return r;
+}
+
+struct StateHeader {
+  uint64_t magic, bytes, step;
+  int32_t dtype, ninst, nm, nbody, nlig, nrec, ntiles, pad;
+  int64_t nodes;
+};
+constexpr uint64_t kMagic = 0x4c4249425354ull;  // "LBIBST"
+
+}  // namespace
+
+// =============================================================== C ABI
+extern "C" {
+
+uint32_t lbib_abi_version(void) { return LBIB_ABI_VERSION; }
+
+const char* lbib_status_string(int32_t s) {
+  switch (s) {
+    case LBIB_OK: return "LBIB_OK";
+    case LBIB_EINVAL: return "LBIB_EINVAL";
+    case LBIB_ESTATE: return "LBIB_ESTATE";
+    case LBIB_EHIP: return "LBIB_EHIP";
+    case LBIB_ENOSPACE: return "LBIB_ENOSPACE";
+    case LBIB_EUNSTABLE: return "LBIB_EUNSTABLE";
+    default: return "LBIB_UNKNOWN";
+  }
+}
+
+const char* lbib_last_error(const lbib_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+lbib_status lbib_create(const lbib_lattice_desc* d, lbib_ctx** out) {
+  if (!d || !out) return fail(nullptr, LBIB_EINVAL, "NULL argument");
+  if (d->nx < 1 || d->ny < 1) return fail(nullptr, LBIB_EINVAL, "nx and ny must be >= 1");
+  if ((long long)d->nx * d->ny > (1ll << 31)) return fail(nullptr, LBIB_EINVAL, "lattice too large");
+  if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return fail(nullptr, LBIB_EINVAL, "tau must be > 1/2");
+  if (d->dtype != LBIB_F32 && d->dtype != LBIB_F64) return fail(nullptr, LBIB_EINVAL, "bad dtype");
+  int tx = d->tile_x, ty = d->tile_y;
+  if (tx == 0 && ty == 0) { tx = 64; ty = 4; }
+  if (!valid_tile(tx, ty)) return fail(nullptr, LBIB_EINVAL, "unsupported tile shape");
+  lbib_ctx* c = new lbib_ctx();
+  c->dtype = d->dtype;
+  c->TX = tx;
+  c->TY = ty;
+  InstHost I;
+  I.lat = *d;
+  I.adh.y_cr = 0.0;  // no bonds unless set
+  I.adh.y_eq = 0.0;
+  I.adh.kbt = 1.0;
+  c->inst.push_back(I);
+  *out = c;
+  return LBIB_OK;
+}
+
+lbib_status lbib_add_body(lbib_ctx* c, const lbib_body_desc* d, const double* xy, int32_t* id) {
+  if (!c || !d || !xy) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 0 || c->is_batch) return fail(c, LBIB_ESTATE, "bodies can only be added during set-up");
+  if (d->nv < 3) return fail(c, LBIB_EINVAL, "a body needs nv >= 3");
+  if (d->kind < 0 || d->kind > 2) return fail(c, LBIB_EINVAL, "bad body kind");
+  if (d->ligand_stride < 0) return fail(c, LBIB_EINVAL, "ligand_stride must be >= 0");
+  if (d->kind != LBIB_RBC_KINEMATIC && !(d->density_ratio > 0))
+    return fail(c, LBIB_EINVAL, "particles need density_ratio > 0");
+  BodyHost b;
+  b.d = *d;
+  b.xy.assign(xy, xy + 2 * (size_t)d->nv);
+  for (double v : b.xy)
+    if (!std::isfinite(v)) return fail(c, LBIB_EINVAL, "non-finite vertex");
+  std::vector<double> l0, th0;
+  double A;
+  rest_state(b.xy, d->nv, l0, th0, A);
+  if (!(A > 0)) return fail(c, LBIB_EINVAL, "vertices must run counter-clockwise (positive area)");
+  for (double l : l0)
+    if (!(l > 0)) return fail(c, LBIB_EINVAL, "coincident consecutive vertices");
+  auto& I = c->inst.back();
+  if (id) *id = (int32_t)I.bodies.size();
+  I.bodies.push_back(b);
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_receptors(lbib_ctx* c, int32_t wall, const double* x, int32_t n) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 0 || c->is_batch) return fail(c, LBIB_ESTATE, "receptors can only be set during set-up");
+  if (wall != 0 && wall != 1) return fail(c, LBIB_EINVAL, "wall must be 0 or 1");
+  if (n < 0 || (n > 0 && !x)) return fail(c, LBIB_EINVAL, "bad receptor array");
+  auto& I = c->inst.back();
+  for (int k = 0; k < n; ++k) {
+    if (!(x[k] >= 0.0 && x[k] < I.lat.nx)) return fail(c, LBIB_EINVAL, "receptor x outside [0, nx)");
+    if (k > 0 && !(x[k] > x[k - 1])) return fail(c, LBIB_EINVAL, "receptor x must increase strictly");
+  }
+  I.rec[wall].assign(x, x + n);
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_adhesion(lbib_ctx* c, const lbib_adhesion_desc* d) {
+  if (!c || !d) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 0 || c->is_batch) return fail(c, LBIB_ESTATE, "adhesion can only be set during set-up");
+  if (!(d->kbt > 0) || d->y_cr < 0 || d->kf0_dt < 0 || d->kr0_dt < 0)
+    return fail(c, LBIB_EINVAL, "bad adhesion parameters");
+  c->inst.back().adh = *d;
+  return LBIB_OK;
+}
+
+lbib_status lbib_init_fields(lbib_ctx* c, const double* rho, const double* ux, const double* uy) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 0 || c->is_batch) return fail(c, LBIB_ESTATE, "fields can only be initialised during set-up");
+  auto& I = c->inst.back();
+  const size_t N = (size_t)I.lat.nx * I.lat.ny;
+  for (const double* a : {rho, ux, uy})
+    if (a)
+      for (size_t k = 0; k < N; ++k)
+        if (!std::isfinite(a[k])) return fail(c, LBIB_EINVAL, "non-finite initial field");
+  if (rho)
+    for (size_t k = 0; k < N; ++k)
+      if (!(rho[k] > 0)) return fail(c, LBIB_EINVAL, "initial density must be positive");
+  I.rho0 = rho ? std::vector<double>(rho, rho + N) : std::vector<double>();
+  I.ux0 = ux ? std::vector<double>(ux, ux + N) : std::vector<double>();
+  I.uy0 = uy ? std::vector<double>(uy, uy + N) : std::vector<double>();
+  return LBIB_OK;
+}
+
+lbib_status lbib_workspace_query(const lbib_ctx* cc, size_t* bytes) {
+  lbib_ctx* c = const_cast<lbib_ctx*>(cc);
+  if (!c || !bytes) return fail(c, LBIB_EINVAL, "NULL argument");
+  compute_sizes(c);
+  compute_layout(c);
+  *bytes = c->L.total;
+  return LBIB_OK;
+}
+
+lbib_status lbib_bind(lbib_ctx* c, void* ws, size_t bytes, void* stream) {
+  if (!c || !ws) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 0) return fail(c, LBIB_ESTATE, "already bound");
+  if (((uintptr_t)ws) & 255) return fail(c, LBIB_EINVAL, "workspace must be 256-byte aligned");
+  compute_sizes(c);
+  compute_layout(c);
+  if (bytes < c->L.total) return fail(c, LBIB_ENOSPACE, "workspace smaller than lbib_workspace_query");
+  c->ws = (char*)ws;
+  c->ws_bytes = bytes;
+  c->stream = (hipStream_t)stream;
+  c->phase = 1;
+  return LBIB_OK;
+}
+
+lbib_status lbib_finalize_setup(lbib_ctx* c) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 1) return fail(c, LBIB_ESTATE, "bind a workspace before finalize_setup");
+  lbib_status s = c->dtype == LBIB_F64 ? upload_all<double>(c) : upload_all<float>(c);
+  if (s != LBIB_OK) return s;
+  c->phase = 2;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_watchdog(lbib_ctx* c, int32_t on) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  c->watchdog = on != 0;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_graph_steps(lbib_ctx* c, int32_t steps) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (steps < 0 || (steps & 1)) return fail(c, LBIB_EINVAL, "graph steps must be even and >= 0");
+  if (steps != c->graph_steps) drop_graphs(c);
+  c->graph_steps = steps;
+  return LBIB_OK;
+}
+
+lbib_status lbib_step(lbib_ctx* c, int64_t n) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "finalize_setup before stepping");
+  if (n < 0) return fail(c, LBIB_EINVAL, "nsteps must be >= 0");
+  lbib_status s = c->dtype == LBIB_F64 ? run_steps<double>(c, n) : run_steps<float>(c, n);
+  if (s != LBIB_OK) return s;
+  if (c->watchdog) {
+    double d[6];
+    s = c->dtype == LBIB_F64 ? diag_impl<double>(c, d) : diag_impl<float>(c, d);
+    if (s != LBIB_OK) return s;
+    if (d[5] > 0 || !(d[3] > 0))
+      return fail(c, LBIB_EUNSTABLE, "watchdog: non-finite population or non-positive density");
+  }
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_fields(lbib_ctx* c, double* rho, double* ux, double* uy) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  return c->dtype == LBIB_F64 ? fields_impl<double>(c, 0, rho, ux, uy)
+                              : fields_impl<float>(c, 0, rho, ux, uy);
+}
+
+static lbib_status copy_marker_pair(lbib_ctx* c, int inst, int body, size_t ox, size_t oy, double* xy) {
+  if (!c || !xy) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  lbib_status s = check_body(c, inst, body);
+  if (s != LBIB_OK) return s;
+  const int v0 = body_v0(c, inst, body), nv = c->inst[inst].bodies[body].d.nv;
+  std::vector<double> a(nv), b(nv);
+  HIPCHK(c, hipMemcpyAsync(a.data(), c->ws + ox + 8 * (size_t)v0, 8 * nv, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(b.data(), c->ws + oy + 8 * (size_t)v0, 8 * nv, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int v = 0; v < nv; ++v) {
+    xy[2 * v] = a[v];
+    xy[2 * v + 1] = b[v];
+  }
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_markers(lbib_ctx* c, int32_t body, double* xy) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  return copy_marker_pair(c, 0, body, c->L.x, c->L.y, xy);
+}
+
+lbib_status lbib_get_marker_forces(lbib_ctx* c, int32_t body, double* fxy) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  return copy_marker_pair(c, 0, body, c->L.fx, c->L.fy, fxy);
+}
+
+lbib_status lbib_set_markers(lbib_ctx* c, int32_t body, const double* xy, const double* xyp) {
+  if (!c || !xy) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  lbib_status s = check_body(c, 0, body);
+  if (s != LBIB_OK) return s;
+  const int v0 = body_v0(c, 0, body), nv = c->inst[0].bodies[body].d.nv;
+  if (!xyp) xyp = xy;
+  std::vector<double> a(nv), b(nv), am(nv), bm(nv);
+  for (int v = 0; v < nv; ++v) {
+    a[v] = xy[2 * v]; b[v] = xy[2 * v + 1];
+    am[v] = xyp[2 * v]; bm[v] = xyp[2 * v + 1];
+    if (!std::isfinite(a[v]) || !std::isfinite(b[v]) || !std::isfinite(am[v]) || !std::isfinite(bm[v]))
+      return fail(c, LBIB_EINVAL, "non-finite marker position");
+  }
+  const size_t o = 8 * (size_t)v0;
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.x + o, a.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.y + o, b.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.xm + o, am.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.ym + o, bm.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBIB_OK;
+}
+
+lbib_status lbib_num_ligands(const lbib_ctx* cc, int32_t* n) {
+  lbib_ctx* c = const_cast<lbib_ctx*>(cc);
+  if (!c || !n) return fail(c, LBIB_EINVAL, "NULL argument");
+  int k = 0;
+  for (auto& b : c->inst[0].bodies)
+    if (b.d.ligand_stride > 0) k += (b.d.nv + b.d.ligand_stride - 1) / b.d.ligand_stride;
+  *n = k;
+  return LBIB_OK;
+}
+
+static lbib_status bonds_get(lbib_ctx* c, int inst, int32_t* l2r, int32_t* nb) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  if (inst < 0 || inst >= c->ninst) return fail(c, LBIB_EINVAL, "instance out of range");
+  const int base = c->lig_base[inst];
+  const int n = (inst + 1 < c->ninst ? c->lig_base[inst + 1] : c->nlig) - base;
+  std::vector<int32_t> v(std::max(n, 1));
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(v.data(), c->ws + c->L.l2r + 4 * (size_t)base, 4 * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  int cnt = 0;
+  for (int k = 0; k < n; ++k) {
+    if (v[k] >= 0) ++cnt;
+    if (l2r) l2r[k] = v[k];
+  }
+  if (nb) *nb = cnt;
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_bonds(lbib_ctx* c, int32_t* l2r, int32_t* nb) { return bonds_get(c, 0, l2r, nb); }
+
+lbib_status lbib_set_bonds(lbib_ctx* c, const int32_t* l2r) {
+  if (!c || !l2r) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  const int n = c->ninst > 1 ? c->lig_base[1] : c->nlig;
+  const int nr = (int)(c->inst[0].rec[0].size() + c->inst[0].rec[1].size());
+  std::vector<int32_t> r2l(std::max(nr, 1), -1);
+  for (int k = 0; k < n; ++k) {
+    const int r = l2r[k];
+    if (r < -1 || r >= nr) return fail(c, LBIB_EINVAL, "receptor index out of range");
+    if (r >= 0) {
+      if (r2l[r] >= 0) return fail(c, LBIB_EINVAL, "receptor bonded twice");
+      r2l[r] = k;  // instance 0: global ligand id == local id
+    }
+  }
+  if (n > 0)
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.l2r, l2r, 4 * n, hipMemcpyHostToDevice, c->stream));
+  if (nr > 0)
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.r2l, r2l.data(), 4 * nr, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_state(lbib_ctx* c, void* blob, size_t* bytes) {
+  if (!c || !bytes) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  auto regs = state_regions(c);
+  size_t total = sizeof(StateHeader);
+  for (auto& r : regs) total += r.second;
+  if (!blob) {
+    *bytes = total;
+    return LBIB_OK;
+  }
+  if (*bytes < total) return fail(c, LBIB_EINVAL, "state buffer too small");
+  StateHeader h{kMagic, total, (uint64_t)c->step, c->dtype, c->ninst, c->nm, c->nbody, c->nlig,
+                c->nrec, c->ntiles, 0, c->nodes};
+  char* o = (char*)blob;
+  std::memcpy(o, &h, sizeof(h));
+  o += sizeof(h);
+  for (auto& r : regs) {
+    HIPCHK(c, hipMemcpyAsync(o, c->ws + r.first, r.second, hipMemcpyDeviceToHost, c->stream));
+    o += r.second;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *bytes = total;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_state(lbib_ctx* c, const void* blob, size_t bytes) {
+  if (!c || !blob) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  StateHeader h;
+  if (bytes < sizeof(h)) return fail(c, LBIB_EINVAL, "state blob too small");
+  std::memcpy(&h, blob, sizeof(h));
+  if (h.magic != kMagic || h.bytes != bytes || h.dtype != c->dtype || h.ninst != c->ninst ||
+      h.nm != c->nm || h.nbody != c->nbody || h.nlig != c->nlig || h.nrec != c->nrec ||
+      h.ntiles != c->ntiles || h.nodes != c->nodes)
+    return fail(c, LBIB_EINVAL, "state blob does not match this context");
+  auto regs = state_regions(c);
+  const char* o = (const char*)blob + sizeof(h);
+  for (auto& r : regs) {
+    HIPCHK(c, hipMemcpyAsync(c->ws + r.first, o, r.second, hipMemcpyHostToDevice, c->stream));
+    o += r.second;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->step = (long long)h.step;
+  return LBIB_OK;
+}
+
+lbib_status lbib_diagnostics(lbib_ctx* c, lbib_diag* out) {
+  if (!c || !out) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  double d[6];
+  lbib_status s = c->dtype == LBIB_F64 ? diag_impl<double>(c, d) : diag_impl<float>(c, d);
+  if (s != LBIB_OK) return s;
+  out->step = c->step;
+  out->mass = d[0];
+  out->mom_x = d[1];
+  out->mom_y = d[2];
+  out->rho_min = d[3];
+  out->u_max = d[4];
+  out->nonfinite = (int64_t)d[5];
+  int32_t nb = 0;
+  int tot = 0;
+  for (int i = 0; i < c->ninst; ++i) {
+    s = bonds_get(c, i, nullptr, &nb);
+    if (s != LBIB_OK) return s;
+    tot += nb;
+  }
+  out->nbonds = tot;
+  return LBIB_OK;
+}
+
+lbib_status lbib_time_lattice_kernel(lbib_ctx* c, int32_t reps, double* avg_ms) {
+  if (!c || !avg_ms) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  if (c->step < 1) return fail(c, LBIB_ESTATE, "needs one completed step");
+  if (reps < 1) return fail(c, LBIB_EINVAL, "reps must be >= 1");
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  const StepArgs a = step_args(c);
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  for (int r = 0; r < reps; ++r) {
+    if (c->dtype == LBIB_F64) launch_lb_fused<double>(make_ptrs<double>(c), a, c->stream);
+    else launch_lb_fused<float>(make_ptrs<float>(c), a, c->stream);
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_step(const lbib_ctx* cc, int64_t* step) {
+  lbib_ctx* c = const_cast<lbib_ctx*>(cc);
+  if (!c || !step) return fail(c, LBIB_EINVAL, "NULL argument");
+  *step = c->step;
+  return LBIB_OK;
+}
+
+lbib_status lbib_destroy(lbib_ctx* c) {
+  if (!c) return LBIB_OK;
+  drop_graphs(c);
+  delete c;
+  return LBIB_OK;
+}
+
+// ------------------------------------------------------------ batch (sweeps)
+lbib_status lbib_batch_create(const lbib_ctx* const* insts, int32_t n, int32_t tile_x, int32_t tile_y,
+                              lbib_ctx** out) {
+  if (!insts || !out || n < 1) return fail(nullptr, LBIB_EINVAL, "bad batch arguments");
+  int tx = tile_x, ty = tile_y;
+  if (tx == 0 && ty == 0) { tx = 64; ty = 4; }
+  if (!valid_tile(tx, ty)) return fail(nullptr, LBIB_EINVAL, "unsupported tile shape");
+  const int dtype = insts[0] ? insts[0]->dtype : -1;
+  for (int i = 0; i < n; ++i) {
+    if (!insts[i]) return fail(nullptr, LBIB_EINVAL, "NULL instance");
+    if (insts[i]->phase != 0 || insts[i]->is_batch || insts[i]->inst.size() != 1)
+      return fail(nullptr, LBIB_ESTATE, "instances must be single-lattice contexts in set-up");
+    if (insts[i]->dtype != dtype) return fail(nullptr, LBIB_EINVAL, "instances must share the dtype");
+  }
+  lbib_ctx* c = new lbib_ctx();
+  c->dtype = dtype;
+  c->TX = tx;
+  c->TY = ty;
+  c->is_batch = true;
+  for (int i = 0; i < n; ++i) c->inst.push_back(insts[i]->inst[0]);
+  *out = c;
+  return LBIB_OK;
+}
+
+lbib_status lbib_batch_size(const lbib_ctx* c, int32_t* n) {
+  if (!c || !n) return LBIB_EINVAL;
+  *n = (int32_t)c->inst.size();
+  return LBIB_OK;
+}
+
+lbib_status lbib_batch_get_fields(lbib_ctx* c, int32_t inst, double* rho, double* ux, double* uy) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  if (inst < 0 || inst >= c->ninst) return fail(c, LBIB_EINVAL, "instance out of range");
+  return c->dtype == LBIB_F64 ? fields_impl<double>(c, inst, rho, ux, uy)
+                              : fields_impl<float>(c, inst, rho, ux, uy);
+}
+
+lbib_status lbib_batch_get_markers(lbib_ctx* c, int32_t inst, int32_t body, double* xy) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  return copy_marker_pair(c, inst, body, c->L.x, c->L.y, xy);
+}
+
+lbib_status lbib_batch_get_bonds(lbib_ctx* c, int32_t inst, int32_t* l2r, int32_t* nb) {
+  return bonds_get(c, inst, l2r, nb);
+}
+
+}  // extern "C"

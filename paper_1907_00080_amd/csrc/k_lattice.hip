@@ -1,0 +1,342 @@
+// k_lattice.hip - fused D2Q9 collide-and-stream with gathered IB spreading (gfx950).
+//
+// One workgroup owns one TX x TY tile of nodes (one node per lane).  Per node:
+//   1. Eulerian force F = g + sum_k F_k delta(x - X_k) (Sec. 2.2 spreading):
+//      gathered from the markers binned in the 3x3 neighbouring tiles, staged
+//      in LDS, summed in a fixed order (bins are sorted by marker id), so the
+//      result is deterministic and needs no atomics.  Tiles whose
+//      neighbourhood holds no marker skip this and use F = g.
+//   2. Pull streaming h_i(x) <- h*_i(x - e_i), x periodic, halfway bounce-back
+//      at y = -1/2 and ny - 1/2 (Sec. 3 walls; Eq. BGK streaming part).
+//   3. rho = 1 + sum h, u = (sum h e + F/2)/rho, BGK relaxation towards the
+//      equilibrium of Eq. (feq) plus Guo's source of Eq. (ForcingTerm):
+//      h* = h + (h_eq - h)/tau + (1 - 1/(2 tau)) w_i [3(e-u) + 9(e.u)e].F
+//   4. Store h*, and u on touched tiles (interpolation input of the markers).
+// Populations are stored shifted by their rest weights (h = f - w) so that
+// float32 keeps the small deviations of the low-Mach flows accurately.
+//
+// Workgroup -> tile mapping is XCD aware: consecutive workgroups go to the 8
+// XCDs in turn, so XCD k receives a contiguous band of tiles (its own L2 then
+// holds the rows that neighbouring tiles share).
+#include "lbib_dev.h"
+
+namespace lbib {
+
+constexpr int kCap = 256;  // markers staged in LDS per chunk
+
+// Sum of the three stencil weights of a marker that land on column/row `d`
+// relative to its centre.  d = node - centre, wrapped into a short range.
+__device__ inline int near_offset(int d, int n, bool periodic) {
+  if (periodic) {
+    if (d > 1) d -= n;
+    else if (d < -1) d += n;
+  }
+  return d;
+}
+
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total) {
+  static_assert(TX * TY == kCap, "one lane per LDS slot");
+  const int g = blockIdx.x;
+  const int per = (ntiles_total + 7) >> 3;
+  const int tile = (g & 7) * per + (g >> 3);
+  if (tile >= ntiles_total) return;
+  const int inst = p.tile_inst[tile];
+  const LatDev& L = p.lat[inst];
+  const int nx = L.nx, ny = L.ny, ntx = L.ntx, nty = L.nty;
+  const bool pery = L.periodic_y != 0;
+  const int local = tile - L.tile_base;
+  const int tx = local % ntx, ty = local / ntx;
+  const int lane = threadIdx.x;
+  const int x = tx * TX + (lane % TX);
+  const int y = ty * TY + (lane / TX);
+  const bool inside = x < nx && y < ny;
+
+  // ---- neighbouring bins: lane k < 9 inspects neighbour (k/3 - 1, k%3 - 1);
+  // duplicates (lattices of fewer than 3 tiles per direction) count once.
+  __shared__ int s_bstart[9], s_bcount[9];
+  if (lane < 9) {
+    const int dy = lane / 3 - 1, dx = lane % 3 - 1;
+    const int c = wrap_i(tx + dx, ntx);
+    bool keep = true;
+    for (int d = -1; d < dx; ++d) keep &= wrap_i(tx + d, ntx) != c;
+    int r = ty + dy;
+    if (pery) {
+      r = wrap_i(r, nty);
+      for (int d = -1; d < dy; ++d) keep &= wrap_i(ty + d, nty) != r;
+    } else {
+      keep &= r >= 0 && r < nty;
+    }
+    int s0 = 0, s1 = 0;
+    if (keep) {
+      const int bi = L.bin_base + r * ntx + c;
+      s0 = p.bin_off[bi];
+      s1 = p.bin_off[bi + 1];
+    }
+    s_bstart[lane] = s0;
+    s_bcount[lane] = s1 - s0;
+  }
+  __syncthreads();
+  int M = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M += s_bcount[k];
+
+  T Fx = T(L.gx), Fy = T(L.gy);
+  if (M > 0) {
+    __shared__ int s_cx[kCap], s_cy[kCap];
+    __shared__ T s_w[8][kCap];   // wx0..2, wy0..2, Fx, Fy
+    double ax = 0.0, ay = 0.0;
+    const bool small_x = nx < 3, small_y = pery && ny < 3;
+    for (int c0 = 0; c0 < M; c0 += kCap) {
+      __syncthreads();
+      int j = c0 + lane;
+      if (j < M) {
+        int k = 0, jj = j;
+        while (jj >= s_bcount[k]) { jj -= s_bcount[k]; ++k; }
+        int m = p.bin_idx[s_bstart[k] + jj];
+        s_cx[lane] = p.cx[m];
+        s_cy[lane] = p.cy[m];
+        const int nm = p.nm_total;
+        s_w[0][lane] = T(p.wx[m]);
+        s_w[1][lane] = T(p.wx[nm + m]);
+        s_w[2][lane] = T(p.wx[2 * nm + m]);
+        s_w[3][lane] = T(p.wy[m]);
+        s_w[4][lane] = T(p.wy[nm + m]);
+        s_w[5][lane] = T(p.wy[2 * nm + m]);
+        s_w[6][lane] = T(p.fx[m]);
+        s_w[7][lane] = T(p.fy[m]);
+      }
+      __syncthreads();
+      const int cnt = min(kCap, M - c0);
+      if (inside) {
+        if (!small_x && !small_y) {
+          for (int q = 0; q < cnt; ++q) {
+            int dx = near_offset(x - s_cx[q], nx, true);
+            if (dx < -1 || dx > 1) continue;
+            int dy = near_offset(y - s_cy[q], ny, pery);
+            if (dy < -1 || dy > 1) continue;
+            T w = s_w[dx + 1][q] * s_w[3 + dy + 1][q];
+            ax += double(s_w[6][q] * w);
+            ay += double(s_w[7][q] * w);
+          }
+        } else {
+          for (int q = 0; q < cnt; ++q) {
+            T wxs = 0, wys = 0;
+            for (int a = 0; a < 3; ++a) {
+              if (wrap_i(s_cx[q] + a - 1, nx) == x) wxs += s_w[a][q];
+              int r = s_cy[q] + a - 1;
+              if (pery) r = wrap_i(r, ny);
+              if (r == y) wys += s_w[3 + a][q];
+            }
+            T w = wxs * wys;
+            ax += double(s_w[6][q] * w);
+            ay += double(s_w[7][q] * w);
+          }
+        }
+      }
+    }
+    Fx = T(double(Fx) + ax);
+    Fy = T(double(Fy) + ay);
+  }
+  if (!inside) return;
+
+  // ---- pull streaming with halfway bounce-back
+  const long long N = (long long)nx * ny;
+  const T* __restrict__ A = p.A + 9 * L.node_base;
+  T* __restrict__ B = p.B + 9 * L.node_base;
+  const long long node = (long long)y * nx + x;
+  T h[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    int xs = x - ex(i);
+    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+    int ys = y - ey(i);
+    if (ys < 0 || ys >= ny) {
+      if (pery) {
+        ys = ys < 0 ? ys + ny : ys - ny;
+        h[i] = A[i * N + (long long)ys * nx + xs];
+      } else {
+        h[i] = A[opp(i) * N + node];
+      }
+    } else {
+      h[i] = A[i * N + (long long)ys * nx + xs];
+    }
+  }
+  // ---- moments and forced BGK collision
+  const T drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+  const T rho = T(1) + drho;
+  const T jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+  const T jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+  const T inv_rho = T(1) / rho;
+  const T ux = (jx + T(0.5) * Fx) * inv_rho;
+  const T uy = (jy + T(0.5) * Fy) * inv_rho;
+  const T uu = ux * ux + uy * uy;
+  const T omega = T(1.0 / L.tau);
+  const T pre = T(1.0 - 0.5 / L.tau);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const T exi = T(ex(i)), eyi = T(ey(i));
+    const T eu = exi * ux + eyi * uy;
+    const T heq = wq<T>(i) * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu));
+    const T src = pre * wq<T>(i) *
+                  ((T(3) * (exi - ux) + T(9) * eu * exi) * Fx + (T(3) * (eyi - uy) + T(9) * eu * eyi) * Fy);
+    B[i * N + node] = h[i] + omega * (heq - h[i]) + src;
+  }
+  if (M > 0) {
+    T* U = p.U + 2 * L.node_base;
+    U[node] = ux;
+    U[N + node] = uy;
+  }
+}
+
+// Physical fields of the last step from its post-collision populations:
+// collision conserves mass, so rho = 1 + sum h*; the forced BGK step leaves
+// a post-collision momentum sum h* e = rho u + F/2, so where F is the uniform
+// drive alone rho u = sum h* e - g/2.  Touched tiles take u from the velocity
+// buffer written by the fused kernel (their F includes the IB forces).
+template <typename T>
+__global__ void k_fields(Ptrs<T> p, int inst, int TX, int TY, double* rho_o, double* ux_o,
+                         double* uy_o) {
+  const LatDev& L = p.lat[inst];
+  const long long N = (long long)L.nx * L.ny;
+  long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int x = (int)(node % L.nx), y = (int)(node / L.nx);
+  const T* A = p.A + 9 * L.node_base;  // A holds the newest post-collision populations
+  double h[kQ];
+  for (int i = 0; i < kQ; ++i) h[i] = double(A[i * N + node]);
+  double drho = 0, jx = 0, jy = 0;
+  for (int i = 0; i < kQ; ++i) {
+    drho += h[i];
+    jx += ex(i) * h[i];
+    jy += ey(i) * h[i];
+  }
+  const double rho = 1.0 + drho;
+  // touched tile?
+  const int tx = x / TX, ty = y / TY;
+  bool touched = false;
+  for (int dy = -1; dy <= 1 && !touched; ++dy) {
+    int r = ty + dy;
+    if (L.periodic_y) r = wrap_i(r, L.nty);
+    else if (r < 0 || r >= L.nty) continue;
+    for (int dx = -1; dx <= 1; ++dx) {
+      int c = wrap_i(tx + dx, L.ntx);
+      int bi = L.bin_base + r * L.ntx + c;
+      if (p.bin_off[bi + 1] > p.bin_off[bi]) { touched = true; break; }
+    }
+  }
+  double ux, uy;
+  if (touched) {
+    const T* U = p.U + 2 * L.node_base;
+    ux = double(U[node]);
+    uy = double(U[N + node]);
+  } else {
+    ux = (jx - 0.5 * L.gx) / rho;
+    uy = (jy - 0.5 * L.gy) / rho;
+  }
+  if (rho_o) rho_o[node] = rho;
+  if (ux_o) ux_o[node] = ux;
+  if (uy_o) uy_o[node] = uy;
+}
+
+// Deterministic two-pass reduction of mass, momentum, min rho, max |u| and
+// non-finite count over all nodes of all instances (diagnostics/watchdog).
+// Pass 1: fixed tree per workgroup into red[6 * block]; pass 2 in order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag1(Ptrs<T> p, long long nodes_total, double* part) {
+  __shared__ double s[6][256];
+  const int t = threadIdx.x;
+  double m = 0, px = 0, py = 0, rmin = 1e300, umax = 0, bad = 0;
+  for (long long g = (long long)blockIdx.x * 256 + t; g < nodes_total; g += (long long)gridDim.x * 256) {
+    // locate instance: linear scan is fine for diagnostics (few instances)
+    int inst = 0;
+    while (inst + 1 < p.ninst && p.lat[inst + 1].node_base <= g) ++inst;
+    const LatDev& L = p.lat[inst];
+    const long long N = (long long)L.nx * L.ny;
+    const long long node = g - L.node_base;
+    const T* A = p.A + 9 * L.node_base;
+    double drho = 0, jx = 0, jy = 0;
+    bool fin = true;
+    for (int i = 0; i < kQ; ++i) {
+      double v = double(A[i * N + node]);
+      fin &= isfinite(v);
+      drho += v;
+      jx += ex(i) * v;
+      jy += ey(i) * v;
+    }
+    const double rho = 1.0 + drho;
+    // momentum of the post-collision state minus the drive's half force;
+    // exact for nodes without IB force, diagnostic elsewhere
+    const double rux = jx - 0.5 * L.gx, ruy = jy - 0.5 * L.gy;
+    if (!fin) { bad += 1; continue; }
+    m += rho;
+    px += rux;
+    py += ruy;
+    rmin = fmin(rmin, rho);
+    umax = fmax(umax, sqrt(rux * rux + ruy * ruy) / rho);
+  }
+  s[0][t] = m; s[1][t] = px; s[2][t] = py; s[3][t] = rmin; s[4][t] = umax; s[5][t] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      s[0][t] += s[0][t + w]; s[1][t] += s[1][t + w]; s[2][t] += s[2][t + w];
+      s[3][t] = fmin(s[3][t], s[3][t + w]); s[4][t] = fmax(s[4][t], s[4][t + w]);
+      s[5][t] += s[5][t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int k = 0; k < 6; ++k) part[6 * blockIdx.x + k] = s[k][0];
+}
+
+__global__ void k_diag2(const double* part, int nblk, double* out) {
+  if (threadIdx.x != 0) return;
+  double m = 0, px = 0, py = 0, rmin = 1e300, umax = 0, bad = 0;
+  for (int b = 0; b < nblk; ++b) {
+    m += part[6 * b]; px += part[6 * b + 1]; py += part[6 * b + 2];
+    rmin = fmin(rmin, part[6 * b + 3]); umax = fmax(umax, part[6 * b + 4]); bad += part[6 * b + 5];
+  }
+  out[0] = m; out[1] = px; out[2] = py; out[3] = rmin; out[4] = umax; out[5] = bad;
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
+  const int per = (a.ntiles_total + 7) / 8;
+  dim3 grid(8 * per), block(kCap);
+  if (a.tile_x == 64 && a.tile_y == 4)
+    hipLaunchKernelGGL((k_lb_fused<T, 64, 4>), grid, block, 0, s, p, a.ntiles_total);
+  else if (a.tile_x == 128 && a.tile_y == 2)
+    hipLaunchKernelGGL((k_lb_fused<T, 128, 2>), grid, block, 0, s, p, a.ntiles_total);
+  else if (a.tile_x == 32 && a.tile_y == 8)
+    hipLaunchKernelGGL((k_lb_fused<T, 32, 8>), grid, block, 0, s, p, a.ntiles_total);
+  else
+    hipLaunchKernelGGL((k_lb_fused<T, 256, 1>), grid, block, 0, s, p, a.ntiles_total);
+}
+
+template <typename T>
+void launch_fields(const Ptrs<T>& p, const StepArgs& a, int inst, double* rho, double* ux,
+                   double* uy, int nx, int ny, long long, hipStream_t s) {
+  long long n = (long long)nx * ny;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  hipLaunchKernelGGL(k_fields<T>, grid, block, 0, s, p, inst, a.tile_x, a.tile_y, rho, ux, uy);
+}
+
+template <typename T>
+void launch_diag(const Ptrs<T>& p, const StepArgs&, long long nodes_total, double* out,
+                 hipStream_t s) {
+  const int nblk = 1024;
+  hipLaunchKernelGGL(k_diag1<T>, dim3(nblk), dim3(256), 0, s, p, nodes_total, p.red);
+  hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, p.red, nblk, out);
+}
+
+template void launch_lb_fused<float>(const Ptrs<float>&, const StepArgs&, hipStream_t);
+template void launch_lb_fused<double>(const Ptrs<double>&, const StepArgs&, hipStream_t);
+template void launch_fields<float>(const Ptrs<float>&, const StepArgs&, int, double*, double*,
+                                   double*, int, int, long long, hipStream_t);
+template void launch_fields<double>(const Ptrs<double>&, const StepArgs&, int, double*, double*,
+                                    double*, int, int, long long, hipStream_t);
+template void launch_diag<float>(const Ptrs<float>&, const StepArgs&, long long, double*, hipStream_t);
+template void launch_diag<double>(const Ptrs<double>&, const StepArgs&, long long, double*, hipStream_t);
+
+}  // namespace lbib

@@ -1,0 +1,170 @@
+// lbib_dev.h - device-side data layout and helpers of the LB-IB library (gfx950).
+//
+// Layout in the caller's workspace (all float64 Lagrangian data, SoA):
+//   populations  A, B : T[9][N] per instance, N = nx*ny, node = y*nx + x,
+//                       stored shifted by the rest weights: h_i = f_i - w_i
+//   velocity     U    : T[2][N] per instance (written on touched tiles only)
+//   markers           : x[Nm], y[Nm] (current), xm/ym (previous), xn/yn (next,
+//                       particles), fx/fy (force handed to the fluid),
+//                       per-marker stencil cx, cy (int) and weights wx[3], wy[3]
+//   bins              : bin_off[ntiles + 1] per instance (global marker ids in
+//                       bin_idx, sorted by id inside a bin)
+//   ligands           : l2r[NL] (-1 free), receptors rec_x[NR], r2l[NR]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbib {
+
+constexpr int kQ = 9;
+// D2Q9 velocity set in the order of Eq. (GaussHermite).
+__host__ __device__ constexpr int ex(int i) {
+  return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int ey(int i) {
+  return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) {
+  return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp axis");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp diag");
+
+template <typename T>
+__host__ __device__ constexpr T wq(int i) {
+  return i == 0 ? T(4) / T(9) : (i <= 4 ? T(1) / T(9) : T(1) / T(36));
+}
+
+enum BodyKind : int { kRBC = 0, kSoft = 1, kRigid = 2 };
+
+// Per-instance lattice description (device copy).
+struct LatDev {
+  int nx, ny, periodic_y;
+  int ntx, nty;          // tiles of the fused kernel / marker bins
+  int tile_base;         // first global tile index of this instance
+  int bin_base;          // first entry of bin_off (= tile_base + instance index)
+  int marker_base, n_markers;
+  int body_base, n_bodies;
+  int lig_base, n_lig;
+  int rec_base, n_rec0, n_rec1;
+  int instance;
+  long long node_base;   // first node of this instance (populations at 9*node_base)
+  double tau, gx, gy;
+  unsigned long long seed;
+  double y_cr, y_eq, kf0_dt, kr0_dt, sigma_ts_frac, kbt;
+  int freeze;
+  int pad_;
+};
+
+// Per-body description and rigid-body state (device copy; rigid state mutable).
+struct BodyDev {
+  int kind, nv, v0, inst;   // v0: global index of vertex 0
+  int lig_base, n_lig, lig_stride, pad_;
+  double ks, kb, ka, p_ref;
+  double A0, mass, mv, inertia, sigma;
+  double xc, yc, theta;     // rigid: reference point and angle
+  double U[2], Um[2];       // rigid: velocity history
+  double Om, Omm;           // rigid: angular velocity history
+};
+
+// Device pointers into the workspace.
+template <typename T>
+struct Ptrs {
+  LatDev* lat;
+  BodyDev* body;
+  T* A;  // populations read this step
+  T* B;  // populations written this step
+  T* U;  // velocity of touched tiles
+  double *x, *y, *xm, *ym, *xn, *yn, *fx, *fy;
+  double *l0, *th0, *r0x, *r0y;
+  int* mbody;
+  int *cx, *cy;
+  double *wx, *wy;       // [3][Nm]
+  double *s_len, *s_nx, *s_ny, *s_bc, *s_bnx, *s_bny, *s_bfl, *s_fex, *s_fey;  // per-vertex scratch
+  int *bin_off, *bin_cnt, *bin_tmp, *bin_idx;
+  int* tile_inst;
+  int *lig_body, *lig_elem, *l2r, *r2l, *lig_flag;
+  double* rec_x;
+  long long *step_next, *step_cur;   // per instance
+  double* red;                        // reduction scratch
+  unsigned long long* ties;           // per instance count of bond draws within 1e-12 of P
+  int nm_total, nbody_total, ntile_total, ninst, nlig_total;
+};
+
+// ------------------------------------------------------------ Roma kernel
+// 3-point kernel of Roma, Peskin & Berger on the 3 nearest nodes.
+__host__ __device__ inline double roma_phi(double r) {
+  double a = fabs(r);
+  if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) * (1.0 / 3.0);
+  if (a <= 1.5) {
+    double b = 1.0 - a;
+    double s = 1.0 - 3.0 * b * b;
+    return (5.0 - 3.0 * a - sqrt(s > 0.0 ? s : 0.0)) * (1.0 / 6.0);
+  }
+  return 0.0;
+}
+__host__ __device__ inline double roma_dphi(double r) {
+  double a = fabs(r);
+  if (a <= 0.5) return -r / sqrt(1.0 - 3.0 * r * r);
+  if (a < 1.5) {
+    double b = 1.0 - a;
+    double v = -0.5 - b / (2.0 * sqrt(1.0 - 3.0 * b * b));
+    return r > 0 ? v : -v;
+  }
+  return 0.0;
+}
+
+__host__ __device__ inline int wrap_i(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// ------------------------------------------------------------ Philox4x32-10
+// Salmon et al., SC'11: 10 rounds of multiply/xor with Weyl key schedule.
+__device__ inline void philox4x32_10(unsigned c[4], unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    unsigned lo0 = 0xD2511F53u * c[0];
+    unsigned hi0 = __umulhi(0xD2511F53u, c[0]);
+    unsigned lo1 = 0xCD9E8D57u * c[2];
+    unsigned hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    unsigned n0 = hi1 ^ c[1] ^ k0;
+    unsigned n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ inline double philox_uniform(unsigned long long seed, long long step, int lig,
+                                        int purpose, int instance) {
+  unsigned c[4] = {(unsigned)(step & 0xffffffffull), (unsigned)lig, (unsigned)purpose,
+                   (unsigned)instance};
+  philox4x32_10(c, (unsigned)(seed & 0xffffffffull), (unsigned)(seed >> 32));
+  return (double)c[0] * (1.0 / 4294967296.0);
+}
+
+// ------------------------------------------------------------ launchers
+// (defined in the kernel translation units, called by the host engine)
+struct StepArgs {
+  int tile_x, tile_y;
+  int ntiles_total;
+};
+
+template <typename T>
+void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
+template <typename T>
+void launch_fields(const Ptrs<T>& p, const StepArgs& a, int inst, double* rho, double* ux,
+                   double* uy, int nx, int ny, long long node_base, hipStream_t s);
+template <typename T>
+void launch_diag(const Ptrs<T>& p, const StepArgs& a, long long nodes_total, double* out,
+                 hipStream_t s);
+template <typename T>
+void launch_init_pop(const Ptrs<T>& p, const double* rho, const double* ux, const double* uy,
+                     long long node_base, long long n, long long nodes_total, hipStream_t s);
+template <typename T>
+void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
+template <typename T>
+void launch_advance(const Ptrs<T>& p, hipStream_t s);
+
+}  // namespace lbib

@@ -1,0 +1,140 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+the headers declare, and rejects bad arguments and wrong-phase calls before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1907_00080_amd as pkg
+from workloads import configs, geometry
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in ("lbib.h", "lbib_batch.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(lbib_[a-z_]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.library()
+    decl = _declared()
+    assert len(decl) >= 30
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert decl == set(pkg.EXPORTS)
+    assert lib.lbib_abi_version() == 1
+    for s, n in pkg.STATUS.items():
+        assert lib.lbib_status_string(s).decode() == n
+
+
+def _desc(**kw):
+    d = dict(nx=16, ny=8, periodic_y=0, dtype=0, tau=1.0, gx=0.0, gy=0.0, seed=1, instance=0,
+             tile_x=0, tile_y=0)
+    d.update(kw)
+    return pkg.LatticeDesc(**d)
+
+
+def _create(**kw):
+    lib = pkg.library()
+    h = ctypes.c_void_p()
+    st = lib.lbib_create(ctypes.byref(_desc(**kw)), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw", [dict(nx=0), dict(ny=0), dict(tau=0.5), dict(tau=float("nan")),
+                                dict(dtype=7), dict(tile_x=48, tile_y=4)])
+def test_create_rejects_bad_lattice(kw):
+    st, h = _create(**kw)
+    assert st == 1 and not h.value
+    assert pkg.library().lbib_last_error(None)
+
+
+def test_body_and_receptor_validation_and_phases():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    try:
+        ccw = geometry.place(geometry.circle(2.0, 12), 0.0, [8.0, 4.0])
+        bd = pkg.BodyDesc(2, 12, 0.0, 0.0, 1.0, 1 / 3, 1.1, 0.0, 0)
+        bid = ctypes.c_int32()
+        ok = np.ascontiguousarray(ccw)
+        assert lib.lbib_add_body(h, ctypes.byref(bd), ok.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 ctypes.byref(bid)) == 0 and bid.value == 0
+        cw = np.ascontiguousarray(ccw[::-1])
+        assert lib.lbib_add_body(h, ctypes.byref(bd), cw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 None) == 1
+        bd.nv = 2
+        assert lib.lbib_add_body(h, ctypes.byref(bd), ok.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 None) == 1
+        bad = np.array([0.0, 3.0, 2.0])
+        assert lib.lbib_set_receptors(h, 0, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 3) == 1
+        good = np.array([0.0, 2.0, 3.5])
+        assert lib.lbib_set_receptors(h, 0, good.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 3) == 0
+        assert lib.lbib_set_receptors(h, 2, good.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 3) == 1
+        out = np.array([0.0, 16.0])
+        assert lib.lbib_set_receptors(h, 1, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2) == 1
+        # running-phase calls refused during set-up (no device work happens)
+        assert lib.lbib_step(h, 1) == 2
+        assert lib.lbib_get_fields(h, None, None, None) == 2
+        assert lib.lbib_finalize_setup(h) == 2
+        nb = ctypes.c_size_t()
+        assert lib.lbib_workspace_query(h, ctypes.byref(nb)) == 0 and nb.value > 16 * 8 * 9 * 4
+        # misaligned and undersized workspaces are refused before any device use
+        assert lib.lbib_bind(h, ctypes.c_void_p(4096 + 8), nb.value, None) == 1
+        assert lib.lbib_bind(h, ctypes.c_void_p(4096), nb.value - 1, None) == 4
+        assert lib.lbib_set_graph_steps(h, 3) == 1
+        assert lib.lbib_set_graph_steps(h, 4) == 0
+        assert lib.lbib_last_error(h)
+    finally:
+        assert lib.lbib_destroy(h) == 0
+    assert lib.lbib_destroy(None) == 0
+
+
+def test_workspace_grows_with_lattice_and_dtype():
+    lib = pkg.library()
+    sizes = {}
+    for dt in (0, 1):
+        for nx in (64, 640):
+            st, h = _create(nx=nx, ny=32, dtype=dt)
+            nb = ctypes.c_size_t()
+            assert lib.lbib_workspace_query(h, ctypes.byref(nb)) == 0
+            sizes[(dt, nx)] = nb.value
+            lib.lbib_destroy(h)
+    # populations A, B (9 each) and velocity (2): 20 values per node
+    assert sizes[(0, 640)] - sizes[(0, 64)] >= 20 * 4 * 576 * 32
+    assert sizes[(1, 640)] - sizes[(1, 64)] >= 20 * 8 * 576 * 32
+
+
+def test_batch_create_rules():
+    lib = pkg.library()
+    a, ha = _create()
+    b, hb = _create(dtype=1)
+    arr = (ctypes.c_void_p * 2)(ha.value, hb.value)
+    out = ctypes.c_void_p()
+    assert lib.lbib_batch_create(arr, 2, 0, 0, ctypes.byref(out)) == 1   # dtype mismatch
+    c, hc = _create(nx=40)
+    arr = (ctypes.c_void_p * 2)(ha.value, hc.value)
+    assert lib.lbib_batch_create(arr, 2, 0, 0, ctypes.byref(out)) == 0
+    n = ctypes.c_int32()
+    assert lib.lbib_batch_size(out, ctypes.byref(n)) == 0 and n.value == 2
+    bd = pkg.BodyDesc(0, 12, 0.0, 0.0, 1.0, 1 / 3, 1.0, 0.0, 0)
+    xy = np.ascontiguousarray(geometry.place(geometry.circle(2.0, 12), 0.0, [8.0, 4.0]))
+    assert lib.lbib_add_body(out, ctypes.byref(bd), xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             None) == 2
+    for h in (ha, hb, hc, out):
+        lib.lbib_destroy(h)
+
+
+def test_product_path_requires_built_library(monkeypatch):
+    monkeypatch.setattr(pkg, "_lib", None)
+    monkeypatch.setattr(pkg, "LIB_PATH", "/nonexistent/liblbib.so")
+    with pytest.raises(ImportError):
+        pkg.Sim(configs.small_case(nx=16, ny=8, n_rbc=0))

@@ -1,0 +1,281 @@
+"""GPU parity of the HIP library with the FP64 oracle (called through the C ABI).
+
+Tolerances: the float64 path must agree with the oracle to round-off
+(1e-9 relative on velocities, 1e-9 lattice units on markers); the float32
+path to velocity rel-L2 <= 1e-5 and marker positions <= 1e-4 lattice units
+after 1000 steps of the 256x64 channel.  Bond tables must agree exactly
+given identical positions (draws within 1e-12 of the probability are
+counted and must not occur in these fixtures).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1907_00080_amd as pkg
+from oracle import adhesion as oadh
+from workloads import configs, geometry
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    num = np.sqrt(np.sum((a - b) ** 2))
+    den = np.sqrt(np.sum(b ** 2))
+    return num / max(den, 1e-300)
+
+
+def vel_err(sim, ref):
+    rho, ux, uy = sim.fields()
+    du = np.sqrt(np.sum((ux - ref.ux) ** 2 + (uy - ref.uy) ** 2))
+    dn = np.sqrt(np.sum(ref.ux ** 2 + ref.uy ** 2))
+    return du / max(dn, 1e-300), np.max(np.abs(rho - ref.rho))
+
+
+def marker_err(sim, ref):
+    if not ref.bodies:
+        return 0.0
+    return float(np.max(np.abs(sim.all_markers() - ref.all_markers())))
+
+
+def announce(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+# ------------------------------------------------------------- lattice only
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+@pytest.mark.parametrize("nx,ny,pery", [(100, 37, 0), (64, 8, 0), (5, 3, 0), (1, 1, 0),
+                                        (2, 9, 0), (70, 13, 1), (3, 2, 1)])
+def test_lattice_only_matches_oracle(dtype, tol, nx, ny, pery):
+    announce(f"lattice-only {nx}x{ny} periodic_y={pery} {dtype}")
+    rng = np.random.default_rng(nx * 100 + ny)
+    u0 = 0.02 * rng.standard_normal((2, ny, nx))
+    rho0 = 1 + 0.01 * rng.standard_normal((ny, nx))
+    wl = configs.Workload("lat", nx, ny, tau=0.8, gx=2e-5, gy=-1e-5, periodic_y=pery,
+                          rho0=rho0, u0=u0)
+    sim = pkg.Sim(wl, dtype=dtype)
+    ref = oracle.Sim(wl)
+    for n in (1, 7, 40):
+        sim.step(n - sim.step_count)
+        ref.step(n - ref.n)
+        e, erho = vel_err(sim, ref)
+        assert e < tol, (n, e)
+        assert erho < (1e-13 if dtype == "f64" else 1e-6)
+    sim.close()
+
+
+@pytest.mark.parametrize("tile", pkg.TILES)
+def test_poiseuille_all_tiles_fp32(tile):
+    announce(f"poiseuille tile {tile}")
+    w = configs.small_case(nx=300, ny=50, n_rbc=0)
+    sim = pkg.Sim(w, dtype="f32", tile=tile)
+    ref = oracle.Sim(w)
+    sim.step(300)
+    ref.step(300)
+    e, _ = vel_err(sim, ref)
+    assert e < 1e-5
+    # the initial Poiseuille state is near steady: profile stays the closed form
+    rho, ux, uy = sim.fields()
+    prof = configs.poiseuille_profile(w.gx, w.ny, w.tau)
+    assert np.max(np.abs(ux - prof[:, None])) < 2e-3 * prof.max()
+
+
+# ------------------------------------------------------------- bodies
+CASES = [
+    ("rbc", dict(nx=96, ny=24, n_rbc=1)),
+    ("rigid", dict(nx=80, ny=30, n_rbc=0, particles=(configs.PARTICLE_RIGID,))),
+    ("soft", dict(nx=80, ny=30, n_rbc=0, particles=(configs.PARTICLE_SOFT,))),
+    ("mixed", dict(nx=160, ny=36, n_rbc=2, particles=(configs.PARTICLE_RIGID, configs.PARTICLE_SOFT))),
+    ("periodic", dict(nx=72, ny=40, n_rbc=1, particles=(configs.PARTICLE_SOFT,), periodic_y=1)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_bodies_fp64_match_oracle_to_roundoff(name, kw):
+    announce(f"bodies fp64 {name}")
+    wl = configs.small_case(**kw)
+    if kw.get("periodic_y"):
+        # stress the cell so that something moves without a drive
+        wl.bodies[0].xy = wl.bodies[0].xy * 1.0
+    sim = pkg.Sim(wl, dtype="f64")
+    ref = oracle.Sim(wl)
+    if kw.get("periodic_y"):
+        rng = np.random.default_rng(5)
+        xy = ref.bodies[0].X + 0.2 * rng.standard_normal(ref.bodies[0].X.shape)
+        ref.bodies[0].X = xy.copy()
+        ref.bodies[0].Xm = xy.copy()
+        sim.set_markers(0, xy)
+    for n in (1, 2, 30, 150):
+        sim.step(n - sim.step_count)
+        ref.step(n - ref.n)
+        e, _ = vel_err(sim, ref)
+        dx = marker_err(sim, ref)
+        assert e < 1e-9, (n, e)
+        assert dx < 1e-9, (n, dx)
+        # forces relative to the largest force handed to the fluid by any body
+        scale = max(np.max(np.abs(f)) for f in ref.marker_force)
+        for b in range(len(wl.bodies)):
+            F = sim.marker_forces(b)
+            Fr = ref.marker_force[b]
+            assert np.max(np.abs(F - Fr)) <= 1e-9 * scale + 1e-13, (n, b)
+    sim.close()
+
+
+def test_cfg1_fp32_1000_steps_meets_tolerance():
+    """256x64 channel, one RBC and one rigid 1 um particle, 1000 steps:
+    velocity rel-L2 <= 1e-5 and markers <= 1e-4 dx against the FP64 oracle."""
+    announce("cfg1 fp32 1000 steps")
+    wl = configs.cfg1_plain_fp64()
+    sim = pkg.Sim(wl, dtype="f32")
+    ref = oracle.Sim(wl)
+    sim.step(1000)
+    ref.step(1000)
+    e, _ = vel_err(sim, ref)
+    dx = marker_err(sim, ref)
+    announce(f"cfg1 fp32: rel-L2 {e:.3e} markers {dx:.3e}")
+    assert e <= 1e-5
+    assert dx <= 1e-4
+
+
+def test_cfg1_fp64_1000_steps_roundoff():
+    announce("cfg1 fp64 1000 steps")
+    wl = configs.cfg1_plain_fp64()
+    sim = pkg.Sim(wl, dtype="f64", graph_steps=100)
+    ref = oracle.Sim(wl)
+    sim.step(1000)
+    ref.step(1000)
+    e, _ = vel_err(sim, ref)
+    dx = marker_err(sim, ref)
+    announce(f"cfg1 fp64: rel-L2 {e:.3e} markers {dx:.3e}")
+    assert e < 1e-10 and dx < 1e-9
+
+
+# ------------------------------------------------------------- bonds
+def adhesive_fixture(kind=configs.PARTICLE_SOFT, nx=64, ny=24, seed=7):
+    r = 3.0
+    xy = geometry.place(geometry.circle(r, 24), 0.1, [20.0, r - 0.2])
+    xy2 = geometry.place(geometry.circle(r, 24), 0.3, [44.0, ny - 1 - r + 0.25])
+    ks = 2e-2
+    bodies = [configs.Body(kind, xy, ks=ks, kb=0.05 * ks * r * r, sigma=5e-3, ligand_stride=2),
+              configs.Body(configs.PARTICLE_RIGID, xy2, sigma=8e-3, ligand_stride=2)]
+    g = configs.poiseuille_force(0.01, ny, 1.0)
+    rho0, u0 = configs.poiseuille_init(nx, ny, g, 1.0)
+    adh = configs.Adhesion(y_cr=1.0, y_eq=0.5, kf0_dt=0.2, kr0_dt=0.01, sigma_ts_frac=0.5,
+                           kbt=1e-3)
+    return configs.Workload("adh", nx, ny, 1.0, gx=g, seed=configs.SEED_BASE + seed,
+                            bodies=bodies, receptors=configs.uniform_receptors(nx),
+                            adhesion=adh, rho0=rho0, u0=u0)
+
+
+def test_bond_topology_replay_bit_exact():
+    """Given the GPU's own positions X^n, the oracle's bond update reproduces
+    the GPU bond table of every step exactly."""
+    announce("bond replay")
+    wl = adhesive_fixture()
+    sim = pkg.Sim(wl, dtype="f32")
+    ref = oracle.Sim(wl)   # only used for ligand bookkeeping and parameters
+    l2r = sim.bonds()
+    changes = 0
+    formed = 0
+    for n in range(120):
+        X = [sim.markers(b) for b in range(len(wl.bodies))]
+        c = np.array([0.5 * (X[bi][e] + X[bi][(e + 1) % X[bi].shape[0]])
+                      for bi, e in zip(ref.lig_body, ref.lig_elem)])
+        sig = np.array([ref.bodies[bi].sigma for bi in ref.lig_body])
+        expect, ties = oadh.bond_update(n, c, sig, l2r, ref.receptors, wl.nx, wl.ny,
+                                        ref.bond_params, ref.seed, ref.instance)
+        sim.step(1)
+        got = sim.bonds()
+        assert ties == 0
+        assert np.array_equal(got, expect), n
+        changes += int(np.sum(got != l2r))
+        formed = max(formed, int(np.sum(got >= 0)))
+        l2r = got
+    announce(f"bond replay: {changes} topology changes, max {formed} bonds")
+    assert changes > 5 and formed > 0
+
+
+def test_adhesive_trajectory_fp64_matches_oracle():
+    announce("adhesive trajectory fp64")
+    wl = adhesive_fixture()
+    sim = pkg.Sim(wl, dtype="f64")
+    ref = oracle.Sim(wl)
+    for n in (1, 10, 80):
+        sim.step(n - sim.step_count)
+        ref.step(n - ref.n)
+        assert np.array_equal(sim.bonds(), ref.l2r)
+        assert marker_err(sim, ref) < 1e-9
+        e, _ = vel_err(sim, ref)
+        assert e < 1e-9
+    assert ref.ties == 0
+    assert int(np.sum(ref.l2r >= 0)) > 0
+
+
+# ------------------------------------------------------------- full size
+def test_cfg2_full_size_steps_match_oracle():
+    """200 x 2000 capillary with 18 RBCs and 12 adhesive particles, float32,
+    in the benchmark's launch configuration: a few steps against the oracle."""
+    announce("cfg2 full size")
+    wl = configs.cfg2_capillary_fp32()
+    sim = pkg.Sim(wl, dtype="f32", graph_steps=2)
+    ref = oracle.Sim(wl)
+    steps = 4
+    sim.step(steps)
+    ref.step(steps)
+    e, erho = vel_err(sim, ref)
+    dx = marker_err(sim, ref)
+    announce(f"cfg2: rel-L2 {e:.3e} markers {dx:.3e}")
+    # velocities are ~1e-5 here: float32 resolves them to ~1e-6 relative
+    assert e < 1e-5
+    assert dx < 1e-6
+    assert np.array_equal(sim.bonds(), ref.l2r)
+
+
+# ------------------------------------------------------------- determinism
+def test_bitwise_determinism_graph_and_resume():
+    announce("determinism")
+    wl = configs.small_case(nx=128, ny=32, n_rbc=2,
+                            particles=(configs.PARTICLE_RIGID, configs.PARTICLE_SOFT))
+    a = pkg.Sim(wl, dtype="f32")
+    b = pkg.Sim(wl, dtype="f32", graph_steps=10)
+    a.step(37)
+    b.step(37)
+    fa, fb = a.fields(), b.fields()
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.all_markers(), b.all_markers())
+    state = a.get_state()
+    a.step(13)
+    ref_fields = a.fields()
+    ref_m = a.all_markers()
+    a.set_state(state)
+    assert a.step_count == 37
+    a.step(13)
+    for x, y in zip(a.fields(), ref_fields):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.all_markers(), ref_m)
+
+
+def test_diagnostics_and_mass_conservation():
+    announce("diagnostics")
+    wl = configs.small_case(nx=96, ny=24, n_rbc=1, particles=(configs.PARTICLE_RIGID,))
+    sim = pkg.Sim(wl, dtype="f64")
+    d0 = sim.diagnostics()
+    sim.step(50)
+    d1 = sim.diagnostics()
+    assert d1["step"] == 50 and d1["nonfinite"] == 0
+    assert abs(d1["mass"] - d0["mass"]) < 1e-9
+    assert d1["rho_min"] > 0.9
+
+
+def test_watchdog_flags_nonfinite_state():
+    announce("watchdog")
+    wl = configs.small_case(nx=64, ny=16, n_rbc=0)
+    sim = pkg.Sim(wl, dtype="f32", watchdog=True)
+    sim.step(2)
+    blob = bytearray(sim.get_state())
+    # the first float of the population block follows the 64-byte header
+    blob[64:68] = np.array([np.nan], dtype=np.float32).tobytes()
+    sim.set_state(bytes(blob))
+    with pytest.raises(pkg.LbibError) as ei:
+        sim.step(1)
+    assert ei.value.status == 5

@@ -131,6 +131,9 @@ typedef struct {
   double u_max;          /* max |u|                                            */
   int64_t nonfinite;     /* nodes with a non-finite population                 */
   int32_t nbonds;
+  int32_t bin_overflow;  /* marker-bin registrations dropped since set-up (a
+                            full bin also poisons its tile's force, so the
+                            watchdog reports it); 0 in any valid run       */
 } lbib_diag;
 
 uint32_t lbib_abi_version(void);

@@ -14,8 +14,8 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbib.h"
-#include "../../include/lbib_batch.h"
+#include "lbib.h"
+#include "lbib_batch.h"
 #include "lbib_dev.h"
 
 using namespace lbib;
@@ -37,6 +37,11 @@ struct InstHost {
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Registrations one tile's bin holds: markers whose 3x3 stencil overlaps a
+// TX x TY tile lie in its (TX+2) x (TY+2) halo; membranes with spacing of
+// about one lattice unit put a few per halo column or row there.
+int bin_capacity(int tx, int ty) { return std::max(1024, 16 * (tx + ty + 2)); }
+
 bool valid_tile(int tx, int ty) {
   return (tx == 64 && ty == 4) || (tx == 128 && ty == 2) || (tx == 32 && ty == 8) ||
          (tx == 256 && ty == 1);
@@ -45,10 +50,10 @@ bool valid_tile(int tx, int ty) {
 struct Layout {
   size_t lat, body, A, B, U;
   size_t x, y, xm, ym, xn, yn, fx, fy, l0, th0, r0x, r0y;
-  size_t mbody, cx, cy, wx, wy;
+  size_t mbody, minfo, cx, cy, wx, wy;
   size_t s[9];
-  size_t bin_off, bin_cnt, bin_tmp, bin_idx, tile_inst;
-  size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x;
+  size_t cnt[2], bins[2], touched, overflow, Uspare, tile_inst;
+  size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma;
   size_t step_next, step_cur, ties, red;
   size_t total;
 };
@@ -76,6 +81,8 @@ struct lbib_ctx {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   std::string err;
   bool is_batch = false;
+  bool stencil_dirty = true;  // marker stencils/bins must be rebuilt from positions
+  int bin_cap = 1024;         // marker registrations per tile and bin set
 };
 
 static std::string g_create_err;
@@ -141,20 +148,27 @@ void compute_layout(lbib_ctx* c) {
                    &L.l0, &L.th0, &L.r0x, &L.r0y};
   for (auto* o : dbl) *o = take(8 * nm);
   L.mbody = take(4 * nm);
+  L.minfo = take(4 * nm);
   L.cx = take(4 * nm);
   L.cy = take(4 * nm);
   L.wx = take(8 * 3 * nm);
   L.wy = take(8 * 3 * nm);
   for (auto& s : L.s) s = take(8 * nm);
-  L.bin_off = take(4 * (c->ntiles + c->ninst));
-  L.bin_cnt = take(4 * c->ntiles);
-  L.bin_tmp = take(4 * nm);
-  L.bin_idx = take(4 * nm);
+  for (int k = 0; k < 2; ++k) {
+    L.cnt[k] = take(4 * (size_t)c->ntiles);
+    L.bins[k] = take(4 * (size_t)c->ntiles * c->bin_cap);
+  }
+  L.touched = take(4 * (size_t)c->ntiles);
+  L.overflow = take(8);
+  L.Uspare = take(es * 2 * c->nodes);   // velocity output of measurement launches
   L.tile_inst = take(4 * c->ntiles);
   L.lig_body = take(4 * nl);
   L.lig_elem = take(4 * nl);
   L.l2r = take(4 * nl);
   L.lig_flag = take(4 * nl);
+  L.lig_va = take(4 * nl);
+  L.lig_vb = take(4 * nl);
+  L.lig_sigma = take(8 * nl);
   L.r2l = take(4 * nr);
   L.rec_x = take(8 * nr);
   L.step_next = take(8 * c->ninst);
@@ -183,19 +197,26 @@ Ptrs<T> make_ptrs(const lbib_ctx* c) {
   p.l0 = (double*)(w + L.l0); p.th0 = (double*)(w + L.th0);
   p.r0x = (double*)(w + L.r0x); p.r0y = (double*)(w + L.r0y);
   p.mbody = (int*)(w + L.mbody);
+  p.minfo = (int*)(w + L.minfo);
   p.cx = (int*)(w + L.cx); p.cy = (int*)(w + L.cy);
   p.wx = (double*)(w + L.wx); p.wy = (double*)(w + L.wy);
   double** sp[] = {&p.s_len, &p.s_nx, &p.s_ny, &p.s_bc, &p.s_bnx, &p.s_bny, &p.s_bfl, &p.s_fex, &p.s_fey};
   for (int k = 0; k < 9; ++k) *sp[k] = (double*)(w + L.s[k]);
-  p.bin_off = (int*)(w + L.bin_off);
-  p.bin_cnt = (int*)(w + L.bin_cnt);
-  p.bin_tmp = (int*)(w + L.bin_tmp);
-  p.bin_idx = (int*)(w + L.bin_idx);
+  p.cnt_cur = (int*)(w + L.cnt[c->parity]);
+  p.cnt_next = (int*)(w + L.cnt[c->parity ^ 1]);
+  p.bin_cur = (int*)(w + L.bins[c->parity]);
+  p.bin_next = (int*)(w + L.bins[c->parity ^ 1]);
+  p.touched = (int*)(w + L.touched);
+  p.overflow = (int*)(w + L.overflow);
+  p.bin_cap = c->bin_cap;
   p.tile_inst = (int*)(w + L.tile_inst);
   p.lig_body = (int*)(w + L.lig_body);
   p.lig_elem = (int*)(w + L.lig_elem);
   p.l2r = (int*)(w + L.l2r);
   p.lig_flag = (int*)(w + L.lig_flag);
+  p.lig_va = (int*)(w + L.lig_va);
+  p.lig_vb = (int*)(w + L.lig_vb);
+  p.lig_sigma = (double*)(w + L.lig_sigma);
   p.r2l = (int*)(w + L.r2l);
   p.rec_x = (double*)(w + L.rec_x);
   p.step_next = (long long*)(w + L.step_next);
@@ -215,6 +236,11 @@ StepArgs step_args(const lbib_ctx* c) {
   a.tile_x = c->TX;
   a.tile_y = c->TY;
   a.ntiles_total = c->ntiles;
+  a.max_inst_tiles = 0;
+  for (size_t i = 0; i < c->inst.size(); ++i) {
+    const int nt = ((c->inst[i].lat.nx + c->TX - 1) / c->TX) * ((c->inst[i].lat.ny + c->TY - 1) / c->TY);
+    a.max_inst_tiles = std::max(a.max_inst_tiles, nt);
+  }
   return a;
 }
 
@@ -246,9 +272,11 @@ lbib_status upload_all(lbib_ctx* c) {
   std::vector<BodyDev> bodies(std::max(c->nbody, 1));
   const size_t nm = std::max(c->nm, 1);
   std::vector<double> x(nm), y(nm), l0(nm), th0(nm), r0x(nm, 0.0), r0y(nm, 0.0);
-  std::vector<int> mbody(nm, 0);
+  std::vector<int> mbody(nm, 0), minfo(nm, 0);
   std::vector<int> tile_inst(std::max(c->ntiles, 1));
   std::vector<int> lig_body(std::max(c->nlig, 1)), lig_elem(std::max(c->nlig, 1));
+  std::vector<int> lig_va(std::max(c->nlig, 1)), lig_vb(std::max(c->nlig, 1));
+  std::vector<double> lig_sigma(std::max(c->nlig, 1), 0.0);
   std::vector<double> rec_x(std::max(c->nrec, 1));
   int bi = 0, li = 0;
   for (int i = 0; i < c->ninst; ++i) {
@@ -298,6 +326,7 @@ lbib_status upload_all(lbib_ctx* c) {
         l0[m + v] = bl0[v];
         th0[m + v] = bth0[v];
         mbody[m + v] = bi;
+        minfo[m + v] = (i << 2) | b.d.kind;
         if (b.d.kind == LBIB_PARTICLE_RIGID) {
           r0x[m + v] = b.xy[2 * v] - xc;
           r0y[m + v] = b.xy[2 * v + 1] - yc;
@@ -311,6 +340,9 @@ lbib_status upload_all(lbib_ctx* c) {
         for (int e = 0; e < b.d.nv; e += b.d.ligand_stride, ++k) {
           lig_body[li] = bi;
           lig_elem[li] = e;
+          lig_va[li] = m + e;
+          lig_vb[li] = m + (e + 1) % b.d.nv;
+          lig_sigma[li] = b.d.sigma;
           ++li;
         }
         B.n_lig = k;
@@ -344,25 +376,24 @@ lbib_status upload_all(lbib_ctx* c) {
   HIPCHK(c, up(L.r0x, r0x.data(), 8 * nm));
   HIPCHK(c, up(L.r0y, r0y.data(), 8 * nm));
   HIPCHK(c, up(L.mbody, mbody.data(), 4 * nm));
+  HIPCHK(c, up(L.minfo, minfo.data(), 4 * nm));
   HIPCHK(c, up(L.tile_inst, tile_inst.data(), 4 * tile_inst.size()));
   HIPCHK(c, up(L.lig_body, lig_body.data(), 4 * lig_body.size()));
   HIPCHK(c, up(L.lig_elem, lig_elem.data(), 4 * lig_elem.size()));
+  HIPCHK(c, up(L.lig_va, lig_va.data(), 4 * lig_va.size()));
+  HIPCHK(c, up(L.lig_vb, lig_vb.data(), 4 * lig_vb.size()));
+  HIPCHK(c, up(L.lig_sigma, lig_sigma.data(), 8 * lig_sigma.size()));
   HIPCHK(c, hipMemsetAsync(w + L.l2r, 0xff, 4 * std::max(c->nlig, 1), s));
   HIPCHK(c, hipMemsetAsync(w + L.r2l, 0xff, 4 * std::max(c->nrec, 1), s));
   HIPCHK(c, up(L.rec_x, rec_x.data(), 8 * rec_x.size()));
   HIPCHK(c, hipMemsetAsync(w + L.step_next, 0, 8 * c->ninst, s));
   HIPCHK(c, hipMemsetAsync(w + L.step_cur, 0, 8 * c->ninst, s));
   HIPCHK(c, hipMemsetAsync(w + L.ties, 0, 8 * c->ninst, s));
-  // bins: empty until the first step
-  {
-    std::vector<int> off(c->ntiles + c->ninst);
-    for (int i = 0; i < c->ninst; ++i) {
-      const int nt = lat[i].ntx * lat[i].nty;
-      for (int t = 0; t <= nt; ++t) off[lat[i].bin_base + t] = lat[i].marker_base;
-    }
-    HIPCHK(c, up(L.bin_off, off.data(), 4 * off.size()));
-    HIPCHK(c, hipStreamSynchronize(s));
-  }
+  // marker bins: empty until the stencil pass before the first step
+  for (int k = 0; k < 2; ++k) HIPCHK(c, hipMemsetAsync(w + L.cnt[k], 0, 4 * (size_t)c->ntiles, s));
+  HIPCHK(c, hipMemsetAsync(w + L.touched, 0, 4 * (size_t)c->ntiles, s));
+  HIPCHK(c, hipMemsetAsync(w + L.overflow, 0, 8, s));
+  HIPCHK(c, hipStreamSynchronize(s));
   // populations: equilibrium of the initial fields, shifted by the weights
   for (int i = 0; i < c->ninst; ++i) {
     InstHost& I = c->inst[i];
@@ -388,6 +419,7 @@ lbib_status upload_all(lbib_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(s));
   c->parity = 0;
   c->step = 0;
+  c->stencil_dirty = true;
   return LBIB_OK;
 }
 
@@ -398,7 +430,7 @@ void enqueue_steps(lbib_ctx* c, long long n) {
     Ptrs<T> p = make_ptrs<T>(c);
     launch_lagrangian<T>(p, a, c->stream);
     launch_lb_fused<T>(p, a, c->stream);
-    launch_advance<T>(p, c->stream);
+    launch_advance<T>(p, a, c->stream);
     c->parity ^= 1;
   }
 }
@@ -413,6 +445,13 @@ void drop_graphs(lbib_ctx* c) {
 
 template <typename T>
 lbib_status run_steps(lbib_ctx* c, long long n) {
+  if (c->stencil_dirty && n > 0) {
+    // rebuild the current bin set from the marker positions (eager, never
+    // part of a captured graph)
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.cnt[c->parity], 0, 4 * (size_t)c->ntiles, c->stream));
+    launch_stencil<T>(make_ptrs<T>(c), step_args(c), c->stream);
+    c->stencil_dirty = false;
+  }
   const int G = c->graph_steps;
   if (G > 0) {
     while (n >= G) {
@@ -494,7 +533,7 @@ std::vector<std::pair<size_t, size_t>> state_regions(const lbib_ctx* c) {
       {L.body, sizeof(BodyDev) * std::max(c->nbody, 1)},
       {L.x, 8 * nm}, {L.y, 8 * nm}, {L.xm, 8 * nm}, {L.ym, 8 * nm}, {L.xn, 8 * nm}, {L.yn, 8 * nm},
       {L.fx, 8 * nm}, {L.fy, 8 * nm}, {L.cx, 4 * nm}, {L.cy, 4 * nm}, {L.wx, 24 * nm}, {L.wy, 24 * nm},
-      {L.bin_off, 4 * (size_t)(c->ntiles + c->ninst)}, {L.bin_idx, 4 * nm},
+      {L.touched, 4 * (size_t)c->ntiles},
       {L.l2r, 4 * nl}, {L.r2l, 4 * nr}, {L.step_next, 8 * (size_t)c->ninst},
       {L.step_cur, 8 * (size_t)c->ninst}, {L.ties, 8 * (size_t)c->ninst}};
   return r;
@@ -541,6 +580,7 @@ lbib_status lbib_create(const lbib_lattice_desc* d, lbib_ctx** out) {
   c->dtype = d->dtype;
   c->TX = tx;
   c->TY = ty;
+  c->bin_cap = bin_capacity(tx, ty);
   InstHost I;
   I.lat = *d;
   I.adh.y_cr = 0.0;  // no bonds unless set
@@ -733,6 +773,7 @@ lbib_status lbib_set_markers(lbib_ctx* c, int32_t body, const double* xy, const 
   HIPCHK(c, hipMemcpyAsync(c->ws + c->L.xm + o, am.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->L.ym + o, bm.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->stencil_dirty = true;
   return LBIB_OK;
 }
 
@@ -833,6 +874,7 @@ lbib_status lbib_set_state(lbib_ctx* c, const void* blob, size_t bytes) {
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->step = (long long)h.step;
+  c->stencil_dirty = true;   // marker bins are rebuilt from the restored positions
   return LBIB_OK;
 }
 
@@ -857,22 +899,35 @@ lbib_status lbib_diagnostics(lbib_ctx* c, lbib_diag* out) {
     tot += nb;
   }
   out->nbonds = tot;
+  int32_t ovf = 0;
+  HIPCHK(c, hipMemcpyAsync(&ovf, c->ws + c->L.overflow, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out->bin_overflow = ovf;
   return LBIB_OK;
 }
 
 lbib_status lbib_time_lattice_kernel(lbib_ctx* c, int32_t reps, double* avg_ms) {
   if (!c || !avg_ms) return fail(c, LBIB_EINVAL, "NULL argument");
   if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
-  if (c->step < 1) return fail(c, LBIB_ESTATE, "needs one completed step");
+  if (c->step < 1 || c->stencil_dirty) return fail(c, LBIB_ESTATE, "needs one completed step");
   if (reps < 1) return fail(c, LBIB_EINVAL, "reps must be >= 1");
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   const StepArgs a = step_args(c);
   HIPCHK(c, hipEventRecord(e0, c->stream));
+  // measurement launches: bins of the coming step are read but not consumed,
+  // the velocity output goes to a spare buffer, populations to the spare set
   for (int r = 0; r < reps; ++r) {
-    if (c->dtype == LBIB_F64) launch_lb_fused<double>(make_ptrs<double>(c), a, c->stream);
-    else launch_lb_fused<float>(make_ptrs<float>(c), a, c->stream);
+    if (c->dtype == LBIB_F64) {
+      Ptrs<double> p = make_ptrs<double>(c);
+      p.U = (double*)(c->ws + c->L.Uspare);
+      launch_lb_fused<double>(p, a, c->stream, 0);
+    } else {
+      Ptrs<float> p = make_ptrs<float>(c);
+      p.U = (float*)(c->ws + c->L.Uspare);
+      launch_lb_fused<float>(p, a, c->stream, 0);
+    }
   }
   HIPCHK(c, hipEventRecord(e1, c->stream));
   HIPCHK(c, hipEventSynchronize(e1));
@@ -916,6 +971,7 @@ lbib_status lbib_batch_create(const lbib_ctx* const* insts, int32_t n, int32_t t
   c->dtype = dtype;
   c->TX = tx;
   c->TY = ty;
+  c->bin_cap = bin_capacity(tx, ty);
   c->is_batch = true;
   for (int i = 0; i < n; ++i) c->inst.push_back(insts[i]->inst[0]);
   *out = c;

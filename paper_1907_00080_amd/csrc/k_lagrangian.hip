@@ -1,11 +1,7 @@
 // k_lagrangian.hip - Lagrangian side of the LB-IB step (gfx950), float64.
 //
 // Per time step n (the order is the one used throughout the library):
-//   k_bin_bonds   one workgroup per lattice instance:
-//                   - stencil of every marker: centre node floor(X + 1/2) and the
-//                     3+3 weights of the Roma 3-point kernel;
-//                   - marker bins per lattice tile (counting sort, each bin then
-//                     ordered by marker id so spreading sums in a fixed order);
+//   k_bonds       one workgroup per lattice instance:
 //                   - bond kinetics: rupture pass, then formation pass in
 //                     ascending ligand order (Sec. 2.2 Wall-Particle Interaction),
 //                     with Philox4x32-10 uniforms keyed by (step, ligand).
@@ -18,7 +14,11 @@
 //                     (Eqs. linearVelRig, angularVelRig), weak-coupling force.
 //   (the fused lattice kernel runs here)
 //   k_advance     one lane per marker: red cells by the kinematic IB
-//                 (Eq. kinematicPos), particles adopt their new positions.
+//                 (Eq. kinematicPos), particles adopt their new positions;
+//                 the stencil of the new position (centre node floor(X + 1/2)
+//                 and the 3+3 weights of the Roma 3-point kernel) is stored
+//                 and the marker joins the bins of every lattice tile that
+//                 stencil overlaps, for the next step's fused kernel.
 #include "lbib_dev.h"
 
 namespace lbib {
@@ -26,21 +26,30 @@ namespace lbib {
 // ------------------------------------------------------------------ helpers
 // Populations at a node after streaming, before forcing (walls: bounce-back).
 template <typename T>
-__device__ inline void pulled_moments(const T* A, long long N, int nx, int ny, bool pery, int x,
-                                      int y, double& drho, double& jx, double& jy) {
-  drho = 0.0; jx = 0.0; jy = 0.0;
+__device__ inline void pull_node(const T* A, long long N, int nx, int ny, bool pery, int x, int y,
+                                 T hv[kQ]) {
   const long long node = (long long)y * nx + x;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    int xs = wrap_i(x - ex(i), nx);
+    int xs = x - ex(i);
+    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
     int ys = y - ey(i);
-    double h;
-    if (ys < 0 || ys >= ny) {
-      if (pery) h = double(A[i * N + (long long)wrap_i(ys, ny) * nx + xs]);
-      else h = double(A[opp(i) * N + node]);
-    } else {
-      h = double(A[i * N + (long long)ys * nx + xs]);
-    }
+    const bool out = ys < 0 || ys >= ny;
+    ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+    const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * nx + xs;
+    hv[i] = A[src];
+  }
+}
+
+template <typename T>
+__device__ inline void pulled_moments(const T* A, long long N, int nx, int ny, bool pery, int x,
+                                      int y, double& drho, double& jx, double& jy) {
+  drho = 0.0; jx = 0.0; jy = 0.0;
+  T hv[kQ];
+  pull_node(A, N, nx, ny, pery, x, y, hv);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const double h = double(hv[i]);
     drho += h;
     jx += ex(i) * h;
     jy += ey(i) * h;
@@ -67,18 +76,72 @@ __device__ inline void interp_star(const T* A, const LatDev& L, double X, double
   rho = 0; ux = 0; uy = 0;
   g[0] = g[1] = g[2] = g[3] = 0;  // du/dx, du/dy, dv/dx, dv/dy
   const bool pery = L.periodic_y != 0;
+  double wxa[3], dwxa[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    wxa[a] = roma_phi((cxr + (a - 1)) - X);
+    dwxa[a] = grad ? roma_dphi((cxr + (a - 1)) - X) : 0.0;
+  }
   for (int b = 0; b < 3; ++b) {
     const double ry = cyr + (b - 1);
     int row = (int)ry;
     if (pery) row = wrap_i(row, L.ny);
     else if (row < 0 || row >= L.ny) continue;
-    const double wy = roma_phi(ry - Y), dwy = roma_dphi(ry - Y);
+    const double wy = roma_phi(ry - Y), dwy = grad ? roma_dphi(ry - Y) : 0.0;
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double rx = cxr + (a - 1);
       const int col = wrap_i((int)rx, L.nx);
-      const double wx = roma_phi(rx - X), dwx = roma_dphi(rx - X);
+      const double wx = wxa[a], dwx = dwxa[a];
       double r, u, v;
       node_star(A, L, col, row, r, u, v);
+      rho += r * wx * wy;
+      ux += u * wx * wy;
+      uy += v * wx * wy;
+      if (grad) {
+        g[0] -= u * dwx * wy;
+        g[1] -= u * wx * dwy;
+        g[2] -= v * dwx * wy;
+        g[3] -= v * wx * dwy;
+      }
+    }
+  }
+}
+
+// rho*, u* of the nodes in a box [bx0, bx0 + bw) x [by0, by0 + bh) cached in
+// LDS (x unwrapped; rows wrapped for a periodic lattice).  Same interpolant
+// as interp_star, read from the cache.
+template <typename T>
+struct StarCache {
+  const T* c;   // 3 values per node: rho, ux, uy
+  int bx0, by0, bw, bh;
+};
+
+template <typename T>
+__device__ inline void interp_cached(const StarCache<T>& C, const LatDev& L, double X, double Y,
+                                     bool grad, double& rho, double& ux, double& uy, double g[4]) {
+  const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
+  rho = 0; ux = 0; uy = 0;
+  g[0] = g[1] = g[2] = g[3] = 0;
+  const bool pery = L.periodic_y != 0;
+  double wxa[3], dwxa[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    wxa[a] = roma_phi((cxr + (a - 1)) - X);
+    dwxa[a] = grad ? roma_dphi((cxr + (a - 1)) - X) : 0.0;
+  }
+  for (int b = 0; b < 3; ++b) {
+    const double ry = cyr + (b - 1);
+    const int row = (int)ry;
+    if (!pery && (row < 0 || row >= L.ny)) continue;
+    const double wy = roma_phi(ry - Y), dwy = grad ? roma_dphi(ry - Y) : 0.0;
+    const int kr = (row - C.by0) * C.bw;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double rx = cxr + (a - 1);
+      const double wx = wxa[a], dwx = dwxa[a];
+      const int k = 3 * (kr + ((int)rx - C.bx0));
+      const double r = double(C.c[k]), u = double(C.c[k + 1]), v = double(C.c[k + 2]);
       rho += r * wx * wy;
       ux += u * wx * wy;
       uy += v * wx * wy;
@@ -110,10 +173,6 @@ __device__ inline double bond_len(double cx, double cy, double xr, int wall, con
   return sqrt(dx * dx + dy * dy);
 }
 
-__device__ inline double ligand_cx(const Ptrs<float>&, const double* x, int v0, int nv, int e) {
-  return 0.5 * (x[v0 + e] + x[v0 + (e + 1) % nv]);
-}
-
 // Block-wide exclusive scan of one int per thread (blockDim <= 1024).
 __device__ inline int block_exclusive_scan(int v, int* s_tmp) {
   const int t = threadIdx.x, n = blockDim.x;
@@ -130,10 +189,129 @@ __device__ inline int block_exclusive_scan(int v, int* s_tmp) {
   return incl - v;
 }
 
-// ---------------------------------------------------------------- k_bin_bonds
+// ---------------------------------------------------------------- marker bins
+// Register marker gm in every tile its 3x3 stencil overlaps (centre cx, cy).
+// Three consecutive columns (rows) touch at most three tiles (a ragged last
+// tile can be one column wide), so a marker joins at most nine bins.  Slots
+// come from wave-aggregated atomics: lanes of a wave that hit the same tile
+// (neighbours along a membrane) share one atomic.  A full bin drops the
+// registration and counts it in *overflow (the fused kernel then poisons
+// that tile's force so the watchdog reports it).
+template <int TX, int TY>
+__device__ inline void register_marker(int* cnt, int* bin, int cap, int* overflow, const LatDev& L,
+                                       int gm, int cx, int cy, bool active) {
+  const bool pery = L.periodic_y != 0;
+  const int nx = L.nx, ny = L.ny;
+  int tc[3], tr[3];
+  int ntc = 0, ntr = 0;
+  if (active) {
+#pragma unroll
+    for (int a = -1; a <= 1; ++a) {
+      int c = cx + a;
+      c = c < 0 ? c + nx : (c >= nx ? c - nx : c);
+      const int t = c / TX;
+      bool dup = false;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dup |= k < ntc && tc[k] == t;
+      if (!dup) { tc[ntc] = t; ++ntc; }
+    }
+#pragma unroll
+    for (int b = -1; b <= 1; ++b) {
+      int r = cy + b;
+      if (pery) r = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+      else if (r < 0 || r >= ny) continue;
+      const int t = r / TY;
+      bool dup = false;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dup |= k < ntr && tr[k] == t;
+      if (!dup) { tr[ntr] = t; ++ntr; }
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  // 1. group the lanes of every slot by tile (no memory traffic)
+  int key[9], leader[9], rank[9], gcount[9];
+#pragma unroll
+  for (int s9 = 0; s9 < 9; ++s9) {
+    const int i = s9 / 3, j = s9 % 3;
+    const bool has = i < ntr && j < ntc;
+    key[s9] = has ? L.tile_base + tr[i] * L.ntx + tc[j] : -1;
+    leader[s9] = lane;
+    rank[s9] = 0;
+    gcount[s9] = 0;
+    unsigned long long pending = __ballot(has);
+    while (pending) {
+      const int ld = __ffsll((long long)pending) - 1;
+      const int k = __shfl(key[s9], ld);
+      const unsigned long long grp = __ballot(key[s9] == k) & pending;
+      if (key[s9] == k) {
+        leader[s9] = ld;
+        rank[s9] = __popcll(grp & lt);
+      }
+      if (lane == ld) gcount[s9] = __popcll(grp);
+      pending &= ~grp;
+    }
+  }
+  // 2. every group leader reserves its slots; the atomics of all groups and
+  //    slots are in flight together
+  int base[9];
+#pragma unroll
+  for (int s9 = 0; s9 < 9; ++s9)
+    base[s9] = gcount[s9] > 0 ? atomicAdd(&cnt[key[s9]], gcount[s9]) : 0;
+  // 3. positions and stores
+#pragma unroll
+  for (int s9 = 0; s9 < 9; ++s9) {
+    const int b = __shfl(base[s9], leader[s9]);
+    if (key[s9] >= 0) {
+      const int pos = b + rank[s9];
+      if (pos < cap) bin[(long long)key[s9] * cap + pos] = gm;
+      else atomicAdd(overflow, 1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- stencils
+// Stencil of a marker at (X, Y): centre node floor(X + 1/2) (column wrapped,
+// row wrapped on a periodic lattice, else kept raw so rows beyond the walls
+// can be recognised) and the 3 + 3 Roma kernel weights (zero for rows beyond
+// the walls).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_bin_bonds(Ptrs<T> p, int TX, int TY) {
+__device__ inline void marker_stencil(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y) {
+  const int nm = p.nm_total;
+  const bool pery = L.periodic_y != 0;
+  const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    p.wx[a * nm + gm] = roma_phi((cxr + (a - 1)) - X);
+    const double ry = cyr + (a - 1);
+    const bool valid = pery || (ry >= 0.0 && ry < (double)L.ny);
+    p.wy[a * nm + gm] = valid ? roma_phi(ry - Y) : 0.0;
+  }
+  p.cx[gm] = wrap_i((int)cxr, L.nx);
+  p.cy[gm] = pery ? wrap_i((int)cyr, L.ny) : (int)fmin(fmax(cyr, -4.0), (double)(L.ny + 3));
+}
+
+// Stencils of all markers from their current positions (after set-up or
+// after positions were overwritten from the host).
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(256) void k_stencil(Ptrs<T> p) {
+  const int gm = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = gm < p.nm_total;
+  const int g = active ? gm : 0;
+  const LatDev& L = p.lat[p.minfo[g] >> 2];
+  if (active) marker_stencil(p, L, gm, p.x[gm], p.y[gm]);
+  const int cx = active ? p.cx[gm] : 0, cy = active ? p.cy[gm] : 0;
+  register_marker<TX, TY>(p.cnt_cur, p.bin_cur, p.bin_cap, p.overflow, L, gm, cx, cy, active);
+}
+
+constexpr int kBodyCacheBytes = 16 * 1024;   // LDS cache of rho*, u* per particle
+
+// ---------------------------------------------------------------- k_bonds
+// Step bookkeeping and bond kinetics of one lattice instance.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_bonds(Ptrs<T> p) {
   __shared__ int s_tmp[1024];
+  __shared__ int s_nelig;
   const int inst = blockIdx.x;
   const LatDev& L = p.lat[inst];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -143,138 +321,63 @@ __global__ __launch_bounds__(1024) void k_bin_bonds(Ptrs<T> p, int TX, int TY) {
     p.step_cur[inst] = n;
     p.step_next[inst] = n + 1;
   }
-  const int nx = L.nx, ny = L.ny, ntx = L.ntx;
-  const bool pery = L.periodic_y != 0;
-  const int ntiles = L.ntx * L.nty;
-  int* cnt = p.bin_cnt + L.tile_base;
-  int* off = p.bin_off + L.bin_base;
-  const int nm = p.nm_total;
-  for (int t = tid; t < ntiles; t += nt) cnt[t] = 0;
-  __syncthreads();
+  const int ny = L.ny, nx = L.nx;
 
-  // 1. stencils and bin counts
-  for (int m = tid; m < L.n_markers; m += nt) {
-    const int gm = L.marker_base + m;
-    const double X = p.x[gm], Y = p.y[gm];
-    const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
-    for (int a = 0; a < 3; ++a) {
-      p.wx[a * nm + gm] = roma_phi((cxr + (a - 1)) - X);
-      const double ry = cyr + (a - 1);
-      const bool valid = pery || (ry >= 0.0 && ry < (double)ny);
-      p.wy[a * nm + gm] = valid ? roma_phi(ry - Y) : 0.0;
-    }
-    const int cx = wrap_i((int)cxr, nx);
-    int cy;
-    if (pery) cy = wrap_i((int)cyr, ny);
-    else cy = (int)fmin(fmax(cyr, -4.0), (double)(ny + 3));
-    p.cx[gm] = cx;
-    p.cy[gm] = cy;
-    const int tx = cx / TX;
-    const int ty = min(max(cy, 0), ny - 1) / TY;
-    atomicAdd(&cnt[ty * ntx + tx], 1);
-  }
-  __syncthreads();
-
-  // 2. exclusive scan -> bin offsets (global marker ids); counts become cursors
-  {
-    const int chunk = (ntiles + nt - 1) / nt;
-    const int lo = min(tid * chunk, ntiles), hi = min(lo + chunk, ntiles);
-    int sum = 0;
-    for (int t = lo; t < hi; ++t) sum += cnt[t];
-    int run = block_exclusive_scan(sum, s_tmp) + L.marker_base;
-    for (int t = lo; t < hi; ++t) {
-      off[t] = run;
-      run += cnt[t];
-      cnt[t] = 0;
-    }
-    if (tid == nt - 1) off[ntiles] = L.marker_base + L.n_markers;
-  }
-  __syncthreads();
-
-  // 3. scatter (arbitrary order inside a bin)
-  for (int m = tid; m < L.n_markers; m += nt) {
-    const int gm = L.marker_base + m;
-    const int tx = p.cx[gm] / TX;
-    const int ty = min(max(p.cy[gm], 0), ny - 1) / TY;
-    const int key = ty * ntx + tx;
-    const int pos = atomicAdd(&cnt[key], 1);
-    p.bin_tmp[off[key] + pos] = gm;
-  }
-  __syncthreads();
-
-  // 4. order every bin by marker id (rank by counting; ids are unique)
-  {
-    const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
-    for (int base = wave * 64; base < ntiles; base += nwave * 64) {
-      const int b = base + lane;
-      int c = 0, s0 = 0;
-      if (b < ntiles) {
-        s0 = off[b];
-        c = off[b + 1] - s0;
-        if (c == 1) p.bin_idx[s0] = p.bin_tmp[s0];
-      }
-      unsigned long long mask = __ballot(c > 1);
-      while (mask) {
-        const int k = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const int bs = __shfl(s0, k), bc = __shfl(c, k);
-        for (int i = lane; i < bc; i += 64) {
-          const int id = p.bin_tmp[bs + i];
-          int rank = 0;
-          for (int j = 0; j < bc; ++j) rank += p.bin_tmp[bs + j] < id;
-          p.bin_idx[bs + rank] = id;
-        }
-      }
-    }
-  }
-
-  // 5. bond kinetics
+  // bond kinetics
   if (L.n_lig == 0 || L.freeze) return;
+  __syncthreads();
+  if (tid == 0) s_nelig = 0;
   __syncthreads();
   const double y_cr = L.y_cr;
   unsigned long long ties = 0;
-  for (int l = tid; l < L.n_lig; l += nt) {
-    const int gl = L.lig_base + l;
-    const int b = p.lig_body[gl], e = p.lig_elem[gl];
-    const BodyDev& Bd = p.body[b];
-    const int v0 = Bd.v0, nv = Bd.nv;
-    const double cx = 0.5 * (p.x[v0 + e] + p.x[v0 + (e + 1) % nv]);
-    const double cy = 0.5 * (p.y[v0 + e] + p.y[v0 + (e + 1) % nv]);
-    const int r = p.l2r[gl];
+  // (a) rupture (independent per bond) and formation eligibility
+  for (int l0 = 0; l0 < L.n_lig; l0 += nt) {
+    const int l = l0 + tid;
     int flag = 0;
-    if (r >= 0) {
-      const int wall = r < L.n_rec0 ? 0 : 1;
-      const double yl = bond_len(cx, cy, p.rec_x[L.rec_base + r], wall, L);
-      const double sig = Bd.sigma, sts = L.sigma_ts_frac * sig;
-      const double dy = yl - L.y_eq;
-      const double kr = L.kr0_dt * exp((sig - sts) * dy * dy / (2.0 * L.kbt));
-      const double P = 1.0 - exp(-kr);
-      const double u = philox_uniform(L.seed, n, l, 1, L.instance);
-      ties += fabs(u - P) < 1e-12;
-      if (u < P) {
-        p.l2r[gl] = -1;
-        p.r2l[L.rec_base + r] = -1;
-      }
-    } else {
-      const double d0 = cy + 0.5, d1 = (ny - 0.5) - cy;
-      const int wall = d0 <= d1 ? 0 : 1;
-      const double d = wall == 0 ? d0 : d1;
-      if (d < y_cr) flag = 1 + wall;
-    }
-    p.lig_flag[gl] = flag;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int l = 0; l < L.n_lig; ++l) {
+    if (l < L.n_lig) {
       const int gl = L.lig_base + l;
-      const int flag = p.lig_flag[gl];
-      if (!flag) continue;
-      const int wall = flag - 1;
-      const int b = p.lig_body[gl], e = p.lig_elem[gl];
-      const BodyDev& Bd = p.body[b];
-      const int v0 = Bd.v0, nv = Bd.nv;
-      const double cx = 0.5 * (p.x[v0 + e] + p.x[v0 + (e + 1) % nv]);
-      const double cy = 0.5 * (p.y[v0 + e] + p.y[v0 + (e + 1) % nv]);
+      const int va = p.lig_va[gl], vb = p.lig_vb[gl];
+      const double cx = 0.5 * (p.x[va] + p.x[vb]);
+      const double cy = 0.5 * (p.y[va] + p.y[vb]);
+      const int r = p.l2r[gl];
+      if (r >= 0) {
+        const int wall = r < L.n_rec0 ? 0 : 1;
+        const double yl = bond_len(cx, cy, p.rec_x[L.rec_base + r], wall, L);
+        const double sig = p.lig_sigma[gl], sts = L.sigma_ts_frac * sig;
+        const double dy = yl - L.y_eq;
+        const double kr = L.kr0_dt * exp((sig - sts) * dy * dy / (2.0 * L.kbt));
+        const double P = 1.0 - exp(-kr);
+        const double u = philox_uniform(L.seed, n, l, 1, L.instance);
+        ties += fabs(u - P) < 1e-12;
+        if (u < P) {
+          p.l2r[gl] = -1;
+          p.r2l[L.rec_base + r] = -1;
+        }
+      } else {
+        const double d0 = cy + 0.5, d1 = (ny - 0.5) - cy;
+        const int wall = d0 <= d1 ? 0 : 1;
+        const double d = wall == 0 ? d0 : d1;
+        if (d < y_cr) flag = 1 + wall;
+      }
+    }
+    // ordered compaction of eligible ligands (ascending ligand id)
+    const int pos = block_exclusive_scan(flag ? 1 : 0, s_tmp);
+    const int base = s_nelig;
+    if (flag) p.lig_flag[L.lig_base + base + pos] = (l << 1) | (flag - 1);
+    __syncthreads();
+    if (tid == nt - 1) s_nelig = base + pos + (flag ? 1 : 0);
+    __syncthreads();
+  }
+  // (b) formation, sequential over the eligible ligands in ascending order
+  if (tid == 0) {
+    const int ne = s_nelig;
+    for (int q = 0; q < ne; ++q) {
+      const int code = p.lig_flag[L.lig_base + q];
+      const int l = code >> 1, wall = code & 1;
+      const int gl = L.lig_base + l;
+      const int va = p.lig_va[gl], vb = p.lig_vb[gl];
+      const double cx = 0.5 * (p.x[va] + p.x[vb]);
+      const double cy = 0.5 * (p.y[va] + p.y[vb]);
       const int nr = wall == 0 ? L.n_rec0 : L.n_rec1;
       if (nr == 0) continue;
       const int roff = wall == 0 ? 0 : L.n_rec0;
@@ -310,7 +413,7 @@ __global__ __launch_bounds__(1024) void k_bin_bonds(Ptrs<T> p, int TX, int TY) {
       }
       if (best < 0) continue;
       const double yl = bond_len(cx, cy, xs[best], wall, L);
-      const double sig = Bd.sigma, sts = L.sigma_ts_frac * sig;
+      const double sig = p.lig_sigma[gl], sts = L.sigma_ts_frac * sig;
       const double dy = yl - L.y_eq;
       const double kf = L.kf0_dt * exp(-sts * dy * dy / (2.0 * L.kbt));
       const double P = 1.0 - exp(-kf);
@@ -341,96 +444,198 @@ __device__ inline void block_sum(double (*s)[256], double* v) {
   __syncthreads();
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_body(Ptrs<T> p) {
-  __shared__ double s_red[3][256];
-  __shared__ double s_rigid[6];
+constexpr int kVmax = 512;   // bodies up to this many vertices keep their scratch in LDS
+
+// SMALL: the body's per-vertex scratch lives in LDS (sm); otherwise in the
+// workspace.  A template parameter, so every access has a known address space.
+template <typename T, bool SMALL>
+__device__ __forceinline__ void body_impl(Ptrs<T>& p, int cache_nodes, double (*sm)[kVmax],
+                                          double (*s_red)[256], double* s_rigid, int* s_box,
+                                          unsigned char* s_dyn) {
   const int b = blockIdx.x;
-  BodyDev& Bd = p.body[b];
-  const int kind = Bd.kind, nv = Bd.nv, v0 = Bd.v0, inst = Bd.inst;
+  BodyDev* Bp = p.body + b;
+  const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0, inst = Bp->inst;
+  const double ks = Bp->ks, kb = Bp->kb, ka = Bp->ka, p_ref = Bp->p_ref, A0 = Bp->A0;
+  const double mv = Bp->mv, sigma = Bp->sigma;
+  const int lig_stride = Bp->lig_stride, lig_base = Bp->lig_base;
   const LatDev& L = p.lat[inst];
   const bool first = p.step_cur[inst] == 0;
   const int t = threadIdx.x, nt = blockDim.x;
-  const double* X = p.x + v0;
-  const double* Y = p.y + v0;
   const T* A = p.A + 9 * L.node_base;
   const double nu = (L.tau - 0.5) / 3.0;
+  const bool pery = L.periodic_y != 0;
+  // per-vertex scratch: LDS for small bodies, workspace otherwise
+  const double* X = SMALL ? sm[0] : p.x + v0;
+  const double* Y = SMALL ? sm[1] : p.y + v0;
+  double* S_len = SMALL ? sm[2] : p.s_len + v0;
+  double* S_nx = SMALL ? sm[3] : p.s_nx + v0;
+  double* S_ny = SMALL ? sm[4] : p.s_ny + v0;
+  double* S_bc = SMALL ? sm[5] : p.s_bc + v0;
+  double* S_bnx = SMALL ? sm[6] : p.s_bnx + v0;
+  double* S_bny = SMALL ? sm[7] : p.s_bny + v0;
+  double* S_fex = SMALL ? sm[8] : p.s_fex + v0;
+  double* S_fey = SMALL ? sm[9] : p.s_fey + v0;
+  if (SMALL) {
+    for (int v = t; v < nv; v += nt) {
+      sm[0][v] = p.x[v0 + v];
+      sm[1][v] = p.y[v0 + v];
+    }
+    __syncthreads();
+  }
 
   // pass 1: element geometry (element v joins v -> v+1), bending data, area
   double shoe = 0.0;
   for (int v = t; v < nv; v += nt) {
     const int vp = v + 1 == nv ? 0 : v + 1, vm = v == 0 ? nv - 1 : v - 1;
-    const double dxr = X[vp] - X[v], dyr = Y[vp] - Y[v];
+    const double xv = X[v], yv = Y[v], xp = X[vp], yp = Y[vp], xm = X[vm], ym = Y[vm];
+    const double dxr = xp - xv, dyr = yp - yv;
     const double lr = sqrt(dxr * dxr + dyr * dyr);
     const double txr = dxr / lr, tyr = dyr / lr;
-    const double dxl = X[v] - X[vm], dyl = Y[v] - Y[vm];
+    const double dxl = xv - xm, dyl = yv - ym;
     const double ll = sqrt(dxl * dxl + dyl * dyl);
     const double txl = dxl / ll, tyl = dyl / ll;
-    p.s_len[v0 + v] = lr;
-    p.s_nx[v0 + v] = tyr;
-    p.s_ny[v0 + v] = -txr;
+    S_len[v] = lr;
+    S_nx[v] = tyr;
+    S_ny[v] = -txr;
     if (kind != kRigid) {
       const double cr = txl * tyr - tyl * txr;
       const double dt = txl * txr + tyl * tyr;
       const double th = atan2(cr, dt);
       const double nsx = tyl + tyr, nsy = -txl - txr;
       const double nn = sqrt(nsx * nsx + nsy * nsy);
-      p.s_bc[v0 + v] = Bd.kb * (th - p.th0[v0 + v]);
-      p.s_bnx[v0 + v] = nsx / nn;
-      p.s_bny[v0 + v] = nsy / nn;
+      S_bc[v] = kb * (th - p.th0[v0 + v]);
+      S_bnx[v] = nsx / nn;
+      S_bny[v] = nsy / nn;
     }
-    shoe += X[v] * Y[vp] - X[vp] * Y[v];
+    shoe += xv * yp - xp * yv;
   }
   double area = shoe;
-  block_sum<1>(s_red, &area);
+  block_sum<1>(s_red, &area);   // its barriers also publish the scratch
   area *= 0.5;
+
+  // particles: cache rho*, u* over the box of nodes the probe and vertex
+  // stencils read (one pass of 9-population pulls per node instead of one
+  // per stencil use); boxes larger than the LDS cache fall back to direct
+  // evaluation
+  bool cached = false;
+  StarCache<T> C{(const T*)s_dyn, 0, 0, 0, 0};
+  if (kind != kRBC) {
+    int mnx = 0x7fffffff, mxx = -0x7fffffff, mny = 0x7fffffff, mxy = -0x7fffffff;
+    for (int v = t; v < nv; v += nt) {
+      const int vp = v + 1 == nv ? 0 : v + 1;
+      const double qx = 0.5 * (X[v] + X[vp]) + 1.2 * S_nx[v];
+      double qy = 0.5 * (Y[v] + Y[vp]) + 1.2 * S_ny[v];
+      if (!pery) qy = fmin(fmax(qy, 0.5), L.ny - 1.5);
+      const int c1x = (int)floor(X[v] + 0.5), c1y = (int)floor(Y[v] + 0.5);
+      const int c2x = (int)floor(qx + 0.5), c2y = (int)floor(qy + 0.5);
+      // stencil reach +-1, plus one node of margin against a one-ulp
+      // difference in the probe position recomputed in pass 2
+      mnx = min(mnx, min(c1x, c2x) - 2); mxx = max(mxx, max(c1x, c2x) + 2);
+      mny = min(mny, min(c1y, c2y) - 2); mxy = max(mxy, max(c1y, c2y) + 2);
+    }
+    // wave reductions first: only one lane per wave touches the LDS words
+    for (int o = 32; o > 0; o >>= 1) {
+      mnx = min(mnx, __shfl_xor(mnx, o)); mxx = max(mxx, __shfl_xor(mxx, o));
+      mny = min(mny, __shfl_xor(mny, o)); mxy = max(mxy, __shfl_xor(mxy, o));
+    }
+    if (t == 0) { s_box[0] = 0x7fffffff; s_box[1] = -0x7fffffff; s_box[2] = 0x7fffffff; s_box[3] = -0x7fffffff; }
+    __syncthreads();
+    if ((t & 63) == 0) {
+      atomicMin(&s_box[0], mnx); atomicMax(&s_box[1], mxx);
+      atomicMin(&s_box[2], mny); atomicMax(&s_box[3], mxy);
+    }
+    __syncthreads();
+    int by0 = s_box[2], by1 = s_box[3];
+    if (!pery) { by0 = max(by0, 0); by1 = min(by1, L.ny - 1); }
+    const int bw = s_box[1] - s_box[0] + 1, bh = by1 - by0 + 1;
+    if (bw > 0 && bh > 0 && (long long)bw * bh <= cache_nodes) {
+      cached = true;
+      C.bx0 = s_box[0]; C.by0 = by0; C.bw = bw; C.bh = bh;
+      T* cw = (T*)s_dyn;
+      const long long N = (long long)L.nx * L.ny;
+      const int nbox = bw * bh;
+      constexpr int NB = 4;   // nodes per lane per batch: 36 loads in flight
+      for (int k0 = 0; k0 < nbox; k0 += NB * nt) {
+        T hv[NB][kQ];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const int k = k0 + q * nt + t;
+          const int kk = k < nbox ? k : 0;
+          const int col = wrap_i(C.bx0 + kk % bw, L.nx);
+          int row = by0 + kk / bw;
+          if (pery) row = wrap_i(row, L.ny);
+          pull_node(A, N, L.nx, L.ny, pery, col, row, hv[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const int k = k0 + q * nt + t;
+          if (k >= nbox) continue;
+          double drho = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+          for (int i = 0; i < kQ; ++i) {
+            const double h = double(hv[q][i]);
+            drho += h;
+            jx += ex(i) * h;
+            jy += ey(i) * h;
+          }
+          const double r = 1.0 + drho;
+          cw[3 * k] = T(r);
+          cw[3 * k + 1] = T((jx + 0.5 * L.gx) / r);
+          cw[3 * k + 2] = T((jy + 0.5 * L.gy) / r);
+        }
+      }
+    }
+    __syncthreads();
+  }
 
   // pass 2: element loads (area penalty, adhesion springs, probe stresses)
   for (int l = t; l < nv; l += nt) {
     const int lp = l + 1 == nv ? 0 : l + 1;
-    const double len = p.s_len[v0 + l], nxl = p.s_nx[v0 + l], nyl = p.s_ny[v0 + l];
+    const double len = S_len[l], nxl = S_nx[l], nyl = S_ny[l];
     double fex = 0.0, fey = 0.0;
     if (kind != kRigid) {
-      const double c = Bd.ka * (1.0 - area / Bd.A0) * Bd.p_ref * len;
+      const double c = ka * (1.0 - area / A0) * p_ref * len;
       fex += c * nxl;
       fey += c * nyl;
     }
     if (kind != kRBC) {
       const double cx = 0.5 * (X[l] + X[lp]), cy = 0.5 * (Y[l] + Y[lp]);
       // adhesion spring on a bonded ligand element
-      if (Bd.lig_stride > 0 && l % Bd.lig_stride == 0) {
-        const int gl = Bd.lig_base + l / Bd.lig_stride;
+      if (lig_stride > 0 && l % lig_stride == 0) {
+        const int gl = lig_base + l / lig_stride;
         const int r = p.l2r[gl];
         if (r >= 0) {
           const int wall = r < L.n_rec0 ? 0 : 1;
           const double yl = bond_len(cx, cy, p.rec_x[L.rec_base + r], wall, L);
-          const double s = Bd.sigma * (yl - L.y_eq);
-          fex += s * nxl;
-          fey += s * nyl;
+          const double sp = sigma * (yl - L.y_eq);
+          fex += sp * nxl;
+          fey += sp * nyl;
         }
       }
       // probe 1.2 dx along the outward normal, kept inside the fluid
       const double qx = cx + 1.2 * nxl;
       double qy = cy + 1.2 * nyl;
-      if (!L.periodic_y) qy = fmin(fmax(qy, 0.5), L.ny - 1.5);
+      if (!pery) qy = fmin(fmax(qy, 0.5), L.ny - 1.5);
       double rho, ux, uy, g[4];
-      interp_star(A, L, qx, qy, true, rho, ux, uy, g);
+      if (cached) interp_cached(C, L, qx, qy, true, rho, ux, uy, g);
+      else interp_star(A, L, qx, qy, true, rho, ux, uy, g);
       const double pr = (rho - 1.0) * (1.0 / 3.0);
       const double txx = 2.0 * nu * g[0], tyy = 2.0 * nu * g[3], txy = nu * (g[1] + g[2]);
       fex += (-pr * nxl + txx * nxl + txy * nyl) * len;
       fey += (-pr * nyl + txy * nxl + tyy * nyl) * len;
     }
-    p.s_fex[v0 + l] = fex;
-    p.s_fey[v0 + l] = fey;
+    S_fex[l] = fex;
+    S_fey[l] = fey;
   }
   __syncthreads();
 
   if (kind == kRigid) {
+    const double xc0 = Bp->xc, yc0 = Bp->yc;
     double r3[3] = {0.0, 0.0, 0.0};
     for (int l = t; l < nv; l += nt) {
       const int lp = l + 1 == nv ? 0 : l + 1;
-      const double fex = p.s_fex[v0 + l], fey = p.s_fey[v0 + l];
-      const double cx = 0.5 * (X[l] + X[lp]) - Bd.xc, cy = 0.5 * (Y[l] + Y[lp]) - Bd.yc;
+      const double fex = S_fex[l], fey = S_fey[l];
+      const double cx = 0.5 * (X[l] + X[lp]) - xc0, cy = 0.5 * (Y[l] + Y[lp]) - yc0;
       r3[0] += fex;
       r3[1] += fey;
       r3[2] += cx * fey - cy * fex;
@@ -439,34 +644,34 @@ __global__ __launch_bounds__(256) void k_body(Ptrs<T> p) {
     if (t == 0) {
       double U[2], Om;
       for (int k = 0; k < 2; ++k) {
-        const double a = r3[k] / Bd.mass;
-        U[k] = first ? Bd.U[k] + a : (2.0 / 3.0) * (2.0 * Bd.U[k] - 0.5 * Bd.Um[k] + a);
+        const double a = r3[k] / Bp->mass;
+        U[k] = first ? Bp->U[k] + a : (2.0 / 3.0) * (2.0 * Bp->U[k] - 0.5 * Bp->Um[k] + a);
       }
-      const double al = r3[2] / Bd.inertia;
-      Om = first ? Bd.Om + al : (2.0 / 3.0) * (2.0 * Bd.Om - 0.5 * Bd.Omm + al);
-      Bd.Um[0] = Bd.U[0]; Bd.Um[1] = Bd.U[1];
-      Bd.U[0] = U[0]; Bd.U[1] = U[1];
-      Bd.Omm = Bd.Om; Bd.Om = Om;
-      Bd.xc += U[0];
-      Bd.yc += U[1];
-      Bd.theta += Om;
+      const double al = r3[2] / Bp->inertia;
+      Om = first ? Bp->Om + al : (2.0 / 3.0) * (2.0 * Bp->Om - 0.5 * Bp->Omm + al);
+      Bp->Um[0] = Bp->U[0]; Bp->Um[1] = Bp->U[1];
+      Bp->U[0] = U[0]; Bp->U[1] = U[1];
+      Bp->Omm = Bp->Om; Bp->Om = Om;
+      const double xc = xc0 + U[0], yc = yc0 + U[1], th = Bp->theta + Om;
+      Bp->xc = xc; Bp->yc = yc; Bp->theta = th;
       s_rigid[0] = U[0]; s_rigid[1] = U[1]; s_rigid[2] = Om;
-      s_rigid[3] = Bd.xc; s_rigid[4] = Bd.yc; s_rigid[5] = Bd.theta;
+      s_rigid[3] = xc; s_rigid[4] = yc; s_rigid[5] = th;
     }
     __syncthreads();
     const double U0 = s_rigid[0], U1 = s_rigid[1], Om = s_rigid[2];
     const double xc = s_rigid[3], yc = s_rigid[4], th = s_rigid[5];
-    const double c = cos(th), s = sin(th);
+    const double c = cos(th), sn = sin(th);
     for (int v = t; v < nv; v += nt) {
       const int gm = v0 + v, vm = v == 0 ? nv - 1 : v - 1;
       const double rx = p.r0x[gm], ry = p.r0y[gm];
-      const double xn = xc + (rx * c + ry * (-s));
-      const double yn = yc + (rx * s + ry * c);
+      const double xn = xc + (rx * c + ry * (-sn));
+      const double yn = yc + (rx * sn + ry * c);
       const double relx = xn - xc, rely = yn - yc;
       const double ukx = U0 + Om * (-rely), uky = U1 + Om * relx;
       double rho, ux, uy, g[4];
-      interp_star(A, L, X[v], Y[v], false, rho, ux, uy, g);
-      const double ds = 0.5 * (p.s_len[v0 + vm] + p.s_len[gm]);
+      if (cached) interp_cached(C, L, X[v], Y[v], false, rho, ux, uy, g);
+      else interp_star(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      const double ds = 0.5 * (S_len[vm] + S_len[v]);
       p.xn[gm] = xn;
       p.yn[gm] = yn;
       p.fx[gm] = (2.0 * (ukx - ux)) * ds;
@@ -481,40 +686,41 @@ __global__ __launch_bounds__(256) void k_body(Ptrs<T> p) {
     const int vm = v == 0 ? nv - 1 : v - 1, vp = v + 1 == nv ? 0 : v + 1;
     const int vmm = vm == 0 ? nv - 1 : vm - 1;
     // strain: element v pulls v along +t, element v-1 pulls v along -t
-    const double lr = p.s_len[gm], ll = p.s_len[v0 + vm];
-    const double sr = Bd.ks * (lr - p.l0[gm]);
-    const double sl = Bd.ks * (ll - p.l0[v0 + vm]);
+    const double lr = S_len[v], ll = S_len[vm];
+    const double sr = ks * (lr - p.l0[gm]);
+    const double sl = ks * (ll - p.l0[v0 + vm]);
     // tangents from normals: t = (-n_y, n_x)
-    double fx = sr * (-p.s_ny[gm]) - sl * (-p.s_ny[v0 + vm]);
-    double fy = sr * p.s_nx[gm] - sl * p.s_nx[v0 + vm];
+    double fx = sr * (-S_ny[v]) - sl * (-S_ny[vm]);
+    double fy = sr * S_nx[v] - sl * S_nx[vm];
     // bending at v-1 (v is its right vertex), v, v+1 (v is its left vertex)
     {
-      const double c = p.s_bc[v0 + vm];
-      const double fr = p.s_len[v0 + vm] / (p.s_len[v0 + vmm] + p.s_len[v0 + vm]);
-      fx += c * fr * p.s_bnx[v0 + vm];
-      fy += c * fr * p.s_bny[v0 + vm];
+      const double c = S_bc[vm];
+      const double fr = S_len[vm] / (S_len[vmm] + S_len[vm]);
+      fx += c * fr * S_bnx[vm];
+      fy += c * fr * S_bny[vm];
     }
     {
-      const double c = p.s_bc[gm];
-      fx -= c * p.s_bnx[gm];
-      fy -= c * p.s_bny[gm];
+      const double c = S_bc[v];
+      fx -= c * S_bnx[v];
+      fy -= c * S_bny[v];
     }
     {
-      const double c = p.s_bc[v0 + vp];
-      const double fl = p.s_len[gm] / (p.s_len[gm] + p.s_len[v0 + vp]);
-      fx += c * fl * p.s_bnx[v0 + vp];
-      fy += c * fl * p.s_bny[v0 + vp];
+      const double c = S_bc[vp];
+      const double fl = S_len[v] / (S_len[v] + S_len[vp]);
+      fx += c * fl * S_bnx[vp];
+      fy += c * fl * S_bny[vp];
     }
-    fx += 0.5 * p.s_fex[gm] + 0.5 * p.s_fex[v0 + vm];
-    fy += 0.5 * p.s_fey[gm] + 0.5 * p.s_fey[v0 + vm];
+    fx += 0.5 * S_fex[v] + 0.5 * S_fex[vm];
+    fy += 0.5 * S_fey[v] + 0.5 * S_fey[vm];
     if (kind == kRBC) {
       p.fx[gm] = fx;
       p.fy[gm] = fy;
     } else {
       double rho, ux, uy, g[4];
-      interp_star(A, L, X[v], Y[v], false, rho, ux, uy, g);
-      const double xn = X[v] + ux + 0.5 * fx / Bd.mv;
-      const double yn = Y[v] + uy + 0.5 * fy / Bd.mv;
+      if (cached) interp_cached(C, L, X[v], Y[v], false, rho, ux, uy, g);
+      else interp_star(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      const double xn = X[v] + ux + 0.5 * fx / mv;
+      const double yn = Y[v] + uy + 0.5 * fy / mv;
       // velocity imposed by the weak coupling: the vertex displacement of the
       // step (the second-order velocity of Eq. verletVel turns the coupling
       // into a marginally stable feedback that grows next to walls)
@@ -528,14 +734,27 @@ __global__ __launch_bounds__(256) void k_body(Ptrs<T> p) {
   }
 }
 
-// ---------------------------------------------------------------- k_advance
 template <typename T>
+__global__ __launch_bounds__(256) void k_body(Ptrs<T> p, int cache_nodes) {
+  __shared__ double s_red[3][256];
+  __shared__ double s_rigid[6];
+  __shared__ int s_box[4];
+  __shared__ double sm[10][kVmax];   // x, y, len, nx, ny, bc, bnx, bny, fex, fey
+  extern __shared__ unsigned char s_dyn[];
+  if (p.body[blockIdx.x].nv <= kVmax)
+    body_impl<T, true>(p, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+  else
+    body_impl<T, false>(p, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+}
+
+// ---------------------------------------------------------------- k_advance
+template <typename T, int TX, int TY>
 __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
-  const int gm = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gm >= p.nm_total) return;
-  const int b = p.mbody[gm];
-  const int kind = p.body[b].kind;
-  const int inst = p.body[b].inst;
+  const int gm0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = gm0 < p.nm_total;
+  const int gm = active ? gm0 : p.nm_total - 1;   // idle lanes shadow the last marker
+  const int info = p.minfo[gm];          // (instance << 2) | body kind
+  const int kind = info & 3, inst = info >> 2;
   const LatDev& L = p.lat[inst];
   const bool first = p.step_cur[inst] == 0;
   const double X = p.x[gm], Y = p.y[gm];
@@ -570,28 +789,59 @@ __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
     xn = p.xn[gm];
     yn = p.yn[gm];
   }
-  p.xm[gm] = X;
-  p.ym[gm] = Y;
-  p.x[gm] = xn;
-  p.y[gm] = yn;
+  int ncx = 0, ncy = 0;
+  if (active) {
+    p.xm[gm] = X;
+    p.ym[gm] = Y;
+    p.x[gm] = xn;
+    p.y[gm] = yn;
+    // stencil of the new position, used by the next step's spreading and
+    // interpolation (this lane has finished reading the old one)
+    marker_stencil(p, L, gm, xn, yn);
+    ncx = p.cx[gm];
+    ncy = p.cy[gm];
+  }
+  // join the bins the next step's fused kernel reads (all lanes take part
+  // in the wave-aggregated registration)
+  register_marker<TX, TY>(p.cnt_next, p.bin_next, p.bin_cap, p.overflow, L, gm, ncx, ncy, active);
 }
 
 // ------------------------------------------------------------------ launchers
+#define LBIB_TILE_DISPATCH(a, KERNEL, ...)                                                   \
+  do {                                                                                     \
+    if ((a).tile_x == 64 && (a).tile_y == 4) hipLaunchKernelGGL((KERNEL<T, 64, 4>), __VA_ARGS__);          \
+    else if ((a).tile_x == 128 && (a).tile_y == 2) hipLaunchKernelGGL((KERNEL<T, 128, 2>), __VA_ARGS__);   \
+    else if ((a).tile_x == 32 && (a).tile_y == 8) hipLaunchKernelGGL((KERNEL<T, 32, 8>), __VA_ARGS__);     \
+    else hipLaunchKernelGGL((KERNEL<T, 256, 1>), __VA_ARGS__);                             \
+  } while (0)
+
 template <typename T>
-void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_bin_bonds<T>, dim3(p.ninst), dim3(1024), 0, s, p, a.tile_x, a.tile_y);
-  if (p.nbody_total > 0) hipLaunchKernelGGL(k_body<T>, dim3(p.nbody_total), dim3(256), 0, s, p);
+void launch_stencil(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
+  if (p.nm_total == 0) return;
+  LBIB_TILE_DISPATCH(a, k_stencil, dim3((p.nm_total + 255) / 256), dim3(256), 0, s, p);
 }
 
 template <typename T>
-void launch_advance(const Ptrs<T>& p, hipStream_t s) {
-  if (p.nm_total == 0) return;
-  hipLaunchKernelGGL(k_advance<T>, dim3((p.nm_total + 255) / 256), dim3(256), 0, s, p);
+void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_bonds<T>, dim3(p.ninst), dim3(1024), 0, s, p);
+  if (p.nbody_total > 0) {
+    const int cache_nodes = kBodyCacheBytes / (3 * (int)sizeof(T));
+    hipLaunchKernelGGL(k_body<T>, dim3(p.nbody_total), dim3(256), kBodyCacheBytes, s, p, cache_nodes);
+  }
 }
+
+template <typename T>
+void launch_advance(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
+  if (p.nm_total == 0) return;
+  LBIB_TILE_DISPATCH(a, k_advance, dim3((p.nm_total + 255) / 256), dim3(256), 0, s, p);
+}
+#undef LBIB_TILE_DISPATCH
 
 template void launch_lagrangian<float>(const Ptrs<float>&, const StepArgs&, hipStream_t);
 template void launch_lagrangian<double>(const Ptrs<double>&, const StepArgs&, hipStream_t);
-template void launch_advance<float>(const Ptrs<float>&, hipStream_t);
-template void launch_advance<double>(const Ptrs<double>&, hipStream_t);
+template void launch_advance<float>(const Ptrs<float>&, const StepArgs&, hipStream_t);
+template void launch_advance<double>(const Ptrs<double>&, const StepArgs&, hipStream_t);
+template void launch_stencil<float>(const Ptrs<float>&, const StepArgs&, hipStream_t);
+template void launch_stencil<double>(const Ptrs<double>&, const StepArgs&, hipStream_t);
 
 }  // namespace lbib

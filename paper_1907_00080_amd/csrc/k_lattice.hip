@@ -2,10 +2,11 @@
 //
 // One workgroup owns one TX x TY tile of nodes (one node per lane).  Per node:
 //   1. Eulerian force F = g + sum_k F_k delta(x - X_k) (Sec. 2.2 spreading):
-//      gathered from the markers binned in the 3x3 neighbouring tiles, staged
-//      in LDS, summed in a fixed order (bins are sorted by marker id), so the
-//      result is deterministic and needs no atomics.  Tiles whose
-//      neighbourhood holds no marker skip this and use F = g.
+//      gathered from the tile's bin of markers whose 3x3 stencil overlaps it
+//      (filled by the previous step's marker advance),
+//      accumulated in LDS in 64-bit fixed point (order independent, hence
+//      deterministic, and free of global atomics).  Tiles with an empty bin
+//      skip this and use F = g.
 //   2. Pull streaming h_i(x) <- h*_i(x - e_i), x periodic, halfway bounce-back
 //      at y = -1/2 and ny - 1/2 (Sec. 3 walls; Eq. BGK streaming part).
 //   3. rho = 1 + sum h, u = (sum h e + F/2)/rho, BGK relaxation towards the
@@ -22,20 +23,12 @@
 
 namespace lbib {
 
-constexpr int kCap = 256;  // markers staged in LDS per chunk
+constexpr int kCap = 256;  // lanes per workgroup = nodes per tile
 
-// Sum of the three stencil weights of a marker that land on column/row `d`
-// relative to its centre.  d = node - centre, wrapped into a short range.
-__device__ inline int near_offset(int d, int n, bool periodic) {
-  if (periodic) {
-    if (d > 1) d -= n;
-    else if (d < -1) d += n;
-  }
-  return d;
-}
-
+// consume = 0 (measurement launches): the marker bins are left in place and
+// the caller points U at a spare buffer, so the simulation state is untouched.
 template <typename T, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total) {
+__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int consume) {
   static_assert(TX * TY == kCap, "one lane per LDS slot");
   const int g = blockIdx.x;
   const int per = (ntiles_total + 7) >> 3;
@@ -52,116 +45,106 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
   const int y = ty * TY + (lane / TX);
   const bool inside = x < nx && y < ny;
 
-  // ---- neighbouring bins: lane k < 9 inspects neighbour (k/3 - 1, k%3 - 1);
-  // duplicates (lattices of fewer than 3 tiles per direction) count once.
-  __shared__ int s_bstart[9], s_bcount[9];
-  if (lane < 9) {
-    const int dy = lane / 3 - 1, dx = lane % 3 - 1;
-    const int c = wrap_i(tx + dx, ntx);
-    bool keep = true;
-    for (int d = -1; d < dx; ++d) keep &= wrap_i(tx + d, ntx) != c;
-    int r = ty + dy;
-    if (pery) {
-      r = wrap_i(r, nty);
-      for (int d = -1; d < dy; ++d) keep &= wrap_i(ty + d, nty) != r;
-    } else {
-      keep &= r >= 0 && r < nty;
-    }
-    int s0 = 0, s1 = 0;
-    if (keep) {
-      const int bi = L.bin_base + r * ntx + c;
-      s0 = p.bin_off[bi];
-      s1 = p.bin_off[bi + 1];
-    }
-    s_bstart[lane] = s0;
-    s_bcount[lane] = s1 - s0;
-  }
-  __syncthreads();
-  int M = 0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) M += s_bcount[k];
-
-  T Fx = T(L.gx), Fy = T(L.gy);
-  if (M > 0) {
-    __shared__ int s_cx[kCap], s_cy[kCap];
-    __shared__ T s_w[8][kCap];   // wx0..2, wy0..2, Fx, Fy
-    double ax = 0.0, ay = 0.0;
-    const bool small_x = nx < 3, small_y = pery && ny < 3;
-    for (int c0 = 0; c0 < M; c0 += kCap) {
-      __syncthreads();
-      int j = c0 + lane;
-      if (j < M) {
-        int k = 0, jj = j;
-        while (jj >= s_bcount[k]) { jj -= s_bcount[k]; ++k; }
-        int m = p.bin_idx[s_bstart[k] + jj];
-        s_cx[lane] = p.cx[m];
-        s_cy[lane] = p.cy[m];
-        const int nm = p.nm_total;
-        s_w[0][lane] = T(p.wx[m]);
-        s_w[1][lane] = T(p.wx[nm + m]);
-        s_w[2][lane] = T(p.wx[2 * nm + m]);
-        s_w[3][lane] = T(p.wy[m]);
-        s_w[4][lane] = T(p.wy[nm + m]);
-        s_w[5][lane] = T(p.wy[2 * nm + m]);
-        s_w[6][lane] = T(p.fx[m]);
-        s_w[7][lane] = T(p.fy[m]);
-      }
-      __syncthreads();
-      const int cnt = min(kCap, M - c0);
-      if (inside) {
-        if (!small_x && !small_y) {
-          for (int q = 0; q < cnt; ++q) {
-            int dx = near_offset(x - s_cx[q], nx, true);
-            if (dx < -1 || dx > 1) continue;
-            int dy = near_offset(y - s_cy[q], ny, pery);
-            if (dy < -1 || dy > 1) continue;
-            T w = s_w[dx + 1][q] * s_w[3 + dy + 1][q];
-            ax += double(s_w[6][q] * w);
-            ay += double(s_w[7][q] * w);
-          }
-        } else {
-          for (int q = 0; q < cnt; ++q) {
-            T wxs = 0, wys = 0;
-            for (int a = 0; a < 3; ++a) {
-              if (wrap_i(s_cx[q] + a - 1, nx) == x) wxs += s_w[a][q];
-              int r = s_cy[q] + a - 1;
-              if (pery) r = wrap_i(r, ny);
-              if (r == y) wys += s_w[3 + a][q];
-            }
-            T w = wxs * wys;
-            ax += double(s_w[6][q] * w);
-            ay += double(s_w[7][q] * w);
-          }
-        }
-      }
-    }
-    Fx = T(double(Fx) + ax);
-    Fy = T(double(Fy) + ay);
-  }
-  if (!inside) return;
-
-  // ---- pull streaming with halfway bounce-back
+  // ---- pull streaming with halfway bounce-back, issued first so that the
+  // population loads are in flight while the tile's IB force is gathered
   const long long N = (long long)nx * ny;
   const T* __restrict__ A = p.A + 9 * L.node_base;
   T* __restrict__ B = p.B + 9 * L.node_base;
   const long long node = (long long)y * nx + x;
   T h[kQ];
+  if (inside) {
+    // source index per direction chosen without branches, so that all nine
+    // loads are issued back to back
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    int xs = x - ex(i);
-    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-    int ys = y - ey(i);
-    if (ys < 0 || ys >= ny) {
-      if (pery) {
-        ys = ys < 0 ? ys + ny : ys - ny;
-        h[i] = A[i * N + (long long)ys * nx + xs];
-      } else {
-        h[i] = A[opp(i) * N + node];
-      }
-    } else {
-      h[i] = A[i * N + (long long)ys * nx + xs];
+    for (int i = 0; i < kQ; ++i) {
+      int xs = x - ex(i);
+      xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+      int ys = y - ey(i);
+      const bool out = ys < 0 || ys >= ny;
+      ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+      const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * nx + xs;
+      h[i] = A[src];
     }
   }
+
+  // ---- Eulerian force: drive plus the markers whose stencil overlaps this tile.
+  // Contributions F_k w_a w_b are accumulated in LDS as 64-bit fixed-point
+  // integers: integer addition is associative, so the sum at every node is
+  // the same whatever order the lanes add in (deterministic, no global
+  // atomics).  The scale 2^S is chosen per tile from the largest force so the
+  // accumulator cannot overflow: |sum| <= M * max|F| < 2^61.
+  const int Mreg = p.cnt_cur[tile];
+  const bool full = Mreg > p.bin_cap;          // registrations were dropped
+  const int M = full ? p.bin_cap : Mreg;
+  const int* bin = p.bin_cur + (long long)tile * p.bin_cap;
+  T Fx = T(L.gx), Fy = T(L.gy);
+  if (M > 0) {
+    __shared__ unsigned long long s_ax[kCap], s_ay[kCap];
+    __shared__ double s_red[kCap / 64];
+    double fm = 0.0;
+    bool bad = false;
+    for (int j = lane; j < M; j += kCap) {
+      const int m = bin[j];
+      const double fx = p.fx[m], fy = p.fy[m];
+      bad |= !isfinite(fx) || !isfinite(fy);
+      fm = fmax(fm, fmax(fabs(fx), fabs(fy)));
+    }
+    for (int o = 32; o > 0; o >>= 1) fm = fmax(fm, __shfl_xor(fm, o));
+    const bool wbad = __any(bad);
+    if ((lane & 63) == 0) s_red[lane >> 6] = wbad ? -1.0 : fm;
+    s_ax[lane] = 0ull;
+    s_ay[lane] = 0ull;
+    __syncthreads();
+    double fmax_t = 0.0;
+    bool tbad = full;
+#pragma unroll
+    for (int w = 0; w < kCap / 64; ++w) {
+      tbad |= s_red[w] < 0.0;
+      fmax_t = fmax(fmax_t, s_red[w]);
+    }
+    if (tbad) {
+      Fx = Fy = T(NAN);
+    } else if (fmax_t > 0.0) {
+      int e;
+      frexp(fmax_t * (double)M, &e);
+      const double sc = ldexp(1.0, 61 - e);
+      const int x0 = tx * TX, y0 = ty * TY;
+      const int nm = p.nm_total;
+      for (int j = lane; j < M; j += kCap) {
+        const int m = bin[j];
+        const int cx = p.cx[m], cy = p.cy[m];
+        const double fx = p.fx[m] * sc, fy = p.fy[m] * sc;
+        const double wxa[3] = {p.wx[m], p.wx[nm + m], p.wx[2 * nm + m]};
+        const double wyb[3] = {p.wy[m], p.wy[nm + m], p.wy[2 * nm + m]};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          int row = cy + b - 1;
+          if (pery) row = wrap_i(row, ny);
+          const int ly = row - y0;
+          if (ly < 0 || ly >= TY) continue;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int lx = wrap_i(cx + a - 1, nx) - x0;
+            if (lx < 0 || lx >= TX) continue;
+            const double w = wxa[a] * wyb[b];
+            atomicAdd(&s_ax[ly * TX + lx], (unsigned long long)__double2ll_rn(fx * w));
+            atomicAdd(&s_ay[ly * TX + lx], (unsigned long long)__double2ll_rn(fy * w));
+          }
+        }
+      }
+      __syncthreads();
+      const double isc = 1.0 / sc;
+      Fx = T(L.gx + (double)(long long)s_ax[lane] * isc);
+      Fy = T(L.gy + (double)(long long)s_ay[lane] * isc);
+    }
+  }
+  if (consume && lane == 0) {
+    // every lane has read the count: clear it for the next use of this set
+    if (Mreg > 0) p.cnt_cur[tile] = 0;
+    p.touched[tile] = Mreg > 0;
+  }
+  if (!inside) return;
+
   // ---- moments and forced BGK collision
   const T drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
   const T rho = T(1) + drho;
@@ -212,19 +195,8 @@ __global__ void k_fields(Ptrs<T> p, int inst, int TX, int TY, double* rho_o, dou
     jy += ey(i) * h[i];
   }
   const double rho = 1.0 + drho;
-  // touched tile?
-  const int tx = x / TX, ty = y / TY;
-  bool touched = false;
-  for (int dy = -1; dy <= 1 && !touched; ++dy) {
-    int r = ty + dy;
-    if (L.periodic_y) r = wrap_i(r, L.nty);
-    else if (r < 0 || r >= L.nty) continue;
-    for (int dx = -1; dx <= 1; ++dx) {
-      int c = wrap_i(tx + dx, L.ntx);
-      int bi = L.bin_base + r * L.ntx + c;
-      if (p.bin_off[bi + 1] > p.bin_off[bi]) { touched = true; break; }
-    }
-  }
+  // touched tile: the fused kernel applied IB forces there in the last step
+  const bool touched = p.touched[L.tile_base + (y / TY) * L.ntx + (x / TX)] != 0;
   double ux, uy;
   if (touched) {
     const T* U = p.U + 2 * L.node_base;
@@ -301,17 +273,17 @@ __global__ void k_diag2(const double* part, int nblk, double* out) {
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
+void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int consume) {
   const int per = (a.ntiles_total + 7) / 8;
   dim3 grid(8 * per), block(kCap);
   if (a.tile_x == 64 && a.tile_y == 4)
-    hipLaunchKernelGGL((k_lb_fused<T, 64, 4>), grid, block, 0, s, p, a.ntiles_total);
+    hipLaunchKernelGGL((k_lb_fused<T, 64, 4>), grid, block, 0, s, p, a.ntiles_total, consume);
   else if (a.tile_x == 128 && a.tile_y == 2)
-    hipLaunchKernelGGL((k_lb_fused<T, 128, 2>), grid, block, 0, s, p, a.ntiles_total);
+    hipLaunchKernelGGL((k_lb_fused<T, 128, 2>), grid, block, 0, s, p, a.ntiles_total, consume);
   else if (a.tile_x == 32 && a.tile_y == 8)
-    hipLaunchKernelGGL((k_lb_fused<T, 32, 8>), grid, block, 0, s, p, a.ntiles_total);
+    hipLaunchKernelGGL((k_lb_fused<T, 32, 8>), grid, block, 0, s, p, a.ntiles_total, consume);
   else
-    hipLaunchKernelGGL((k_lb_fused<T, 256, 1>), grid, block, 0, s, p, a.ntiles_total);
+    hipLaunchKernelGGL((k_lb_fused<T, 256, 1>), grid, block, 0, s, p, a.ntiles_total, consume);
 }
 
 template <typename T>
@@ -330,8 +302,8 @@ void launch_diag(const Ptrs<T>& p, const StepArgs&, long long nodes_total, doubl
   hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, p.red, nblk, out);
 }
 
-template void launch_lb_fused<float>(const Ptrs<float>&, const StepArgs&, hipStream_t);
-template void launch_lb_fused<double>(const Ptrs<double>&, const StepArgs&, hipStream_t);
+template void launch_lb_fused<float>(const Ptrs<float>&, const StepArgs&, hipStream_t, int);
+template void launch_lb_fused<double>(const Ptrs<double>&, const StepArgs&, hipStream_t, int);
 template void launch_fields<float>(const Ptrs<float>&, const StepArgs&, int, double*, double*,
                                    double*, int, int, long long, hipStream_t);
 template void launch_fields<double>(const Ptrs<double>&, const StepArgs&, int, double*, double*,

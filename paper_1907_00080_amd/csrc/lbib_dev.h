@@ -7,8 +7,8 @@
 //   markers           : x[Nm], y[Nm] (current), xm/ym (previous), xn/yn (next,
 //                       particles), fx/fy (force handed to the fluid),
 //                       per-marker stencil cx, cy (int) and weights wx[3], wy[3]
-//   bins              : bin_off[ntiles + 1] per instance (global marker ids in
-//                       bin_idx, sorted by id inside a bin)
+//   bins              : per tile, the markers whose 3x3 stencil overlaps it
+//                       (fixed capacity, two sets used alternately)
 //   ligands           : l2r[NL] (-1 free), receptors rec_x[NR], r2l[NR]
 #pragma once
 #include <hip/hip_runtime.h>
@@ -42,7 +42,7 @@ struct LatDev {
   int nx, ny, periodic_y;
   int ntx, nty;          // tiles of the fused kernel / marker bins
   int tile_base;         // first global tile index of this instance
-  int bin_base;          // first entry of bin_off (= tile_base + instance index)
+  int bin_base;          // unused (kept for layout stability)
   int marker_base, n_markers;
   int body_base, n_bodies;
   int lig_base, n_lig;
@@ -78,12 +78,22 @@ struct Ptrs {
   double *x, *y, *xm, *ym, *xn, *yn, *fx, *fy;
   double *l0, *th0, *r0x, *r0y;
   int* mbody;
+  int* minfo;            // per marker: (instance << 2) | body kind
   int *cx, *cy;
   double *wx, *wy;       // [3][Nm]
   double *s_len, *s_nx, *s_ny, *s_bc, *s_bnx, *s_bny, *s_bfl, *s_fex, *s_fey;  // per-vertex scratch
-  int *bin_off, *bin_cnt, *bin_tmp, *bin_idx;
+  // marker bins of fixed capacity per tile, double buffered: the fused
+  // kernel consumes (and clears) the current set while the marker advance
+  // fills the other one for the next step
+  int *cnt_cur, *cnt_next;   // registrations per tile
+  int *bin_cur, *bin_next;   // [tile * bin_cap + k] = marker id
+  int* touched;              // per tile: IB force applied in the last step
+  int* overflow;             // registrations dropped because a bin was full
+  int bin_cap;
   int* tile_inst;
   int *lig_body, *lig_elem, *l2r, *r2l, *lig_flag;
+  int *lig_va, *lig_vb;  // global vertex ids of a ligand element's two ends
+  double* lig_sigma;     // bond spring constant of each ligand's body
   double* rec_x;
   long long *step_next, *step_cur;   // per instance
   double* red;                        // reduction scratch
@@ -149,10 +159,11 @@ __device__ inline double philox_uniform(unsigned long long seed, long long step,
 struct StepArgs {
   int tile_x, tile_y;
   int ntiles_total;
+  int max_inst_tiles;   // largest tile count of any instance
 };
 
 template <typename T>
-void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
+void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int consume = 1);
 template <typename T>
 void launch_fields(const Ptrs<T>& p, const StepArgs& a, int inst, double* rho, double* ux,
                    double* uy, int nx, int ny, long long node_base, hipStream_t s);
@@ -165,6 +176,8 @@ void launch_init_pop(const Ptrs<T>& p, const double* rho, const double* ux, cons
 template <typename T>
 void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
 template <typename T>
-void launch_advance(const Ptrs<T>& p, hipStream_t s);
+void launch_advance(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
+template <typename T>
+void launch_stencil(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
 
 }  // namespace lbib

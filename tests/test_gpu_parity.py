@@ -120,6 +120,52 @@ def test_bodies_fp64_match_oracle_to_roundoff(name, kw):
     sim.close()
 
 
+def _large_and_seam_cases():
+    """Bodies beyond the LDS scratch (> 512 vertices), a particle whose
+    stencil box exceeds the LDS cache, and bodies straddling the periodic
+    seam of a 129-wide lattice whose last 64-wide tile is one column wide."""
+    out = []
+    nx, ny = 260, 130
+    rbc = geometry.place(geometry.rbc_contour(40.0, 600), 0.2, [70.0, 62.0])
+    big = geometry.place(geometry.circle(22.0, 140), 0.0, [180.0, 60.0])
+    g = configs.poiseuille_force(0.02, ny, 1.0)
+    rho0, u0 = configs.poiseuille_init(nx, ny, g, 1.0)
+    out.append(("large", configs.Workload(
+        "large", nx, ny, 1.0, gx=g,
+        bodies=[configs.Body(configs.RBC_KINEMATIC, rbc, ks=0.01, kb=0.002),
+                configs.Body(configs.PARTICLE_RIGID, big)],
+        rho0=rho0, u0=u0)))
+    nx, ny = 129, 33
+    soft = geometry.place(geometry.circle(4.0, 30), 0.3, [128.4, 15.0])
+    rig = geometry.place(geometry.circle(3.0, 24), 0.0, [0.3, 25.0])
+    cell = geometry.place(geometry.rbc_contour(8.0, 60), 0.1, [63.6, 8.0])
+    g = configs.poiseuille_force(0.02, ny, 1.0)
+    rho0, u0 = configs.poiseuille_init(nx, ny, g, 1.0)
+    ks = 0.02
+    out.append(("seam", configs.Workload(
+        "seam", nx, ny, 1.0, gx=g,
+        bodies=[configs.Body(configs.PARTICLE_SOFT, soft, ks=ks, kb=0.05 * ks * 16),
+                configs.Body(configs.PARTICLE_RIGID, rig),
+                configs.Body(configs.RBC_KINEMATIC, cell, ks=0.02, kb=0.001)],
+        rho0=rho0, u0=u0)))
+    return out
+
+
+@pytest.mark.parametrize("name,wl", _large_and_seam_cases(), ids=["large", "seam"])
+@pytest.mark.parametrize("tile", [(64, 4), (256, 1)])
+def test_large_bodies_and_seam_fp64(name, wl, tile):
+    announce(f"{name} fp64 tile {tile}")
+    sim = pkg.Sim(wl, dtype="f64", tile=tile)
+    ref = oracle.Sim(wl)
+    for n in (1, 20, 60):
+        sim.step(n - sim.step_count)
+        ref.step(n - ref.n)
+        e, _ = vel_err(sim, ref)
+        dx = marker_err(sim, ref)
+        assert e < 1e-9, (n, e)
+        assert dx < 1e-9, (n, dx)
+
+
 def test_cfg1_fp32_1000_steps_meets_tolerance():
     """256x64 channel, one RBC and one rigid 1 um particle, 1000 steps:
     velocity rel-L2 <= 1e-5 and markers <= 1e-4 dx against the FP64 oracle."""

@@ -134,6 +134,8 @@ typedef struct {
   int32_t bin_overflow;  /* marker-bin registrations dropped since set-up (a
                             full bin also poisons its tile's force, so the
                             watchdog reports it); 0 in any valid run       */
+  int32_t sync_timeouts; /* in-kernel waits for the bond update that gave up
+                            (0 in any valid run)                           */
 } lbib_diag;
 
 uint32_t lbib_abi_version(void);

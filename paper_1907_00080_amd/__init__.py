@@ -63,7 +63,7 @@ class Diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("mass", ctypes.c_double), ("mom_x", ctypes.c_double),
                 ("mom_y", ctypes.c_double), ("rho_min", ctypes.c_double), ("u_max", ctypes.c_double),
                 ("nonfinite", ctypes.c_int64), ("nbonds", ctypes.c_int32),
-                ("bin_overflow", ctypes.c_int32)]
+                ("bin_overflow", ctypes.c_int32), ("sync_timeouts", ctypes.c_int32)]
 
 
 class LbibError(RuntimeError):

@@ -52,7 +52,7 @@ struct Layout {
   size_t x, y, xm, ym, xn, yn, fx, fy, l0, th0, r0x, r0y;
   size_t mbody, minfo, cx, cy, wx, wy;
   size_t s[9];
-  size_t cnt[2], bins[2], touched, overflow, Uspare, tile_inst;
+  size_t cnt[2], bins[2], touched, overflow, fmax, bond_flag, spin, Uspare, tile_inst;
   size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma;
   size_t step_next, step_cur, ties, red;
   size_t total;
@@ -160,6 +160,9 @@ void compute_layout(lbib_ctx* c) {
   }
   L.touched = take(4 * (size_t)c->ntiles);
   L.overflow = take(8);
+  L.fmax = take(8 * (size_t)c->ninst);
+  L.bond_flag = take(4 * (size_t)c->ninst);
+  L.spin = take(8);
   L.Uspare = take(es * 2 * c->nodes);   // velocity output of measurement launches
   L.tile_inst = take(4 * c->ntiles);
   L.lig_body = take(4 * nl);
@@ -208,6 +211,9 @@ Ptrs<T> make_ptrs(const lbib_ctx* c) {
   p.bin_next = (int*)(w + L.bins[c->parity ^ 1]);
   p.touched = (int*)(w + L.touched);
   p.overflow = (int*)(w + L.overflow);
+  p.fmax_bits = (unsigned long long*)(w + L.fmax);
+  p.bond_flag = (int*)(w + L.bond_flag);
+  p.spin_timeouts = (int*)(w + L.spin);
   p.bin_cap = c->bin_cap;
   p.tile_inst = (int*)(w + L.tile_inst);
   p.lig_body = (int*)(w + L.lig_body);
@@ -393,6 +399,9 @@ lbib_status upload_all(lbib_ctx* c) {
   for (int k = 0; k < 2; ++k) HIPCHK(c, hipMemsetAsync(w + L.cnt[k], 0, 4 * (size_t)c->ntiles, s));
   HIPCHK(c, hipMemsetAsync(w + L.touched, 0, 4 * (size_t)c->ntiles, s));
   HIPCHK(c, hipMemsetAsync(w + L.overflow, 0, 8, s));
+  HIPCHK(c, hipMemsetAsync(w + L.fmax, 0, 8 * (size_t)c->ninst, s));
+  HIPCHK(c, hipMemsetAsync(w + L.bond_flag, 0, 4 * (size_t)c->ninst, s));
+  HIPCHK(c, hipMemsetAsync(w + L.spin, 0, 8, s));
   HIPCHK(c, hipStreamSynchronize(s));
   // populations: equilibrium of the initial fields, shifted by the weights
   for (int i = 0; i < c->ninst; ++i) {
@@ -899,10 +908,12 @@ lbib_status lbib_diagnostics(lbib_ctx* c, lbib_diag* out) {
     tot += nb;
   }
   out->nbonds = tot;
-  int32_t ovf = 0;
+  int32_t ovf = 0, spin = 0;
   HIPCHK(c, hipMemcpyAsync(&ovf, c->ws + c->L.overflow, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&spin, c->ws + c->L.spin, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   out->bin_overflow = ovf;
+  out->sync_timeouts = spin;
   return LBIB_OK;
 }
 

@@ -1,11 +1,11 @@
 // k_lagrangian.hip - Lagrangian side of the LB-IB step (gfx950), float64.
 //
 // Per time step n (the order is the one used throughout the library):
-//   k_bonds       one workgroup per lattice instance:
+//   k_body        first one workgroup per lattice instance:
 //                   - bond kinetics: rupture pass, then formation pass in
 //                     ascending ligand order (Sec. 2.2 Wall-Particle Interaction),
 //                     with Philox4x32-10 uniforms keyed by (step, ligand).
-//   k_body        one workgroup per body:
+//                 then one workgroup per body:
 //                   - membrane strain, bending and area forces (Eqs. strainFor,
 //                     bendFor, areaFor), adhesion springs (Eq. adhFor);
 //                   - particles: probe pressure/viscous loads (Eqs. hydroForP,
@@ -307,23 +307,11 @@ __global__ __launch_bounds__(256) void k_stencil(Ptrs<T> p) {
 constexpr int kBodyCacheBytes = 16 * 1024;   // LDS cache of rho*, u* per particle
 
 // ---------------------------------------------------------------- k_bonds
-// Step bookkeeping and bond kinetics of one lattice instance.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_bonds(Ptrs<T> p) {
-  __shared__ int s_tmp[1024];
-  __shared__ int s_nelig;
-  const int inst = blockIdx.x;
-  const LatDev& L = p.lat[inst];
+__device__ __forceinline__ void bonds_kinetics(Ptrs<T>& p, const LatDev& L, int inst, long long n,
+                                               int nx, int ny, int* s_tmp, int& s_nelig) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const long long n = p.step_next[inst];
-  __syncthreads();
-  if (tid == 0) {
-    p.step_cur[inst] = n;
-    p.step_next[inst] = n + 1;
-  }
-  const int ny = L.ny, nx = L.nx;
-
-  // bond kinetics
+  // bond kinetics (Sec. 2.2): rupture then formation
   if (L.n_lig == 0 || L.freeze) return;
   __syncthreads();
   if (tid == 0) s_nelig = 0;
@@ -428,20 +416,67 @@ __global__ __launch_bounds__(1024) void k_bonds(Ptrs<T> p) {
   if (ties) atomicAdd(&p.ties[inst], ties);
 }
 
+// Step bookkeeping and bond kinetics of one lattice instance (the first
+// workgroups of the body kernel).  Ends by raising the instance's flag that
+// particle workgroups wait for before they read the bond table.
+template <typename T>
+__device__ __forceinline__ void bonds_impl(Ptrs<T>& p, int inst, int* s_tmp, int* s_nelig_p) {
+  int& s_nelig = *s_nelig_p;
+  const LatDev& L = p.lat[inst];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long n = p.step_next[inst];
+  __syncthreads();
+  if (tid == 0) {
+    p.step_cur[inst] = n;
+    p.step_next[inst] = n + 1;
+  }
+  const int ny = L.ny, nx = L.nx;
+  bonds_kinetics(p, L, inst, n, nx, ny, s_tmp, s_nelig);
+  // publish: every lane's writes, then the flag
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(&p.bond_flag[inst], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+
+
 // ---------------------------------------------------------------- k_body
 // Block reduction (fixed tree order) of NV values per thread slot.
+// Block sum of NV values per lane in a fixed order (butterfly inside each
+// wave, then the wave sums in wave order): deterministic.
+constexpr int kBodyThreads = 256;
+constexpr int kSpinMax = 1 << 22;   // bounded wait for the bond flag (~0.2 s)
 template <int NV>
-__device__ inline void block_sum(double (*s)[256], double* v) {
-  const int t = threadIdx.x;
-  for (int k = 0; k < NV; ++k) s[k][t] = v[k];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w)
-      for (int k = 0; k < NV; ++k) s[k][t] += s[k][t + w];
-    __syncthreads();
+__device__ inline void block_sum(double (*s)[kBodyThreads / 64], double* v) {
+  const int t = threadIdx.x, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if ((t & 63) == 0) s[k][t >> 6] = x;
   }
-  for (int k = 0; k < NV; ++k) v[k] = s[k][0];
   __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = 0.0;
+    for (int w = 0; w < nw; ++w) x += s[k][w];
+    v[k] = x;
+  }
+  __syncthreads();
+}
+
+// max that propagates NaN (fmax drops it)
+__device__ inline double fmax_nan(double a, double b) { return (a > b || a != a) ? a : b; }
+
+// Largest |F| a body hands to the fluid, folded into the instance maximum
+// (non-negative doubles order like their bit patterns; NaN and Inf sort above
+// every finite value, so a broken force shows up as a non-finite maximum).
+__device__ inline void record_fmax(unsigned long long* slot, double m, double (*s)[kBodyThreads / 64]) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double other = __shfl_xor(m, o);
+    m = (other > m || other != other) ? other : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m != 0.0) atomicMax(slot, (unsigned long long)__double_as_longlong(m));
 }
 
 constexpr int kVmax = 512;   // bodies up to this many vertices keep their scratch in LDS
@@ -449,17 +484,15 @@ constexpr int kVmax = 512;   // bodies up to this many vertices keep their scrat
 // SMALL: the body's per-vertex scratch lives in LDS (sm); otherwise in the
 // workspace.  A template parameter, so every access has a known address space.
 template <typename T, bool SMALL>
-__device__ __forceinline__ void body_impl(Ptrs<T>& p, int cache_nodes, double (*sm)[kVmax],
-                                          double (*s_red)[256], double* s_rigid, int* s_box,
+__device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, double (*sm)[kVmax],
+                                          double (*s_red)[kBodyThreads / 64], double* s_rigid, int* s_box,
                                           unsigned char* s_dyn) {
-  const int b = blockIdx.x;
   BodyDev* Bp = p.body + b;
   const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0, inst = Bp->inst;
   const double ks = Bp->ks, kb = Bp->kb, ka = Bp->ka, p_ref = Bp->p_ref, A0 = Bp->A0;
   const double mv = Bp->mv, sigma = Bp->sigma;
   const int lig_stride = Bp->lig_stride, lig_base = Bp->lig_base;
   const LatDev& L = p.lat[inst];
-  const bool first = p.step_cur[inst] == 0;
   const int t = threadIdx.x, nt = blockDim.x;
   const T* A = p.A + 9 * L.node_base;
   const double nu = (L.tau - 0.5) / 3.0;
@@ -588,6 +621,25 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int cache_nodes, double (*
     __syncthreads();
   }
 
+  // particles read the bond table (and rigid ones the step counter) written
+  // by this instance's bond workgroup: wait for its flag (bounded spin; the
+  // bond workgroups have the lowest ids, so they are always dispatched)
+  bool first = false;
+  if (kind != kRBC) {
+    if (t == 0) {
+      int it = 0;
+      while (__hip_atomic_load(&p.bond_flag[inst], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+             it < kSpinMax) {
+        __builtin_amdgcn_s_sleep(2);
+        ++it;
+      }
+      if (it == kSpinMax) atomicAdd(p.spin_timeouts, 1);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    first = p.step_cur[inst] == 0;
+  }
+
   // pass 2: element loads (area penalty, adhesion springs, probe stresses)
   for (int l = t; l < nv; l += nt) {
     const int lp = l + 1 == nv ? 0 : l + 1;
@@ -658,6 +710,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int cache_nodes, double (*
       s_rigid[3] = xc; s_rigid[4] = yc; s_rigid[5] = th;
     }
     __syncthreads();
+    double fm = 0.0;
     const double U0 = s_rigid[0], U1 = s_rigid[1], Om = s_rigid[2];
     const double xc = s_rigid[3], yc = s_rigid[4], th = s_rigid[5];
     const double c = cos(th), sn = sin(th);
@@ -674,13 +727,17 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int cache_nodes, double (*
       const double ds = 0.5 * (S_len[vm] + S_len[v]);
       p.xn[gm] = xn;
       p.yn[gm] = yn;
-      p.fx[gm] = (2.0 * (ukx - ux)) * ds;
-      p.fy[gm] = (2.0 * (uky - uy)) * ds;
+      const double fx = (2.0 * (ukx - ux)) * ds, fy = (2.0 * (uky - uy)) * ds;
+      p.fx[gm] = fx;
+      p.fy[gm] = fy;
+      fm = fmax_nan(fm, fmax_nan(fabs(fx), fabs(fy)));
     }
+    record_fmax(p.fmax_bits + inst, fm, s_red);
     return;
   }
 
   // membrane vertex forces: strain + bending + shared element loads
+  double fm = 0.0;
   for (int v = t; v < nv; v += nt) {
     const int gm = v0 + v;
     const int vm = v == 0 ? nv - 1 : v - 1, vp = v + 1 == nv ? 0 : v + 1;
@@ -715,6 +772,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int cache_nodes, double (*
     if (kind == kRBC) {
       p.fx[gm] = fx;
       p.fy[gm] = fy;
+      fm = fmax_nan(fm, fmax_nan(fabs(fx), fabs(fy)));
     } else {
       double rho, ux, uy, g[4];
       if (cached) interp_cached(C, L, X[v], Y[v], false, rho, ux, uy, g);
@@ -728,23 +786,35 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int cache_nodes, double (*
       const double ds = 0.5 * (ll + lr);
       p.xn[gm] = xn;
       p.yn[gm] = yn;
-      p.fx[gm] = (2.0 * (Ux - ux)) * ds;
-      p.fy[gm] = (2.0 * (Uy - uy)) * ds;
+      const double ffx = (2.0 * (Ux - ux)) * ds, ffy = (2.0 * (Uy - uy)) * ds;
+      p.fx[gm] = ffx;
+      p.fy[gm] = ffy;
+      fm = fmax_nan(fm, fmax_nan(fabs(ffx), fabs(ffy)));
     }
   }
+  record_fmax(p.fmax_bits + inst, fm, s_red);
 }
 
+// Workgroups [0, ninst): bond kinetics of each instance; then one workgroup
+// per body: membrane forces, particle loads and motion.
 template <typename T>
-__global__ __launch_bounds__(256) void k_body(Ptrs<T> p, int cache_nodes) {
-  __shared__ double s_red[3][256];
+__global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_nodes) {
+  __shared__ double s_red[3][kBodyThreads / 64];
   __shared__ double s_rigid[6];
   __shared__ int s_box[4];
   __shared__ double sm[10][kVmax];   // x, y, len, nx, ny, bc, bnx, bny, fex, fey
+  __shared__ int s_tmp[kBodyThreads];
+  __shared__ int s_nelig;
   extern __shared__ unsigned char s_dyn[];
-  if (p.body[blockIdx.x].nv <= kVmax)
-    body_impl<T, true>(p, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+  if ((int)blockIdx.x < p.ninst) {
+    bonds_impl(p, blockIdx.x, s_tmp, &s_nelig);
+    return;
+  }
+  const int b = blockIdx.x - p.ninst;
+  if (p.body[b].nv <= kVmax)
+    body_impl<T, true>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
   else
-    body_impl<T, false>(p, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+    body_impl<T, false>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
 }
 
 // ---------------------------------------------------------------- k_advance
@@ -754,7 +824,12 @@ __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
   const bool active = gm0 < p.nm_total;
   const int gm = active ? gm0 : p.nm_total - 1;   // idle lanes shadow the last marker
   const int info = p.minfo[gm];          // (instance << 2) | body kind
-  const int kind = info & 3, inst = info >> 2;
+  const int kind = info & 3;
+  // the instance is almost always the same across a wave: then make it a
+  // scalar so the lattice descriptor comes through scalar loads
+  int inst = info >> 2;
+  const int inst0 = __builtin_amdgcn_readfirstlane(inst);
+  if (__ballot(inst != inst0) == 0ull) inst = inst0;
   const LatDev& L = p.lat[inst];
   const bool first = p.step_cur[inst] == 0;
   const double X = p.x[gm], Y = p.y[gm];
@@ -801,6 +876,14 @@ __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
     ncx = p.cx[gm];
     ncy = p.cy[gm];
   }
+  if (gm0 == 0) {
+    // the fused kernel of this step has read the force maximum and the body
+    // kernel has passed its bond flags: reset both for the next step
+    for (int i = 0; i < p.ninst; ++i) {
+      p.fmax_bits[i] = 0ull;
+      p.bond_flag[i] = 0;
+    }
+  }
   // join the bins the next step's fused kernel reads (all lanes take part
   // in the wave-aggregated registration)
   register_marker<TX, TY>(p.cnt_next, p.bin_next, p.bin_cap, p.overflow, L, gm, ncx, ncy, active);
@@ -823,11 +906,9 @@ void launch_stencil(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
 
 template <typename T>
 void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_bonds<T>, dim3(p.ninst), dim3(1024), 0, s, p);
-  if (p.nbody_total > 0) {
-    const int cache_nodes = kBodyCacheBytes / (3 * (int)sizeof(T));
-    hipLaunchKernelGGL(k_body<T>, dim3(p.nbody_total), dim3(256), kBodyCacheBytes, s, p, cache_nodes);
-  }
+  const int cache_nodes = kBodyCacheBytes / (3 * (int)sizeof(T));
+  hipLaunchKernelGGL(k_body<T>, dim3(p.ninst + p.nbody_total), dim3(kBodyThreads), kBodyCacheBytes, s,
+                     p, cache_nodes);
 }
 
 template <typename T>

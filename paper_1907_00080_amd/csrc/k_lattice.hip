@@ -71,8 +71,9 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
   // Contributions F_k w_a w_b are accumulated in LDS as 64-bit fixed-point
   // integers: integer addition is associative, so the sum at every node is
   // the same whatever order the lanes add in (deterministic, no global
-  // atomics).  The scale 2^S is chosen per tile from the largest force so the
-  // accumulator cannot overflow: |sum| <= M * max|F| < 2^61.
+  // atomics).  The scale 2^S is chosen per tile from the largest force of the
+  // instance and the bin size so the accumulator cannot overflow:
+  // |sum| <= M * max|F| < 2^61.
   const int Mreg = p.cnt_cur[tile];
   const bool full = Mreg > p.bin_cap;          // registrations were dropped
   const int M = full ? p.bin_cap : Mreg;
@@ -80,29 +81,13 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
   T Fx = T(L.gx), Fy = T(L.gy);
   if (M > 0) {
     __shared__ unsigned long long s_ax[kCap], s_ay[kCap];
-    __shared__ double s_red[kCap / 64];
-    double fm = 0.0;
-    bool bad = false;
-    for (int j = lane; j < M; j += kCap) {
-      const int m = bin[j];
-      const double fx = p.fx[m], fy = p.fy[m];
-      bad |= !isfinite(fx) || !isfinite(fy);
-      fm = fmax(fm, fmax(fabs(fx), fabs(fy)));
-    }
-    for (int o = 32; o > 0; o >>= 1) fm = fmax(fm, __shfl_xor(fm, o));
-    const bool wbad = __any(bad);
-    if ((lane & 63) == 0) s_red[lane >> 6] = wbad ? -1.0 : fm;
+    // largest |F| any body of this instance handed to the fluid this step
+    // (recorded by the body kernel); non-finite means a broken force
+    const double fmax_t = __longlong_as_double((long long)p.fmax_bits[inst]);
     s_ax[lane] = 0ull;
     s_ay[lane] = 0ull;
     __syncthreads();
-    double fmax_t = 0.0;
-    bool tbad = full;
-#pragma unroll
-    for (int w = 0; w < kCap / 64; ++w) {
-      tbad |= s_red[w] < 0.0;
-      fmax_t = fmax(fmax_t, s_red[w]);
-    }
-    if (tbad) {
+    if (full || !isfinite(fmax_t)) {
       Fx = Fy = T(NAN);
     } else if (fmax_t > 0.0) {
       int e;

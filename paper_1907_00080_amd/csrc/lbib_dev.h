@@ -89,6 +89,9 @@ struct Ptrs {
   int *bin_cur, *bin_next;   // [tile * bin_cap + k] = marker id
   int* touched;              // per tile: IB force applied in the last step
   int* overflow;             // registrations dropped because a bin was full
+  unsigned long long* fmax_bits;  // per instance: bit pattern of max |F| this step
+  int* bond_flag;            // per instance: bond update of this step done
+  int* spin_timeouts;        // waits for a bond flag that hit their bound
   int bin_cap;
   int* tile_inst;
   int *lig_body, *lig_elem, *l2r, *r2l, *lig_flag;

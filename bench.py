@@ -1,6 +1,6 @@
 """Benchmark of the fused LB-IB time step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg1]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload capillary-2000x200|capillary-6667x667|channel-256x64]
 
 Workload (default): the 10 um x 100 um capillary at dx = 50 nm, 2000 x 200
 nodes, float32, 18 red cells (352 markers each), 12 adhesive 1 um particles
@@ -9,9 +9,11 @@ whole time step (binning + bonds, membrane and particle forces, fused
 collide-stream-spread, interpolation + marker advance) runs each step.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second of the
-whole step), the roofline of the dominant kernel (the fused lattice kernel,
-timed live with HIP events on its stream) and the FP64 oracle timed on a
-bounded sample on the host CPU.
+whole step, graph-captured chunks of steps), the roofline of the dominant
+kernel (the fused lattice kernel, timed in-step with HIP events on its
+stream over plain-launched steps of the same run), the same figures for the
+HBM-bound 6667 x 667 capillary, and the FP64 oracle timed on a bounded
+sample on the host CPU.
 """
 from __future__ import annotations
 
@@ -30,18 +32,22 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "lb_fused_traffic.json")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the fused kernel's device code (the lattice source up to its
+    host launchers), which the stored counter figures are tied to."""
     with open(os.path.join(ROOT, "paper_1907_00080_amd", "csrc", "k_lattice.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        text = f.read()
+    cut = text.find(b"// ------------------------------------------------------------------ launchers")
+    return hashlib.sha256(text if cut < 0 else text[:cut]).hexdigest()[:16]
 
 
 def make_workload(name: str):
     from workloads import configs
-    if name == "cfg2":
-        return configs.cfg2_capillary_fp32()
-    if name == "cfg3":
-        return configs.cfg3_fine_fp32()
-    if name == "cfg1":
-        w = configs.cfg1_plain_fp64()
+    if name == "capillary-2000x200":
+        return configs.capillary_2000x200()
+    if name == "capillary-6667x667":
+        return configs.capillary_6667x667()
+    if name == "channel-256x64":
+        w = configs.channel_256x64()
         w.dtype = "f32"
         return w
     raise SystemExit(f"unknown workload {name}")
@@ -71,8 +77,9 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
                       f"step), float64 NumPy, one thread, {dt:.1f} s"}
 
 
-def traffic_from_profile(bytes_alg: float):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+def traffic_from_profile(workload_name: str):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), if
     it was taken with the current kernel source; else None."""
     try:
         with open(PROFILE_TRAFFIC) as f:
@@ -81,7 +88,7 @@ def traffic_from_profile(bytes_alg: float):
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", {}).get(workload_name)
 
 
 def main():
@@ -89,10 +96,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="capillary-2000x200")
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--tile", default="64x4")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 6667 x 667 capillary")
+    ap.add_argument("--kernel-steps", type=int, default=200,
+                    help="plain-launched steps over which the fused kernel is timed")
+    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 320 MiB x 10 (for counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -101,50 +114,32 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        # reference for the HBM byte counters: each copy reads and writes 320 MiB
+        a = torch.ones(80 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4,
+                          "copies": 10}), flush=True)
+        return
     import paper_1907_00080_amd as pkg
 
     tile = tuple(int(v) for v in args.tile.split("x"))
     wl = make_workload(args.workload)
-    print(f"bench: workload {wl.name} nodes={wl.nodes} markers={wl.n_markers} "
-          f"bodies={len(wl.bodies)}", file=sys.stderr, flush=True)
-    sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=args.graph_steps)
-    stream = sim.stream
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record(stream)
-    sim.step(args.steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end)
-    ms_step = ms / args.steps
-    mlups = wl.nodes * args.steps / (ms / 1e3) / 1e6
-    d = sim.diagnostics()
-    print(f"bench: {args.steps} steps in {ms:.1f} ms (wall {wall:.2f} s), {ms_step * 1e3:.2f} us/step, "
-          f"{mlups:.0f} MLUPS, nonfinite={d['nonfinite']}", file=sys.stderr, flush=True)
-    if d["nonfinite"]:
-        raise SystemExit("non-finite state after the benchmark")
-
-    # dominant kernel: fused collide-stream-spread, timed alone on its stream
-    k_ms = sim.time_lattice_kernel(50)
-    bytes_alg = 72.0 * wl.nodes           # 9 loads + 9 stores of 4 B per node
-    achieved = bytes_alg / (k_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(bytes_alg),
-            "kernel": "k_lb_fused", "kernel_us": round(k_ms * 1e3, 3),
-            "bytes_per_launch": bytes_alg}
+    res = run_workload(pkg, torch, wl, tile, args.steps, args.warmup, args.graph_steps,
+                       args.kernel_steps)
+    roof = roofline(res, wl)
 
     out = {
         "metric": "MLUPS of fused LB-IB step",
-        "value": round(mlups, 1),
+        "value": round(res["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": round(res["ms_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -156,10 +151,67 @@ def main():
                    "markers": wl.n_markers, "tile": args.tile, "graph_steps": args.graph_steps},
         "roofline": roof,
     }
+    if not args.no_large and args.workload != "capillary-6667x667":
+        # the HBM-bound case: 10 um x 100 um capillary at dx = 15 nm
+        lw = make_workload("capillary-6667x667")
+        lres = run_workload(pkg, torch, lw, tile, args.large_steps, 20, args.graph_steps,
+                            args.large_steps)
+        out["large_lattice"] = {"workload": lw.name, "nodes": lw.nodes, "markers": lw.n_markers,
+                                "mlups": round(lres["mlups"], 1),
+                                "ms_per_step": round(lres["ms_step"], 5),
+                                "roofline": roofline(lres, lw)}
     if not args.no_cpu:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
+
+
+def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps):
+    """Time `steps` whole steps (graph-captured chunks), then measure the fused
+    lattice kernel in-step over `kernel_steps` plain-launched steps."""
+    print(f"bench: workload {wl.name} nodes={wl.nodes} markers={wl.n_markers} "
+          f"bodies={len(wl.bodies)}", file=sys.stderr, flush=True)
+    sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=graph_steps)
+    stream = sim.stream
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end)
+    ms_step = ms / steps
+    mlups = wl.nodes * steps / (ms / 1e3) / 1e6
+    d = sim.diagnostics()
+    print(f"bench: {steps} steps in {ms:.1f} ms (wall {wall:.2f} s), {ms_step * 1e3:.2f} us/step, "
+          f"{mlups:.0f} MLUPS, nonfinite={d['nonfinite']} bin_overflow={d['bin_overflow']}",
+          file=sys.stderr, flush=True)
+    if d["nonfinite"] or d["bin_overflow"] or d["sync_timeouts"]:
+        raise SystemExit("invalid state after the benchmark")
+    # dominant kernel: fused collide-stream-spread, bracketed by HIP events on
+    # its own stream during plain-launched steps of the same run
+    sim.set_kernel_timing(True)
+    sim.step(kernel_steps)
+    k_ms, k_n = sim.kernel_timing()
+    sim.set_kernel_timing(False)
+    print(f"bench: fused lattice kernel {k_ms * 1e3:.2f} us over {k_n} in-step launches",
+          file=sys.stderr, flush=True)
+    sim.close()
+    return {"mlups": mlups, "ms_step": ms_step, "kernel_ms": k_ms, "kernel_launches": k_n}
+
+
+def roofline(res, wl):
+    bytes_alg = 72.0 * wl.nodes           # 9 loads + 9 stores of 4 B per node
+    achieved = bytes_alg / (res["kernel_ms"] / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profile(wl.name),
+            "kernel": "k_lb_fused", "kernel_us": round(res["kernel_ms"] * 1e3, 3),
+            "launches": res["kernel_launches"], "bytes_per_launch": bytes_alg}
 
 
 if __name__ == "__main__":

@@ -241,6 +241,15 @@ lbib_status lbib_diagnostics(lbib_ctx* ctx, lbib_diag* out);
  * Requires at least one completed step (the marker bins of that step). */
 lbib_status lbib_time_lattice_kernel(lbib_ctx* ctx, int32_t reps, double* avg_ms);
 
+/* Measurement: while on != 0, lbib_step launches kernels one by one (no
+ * graphs) and binds a pair of HIP events to every fused lattice-kernel
+ * dispatch on the bound stream (start and end of that dispatch, not separate
+ * markers).  lbib_get_kernel_timing returns the mean duration (ms) of those
+ * launches since timing was switched on, and their number (synchronises).
+ * Switching on or off discards the collected events. */
+lbib_status lbib_set_kernel_timing(lbib_ctx* ctx, int32_t on);
+lbib_status lbib_get_kernel_timing(lbib_ctx* ctx, double* lattice_ms_avg, int64_t* launches);
+
 /* Completed step count. */
 lbib_status lbib_get_step(const lbib_ctx* ctx, int64_t* step);
 

@@ -34,7 +34,8 @@ EXPORTS = [
     "lbib_set_watchdog", "lbib_set_graph_steps", "lbib_get_fields", "lbib_get_markers",
     "lbib_set_markers", "lbib_get_marker_forces", "lbib_num_ligands", "lbib_get_bonds",
     "lbib_set_bonds", "lbib_get_state", "lbib_set_state", "lbib_diagnostics",
-    "lbib_get_step", "lbib_time_lattice_kernel", "lbib_destroy", "lbib_batch_create", "lbib_batch_size",
+    "lbib_get_step", "lbib_time_lattice_kernel", "lbib_set_kernel_timing",
+    "lbib_get_kernel_timing", "lbib_destroy", "lbib_batch_create", "lbib_batch_size",
     "lbib_batch_get_fields", "lbib_batch_get_markers", "lbib_batch_get_bonds",
 ]
 
@@ -114,6 +115,9 @@ def library() -> ctypes.CDLL:
         "lbib_diagnostics": (I32, [P, ctypes.POINTER(Diag)]),
         "lbib_get_step": (I32, [P, ctypes.POINTER(ctypes.c_int64)]),
         "lbib_time_lattice_kernel": (I32, [P, I32, ctypes.POINTER(ctypes.c_double)]),
+        "lbib_set_kernel_timing": (I32, [P, I32]),
+        "lbib_get_kernel_timing": (I32, [P, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]),
         "lbib_destroy": (I32, [P]),
         "lbib_batch_create": (I32, [ctypes.POINTER(P), I32, I32, I32, ctypes.POINTER(P)]),
         "lbib_batch_size": (I32, [P, ip]),
@@ -174,6 +178,40 @@ class _Ctx:
                                       ctypes.c_void_p(stream.cuda_stream)))
         self.check(self.lib.lbib_finalize_setup(self.h))
         self.workspace_bytes = nb.value
+
+    # ----------------------------------------------------------- stepping (plain and batch)
+    def step(self, n: int = 1):
+        self.check(self.lib.lbib_step(self.h, int(n)))
+
+    def set_graph_steps(self, n: int):
+        self.check(self.lib.lbib_set_graph_steps(self.h, int(n)))
+
+    def time_lattice_kernel(self, reps: int = 20) -> float:
+        """Mean duration (ms) of one fused lattice-kernel launch, HIP events."""
+        ms = ctypes.c_double()
+        self.check(self.lib.lbib_time_lattice_kernel(self.h, int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def set_kernel_timing(self, on: bool):
+        self.check(self.lib.lbib_set_kernel_timing(self.h, int(bool(on))))
+
+    def kernel_timing(self):
+        """(mean ms of the in-step fused lattice kernel, launches) since timing was switched on."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self.check(self.lib.lbib_get_kernel_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    @property
+    def step_count(self) -> int:
+        s = ctypes.c_int64()
+        self.check(self.lib.lbib_get_step(self.h, ctypes.byref(s)))
+        return s.value
+
+    def diagnostics(self) -> dict:
+        d = Diag()
+        self.check(self.lib.lbib_diagnostics(self.h, ctypes.byref(d)))
+        return {k: getattr(d, k) for k, _ in Diag._fields_}
 
     def close(self):
         if self.h:
@@ -254,25 +292,6 @@ class Sim(_Ctx):
         self.check(self.lib.lbib_num_ligands(self.h, ctypes.byref(n)))
         self.n_ligands = n.value
 
-    # ----------------------------------------------------------- stepping
-    def step(self, n: int = 1):
-        self.check(self.lib.lbib_step(self.h, int(n)))
-
-    def set_graph_steps(self, n: int):
-        self.check(self.lib.lbib_set_graph_steps(self.h, int(n)))
-
-    def time_lattice_kernel(self, reps: int = 20) -> float:
-        """Mean duration (ms) of one fused lattice-kernel launch, HIP events."""
-        ms = ctypes.c_double()
-        self.check(self.lib.lbib_time_lattice_kernel(self.h, int(reps), ctypes.byref(ms)))
-        return ms.value
-
-    @property
-    def step_count(self) -> int:
-        s = ctypes.c_int64()
-        self.check(self.lib.lbib_get_step(self.h, ctypes.byref(s)))
-        return s.value
-
     # ----------------------------------------------------------- readback
     def fields(self):
         N = self.nx * self.ny
@@ -311,10 +330,6 @@ class Sim(_Ctx):
         a = np.ascontiguousarray(l2r, dtype=np.int32)
         self.check(self.lib.lbib_set_bonds(self.h, _iptr(a)))
 
-    def diagnostics(self) -> dict:
-        d = Diag()
-        self.check(self.lib.lbib_diagnostics(self.h, ctypes.byref(d)))
-        return {k: getattr(d, k) for k, _ in Diag._fields_}
 
     def get_state(self) -> bytes:
         n = ctypes.c_size_t()
@@ -362,12 +377,6 @@ class Batch(_Ctx):
     def nodes(self) -> int:
         return sum(nx * ny for nx, ny in self.shapes)
 
-    def step(self, n: int = 1):
-        self.check(self.lib.lbib_step(self.h, int(n)))
-
-    def set_graph_steps(self, n: int):
-        self.check(self.lib.lbib_set_graph_steps(self.h, int(n)))
-
     def fields(self, inst: int):
         nx, ny = self.shapes[inst]
         N = nx * ny
@@ -387,7 +396,3 @@ class Batch(_Ctx):
         self.check(self.lib.lbib_batch_get_bonds(self.h, int(inst), _iptr(out), ctypes.byref(nb)))
         return out[:n].copy()
 
-    def diagnostics(self) -> dict:
-        d = Diag()
-        self.check(self.lib.lbib_diagnostics(self.h, ctypes.byref(d)))
-        return {k: getattr(d, k) for k, _ in Diag._fields_}

@@ -82,6 +82,8 @@ struct lbib_ctx {
   std::string err;
   bool is_batch = false;
   bool stencil_dirty = true;  // marker stencils/bins must be rebuilt from positions
+  bool ktiming = false;       // bracket fused-kernel launches with events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> kevents;
   int bin_cap = 1024;         // marker registrations per tile and bin set
 };
 
@@ -438,10 +440,24 @@ void enqueue_steps(lbib_ctx* c, long long n) {
   for (long long k = 0; k < n; ++k) {
     Ptrs<T> p = make_ptrs<T>(c);
     launch_lagrangian<T>(p, a, c->stream);
-    launch_lb_fused<T>(p, a, c->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->ktiming && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+      launch_lb_fused<T>(p, a, c->stream, 1, e0, e1);
+      c->kevents.emplace_back(e0, e1);
+    } else {
+      launch_lb_fused<T>(p, a, c->stream);
+    }
     launch_advance<T>(p, a, c->stream);
     c->parity ^= 1;
   }
+}
+
+void drop_kevents(lbib_ctx* c) {
+  for (auto& e : c->kevents) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  c->kevents.clear();
 }
 
 void drop_graphs(lbib_ctx* c) {
@@ -454,6 +470,18 @@ void drop_graphs(lbib_ctx* c) {
 
 template <typename T>
 lbib_status run_steps(lbib_ctx* c, long long n) {
+  if (c->ktiming) {
+    // measurement mode: plain launches with event pairs around the fused kernel
+    if (c->stencil_dirty && n > 0) {
+      HIPCHK(c, hipMemsetAsync(c->ws + c->L.cnt[c->parity], 0, 4 * (size_t)c->ntiles, c->stream));
+      launch_stencil<T>(make_ptrs<T>(c), step_args(c), c->stream);
+      c->stencil_dirty = false;
+    }
+    enqueue_steps<T>(c, n);
+    c->step += n;
+    HIPCHK(c, hipGetLastError());
+    return LBIB_OK;
+  }
   if (c->stencil_dirty && n > 0) {
     // rebuild the current bin set from the marker positions (eager, never
     // part of a captured graph)
@@ -950,6 +978,27 @@ lbib_status lbib_time_lattice_kernel(lbib_ctx* c, int32_t reps, double* avg_ms) 
   return LBIB_OK;
 }
 
+lbib_status lbib_set_kernel_timing(lbib_ctx* c, int32_t on) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  c->ktiming = on != 0;
+  drop_kevents(c);
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_kernel_timing(lbib_ctx* c, double* avg_ms, int64_t* launches) {
+  if (!c || !avg_ms) return fail(c, LBIB_EINVAL, "NULL argument");
+  double sum = 0.0;
+  for (auto& e : c->kevents) {
+    HIPCHK(c, hipEventSynchronize(e.second));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e.first, e.second));
+    sum += ms;
+  }
+  *avg_ms = c->kevents.empty() ? 0.0 : sum / (double)c->kevents.size();
+  if (launches) *launches = (int64_t)c->kevents.size();
+  return LBIB_OK;
+}
+
 lbib_status lbib_get_step(const lbib_ctx* cc, int64_t* step) {
   lbib_ctx* c = const_cast<lbib_ctx*>(cc);
   if (!c || !step) return fail(c, LBIB_EINVAL, "NULL argument");
@@ -960,6 +1009,7 @@ lbib_status lbib_get_step(const lbib_ctx* cc, int64_t* step) {
 lbib_status lbib_destroy(lbib_ctx* c) {
   if (!c) return LBIB_OK;
   drop_graphs(c);
+  drop_kevents(c);
   delete c;
   return LBIB_OK;
 }

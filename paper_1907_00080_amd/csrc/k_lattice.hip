@@ -258,17 +258,24 @@ __global__ void k_diag2(const double* part, int nblk, double* out) {
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int consume) {
+void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int consume,
+                     hipEvent_t ev0, hipEvent_t ev1) {
   const int per = (a.ntiles_total + 7) / 8;
   dim3 grid(8 * per), block(kCap);
+  // the optional events are bound to the dispatch itself, so their elapsed
+  // time is the kernel's execution time and not that of separate markers
   if (a.tile_x == 64 && a.tile_y == 4)
-    hipLaunchKernelGGL((k_lb_fused<T, 64, 4>), grid, block, 0, s, p, a.ntiles_total, consume);
+    hipExtLaunchKernelGGL((k_lb_fused<T, 64, 4>), grid, block, 0, s, ev0, ev1, 0, p,
+                          a.ntiles_total, consume);
   else if (a.tile_x == 128 && a.tile_y == 2)
-    hipLaunchKernelGGL((k_lb_fused<T, 128, 2>), grid, block, 0, s, p, a.ntiles_total, consume);
+    hipExtLaunchKernelGGL((k_lb_fused<T, 128, 2>), grid, block, 0, s, ev0, ev1, 0, p,
+                          a.ntiles_total, consume);
   else if (a.tile_x == 32 && a.tile_y == 8)
-    hipLaunchKernelGGL((k_lb_fused<T, 32, 8>), grid, block, 0, s, p, a.ntiles_total, consume);
+    hipExtLaunchKernelGGL((k_lb_fused<T, 32, 8>), grid, block, 0, s, ev0, ev1, 0, p,
+                          a.ntiles_total, consume);
   else
-    hipLaunchKernelGGL((k_lb_fused<T, 256, 1>), grid, block, 0, s, p, a.ntiles_total, consume);
+    hipExtLaunchKernelGGL((k_lb_fused<T, 256, 1>), grid, block, 0, s, ev0, ev1, 0, p,
+                          a.ntiles_total, consume);
 }
 
 template <typename T>
@@ -287,8 +294,10 @@ void launch_diag(const Ptrs<T>& p, const StepArgs&, long long nodes_total, doubl
   hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, p.red, nblk, out);
 }
 
-template void launch_lb_fused<float>(const Ptrs<float>&, const StepArgs&, hipStream_t, int);
-template void launch_lb_fused<double>(const Ptrs<double>&, const StepArgs&, hipStream_t, int);
+template void launch_lb_fused<float>(const Ptrs<float>&, const StepArgs&, hipStream_t, int,
+                                     hipEvent_t, hipEvent_t);
+template void launch_lb_fused<double>(const Ptrs<double>&, const StepArgs&, hipStream_t, int,
+                                      hipEvent_t, hipEvent_t);
 template void launch_fields<float>(const Ptrs<float>&, const StepArgs&, int, double*, double*,
                                    double*, int, int, long long, hipStream_t);
 template void launch_fields<double>(const Ptrs<double>&, const StepArgs&, int, double*, double*,

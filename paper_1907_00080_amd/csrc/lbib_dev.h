@@ -12,6 +12,7 @@
 //   ligands           : l2r[NL] (-1 free), receptors rec_x[NR], r2l[NR]
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace lbib {
@@ -166,7 +167,8 @@ struct StepArgs {
 };
 
 template <typename T>
-void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int consume = 1);
+void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int consume = 1,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_fields(const Ptrs<T>& p, const StepArgs& a, int inst, double* rho, double* ux,
                    double* uy, int nx, int ny, long long node_base, hipStream_t s);

@@ -166,32 +166,32 @@ def test_large_bodies_and_seam_fp64(name, wl, tile):
         assert dx < 1e-9, (n, dx)
 
 
-def test_cfg1_fp32_1000_steps_meets_tolerance():
+def test_channel_fp32_1000_steps_meets_tolerance():
     """256x64 channel, one RBC and one rigid 1 um particle, 1000 steps:
     velocity rel-L2 <= 1e-5 and markers <= 1e-4 dx against the FP64 oracle."""
-    announce("cfg1 fp32 1000 steps")
-    wl = configs.cfg1_plain_fp64()
+    announce("channel 256x64 fp32 1000 steps")
+    wl = configs.channel_256x64()
     sim = pkg.Sim(wl, dtype="f32")
     ref = oracle.Sim(wl)
     sim.step(1000)
     ref.step(1000)
     e, _ = vel_err(sim, ref)
     dx = marker_err(sim, ref)
-    announce(f"cfg1 fp32: rel-L2 {e:.3e} markers {dx:.3e}")
+    announce(f"channel 256x64 fp32: rel-L2 {e:.3e} markers {dx:.3e}")
     assert e <= 1e-5
     assert dx <= 1e-4
 
 
-def test_cfg1_fp64_1000_steps_roundoff():
-    announce("cfg1 fp64 1000 steps")
-    wl = configs.cfg1_plain_fp64()
+def test_channel_fp64_1000_steps_roundoff():
+    announce("channel 256x64 fp64 1000 steps")
+    wl = configs.channel_256x64()
     sim = pkg.Sim(wl, dtype="f64", graph_steps=100)
     ref = oracle.Sim(wl)
     sim.step(1000)
     ref.step(1000)
     e, _ = vel_err(sim, ref)
     dx = marker_err(sim, ref)
-    announce(f"cfg1 fp64: rel-L2 {e:.3e} markers {dx:.3e}")
+    announce(f"channel 256x64 fp64: rel-L2 {e:.3e} markers {dx:.3e}")
     assert e < 1e-10 and dx < 1e-9
 
 
@@ -257,11 +257,11 @@ def test_adhesive_trajectory_fp64_matches_oracle():
 
 
 # ------------------------------------------------------------- full size
-def test_cfg2_full_size_steps_match_oracle():
+def test_capillary_2000x200_full_size_steps_match_oracle():
     """200 x 2000 capillary with 18 RBCs and 12 adhesive particles, float32,
     in the benchmark's launch configuration: a few steps against the oracle."""
-    announce("cfg2 full size")
-    wl = configs.cfg2_capillary_fp32()
+    announce("capillary 2000x200 full size")
+    wl = configs.capillary_2000x200()
     sim = pkg.Sim(wl, dtype="f32", graph_steps=2)
     ref = oracle.Sim(wl)
     steps = 4
@@ -269,7 +269,7 @@ def test_cfg2_full_size_steps_match_oracle():
     ref.step(steps)
     e, erho = vel_err(sim, ref)
     dx = marker_err(sim, ref)
-    announce(f"cfg2: rel-L2 {e:.3e} markers {dx:.3e}")
+    announce(f"capillary 2000x200: rel-L2 {e:.3e} markers {dx:.3e}")
     # velocities are ~1e-5 here: float32 resolves them to ~1e-6 relative
     assert e < 1e-5
     assert dx < 1e-6

@@ -133,7 +133,7 @@ def uniform_receptors(nx: int) -> List[np.ndarray]:
 
 # ---------------------------------------------------------------- configs
 
-def cfg1_plain_fp64(seed_offset: int = 1, with_particle: bool = True) -> Workload:
+def channel_256x64(seed_offset: int = 1, with_particle: bool = True) -> Workload:
     """256x64 channel, tau = 1, Poiseuille at Mach 0.05; one RBC (120 markers)
     and one rigid 1 um particle (40 markers); constants from a seed."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + seed_offset))
@@ -163,7 +163,7 @@ def cfg1_plain_fp64(seed_offset: int = 1, with_particle: bool = True) -> Workloa
             raise RuntimeError("particle placement failed")
         bodies.append(Body(PARTICLE_RIGID, part, ks=0.0, kb=0.0))
     rho0, u0 = poiseuille_init(nx, ny, g, tau)
-    return Workload("cfg1-256x64", nx, ny, tau, gx=g, seed=SEED_BASE + seed_offset,
+    return Workload("channel-256x64", nx, ny, tau, gx=g, seed=SEED_BASE + seed_offset,
                     bodies=bodies, rho0=rho0, u0=u0, steps=1000, dtype="f64")
 
 
@@ -223,25 +223,25 @@ def _capillary(name: str, nx: int, ny: int, dx_um: float, n_rbc: int, rbc_marker
                     steps=steps, dtype="f32")
 
 
-def cfg2_capillary_fp32() -> Workload:
+def capillary_2000x200() -> Workload:
     """10 um x 100 um capillary at dx = 50 nm (200 x 2000), 20 % hematocrit as
     18 RBCs (352 markers), 12 adhesive 1 um particles (6 rigid, 6 Ca = 1e-2),
     receptors on every wall node, sigma = 1."""
     parts = [(PARTICLE_RIGID, 1.0)] * 6 + [(PARTICLE_SOFT, 1.0)] * 6
-    return _capillary("cfg2-2000x200", 2000, 200, 0.05, 18, 352, parts,
+    return _capillary("capillary-2000x200", 2000, 200, 0.05, 18, 352, parts,
                       SEED_BASE + 2, 100000)
 
 
-def cfg3_fine_fp32(soft: bool = False) -> Workload:
+def capillary_6667x667(soft: bool = False) -> Workload:
     """10 um x 100 um capillary at dx = 15 nm (6667 x 667), 18 RBCs (1152 markers),
     three 1 um particles with sigma = 0.5, 1, 2."""
     kind = PARTICLE_SOFT if soft else PARTICLE_RIGID
     parts = [(kind, 0.5), (kind, 1.0), (kind, 2.0)]
-    return _capillary("cfg3-6667x667", 6667, 667, 0.015, 18, 1152, parts,
+    return _capillary("capillary-6667x667", 6667, 667, 0.015, 18, 1152, parts,
                       SEED_BASE + 3, 50000, place_res=4.0)
 
 
-def cfg4_instances(n_inst: int = 64, seed_offset: int = 4) -> List[Workload]:
+def sweep_instances(n_inst: int = 64, seed_offset: int = 4) -> List[Workload]:
     """Uneven capillary instances (20-100 um long, dx = 50 nm, 200 rows),
     20 % hematocrit, four particles each; (Ca, sigma) cycle over
     {0, 1e-2} x {0.5, 1, 2}."""
@@ -254,7 +254,7 @@ def cfg4_instances(n_inst: int = 64, seed_offset: int = 4) -> List[Workload]:
         nx = int(round(L / 0.05))
         n_rbc = int(round(0.2 * 10.0 * L / 10.92))
         kind, sig = combos[i % len(combos)]
-        w = _capillary(f"cfg4-inst{i}", nx, 200, 0.05, n_rbc, 352, [(kind, sig)] * 4,
+        w = _capillary(f"sweep-inst{i}", nx, 200, 0.05, n_rbc, 352, [(kind, sig)] * 4,
                        SEED_BASE + seed_offset + i, 20000)
         w.instance = i
         w.seed = SEED_BASE + seed_offset

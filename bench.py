@@ -10,10 +10,11 @@ collide-stream-spread, interpolation + marker advance) runs each step.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second of the
 whole step, graph-captured chunks of steps), the roofline of the dominant
-kernel (the fused lattice kernel, timed in-step with HIP events on its
-stream over plain-launched steps of the same run), the same figures for the
-HBM-bound 6667 x 667 capillary, and the FP64 oracle timed on a bounded
-sample on the host CPU.
+kernel (the fused lattice kernel, timed in-step with HIP events bound to its
+dispatches over plain-launched steps of the same run), the same figures for
+the HBM-bound 6667 x 667 capillary, a sweep of 64 uneven instances run as one
+autotuned batch against the same instances run one by one, and the FP64
+oracle timed on a bounded sample on the host CPU.
 """
 from __future__ import annotations
 
@@ -104,6 +105,9 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=200,
                     help="plain-launched steps over which the fused kernel is timed")
     ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain sweep")
+    ap.add_argument("--batch-instances", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 320 MiB x 10 (for counter calibration)")
     args = ap.parse_args()
@@ -133,7 +137,7 @@ def main():
     roof = roofline(res, wl)
 
     out = {
-        "metric": "MLUPS of fused LB-IB step",
+        "metric": "MLUPS of fused LB-IB step; batched vs plain MLUPS; adjoint/forward time",
         "value": round(res["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -160,6 +164,8 @@ def main():
                                 "mlups": round(lres["mlups"], 1),
                                 "ms_per_step": round(lres["ms_step"], 5),
                                 "roofline": roofline(lres, lw)}
+    if not args.no_batch:
+        out["batched"] = batched_vs_plain(pkg, torch, args.batch_instances, args.batch_steps)
     if not args.no_cpu:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
@@ -202,6 +208,53 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps)
           file=sys.stderr, flush=True)
     sim.close()
     return {"mlups": mlups, "ms_step": ms_step, "kernel_ms": k_ms, "kernel_launches": k_n}
+
+
+def _timed(torch, ctx, steps):
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(ctx.stream)
+    ctx.step(steps)
+    end.record(ctx.stream)
+    end.synchronize()
+    return start.elapsed_time(end)
+
+
+def batched_vs_plain(pkg, torch, n_inst, steps):
+    """Sweep of uneven capillary instances (20-100 um long, 200 rows): one
+    batch with autotuned tiles and graph chunks, against the same instances
+    run one after another through plain launches (no graphs, default tile)."""
+    from workloads import configs
+    from paper_1907_00080_amd.tune import autotune
+    ws = configs.sweep_instances(n_inst)
+    nodes = sum(w.nodes for w in ws)
+    print(f"bench: sweep of {len(ws)} instances, {nodes} nodes, "
+          f"{sum(w.n_markers for w in ws)} markers; autotuning", file=sys.stderr, flush=True)
+    tuned = autotune(ws, "f32", device="cuda:0", steps=100, warmup=20)
+    tile = tuple(tuned["tile"])
+    b = pkg.Batch(ws, dtype="f32", tile=tile, device="cuda:0", graph_steps=tuned["graph_steps"])
+    b.step(max(20, tuned["graph_steps"]))
+    ms_b = _timed(torch, b, steps)
+    d = b.diagnostics()
+    b.close()
+    if d["nonfinite"] or d["bin_overflow"] or d["sync_timeouts"]:
+        raise SystemExit("invalid batch state after the benchmark")
+    ms_p = 0.0
+    for w in ws:
+        s = pkg.Sim(w, dtype="f32", tile=(64, 4), device="cuda:0", graph_steps=0)
+        s.step(5)
+        ms_p += _timed(torch, s, steps)
+        s.close()
+    mb = nodes * steps / (ms_b * 1e-3) / 1e6
+    mp = nodes * steps / (ms_p * 1e-3) / 1e6
+    print(f"bench: batched {mb:.0f} MLUPS (tile {tile[0]}x{tile[1]}, graphs of "
+          f"{tuned['graph_steps']}), plain sequential {mp:.0f} MLUPS", file=sys.stderr, flush=True)
+    return {"workload": f"sweep-{len(ws)}-instances", "instances": len(ws), "nodes": nodes,
+            "steps": steps, "batched_mlups": round(mb, 1), "plain_mlups": round(mp, 1),
+            "speedup": round(mb / mp, 3), "tile": f"{tile[0]}x{tile[1]}",
+            "graph_steps": tuned["graph_steps"],
+            "candidates": [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "graph_steps": c["graph_steps"],
+                            "mlups": round(c["mlups"], 1)} for c in tuned["candidates"]]}
 
 
 def roofline(res, wl):

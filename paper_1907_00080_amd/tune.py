@@ -1,0 +1,147 @@
+"""Tile-shape and graph-chunk autotuner for batched sweeps (host logic).
+
+A batch advances many uneven capillary instances together (one launch per
+kernel per step for all of them).  Which tile shape of the fused lattice
+kernel and which number of steps per captured HIP graph run fastest depends
+on the instance mix and the device, so `autotune` times whole steps of the
+actual batch for every candidate and keeps the fastest.  Results are cached
+in a JSON file keyed by the batch signature (lattice shapes, body and marker
+counts, dtype) and the device name, so a sweep pays for tuning once.
+
+Nothing here computes a step of the method; every step runs in the library.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import tempfile
+from typing import Callable, Iterable, Optional, Sequence, Tuple
+
+TILES: Tuple[Tuple[int, int], ...] = ((64, 4), (128, 2), (32, 8), (256, 1))
+GRAPH_STEPS: Tuple[int, ...] = (10, 100)
+
+
+def signature(workloads: Sequence, dtype: str) -> str:
+    """Stable key of a batch: dtype plus, per instance, lattice shape, wall
+    mode, body count and marker count."""
+    h = hashlib.sha256()
+    h.update(str(dtype).encode())
+    for w in workloads:
+        h.update(f"{int(w.nx)}x{int(w.ny)}:{int(w.periodic_y)}:{len(w.bodies)}:"
+                 f"{int(w.n_markers)};".encode())
+    return h.hexdigest()[:24]
+
+
+def load_cache(path: Optional[str]) -> dict:
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        data = json.load(f)
+    return data if isinstance(data, dict) else {}
+
+
+def store_cache(path: str, key: str, record: dict) -> None:
+    """Add one record; the file is replaced atomically."""
+    data = load_cache(path)
+    data[key] = record
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=d, prefix=".tune", suffix=".json")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def choose(results: Iterable[dict]) -> dict:
+    """Fastest candidate; ties go to the earlier one (candidate order)."""
+    best = None
+    for r in results:
+        if best is None or r["ms_per_step"] < best["ms_per_step"]:
+            best = r
+    if best is None:
+        raise ValueError("no tuning results")
+    return best
+
+
+def _time_steps(batch, steps: int) -> float:
+    """Milliseconds for `steps` steps of `batch`, HIP events on its stream."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(batch.stream)
+    batch.step(steps)
+    end.record(batch.stream)
+    end.synchronize()
+    return start.elapsed_time(end)
+
+
+def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = None,
+             device=None, steps: int = 100, warmup: int = 20,
+             tiles: Sequence[Tuple[int, int]] = TILES,
+             graph_steps: Sequence[int] = GRAPH_STEPS,
+             measure: Optional[Callable] = None) -> dict:
+    """Pick the tile shape and graph chunk for a batch of `workloads`.
+
+    Returns {"tile": [tx, ty], "graph_steps": g, "ms_per_step": t, "mlups": m,
+    "candidates": [...], "device": name, "cached": bool}.  `steps` is rounded
+    up to a multiple of every graph chunk.  `measure(tile, g)` replaces the
+    GPU timing (returns ms per step); it exists for tests of the selection
+    and caching logic.
+    """
+    nodes = sum(int(w.nx) * int(w.ny) for w in workloads)
+    dev_name = _device_name(device) if measure is None else "measure-callback"
+    key = f"{signature(workloads, dtype)}@{dev_name}"
+    cached = load_cache(cache).get(key)
+    if cached is not None:
+        out = dict(cached)
+        out["cached"] = True
+        return out
+    lcm = 1
+    for g in graph_steps:
+        lcm = lcm * g // _gcd(lcm, g)
+    steps = max(lcm, ((int(steps) + lcm - 1) // lcm) * lcm)
+    results = []
+    for tile in tiles:
+        if measure is not None:
+            for g in graph_steps:
+                ms = float(measure(tuple(tile), int(g)))
+                results.append(_record(tile, g, ms, nodes))
+            continue
+        from . import Batch
+        b = Batch(workloads, dtype=dtype, tile=tuple(tile), device=device, graph_steps=0)
+        try:
+            for g in graph_steps:
+                b.set_graph_steps(int(g))
+                b.step(max(int(warmup), int(g)))
+                ms = _time_steps(b, steps) / steps
+                results.append(_record(tile, g, ms, nodes))
+        finally:
+            b.close()
+    best = choose(results)
+    rec = {"tile": list(best["tile"]), "graph_steps": best["graph_steps"],
+           "ms_per_step": best["ms_per_step"], "mlups": best["mlups"],
+           "candidates": results, "device": dev_name, "nodes": nodes,
+           "instances": len(workloads), "dtype": str(dtype)}
+    if cache:
+        store_cache(cache, key, rec)
+    rec = dict(rec)
+    rec["cached"] = False
+    return rec
+
+
+def _record(tile, g, ms, nodes) -> dict:
+    return {"tile": [int(tile[0]), int(tile[1])], "graph_steps": int(g), "ms_per_step": ms,
+            "mlups": nodes / (ms * 1e-3) / 1e6 if ms > 0 else float("inf")}
+
+
+def _gcd(a: int, b: int) -> int:
+    while b:
+        a, b = b, a % b
+    return a
+
+
+def _device_name(device) -> str:
+    import torch
+    dev = torch.device(device if device is not None else "cuda")
+    return torch.cuda.get_device_name(dev)

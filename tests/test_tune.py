@@ -1,0 +1,62 @@
+"""Selection and caching logic of the batch autotuner (host only, no GPU)."""
+import json
+
+from paper_1907_00080_amd import tune
+from workloads import configs
+
+
+def _ws():
+    return [configs.small_case(nx=48, ny=24, n_rbc=1, seed_offset=31),
+            configs.small_case(nx=64, ny=20, n_rbc=0, seed_offset=32)]
+
+
+def test_signature_is_stable_and_sensitive():
+    a, b = _ws(), _ws()
+    assert tune.signature(a, "f32") == tune.signature(b, "f32")
+    assert tune.signature(a, "f32") != tune.signature(a, "f64")
+    assert tune.signature(a, "f32") != tune.signature(a[:1], "f32")
+    c = _ws()
+    c[1] = configs.small_case(nx=65, ny=20, n_rbc=0, seed_offset=32)
+    assert tune.signature(a, "f32") != tune.signature(c, "f32")
+
+
+def test_choose_fastest_and_first_on_ties():
+    rs = [{"tile": [64, 4], "graph_steps": 10, "ms_per_step": 2.0},
+          {"tile": [32, 8], "graph_steps": 10, "ms_per_step": 1.0},
+          {"tile": [256, 1], "graph_steps": 100, "ms_per_step": 1.0}]
+    assert tune.choose(rs)["tile"] == [32, 8]
+
+
+def test_autotune_selects_minimum_and_caches(tmp_path):
+    calls = []
+    cost = {((64, 4), 10): 3.0, ((64, 4), 100): 2.5, ((128, 2), 10): 2.9,
+            ((128, 2), 100): 1.5, ((32, 8), 10): 4.0, ((32, 8), 100): 1.7,
+            ((256, 1), 10): 2.2, ((256, 1), 100): 2.0}
+
+    def measure(tile, g):
+        calls.append((tile, g))
+        return cost[(tile, g)]
+
+    path = str(tmp_path / "sub" / "tune.json")
+    ws = _ws()
+    rec = tune.autotune(ws, "f32", cache=path, measure=measure)
+    assert rec["tile"] == [128, 2] and rec["graph_steps"] == 100 and not rec["cached"]
+    assert len(calls) == 8
+    nodes = sum(w.nodes for w in ws)
+    assert abs(rec["mlups"] - nodes / 1.5e-3 / 1e6) < 1e-9
+    with open(path) as f:
+        data = json.load(f)
+    assert len(data) == 1
+    again = tune.autotune(ws, "f32", cache=path, measure=measure)
+    assert again["cached"] and again["tile"] == [128, 2] and len(calls) == 8
+    # another batch adds a second record and keeps the first
+    tune.autotune(ws[:1], "f32", cache=path, measure=measure)
+    with open(path) as f:
+        assert len(json.load(f)) == 2
+
+
+def test_autotune_without_cache_measures_every_time():
+    n = []
+    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g: n.append(1) or 1.0)
+    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g: n.append(1) or 1.0)
+    assert len(n) == 16

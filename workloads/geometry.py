@@ -79,6 +79,24 @@ def _inside(xy: np.ndarray, px: np.ndarray, py: np.ndarray) -> np.ndarray:
     return inside
 
 
+def _inside_rows(xy: np.ndarray, xs: np.ndarray, ys: np.ndarray) -> np.ndarray:
+    """Even-odd test on the raster xs (columns) x ys (rows); the same
+    crossing abscissae and comparisons as `_inside`, organised per row."""
+    x0, y0 = xy[:, 0], xy[:, 1]
+    x1, y1 = np.roll(x0, -1), np.roll(y0, -1)
+    out = np.zeros((ys.size, xs.size), dtype=bool)
+    for r, yv in enumerate(ys):
+        cond = (y0 > yv) != (y1 > yv)
+        if not cond.any():
+            continue
+        a, b, c, d = x0[cond], y0[cond], x1[cond], y1[cond]
+        xi = np.sort(a + (yv - b) * (c - a) / (d - b))
+        # number of crossings with xs < xi
+        n_right = xi.size - np.searchsorted(xi, xs, side="right")
+        out[r] = (n_right & 1).astype(bool)
+    return out
+
+
 class Occupancy:
     """Raster occupancy of a periodic-x channel used for non-overlapping placement.
 
@@ -97,13 +115,24 @@ class Occupancy:
         hi = xy.max(axis=0) + gap
         ix = np.arange(int(np.floor(lo[0] / self.res)), int(np.ceil(hi[0] / self.res)) + 1)
         iy = np.arange(int(np.floor(lo[1] / self.res)), int(np.ceil(hi[1] / self.res)) + 1)
-        PX, PY = np.meshgrid(ix * self.res, iy * self.res)
-        ins = _inside(xy, PX.ravel(), PY.ravel())
-        # dilation: any cell within `gap` of a vertex or inside
-        d2 = np.full(PX.size, np.inf)
-        for v in xy:
-            d2 = np.minimum(d2, (PX.ravel() - v[0]) ** 2 + (PY.ravel() - v[1]) ** 2)
-        sel = ins | (d2 <= gap * gap)
+        xs, ys = ix * self.res, iy * self.res
+        PX, PY = np.meshgrid(xs, ys)
+        ins = _inside_rows(xy, xs, ys)
+        # dilation: any cell within `gap` of a vertex; only the window of
+        # cells around each vertex can qualify
+        near = np.zeros_like(ins)
+        k = int(np.ceil(2.0 * gap / self.res)) + 3
+        bx = np.floor((xy[:, 0] - gap) / self.res).astype(np.int64) - 1 - ix[0]
+        by = np.floor((xy[:, 1] - gap) / self.res).astype(np.int64) - 1 - iy[0]
+        off = np.arange(k)
+        cx = np.clip(bx[:, None] + off[None, :], 0, ix.size - 1)        # (nv, k)
+        cy = np.clip(by[:, None] + off[None, :], 0, iy.size - 1)
+        dx2 = (xs[cx] - xy[:, 0:1]) ** 2                                  # (nv, k)
+        dy2 = (ys[cy] - xy[:, 1:2]) ** 2
+        hit = (dy2[:, :, None] + dx2[:, None, :]) <= gap * gap           # (nv, k, k)
+        v, jy, jx = np.nonzero(hit)
+        near[cy[v, jy], cx[v, jx]] = True
+        sel = (ins | near).ravel()
         return ix, iy, PX.ravel()[sel], PY.ravel()[sel], sel.reshape(PX.shape)
 
     def try_add(self, xy: np.ndarray, gap: float) -> bool:

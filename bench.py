@@ -106,6 +106,8 @@ def main():
                     help="plain-launched steps over which the fused kernel is timed")
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain sweep")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient window")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -166,6 +168,8 @@ def main():
                                 "roofline": roofline(lres, lw)}
     if not args.no_batch:
         out["batched"] = batched_vs_plain(pkg, torch, args.batch_instances, args.batch_steps)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_window(pkg, torch, args.adjoint_steps, 100)
     if not args.no_cpu:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
@@ -255,6 +259,83 @@ def batched_vs_plain(pkg, torch, n_inst, steps):
             "graph_steps": tuned["graph_steps"],
             "candidates": [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "graph_steps": c["graph_steps"],
                             "mlups": round(c["mlups"], 1)} for c in tuned["candidates"]]}
+
+
+def adjoint_window(pkg, torch, steps, ckpt):
+    """Gradient window on the 256 x 64 channel (red cell + soft adhesive
+    particle, bonds frozen after the first step): wall time of the adjoint
+    (forward window with checkpoints + checkpointed reverse sweep) over the
+    wall time of the same steps run forward only; gradient accuracy of the
+    float64 adjoint against float64 central differences (h = 1e-4 relative)
+    of the GPU forward, and the float32-forward gradient against it."""
+    from workloads import configs
+    from paper_1907_00080_amd.adjoint import AdjointWindow
+    wl = configs.adjoint_channel()
+    print(f"bench: gradient window {wl.name}, {steps} steps, checkpoints every {ckpt}",
+          file=sys.stderr, flush=True)
+
+    def params(P, sim):
+        for b in range(P.shape[0]):
+            sim.set_body_params(b, *P[b])
+
+    import numpy as np
+    P0 = np.array([[b.ks, b.kb, b.sigma] for b in wl.bodies])
+    res = {}
+    for dtype in ("f32", "f64"):
+        sim = pkg.Sim(wl, dtype=dtype, device="cuda:0", graph_steps=100)
+        sim.step(1)
+        state = sim.get_state()
+        win = AdjointWindow(sim, steps, ckpt)
+        sim.step(steps)                       # warm-up: graphs of the forward
+        sim.set_state(state)
+        win.forward()
+        win.backward(1.0)                     # warm-up: graphs of the segments
+        sim.set_state(state)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        sim.set_state(state)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, nb = win.forward()
+        g = win.backward(1.0)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        res[dtype] = dict(J=J, g=g, t_fwd=t_fwd, t_adj=t_adj, bonds=nb)
+        if dtype == "f64":
+            errs = {}
+            for (b, q, name) in ((1, 0, "ks_particle"), (1, 2, "sigma_particle"), (0, 0, "ks_rbc")):
+                h = 1e-4 * P0[b, q]
+                Js = []
+                for sgn in (1, -1):
+                    P = P0.copy()
+                    P[b, q] += sgn * h
+                    sim.set_state(state)
+                    params(P, sim)
+                    Js.append(win.forward()[0])
+                fd = (Js[0] - Js[1]) / (2 * h)
+                errs[name] = abs(g[b, q] - fd) / abs(fd)
+            res[dtype]["fd_rel_err"] = errs
+        sim.close()
+    r32, r64 = res["f32"], res["f64"]
+    ratio = r32["t_adj"] / r32["t_fwd"]
+    g32, g64 = r32["g"], r64["g"]
+    sel = [(1, 0), (1, 1), (1, 2), (0, 0)]
+    f32_vs_f64 = max(abs(g32[b, q] - g64[b, q]) / abs(g64[b, q]) for b, q in sel)
+    print(f"bench: adjoint/forward {ratio:.2f} (fp32: forward {1e3 * r32['t_fwd']:.1f} ms, "
+          f"adjoint {1e3 * r32['t_adj']:.1f} ms), fp64 FD rel err {r64['fd_rel_err']}",
+          file=sys.stderr, flush=True)
+    return {"workload": wl.name, "steps": steps, "ckpt_every": ckpt, "dtype": "f32 forward, f64 adjoint",
+            "adjoint_over_forward": round(ratio, 3),
+            "forward_ms": round(1e3 * r32["t_fwd"], 2), "adjoint_ms": round(1e3 * r32["t_adj"], 2),
+            "J": r32["J"], "bonds": r32["bonds"],
+            "grad_fp32": {"ks_particle": g32[1, 0], "kb_particle": g32[1, 1],
+                          "sigma_particle": g32[1, 2], "ks_rbc": g32[0, 0]},
+            "fp64_adjoint_vs_fp64_fd_rel_err": {k: float(f"{v:.3e}") for k, v in r64["fd_rel_err"].items()},
+            "fp32_vs_fp64_gradient_rel_diff": float(f"{f32_vs_f64:.3e}"),
+            "fp64_adjoint_over_forward": round(r64["t_adj"] / r64["t_fwd"], 3)}
 
 
 def roofline(res, wl):

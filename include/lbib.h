@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define LBIB_ABI_VERSION 1u
+#define LBIB_ABI_VERSION 2u
 
 typedef struct lbib_ctx lbib_ctx;
 
@@ -249,6 +249,49 @@ lbib_status lbib_time_lattice_kernel(lbib_ctx* ctx, int32_t reps, double* avg_ms
  * Switching on or off discards the collected events. */
 lbib_status lbib_set_kernel_timing(lbib_ctx* ctx, int32_t on);
 lbib_status lbib_get_kernel_timing(lbib_ctx* ctx, double* lattice_ms_avg, int64_t* launches);
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint of a window of steps (single-lattice contexts with red
+ * cells and soft particles; rigid particles are refused with LBIB_EINVAL).
+ *
+ * The window advances nsteps steps from the current state with the bond
+ * topology frozen (no bond kinetics; bonded springs keep acting, Eq. adhFor),
+ * keeping a device checkpoint of the dynamic state every ckpt_every steps.
+ * The objective is
+ *   J = mean over the vertices of all particles of the distance to the
+ *       nearer wall, min(y + 1/2, ny - 1/2 - y), at the end of the window.
+ * The backward pass recomputes each segment from its checkpoint, then applies
+ * the transposed Jacobian of every step (Sec. 2.1 collision and streaming,
+ * Sec. 2.2 spreading, interpolation, membrane, spring and probe loads,
+ * Sec. 2.3 soft-particle and kinematic marker updates) in reverse order.
+ *
+ * lbib_adjoint_workspace_query / lbib_adjoint_bind: size and bind the
+ *   caller-owned device workspace (256-byte aligned, must outlive the
+ *   context's use of it) for a window of nsteps with a checkpoint every
+ *   ckpt_every steps (both >= 1).  After finalize_setup.
+ * lbib_adjoint_forward: run the window; *J receives the objective, *nbonds
+ *   (may be NULL) the number of bonds held during the window.  Leaves the
+ *   context at the end of the window.
+ * lbib_adjoint_backward: after lbib_adjoint_forward (and no parameter
+ *   change since): grad[3*b + 0..2] = dJ * dJ/dk_s, dJ * dJ/dk_b,
+ *   dJ * dJ/dsigma of body b (all bodies of the context, host array).  The
+ *   context is left at the end of the window.
+ * Errors: LBIB_ESTATE before finalize_setup, without a bound workspace or
+ *   forward window; LBIB_EINVAL for batches, rigid bodies or bad sizes;
+ *   LBIB_ENOSPACE for a workspace that is too small. */
+lbib_status lbib_adjoint_workspace_query(const lbib_ctx* ctx, int64_t nsteps, int32_t ckpt_every,
+                                         size_t* bytes);
+lbib_status lbib_adjoint_bind(lbib_ctx* ctx, void* dev_workspace, size_t bytes, int64_t nsteps,
+                              int32_t ckpt_every);
+lbib_status lbib_adjoint_forward(lbib_ctx* ctx, double* J, int32_t* nbonds);
+lbib_status lbib_adjoint_backward(lbib_ctx* ctx, double dJ, double* grad);
+
+/* Change the strain constant k_s (Eq. strainFor), bending constant k_b
+ * (Eq. bendFor) and bond spring constant sigma (Eq. adhFor) of body `body`
+ * of a running single-lattice context (instance 0 of a batch).  All >= 0 and
+ * finite, else LBIB_EINVAL; LBIB_ESTATE before finalize_setup.  Invalidates
+ * the last adjoint forward window. */
+lbib_status lbib_set_body_params(lbib_ctx* ctx, int32_t body, double ks, double kb, double sigma);
 
 /* Completed step count. */
 lbib_status lbib_get_step(const lbib_ctx* ctx, int64_t* step);

@@ -37,6 +37,8 @@ EXPORTS = [
     "lbib_get_step", "lbib_time_lattice_kernel", "lbib_set_kernel_timing",
     "lbib_get_kernel_timing", "lbib_destroy", "lbib_batch_create", "lbib_batch_size",
     "lbib_batch_get_fields", "lbib_batch_get_markers", "lbib_batch_get_bonds",
+    "lbib_adjoint_workspace_query", "lbib_adjoint_bind", "lbib_adjoint_forward",
+    "lbib_adjoint_backward", "lbib_set_body_params",
 ]
 
 
@@ -84,6 +86,10 @@ def library() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"liblbib.so not found at {LIB_PATH}; build it with "
                           "python -m paper_1907_00080_amd.build")
+    # torch ships its own HIP runtime; load it before the library so that the
+    # process initialises HIP the way torch expects (loading the library
+    # first leaves HIP without a device once torch starts)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     dp = ctypes.POINTER(ctypes.c_double)
@@ -124,6 +130,11 @@ def library() -> ctypes.CDLL:
         "lbib_batch_get_fields": (I32, [P, I32, dp, dp, dp]),
         "lbib_batch_get_markers": (I32, [P, I32, I32, dp]),
         "lbib_batch_get_bonds": (I32, [P, I32, ip, ip]),
+        "lbib_adjoint_workspace_query": (I32, [P, I64, I32, ctypes.POINTER(ctypes.c_size_t)]),
+        "lbib_adjoint_bind": (I32, [P, P, ctypes.c_size_t, I64, I32]),
+        "lbib_adjoint_forward": (I32, [P, ctypes.POINTER(ctypes.c_double), ip]),
+        "lbib_adjoint_backward": (I32, [P, D, dp]),
+        "lbib_set_body_params": (I32, [P, I32, D, D, D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -329,6 +340,11 @@ class Sim(_Ctx):
     def set_bonds(self, l2r):
         a = np.ascontiguousarray(l2r, dtype=np.int32)
         self.check(self.lib.lbib_set_bonds(self.h, _iptr(a)))
+
+    def set_body_params(self, body: int, ks: float, kb: float, sigma: float):
+        """Strain, bending and bond spring constants of one body."""
+        self.check(self.lib.lbib_set_body_params(self.h, int(body), float(ks), float(kb),
+                                                 float(sigma)))
 
 
     def get_state(self) -> bytes:

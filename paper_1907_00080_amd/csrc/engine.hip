@@ -12,8 +12,11 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <tuple>
 #include <vector>
 
+#include <cstddef>
 #include "lbib.h"
 #include "lbib_batch.h"
 #include "lbib_dev.h"
@@ -85,6 +88,17 @@ struct lbib_ctx {
   bool ktiming = false;       // bracket fused-kernel launches with events
   std::vector<std::pair<hipEvent_t, hipEvent_t>> kevents;
   int bin_cap = 1024;         // marker registrations per tile and bin set
+  // adjoint window (single-instance contexts): caller-owned workspace
+  char* aws = nullptr;
+  size_t aws_bytes = 0;
+  long long adjK = 0;         // window length the workspace was sized for
+  int adjk = 0;               // checkpoint spacing
+  bool adj_ready = false;     // a forward window has run since the last change
+  std::vector<long long> ck_step;   // step of each checkpoint (last: end of window)
+  // captured recompute + reverse sweep of a segment, keyed by
+  // (steps, start parity, segment starts at step 0)
+  std::map<std::tuple<long long, int, int>, hipGraphExec_t> adj_graphs;
+  std::vector<double> adj_y;        // marker ordinates at the end of the window
 };
 
 static std::string g_create_err;
@@ -460,6 +474,11 @@ void drop_kevents(lbib_ctx* c) {
   c->kevents.clear();
 }
 
+void drop_adjoint_graphs(lbib_ctx* c) {
+  for (auto& kv : c->adj_graphs) (void)hipGraphExecDestroy(kv.second);
+  c->adj_graphs.clear();
+}
+
 void drop_graphs(lbib_ctx* c) {
   for (auto& g : c->gexec)
     if (g) {
@@ -582,6 +601,273 @@ struct StateHeader {
   int64_t nodes;
 };
 constexpr uint64_t kMagic = 0x4c4249425354ull;  // "LBIBST"
+
+
+// ------------------------------------------------------------ adjoint window
+// Workspace of the adjoint: checkpoints of the dynamic state every k steps
+// (plus the end of the window), a segment store with the forward data of k
+// steps, and the float64 adjoint state and per-step scratch.
+struct AdjLayout {
+  size_t ck_bytes;
+  int nseg, nck;
+  size_t ck;
+  size_t rec_bytes, r_h, r_x, r_y, r_fx, r_fy, r_xn, r_yn, r_u;
+  size_t seg;
+  size_t ha, fph, FE, FEh, mom, Uh, Rh, xa, ya, xma, yma;
+  size_t mk[13];
+  size_t grad;
+  size_t total;
+};
+
+AdjLayout adj_layout(const lbib_ctx* c, long long K, int k) {
+  AdjLayout A{};
+  size_t cur = 0;
+  auto take = [&](size_t b) {
+    size_t o = cur;
+    cur = align256(cur + std::max<size_t>(b, 8));
+    return o;
+  };
+  for (auto& r : state_regions(c)) A.ck_bytes += align256(r.second);
+  A.nseg = (int)((K + k - 1) / k);
+  A.nck = A.nseg + 1;
+  A.ck = take(A.ck_bytes * (size_t)A.nck);
+  const size_t es = elem_size(c->dtype), nm = std::max(c->nm, 1);
+  const size_t N = (size_t)c->nodes;
+  size_t rb = 0;
+  auto rt = [&](size_t b) {
+    size_t o = rb;
+    rb = align256(rb + std::max<size_t>(b, 8));
+    return o;
+  };
+  A.r_h = rt(es * 9 * N);
+  A.r_x = rt(8 * nm); A.r_y = rt(8 * nm);
+  A.r_fx = rt(8 * nm); A.r_fy = rt(8 * nm);
+  A.r_xn = rt(8 * nm); A.r_yn = rt(8 * nm);
+  A.r_u = rt(es * 2 * N);
+  A.rec_bytes = rb;
+  A.seg = take(rb * (size_t)k);
+  A.ha = take(8 * 9 * N); A.fph = take(8 * 9 * N);
+  A.FE = take(16 * N); A.FEh = take(16 * N); A.mom = take(24 * N);
+  A.Uh = take(16 * N); A.Rh = take(24 * N);
+  A.xa = take(8 * nm); A.ya = take(8 * nm); A.xma = take(8 * nm); A.yma = take(8 * nm);
+  for (auto& o : A.mk) o = take(8 * nm);
+  A.grad = take(24 * (size_t)std::max(c->nbody, 1));
+  A.total = cur;
+  return A;
+}
+
+AdjPtrs adj_ptrs(const lbib_ctx* c, const AdjLayout& A) {
+  char* w = c->aws;
+  AdjPtrs a{};
+  a.ha = (double*)(w + A.ha); a.fph = (double*)(w + A.fph);
+  a.FE = (double*)(w + A.FE); a.FEh = (double*)(w + A.FEh); a.mom = (double*)(w + A.mom);
+  a.Uh = (double*)(w + A.Uh); a.Rh = (double*)(w + A.Rh);
+  a.xa = (double*)(w + A.xa); a.ya = (double*)(w + A.ya);
+  a.xma = (double*)(w + A.xma); a.yma = (double*)(w + A.yma);
+  double** m[13] = {&a.dirx, &a.diry, &a.fvx, &a.fvy, &a.dsh, &a.Dx, &a.Dy,
+                    &a.Cx, &a.Cy, &a.BLx, &a.BLy, &a.BRx, &a.BRy};
+  for (int k = 0; k < 13; ++k) *m[k] = (double*)(w + A.mk[k]);
+  a.grad = (double*)(w + A.grad);
+  return a;
+}
+
+// Save (or restore) the dynamic state to (from) checkpoint j.
+void adj_checkpoint(lbib_ctx* c, const AdjLayout& A, int j, bool save) {
+  char* base = c->aws + A.ck + (size_t)j * A.ck_bytes;
+  CopyList cl{};
+  size_t off = 0;
+  for (auto& r : state_regions(c)) {
+    if (cl.n == 24) {
+      launch_copies(cl, c->stream);
+      cl.n = 0;
+    }
+    cl.src[cl.n] = save ? c->ws + r.first : base + off;
+    cl.dst[cl.n] = save ? base + off : c->ws + r.first;
+    cl.bytes[cl.n] = r.second;
+    ++cl.n;
+    off += align256(r.second);
+  }
+  launch_copies(cl, c->stream);
+}
+
+lbib_status set_freeze(lbib_ctx* c, int32_t f) {
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.lat + offsetof(LatDev, freeze), &f, 4, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBIB_OK;
+}
+
+lbib_status adj_check_sizes(lbib_ctx* c) {
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "finalize_setup before binding an adjoint workspace");
+  if (c->ninst != 1) return fail(c, LBIB_EINVAL, "the adjoint runs on single-lattice contexts");
+  return LBIB_OK;
+}
+
+lbib_status adj_check(lbib_ctx* c) {
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  if (c->ninst != 1) return fail(c, LBIB_EINVAL, "the adjoint runs on single-lattice contexts");
+  for (auto& b : c->inst[0].bodies)
+    if (b.d.kind == LBIB_PARTICLE_RIGID)
+      return fail(c, LBIB_EINVAL, "the adjoint covers red cells and soft particles (no rigid bodies)");
+  if (!c->aws) return fail(c, LBIB_ESTATE, "bind an adjoint workspace first");
+  return LBIB_OK;
+}
+
+// J = mean over particle vertices of the distance to the nearer wall.
+double wall_objective(const lbib_ctx* c, const std::vector<double>& y, std::vector<double>* dJdy) {
+  const InstHost& I = c->inst[0];
+  const double ny = I.lat.ny;
+  int v = 0, np = 0;
+  double s = 0.0;
+  if (dJdy) dJdy->assign(y.size(), 0.0);
+  for (auto& b : I.bodies) {
+    if (b.d.kind != LBIB_RBC_KINEMATIC) np += b.d.nv;
+  }
+  for (auto& b : I.bodies) {
+    for (int k = 0; k < b.d.nv; ++k, ++v) {
+      if (b.d.kind == LBIB_RBC_KINEMATIC) continue;
+      const double lo = y[v] + 0.5, hi = ny - 0.5 - y[v];
+      s += lo <= hi ? lo : hi;
+      if (dJdy) (*dJdy)[v] = (lo <= hi ? 1.0 : -1.0) / np;
+    }
+  }
+  return np > 0 ? s / np : 0.0;
+}
+
+template <typename T>
+lbib_status adjoint_forward_impl(lbib_ctx* c, double* J) {
+  const AdjLayout A = adj_layout(c, c->adjK, c->adjk);
+  const bool kt = c->ktiming;
+  c->ktiming = false;
+  lbib_status st = set_freeze(c, 1);
+  if (st != LBIB_OK) return st;
+  c->ck_step.assign(A.nck, 0);
+  for (int j = 0; j < A.nseg; ++j) {
+    c->ck_step[j] = c->step;
+    adj_checkpoint(c, A, j, true);
+    const long long n = std::min<long long>(c->adjk, c->adjK - (long long)j * c->adjk);
+    st = run_steps<T>(c, n);
+    if (st != LBIB_OK) return st;
+  }
+  c->ck_step[A.nseg] = c->step;
+  adj_checkpoint(c, A, A.nseg, true);
+  HIPCHK(c, hipGetLastError());
+  c->adj_y.assign(std::max(c->nm, 1), 0.0);
+  HIPCHK(c, hipMemcpyAsync(c->adj_y.data(), c->ws + c->L.y, 8 * (size_t)c->nm, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->adj_y.resize(c->nm);
+  if (J) *J = wall_objective(c, c->adj_y, nullptr);
+  st = set_freeze(c, c->inst[0].adh.freeze_topology);
+  if (st != LBIB_OK) return st;
+  c->ktiming = kt;
+  c->adj_ready = true;
+  return LBIB_OK;
+}
+
+// Recompute n steps from the restored state, keeping the forward data of
+// each step, then run the reverse sweep over them (captured as one graph).
+template <typename T>
+void enqueue_adjoint_segment(lbib_ctx* c, const AdjLayout& A, AdjPtrs a, long long n, bool first) {
+  const long long N = c->nodes;
+  const size_t es = elem_size(c->dtype), nmb = 8 * (size_t)c->nm;
+  for (long long s = 0; s < n; ++s) {
+    char* rec = c->aws + A.seg + (size_t)s * A.rec_bytes;
+    Ptrs<T> p = make_ptrs<T>(c);
+    CopyList pre{};
+    pre.n = 3;
+    pre.src[0] = (const char*)p.A; pre.dst[0] = rec + A.r_h; pre.bytes[0] = es * 9 * N;
+    pre.src[1] = (const char*)p.x; pre.dst[1] = rec + A.r_x; pre.bytes[1] = nmb;
+    pre.src[2] = (const char*)p.y; pre.dst[2] = rec + A.r_y; pre.bytes[2] = nmb;
+    launch_copies(pre, c->stream);
+    enqueue_steps<T>(c, 1);
+    CopyList post{};
+    post.n = 5;
+    post.src[0] = (const char*)p.fx; post.dst[0] = rec + A.r_fx; post.bytes[0] = nmb;
+    post.src[1] = (const char*)p.fy; post.dst[1] = rec + A.r_fy; post.bytes[1] = nmb;
+    post.src[2] = (const char*)p.xn; post.dst[2] = rec + A.r_xn; post.bytes[2] = nmb;
+    post.src[3] = (const char*)p.yn; post.dst[3] = rec + A.r_yn; post.bytes[3] = nmb;
+    post.src[4] = (const char*)p.U; post.dst[4] = rec + A.r_u; post.bytes[4] = es * 2 * N;
+    launch_copies(post, c->stream);
+  }
+  for (long long s = n - 1; s >= 0; --s) {
+    const char* rec = c->aws + A.seg + (size_t)s * A.rec_bytes;
+    a.h = rec + A.r_h;
+    a.x = (const double*)(rec + A.r_x); a.y = (const double*)(rec + A.r_y);
+    a.fx = (const double*)(rec + A.r_fx); a.fy = (const double*)(rec + A.r_fy);
+    a.xn = (const double*)(rec + A.r_xn); a.yn = (const double*)(rec + A.r_yn);
+    a.u = rec + A.r_u;
+    a.first = first && s == 0;
+    launch_adjoint_step<T>(make_ptrs<T>(c), a, N, c->stream);
+  }
+}
+
+template <typename T>
+lbib_status adjoint_backward_impl(lbib_ctx* c, double dJ, double* grad) {
+  const AdjLayout A = adj_layout(c, c->adjK, c->adjk);
+  AdjPtrs a = adj_ptrs(c, A);
+  const bool kt = c->ktiming;
+  c->ktiming = false;
+  lbib_status st = set_freeze(c, 1);
+  if (st != LBIB_OK) return st;
+  const long long N = c->nodes;
+  const int nm = c->nm;
+  launch_fill(a.ha, 9 * N, 0.0, c->stream);
+  launch_fill(a.xa, nm, 0.0, c->stream);
+  launch_fill(a.xma, nm, 0.0, c->stream);
+  launch_fill(a.yma, nm, 0.0, c->stream);
+  launch_fill(a.grad, 3 * (long long)std::max(c->nbody, 1), 0.0, c->stream);
+  std::vector<double> seed;
+  wall_objective(c, c->adj_y, &seed);
+  for (auto& v : seed) v *= dJ;
+  if (nm > 0)
+    HIPCHK(c, hipMemcpyAsync(a.ya, seed.data(), 8 * (size_t)nm, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  launch_fill(a.FE, 2 * N, 0.0, c->stream);
+  launch_fill(a.Uh, 2 * N, 0.0, c->stream);
+  launch_fill(a.Rh, 3 * N, 0.0, c->stream);
+  for (int j = A.nseg - 1; j >= 0; --j) {
+    adj_checkpoint(c, A, j, false);
+    c->step = c->ck_step[j];
+    // marker bins of the restored positions (eager, outside the graph)
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.cnt[c->parity], 0, 4 * (size_t)c->ntiles, c->stream));
+    launch_stencil<T>(make_ptrs<T>(c), step_args(c), c->stream);
+    c->stencil_dirty = false;
+    const long long n = std::min<long long>(c->adjk, c->adjK - (long long)j * c->adjk);
+    const int par = c->parity, first = c->ck_step[j] == 0 ? 1 : 0;
+    const auto key = std::make_tuple(n, par, first);
+    auto it = c->adj_graphs.find(key);
+    if (it == c->adj_graphs.end()) {
+      hipGraph_t graph;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      enqueue_adjoint_segment<T>(c, A, a, n, first != 0);
+      HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+      c->parity = par;   // capture ran nothing
+      hipGraphExec_t ex_;
+      hipError_t e = hipGraphInstantiate(&ex_, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess)
+        return fail(c, LBIB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      it = c->adj_graphs.emplace(key, ex_).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    c->parity = par ^ (int)(n & 1);
+    c->step += n;
+  }
+  HIPCHK(c, hipGetLastError());
+  // leave the context at the end of the window
+  adj_checkpoint(c, A, A.nseg, false);
+  c->step = c->ck_step[A.nseg];
+  c->stencil_dirty = true;
+  std::vector<double> g(3 * (size_t)std::max(c->nbody, 1));
+  HIPCHK(c, hipMemcpyAsync(g.data(), a.grad, 8 * g.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (grad) std::memcpy(grad, g.data(), 8 * 3 * (size_t)c->nbody);
+  st = set_freeze(c, c->inst[0].adh.freeze_topology);
+  if (st != LBIB_OK) return st;
+  c->ktiming = kt;
+  return LBIB_OK;
+}
 
 }  // namespace
 
@@ -1009,8 +1295,91 @@ lbib_status lbib_get_step(const lbib_ctx* cc, int64_t* step) {
 lbib_status lbib_destroy(lbib_ctx* c) {
   if (!c) return LBIB_OK;
   drop_graphs(c);
+  drop_adjoint_graphs(c);
   drop_kevents(c);
   delete c;
+  return LBIB_OK;
+}
+
+
+// ------------------------------------------------------------ adjoint window
+lbib_status lbib_adjoint_workspace_query(const lbib_ctx* cc, int64_t nsteps, int32_t ckpt_every,
+                                         size_t* bytes) {
+  lbib_ctx* c = const_cast<lbib_ctx*>(cc);
+  if (!c || !bytes) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (nsteps < 1 || ckpt_every < 1) return fail(c, LBIB_EINVAL, "nsteps and ckpt_every must be >= 1");
+  lbib_status s = adj_check_sizes(c);
+  if (s != LBIB_OK) return s;
+  *bytes = adj_layout(c, nsteps, ckpt_every).total;
+  return LBIB_OK;
+}
+
+lbib_status lbib_adjoint_bind(lbib_ctx* c, void* ws, size_t bytes, int64_t nsteps, int32_t ckpt_every) {
+  if (!c || !ws) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (nsteps < 1 || ckpt_every < 1) return fail(c, LBIB_EINVAL, "nsteps and ckpt_every must be >= 1");
+  if (((uintptr_t)ws) & 255) return fail(c, LBIB_EINVAL, "workspace must be 256-byte aligned");
+  lbib_status s = adj_check_sizes(c);
+  if (s != LBIB_OK) return s;
+  if (bytes < adj_layout(c, nsteps, ckpt_every).total)
+    return fail(c, LBIB_ENOSPACE, "adjoint workspace smaller than lbib_adjoint_workspace_query");
+  drop_adjoint_graphs(c);   // they hold pointers into the previous workspace
+  c->aws = (char*)ws;
+  c->aws_bytes = bytes;
+  c->adjK = nsteps;
+  c->adjk = ckpt_every;
+  c->adj_ready = false;
+  return LBIB_OK;
+}
+
+lbib_status lbib_adjoint_forward(lbib_ctx* c, double* J, int32_t* nbonds) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  lbib_status s = adj_check(c);
+  if (s != LBIB_OK) return s;
+  s = c->dtype == LBIB_F64 ? adjoint_forward_impl<double>(c, J) : adjoint_forward_impl<float>(c, J);
+  if (s != LBIB_OK) return s;
+  return bonds_get(c, 0, nullptr, nbonds);
+}
+
+lbib_status lbib_adjoint_backward(lbib_ctx* c, double dJ, double* grad) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  lbib_status s = adj_check(c);
+  if (s != LBIB_OK) return s;
+  if (!c->adj_ready) return fail(c, LBIB_ESTATE, "run lbib_adjoint_forward first");
+  return c->dtype == LBIB_F64 ? adjoint_backward_impl<double>(c, dJ, grad)
+                              : adjoint_backward_impl<float>(c, dJ, grad);
+}
+
+lbib_status lbib_set_body_params(lbib_ctx* c, int32_t body, double ks, double kb, double sigma) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  lbib_status s = check_body(c, 0, body);
+  if (s != LBIB_OK) return s;
+  if (!std::isfinite(ks) || !std::isfinite(kb) || !std::isfinite(sigma) || ks < 0 || kb < 0 || sigma < 0)
+    return fail(c, LBIB_EINVAL, "body constants must be finite and >= 0");
+  BodyHost& B = c->inst[0].bodies[body];
+  B.d.ks = ks;
+  B.d.kb = kb;
+  B.d.sigma = sigma;
+  const int gb = c->body_base[0] + body;
+  char* bd = c->ws + c->L.body + sizeof(BodyDev) * (size_t)gb;
+  const double v3[3] = {ks, kb, sigma};
+  HIPCHK(c, hipMemcpyAsync(bd + offsetof(BodyDev, ks), &v3[0], 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(bd + offsetof(BodyDev, kb), &v3[1], 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(bd + offsetof(BodyDev, sigma), &v3[2], 8, hipMemcpyHostToDevice, c->stream));
+  if (B.d.ligand_stride > 0) {
+    int lb = c->lig_base[0];
+    for (int k = 0; k < body; ++k) {
+      const auto& o = c->inst[0].bodies[k].d;
+      if (o.ligand_stride > 0) lb += (o.nv + o.ligand_stride - 1) / o.ligand_stride;
+    }
+    const int nl = (B.d.nv + B.d.ligand_stride - 1) / B.d.ligand_stride;
+    std::vector<double> sg(nl, sigma);
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.lig_sigma + 8 * (size_t)lb, sg.data(), 8 * (size_t)nl,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->adj_ready = false;
   return LBIB_OK;
 }
 

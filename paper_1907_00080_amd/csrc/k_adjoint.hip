@@ -1,0 +1,489 @@
+// k_adjoint.hip - reverse sweep of one LB-IB time step (discrete adjoint).
+//
+// Forward step n (bond topology frozen; order as in the forward kernels):
+//   f_pre = pull(h^n)                       streaming, halfway bounce-back
+//   rho*, u* = moments of f_pre, u* = (j + g/2)/rho*
+//   RBC:   F_k = membrane forces at X^n                    (Sec. 2.2)
+//   soft:  F_el = probe loads(rho*, u*) + springs,          (Sec. 2.2, 2.3)
+//          X^{n+1} = X + U0 + Fv/(2 m_v), U0 = interp(u*, X),
+//          F_k = 2 (X^{n+1} - X - U0) ds_k
+//   F_E = g + sum_k F_k delta(x - X_k)                     spreading
+//   h^{n+1}, u = collide(f_pre, F_E)                       (Sec. 2.1)
+//   RBC:   X^{n+1} = 2/3 (2 X^n - X^{n-1}/2 + interp(u, X^n))  (Eq. kinematicPos;
+//          forward Euler on the first step)
+// The kernels below apply the transposed Jacobian of this map to the
+// adjoint state (h^, X^, X^_prev) in reverse order, and accumulate the
+// derivatives with respect to each body's k_s, k_b and bond constant sigma.
+// All adjoint arithmetic is float64; the forward data of step n come from
+// the segment store of the checkpointed recomputation.
+//
+// Scatter-form adjoints (transpose of an interpolation, of a probe
+// evaluation) use float64 atomics into dense adjoint fields.
+#include "adj_math.h"
+#include "lbib_dev.h"
+
+namespace lbib {
+
+namespace {
+
+// 3x3 stencil of a point with kernel weights and their derivatives
+// (weights are phi(node - X); rows beyond the walls are marked invalid).
+struct Stencil {
+  int col[3], row[3];
+  bool ok[3];
+  double wx[3], dwx[3], ddwx[3], wy[3], dwy[3], ddwy[3];
+};
+
+__device__ inline void stencil_at(const LatDev& L, double X, double Y, bool second, Stencil& s) {
+  const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
+  const bool pery = L.periodic_y != 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double rx = cxr + (a - 1);
+    s.col[a] = wrap_i((int)rx, L.nx);
+    s.wx[a] = roma_phi(rx - X);
+    s.dwx[a] = roma_dphi(rx - X);
+    s.ddwx[a] = second ? roma_ddphi(rx - X) : 0.0;
+    const double ry = cyr + (a - 1);
+    int row = (int)ry;
+    bool ok = true;
+    if (pery) row = wrap_i(row, L.ny);
+    else ok = row >= 0 && row < L.ny;
+    s.row[a] = row;
+    s.ok[a] = ok;
+    s.wy[a] = roma_phi(ry - Y);
+    s.dwy[a] = roma_dphi(ry - Y);
+    s.ddwy[a] = second ? roma_ddphi(ry - Y) : 0.0;
+  }
+}
+
+__device__ inline int wrap_idx(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+constexpr int kAdjThreads = 256;
+
+__device__ inline void block_sum4(double v[4], double (*s)[kAdjThreads / 64]) {
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double x = v[k];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0) s[k][w] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double x = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) x += s[k][i];
+    v[k] = x;
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- markers
+// Every marker: (a) spreading of its stored force into the Eulerian IB force
+// of step n (without g); (b) X^n gets the adjoint carried by
+// X_prev^{n+1} = X^n; (c) red cells: reverse of the kinematic BDF2 / Euler
+// update, whose interpolation of the stored velocity u^n scatters into the
+// adjoint of u.
+template <typename T>
+__global__ void ka_marker(Ptrs<T> p, AdjPtrs a) {
+  const int gm = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gm >= p.nm_total) return;
+  const LatDev& L = p.lat[0];
+  const long long N = (long long)L.nx * L.ny;
+  const int kind = p.minfo[gm] & 3;
+  Stencil s;
+  stencil_at(L, a.x[gm], a.y[gm], false, s);
+  const double fx = a.fx[gm], fy = a.fy[gm];
+  const bool rbc = kind == kRBC;
+  const double c1 = a.first ? 1.0 : 4.0 / 3.0, c2 = a.first ? 0.0 : -1.0 / 3.0;
+  const double c3 = a.first ? 1.0 : 2.0 / 3.0;
+  const double ux = rbc ? c3 * a.xa[gm] : 0.0, uy = rbc ? c3 * a.ya[gm] : 0.0;
+  const T* U = (const T*)a.u;
+  double gx = 0.0, gy = 0.0;
+  for (int b = 0; b < 3; ++b) {
+    if (!s.ok[b]) continue;
+    for (int c = 0; c < 3; ++c) {
+      const long long node = (long long)s.row[b] * L.nx + s.col[c];
+      const double w = s.wx[c] * s.wy[b];
+      atomicAdd(&a.FE[node], fx * w);
+      atomicAdd(&a.FE[N + node], fy * w);
+      if (rbc) {
+        atomicAdd(&a.Uh[node], ux * w);
+        atomicAdd(&a.Uh[N + node], uy * w);
+        const double uu = ux * double(U[node]) + uy * double(U[N + node]);
+        gx -= uu * s.dwx[c] * s.wy[b];
+        gy -= uu * s.wx[c] * s.dwy[b];
+      }
+    }
+  }
+  double dx = a.xma[gm], dy = a.yma[gm];
+  if (rbc) {
+    dx += c1 * a.xa[gm] + gx;
+    dy += c1 * a.ya[gm] + gy;
+    a.xma[gm] = c2 * a.xa[gm];
+    a.yma[gm] = c2 * a.ya[gm];
+  } else {
+    a.xma[gm] = 0.0;
+    a.yma[gm] = 0.0;
+  }
+  a.dirx[gm] = dx;
+  a.diry[gm] = dy;
+}
+
+// --------------------------------------------------------------- collide
+// Per node: reverse of the forced collision; adjoint of the pulled
+// populations and of the Eulerian force.
+template <typename T>
+__global__ void ka_collide(Ptrs<T> p, AdjPtrs a) {
+  const LatDev& L = p.lat[0];
+  const long long N = (long long)L.nx * L.ny;
+  const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int x = (int)(node % L.nx), y = (int)(node / L.nx);
+  const T* H = (const T*)a.h;
+  double h[kQ], ah[kQ], hh[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    int xs = wrap_idx(x - ex(i), L.nx);
+    int ys = y - ey(i);
+    const bool out = ys < 0 || ys >= L.ny;
+    ys = wrap_idx(ys, L.ny);
+    const long long src = (out && !L.periodic_y) ? opp(i) * N + node : i * N + (long long)ys * L.nx + xs;
+    h[i] = double(H[src]);
+    ah[i] = a.ha[i * N + node];
+  }
+  const double Fx = L.gx + a.FE[node], Fy = L.gy + a.FE[N + node];
+  const double omega = 1.0 / L.tau, pre = 1.0 - 0.5 / L.tau;
+  double Fhx, Fhy;
+  adj::collide_vjp(h, Fx, Fy, omega, pre, ah, a.Uh[node], a.Uh[N + node], hh, Fhx, Fhy);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) a.fph[i * N + node] = hh[i];
+  a.FEh[node] = Fhx;
+  a.FEh[N + node] = Fhy;
+  // pre-forcing moments rho*, u* (probe and particle-vertex interpolation)
+  double drho = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    drho += h[i];
+    jx += ex(i) * h[i];
+    jy += ey(i) * h[i];
+  }
+  const double rho = 1.0 + drho;
+  a.mom[node] = rho;
+  a.mom[N + node] = (jx + 0.5 * L.gx) / rho;
+  a.mom[2 * N + node] = (jy + 0.5 * L.gy) / rho;
+  // this node's accumulators are consumed: clear them for the next step
+  // (rho^*, u^* are filled by the body kernel that follows)
+  a.FE[node] = 0.0;
+  a.FE[N + node] = 0.0;
+  a.Uh[node] = 0.0;
+  a.Uh[N + node] = 0.0;
+  a.Rh[node] = 0.0;
+  a.Rh[N + node] = 0.0;
+  a.Rh[2 * N + node] = 0.0;
+}
+
+// --------------------------------------------------------------- bodies
+// One workgroup per deformable body (red cells and soft particles).
+template <typename T>
+__global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
+  __shared__ double s_red[4][kAdjThreads / 64];
+  const int b = blockIdx.x;
+  const BodyDev* Bp = p.body + b;
+  const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0;
+  if (kind == kRigid) return;   // refused by the host
+  const LatDev& L = p.lat[0];
+  const long long N = (long long)L.nx * L.ny;
+  const bool pery = L.periodic_y != 0;
+  const double nu = (L.tau - 0.5) / 3.0;
+  const double ks = Bp->ks, kb = Bp->kb, ka = Bp->ka, p_ref = Bp->p_ref, A0 = Bp->A0;
+  const double mv = Bp->mv, sigma = Bp->sigma;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const double* X = a.x + v0;
+  const double* Y = a.y + v0;
+  const double* mom = a.mom;
+
+  // ---- phase A (vertices): spread adjoint; soft Verlet / coupling chain
+  double shoe = 0.0;
+  for (int v = t; v < nv; v += nt) {
+    const int gm = v0 + v;
+    const int vp = v + 1 == nv ? 0 : v + 1, vm = v == 0 ? nv - 1 : v - 1;
+    shoe += X[v] * Y[vp] - X[vp] * Y[v];
+    Stencil s;
+    stencil_at(L, X[v], Y[v], false, s);
+    const double Fx = a.fx[gm], Fy = a.fy[gm];
+    double fhx = 0.0, fhy = 0.0, gx = 0.0, gy = 0.0;
+    for (int bb = 0; bb < 3; ++bb) {
+      if (!s.ok[bb]) continue;
+      for (int c = 0; c < 3; ++c) {
+        const long long node = (long long)s.row[bb] * L.nx + s.col[c];
+        const double w = s.wx[c] * s.wy[bb];
+        const double ex_ = a.FEh[node], ey_ = a.FEh[N + node];
+        fhx += ex_ * w;
+        fhy += ey_ * w;
+        const double sf = Fx * ex_ + Fy * ey_;
+        gx -= sf * s.dwx[c] * s.wy[bb];
+        gy -= sf * s.wx[c] * s.dwy[bb];
+      }
+    }
+    double dxv = a.dirx[gm] + gx, dyv = a.diry[gm] + gy;
+    double fvx = fhx, fvy = fhy, dsh = 0.0;
+    if (kind == kSoft) {
+      const double xa = a.xa[gm], ya = a.ya[gm];
+      const double lr = sqrt((X[vp] - X[v]) * (X[vp] - X[v]) + (Y[vp] - Y[v]) * (Y[vp] - Y[v]));
+      const double ll = sqrt((X[v] - X[vm]) * (X[v] - X[vm]) + (Y[v] - Y[vm]) * (Y[v] - Y[vm]));
+      const double ds = 0.5 * (ll + lr);
+      // U0 = interp(u*, X) and its adjoint (= the adjoint of X^{n+1})
+      double U0x = 0.0, U0y = 0.0, g2x = 0.0, g2y = 0.0;
+      for (int bb = 0; bb < 3; ++bb) {
+        if (!s.ok[bb]) continue;
+        for (int c = 0; c < 3; ++c) {
+          const long long node = (long long)s.row[bb] * L.nx + s.col[c];
+          const double w = s.wx[c] * s.wy[bb];
+          const double us = mom[N + node], vs = mom[2 * N + node];
+          U0x += us * w;
+          U0y += vs * w;
+          atomicAdd(&a.Rh[N + node], xa * w);
+          atomicAdd(&a.Rh[2 * N + node], ya * w);
+          const double uu = xa * us + ya * vs;
+          g2x -= uu * s.dwx[c] * s.wy[bb];
+          g2y -= uu * s.wx[c] * s.dwy[bb];
+        }
+      }
+      const double xn1h = xa + 2.0 * ds * fhx, yn1h = ya + 2.0 * ds * fhy;
+      dxv += xa + g2x;
+      dyv += ya + g2y;
+      fvx = 0.5 * xn1h / mv;
+      fvy = 0.5 * yn1h / mv;
+      dsh = 2.0 * ((a.xn[gm] - X[v] - U0x) * fhx + (a.yn[gm] - Y[v] - U0y) * fhy);
+    }
+    a.dirx[gm] = dxv;
+    a.diry[gm] = dyv;
+    a.fvx[gm] = fvx;
+    a.fvy[gm] = fvy;
+    a.dsh[gm] = dsh;
+  }
+  {
+    double v4[4] = {shoe, 0.0, 0.0, 0.0};
+    block_sum4(v4, s_red);   // barriers also publish phase A
+    shoe = v4[0];
+  }
+  const double area = 0.5 * shoe;
+  const double kappa = ka * (1.0 - area / A0) * p_ref;
+
+  // ---- phase B (elements l: v -> v+1) and bending (vertices)
+  double ksh = 0.0, kbh = 0.0, sigh = 0.0, kaph = 0.0;
+  for (int l = t; l < nv; l += nt) {
+    const int gl = v0 + l;
+    const int lp = l + 1 == nv ? 0 : l + 1, lm = l == 0 ? nv - 1 : l - 1;
+    const double dx = X[lp] - X[l], dy = Y[lp] - Y[l];
+    const double len = sqrt(dx * dx + dy * dy);
+    const double f0x = a.fvx[gl], f0y = a.fvy[gl], f1x = a.fvx[v0 + lp], f1y = a.fvy[v0 + lp];
+    double Dhx = 0.0, Dhy = 0.0, Chx = 0.0, Chy = 0.0, lenh = 0.0;
+    adj::strain_vjp(dx, dy, p.l0[gl], ks, f0x - f1x, f0y - f1y, Dhx, Dhy, ksh);
+    const double Fex = 0.5 * (f0x + f1x), Fey = 0.5 * (f0y + f1y);   // element-load adjoint
+    kaph += adj::area_vjp(dx, dy, kappa, Fex, Fey, Dhx, Dhy);
+    if (kind == kSoft) {
+      lenh += 0.5 * (a.dsh[gl] + a.dsh[v0 + lp]);
+      const double cx = 0.5 * (X[l] + X[lp]), cy = 0.5 * (Y[l] + Y[lp]);
+      const double nxl = dy / len, nyl = -dx / len;
+      // adhesion spring on a bonded ligand element
+      if (Bp->lig_stride > 0 && l % Bp->lig_stride == 0) {
+        const int r = p.l2r[Bp->lig_base + l / Bp->lig_stride];
+        if (r >= 0) {
+          const int wall = r < L.n_rec0 ? 0 : 1;
+          const double xr = p.rec_x[L.rec_base + r];
+          const double cxw = cx - L.nx * floor(cx / L.nx);
+          double ddx = xr - cxw;
+          if (ddx > 0.5 * L.nx) ddx -= L.nx;
+          else if (ddx < -0.5 * L.nx) ddx += L.nx;
+          const double yw = wall == 0 ? -0.5 : L.ny - 0.5;
+          const double ddy = cy - yw;
+          const double yl = sqrt(ddx * ddx + ddy * ddy);
+          adj::spring_vjp(dx, dy, yl, -ddx / yl, ddy / yl, sigma, L.y_eq, Fex, Fey, Dhx, Dhy, Chx,
+                          Chy, sigh);
+        }
+      }
+      // probe load at q = c + 1.2 n (ordinate clamped into the fluid)
+      const double qx = cx + 1.2 * nxl;
+      const double qy_raw = cy + 1.2 * nyl;
+      double qy = qy_raw;
+      bool clamped = false;
+      if (!pery) {
+        qy = fmin(fmax(qy_raw, 0.5), L.ny - 1.5);
+        clamped = qy != qy_raw;
+      }
+      Stencil s;
+      stencil_at(L, qx, qy, true, s);
+      double rq = 0.0, g[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int bb = 0; bb < 3; ++bb) {
+        if (!s.ok[bb]) continue;
+        for (int c = 0; c < 3; ++c) {
+          const long long node = (long long)s.row[bb] * L.nx + s.col[c];
+          const double w = s.wx[c] * s.wy[bb];
+          const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
+          rq += r0 * w;
+          g[0] -= us * s.dwx[c] * s.wy[bb];
+          g[1] -= us * s.wx[c] * s.dwy[bb];
+          g[2] -= vs * s.dwx[c] * s.wy[bb];
+          g[3] -= vs * s.wx[c] * s.dwy[bb];
+        }
+      }
+      const double pr = (rq - 1.0) * (1.0 / 3.0);
+      double prh = 0.0, gh[4] = {0.0, 0.0, 0.0, 0.0}, nhx = 0.0, nhy = 0.0;
+      adj::hydro_vjp(pr, g, nu, nxl, nyl, len, Fex, Fey, prh, gh, nhx, nhy, lenh);
+      const double rqh = prh * (1.0 / 3.0);
+      double qhx = 0.0, qhy = 0.0;
+      for (int bb = 0; bb < 3; ++bb) {
+        if (!s.ok[bb]) continue;
+        for (int c = 0; c < 3; ++c) {
+          const long long node = (long long)s.row[bb] * L.nx + s.col[c];
+          const double wx = s.wx[c], wy = s.wy[bb], dwx = s.dwx[c], dwy = s.dwy[bb];
+          const double ddwx = s.ddwx[c], ddwy = s.ddwy[bb];
+          const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
+          atomicAdd(&a.Rh[node], rqh * wx * wy);
+          atomicAdd(&a.Rh[N + node], -gh[0] * dwx * wy - gh[1] * wx * dwy);
+          atomicAdd(&a.Rh[2 * N + node], -gh[2] * dwx * wy - gh[3] * wx * dwy);
+          qhx += -rqh * r0 * dwx * wy + gh[0] * us * ddwx * wy + gh[1] * us * dwx * dwy +
+                 gh[2] * vs * ddwx * wy + gh[3] * vs * dwx * dwy;
+          qhy += -rqh * r0 * wx * dwy + gh[0] * us * dwx * dwy + gh[1] * us * wx * ddwy +
+                 gh[2] * vs * dwx * dwy + gh[3] * vs * wx * ddwy;
+        }
+      }
+      if (clamped) qhy = 0.0;
+      Chx += qhx;
+      Chy += qhy;
+      nhx += 1.2 * qhx;
+      nhy += 1.2 * qhy;
+      // n = (t_y, -t_x)
+      adj::unit_vjp(dx, dy, -nhy, nhx, 0.0, Dhx, Dhy);
+    }
+    adj::unit_vjp(dx, dy, 0.0, 0.0, lenh, Dhx, Dhy);
+    a.Dx[gl] = Dhx;
+    a.Dy[gl] = Dhy;
+    a.Cx[gl] = Chx;
+    a.Cy[gl] = Chy;
+    // bending at vertex l (left element lm, right element l)
+    const double dLx = X[l] - X[lm], dLy = Y[l] - Y[lm];
+    const double Fhm[2] = {a.fvx[v0 + lm], a.fvy[v0 + lm]};
+    const double Fhu[2] = {f0x, f0y};
+    const double Fhp[2] = {f1x, f1y};
+    double dLh[2] = {0.0, 0.0}, dRh[2] = {0.0, 0.0};
+    adj::bend_vjp(dLx, dLy, dx, dy, p.th0[gl], kb, Fhm, Fhu, Fhp, dLh, dRh, kbh);
+    a.BLx[gl] = dLh[0];
+    a.BLy[gl] = dLh[1];
+    a.BRx[gl] = dRh[0];
+    a.BRy[gl] = dRh[1];
+  }
+  double v4[4] = {ksh, kbh, sigh, kaph};
+  block_sum4(v4, s_red);
+  const double Ah = -v4[3] * ka * p_ref / A0;
+
+  // ---- phase D (vertices): gather element terms into the adjoint of X^n
+  for (int v = t; v < nv; v += nt) {
+    const int gm = v0 + v;
+    const int vp = v + 1 == nv ? 0 : v + 1, vm = v == 0 ? nv - 1 : v - 1;
+    // element l = v-1 ends at v (+d^), element v starts at v (-d^)
+    const double Dmx = a.Dx[v0 + vm] + a.BRx[v0 + vm] + a.BLx[gm];
+    const double Dmy = a.Dy[v0 + vm] + a.BRy[v0 + vm] + a.BLy[gm];
+    const double Dvx = a.Dx[gm] + a.BRx[gm] + a.BLx[v0 + vp];
+    const double Dvy = a.Dy[gm] + a.BRy[gm] + a.BLy[v0 + vp];
+    double xh = a.dirx[gm] + Dmx - Dvx + 0.5 * (a.Cx[gm] + a.Cx[v0 + vm]);
+    double yh = a.diry[gm] + Dmy - Dvy + 0.5 * (a.Cy[gm] + a.Cy[v0 + vm]);
+    xh += Ah * 0.5 * (Y[vp] - Y[vm]);
+    yh += Ah * 0.5 * (X[vm] - X[vp]);
+    a.xa[gm] = xh;
+    a.ya[gm] = yh;
+  }
+  if (t == 0) {
+    a.grad[3 * b + 0] += v4[0];
+    a.grad[3 * b + 1] += v4[1];
+    a.grad[3 * b + 2] += v4[2];
+  }
+}
+
+// --------------------------------------------------------------- stream
+// Reverse of the pull streaming: h^_j(y) = f^_j(y + e_j), or, where the pull
+// bounced at a wall, f^_{opp(j)}(y).  f^ includes the pre-forcing moment
+// terms of rho*, u*.
+template <typename T>
+__global__ void ka_stream(Ptrs<T> p, AdjPtrs a) {
+  const LatDev& L = p.lat[0];
+  const long long N = (long long)L.nx * L.ny;
+  const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int x = (int)(node % L.nx), y = (int)(node / L.nx);
+#pragma unroll
+  for (int j = 0; j < kQ; ++j) {
+    int xs = wrap_idx(x + ex(j), L.nx), ys = y + ey(j);
+    int i = j;
+    long long src;
+    if ((ys < 0 || ys >= L.ny) && !L.periodic_y) {
+      src = node;
+      i = opp(j);
+    } else {
+      ys = wrap_idx(ys, L.ny);
+      src = (long long)ys * L.nx + xs;
+    }
+    const double rho = a.mom[src], us = a.mom[N + src], vs = a.mom[2 * N + src];
+    const double rh = a.Rh[src], uh = a.Rh[N + src], vh = a.Rh[2 * N + src];
+    const double r = rh - (uh * us + vh * vs) / rho;
+    a.ha[j * N + node] = a.fph[i * N + src] + r + (ex(i) * uh + ey(i) * vh) / rho;
+  }
+}
+
+// --------------------------------------------------------------- copies
+// Several device-to-device copies in one launch (4-byte words).
+__global__ void ka_copy(CopyList c) {
+  const int r = blockIdx.y;
+  if (r >= c.n) return;
+  const unsigned* s = (const unsigned*)c.src[r];
+  unsigned* d = (unsigned*)c.dst[r];
+  const unsigned long long n = c.bytes[r] >> 2;
+  for (unsigned long long k = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (unsigned long long)gridDim.x * blockDim.x)
+    d[k] = s[k];
+}
+
+// Set the adjoint seed / clear accumulators: out[k] = v for k < n.
+__global__ void ka_fill(double* out, long long n, double v) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    out[k] = v;
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+void launch_adjoint_step(const Ptrs<T>& p, const AdjPtrs& a, long long N, hipStream_t s) {
+  const int nm = p.nm_total;
+  const unsigned gn = (unsigned)((N + 255) / 256), gm = (unsigned)((nm + 255) / 256);
+  // FE, Uh (and Rh) start the step cleared: by the previous reverse step's
+  // collide kernel, or by the fill before the first one
+  if (nm > 0) hipLaunchKernelGGL(ka_marker<T>, dim3(gm), dim3(256), 0, s, p, a);
+  hipLaunchKernelGGL(ka_collide<T>, dim3(gn), dim3(256), 0, s, p, a);
+  if (p.nbody_total > 0)
+    hipLaunchKernelGGL(ka_body<T>, dim3(p.nbody_total), dim3(kAdjThreads), 0, s, p, a);
+  hipLaunchKernelGGL(ka_stream<T>, dim3(gn), dim3(256), 0, s, p, a);
+}
+
+void launch_copies(const CopyList& c, hipStream_t s) {
+  if (c.n <= 0) return;
+  unsigned long long mx = 0;
+  for (int r = 0; r < c.n; ++r) mx = std::max(mx, c.bytes[r] >> 2);
+  const unsigned gx = (unsigned)std::min<unsigned long long>((mx + 255) / 256, 1024ull);
+  hipLaunchKernelGGL(ka_copy, dim3(std::max(gx, 1u), c.n), dim3(256), 0, s, c);
+}
+
+void launch_fill(double* out, long long n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(ka_fill, dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)), dim3(256), 0,
+                     s, out, n, v);
+}
+
+template void launch_adjoint_step<float>(const Ptrs<float>&, const AdjPtrs&, long long, hipStream_t);
+template void launch_adjoint_step<double>(const Ptrs<double>&, const AdjPtrs&, long long, hipStream_t);
+
+}  // namespace lbib

@@ -13,6 +13,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include "roma.h"
 #include <stdint.h>
 
 namespace lbib {
@@ -105,29 +106,6 @@ struct Ptrs {
   int nm_total, nbody_total, ntile_total, ninst, nlig_total;
 };
 
-// ------------------------------------------------------------ Roma kernel
-// 3-point kernel of Roma, Peskin & Berger on the 3 nearest nodes.
-__host__ __device__ inline double roma_phi(double r) {
-  double a = fabs(r);
-  if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) * (1.0 / 3.0);
-  if (a <= 1.5) {
-    double b = 1.0 - a;
-    double s = 1.0 - 3.0 * b * b;
-    return (5.0 - 3.0 * a - sqrt(s > 0.0 ? s : 0.0)) * (1.0 / 6.0);
-  }
-  return 0.0;
-}
-__host__ __device__ inline double roma_dphi(double r) {
-  double a = fabs(r);
-  if (a <= 0.5) return -r / sqrt(1.0 - 3.0 * r * r);
-  if (a < 1.5) {
-    double b = 1.0 - a;
-    double v = -0.5 - b / (2.0 * sqrt(1.0 - 3.0 * b * b));
-    return r > 0 ? v : -v;
-  }
-  return 0.0;
-}
-
 __host__ __device__ inline int wrap_i(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;
@@ -157,6 +135,38 @@ __device__ inline double philox_uniform(unsigned long long seed, long long step,
   philox4x32_10(c, (unsigned)(seed & 0xffffffffull), (unsigned)(seed >> 32));
   return (double)c[0] * (1.0 / 4294967296.0);
 }
+
+// ------------------------------------------------------------ adjoint
+// Pointers of one reverse step (single lattice instance).  Forward data of
+// step n come from the segment store; everything else is float64 adjoint
+// state or per-step scratch.
+struct AdjPtrs {
+  const void* h;                      // h^n (T[9][N])
+  const double *x, *y;                // X^n
+  const double *fx, *fy;              // marker forces of step n
+  const double *xn, *yn;              // X^{n+1} of particles
+  const void* u;                      // physical velocity u^n (T[2][N], valid where touched)
+  int first;                          // step n is the first step
+  double* ha;                         // [9][N] adjoint of h^{n+1} in, of h^n out
+  double *xa, *ya;                    // adjoint of X^{n+1} in, of X^n out
+  double *xma, *yma;                  // adjoint of X_prev^{n+1} in, of X_prev^n out
+  double *fph, *FE, *FEh, *mom, *Uh, *Rh;   // [9N] [2N] [2N] [3N] [2N] [3N]
+  double *dirx, *diry, *fvx, *fvy, *dsh, *Dx, *Dy, *Cx, *Cy, *BLx, *BLy, *BRx, *BRy;  // [nm]
+  double* grad;                       // [nbody][3]: d/dks, d/dkb, d/dsigma
+};
+
+// Up to 24 device-to-device copies in one launch (sizes multiple of 4 bytes).
+struct CopyList {
+  int n;
+  const char* src[24];
+  char* dst[24];
+  unsigned long long bytes[24];
+};
+
+template <typename T>
+void launch_adjoint_step(const Ptrs<T>& p, const AdjPtrs& a, long long N, hipStream_t s);
+void launch_copies(const CopyList& c, hipStream_t s);
+void launch_fill(double* out, long long n, double v, hipStream_t s);
 
 // ------------------------------------------------------------ launchers
 // (defined in the kernel translation units, called by the host engine)

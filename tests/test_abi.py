@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for name in decl:
         assert hasattr(lib, name), name
     assert decl == set(pkg.EXPORTS)
-    assert lib.lbib_abi_version() == 1
+    assert lib.lbib_abi_version() == 2
     for s, n in pkg.STATUS.items():
         assert lib.lbib_status_string(s).decode() == n
 
@@ -138,3 +138,20 @@ def test_product_path_requires_built_library(monkeypatch):
     monkeypatch.setattr(pkg, "LIB_PATH", "/nonexistent/liblbib.so")
     with pytest.raises(ImportError):
         pkg.Sim(configs.small_case(nx=16, ny=8, n_rbc=0))
+
+
+def test_adjoint_calls_need_a_running_single_context():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    n = ctypes.c_size_t()
+    assert lib.lbib_adjoint_workspace_query(h, 10, 5, ctypes.byref(n)) == 2
+    assert lib.lbib_adjoint_workspace_query(h, 0, 5, ctypes.byref(n)) == 1
+    assert lib.lbib_adjoint_workspace_query(h, 10, 0, ctypes.byref(n)) == 1
+    assert lib.lbib_adjoint_bind(h, None, 0, 10, 5) == 1
+    J = ctypes.c_double()
+    assert lib.lbib_adjoint_forward(h, ctypes.byref(J), None) == 2
+    g = (ctypes.c_double * 3)()
+    assert lib.lbib_adjoint_backward(h, 1.0, g) == 2
+    assert lib.lbib_set_body_params(h, 0, 1.0, 0.0, 0.0) == 2
+    lib.lbib_destroy(h)

@@ -97,8 +97,9 @@ typedef struct {
  * p_ref: reference pressure of the area penalty.  density_ratio: rho_P/rho
  * (particle mass = ratio * rest area, Sec. 3).  sigma: bond spring constant.
  * ligand_stride: 0 = no ligands; s > 0: a ligand on every element l with
- * l % s == 0 (s = 2 is the density rho_L = 0.5 of Sec. 3).  Ligands are
- * only meaningful on particles. */
+ * l % s == 0 (s = 2 is the density rho_L = 0.5 of Sec. 3).  Ligands sit on
+ * particles only: a kinematic red cell with ligand_stride > 0 is refused
+ * (LBIB_EINVAL). */
 typedef struct {
   int32_t kind;
   int32_t nv;

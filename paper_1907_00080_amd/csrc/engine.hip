@@ -55,7 +55,7 @@ struct Layout {
   size_t x, y, xm, ym, xn, yn, fx, fy, l0, th0, r0x, r0y;
   size_t mbody, minfo, cx, cy, wx, wy;
   size_t s[9];
-  size_t cnt[2], bins[2], touched, overflow, fmax, bond_flag, spin, Uspare, tile_inst;
+  size_t cnt[2], bins[2], touched, overflow, fmax, bond_flag, step_slot, spin, Uspare, tile_inst;
   size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma;
   size_t step_next, step_cur, ties, red;
   size_t total;
@@ -88,6 +88,11 @@ struct lbib_ctx {
   bool ktiming = false;       // bracket fused-kernel launches with events
   std::vector<std::pair<hipEvent_t, hipEvent_t>> kevents;
   int bin_cap = 1024;         // marker registrations per tile and bin set
+  int body_cache = 16 * 1024; // LDS bytes of a particle workgroup's rho*, u* cache
+  // steps inside a run finish the previous step's marker advance in the body
+  // kernel; only when every body is small enough that its workgroup covers
+  // its vertices in two rounds (else the separate advance kernel is faster)
+  bool merge_advance = true;
   // adjoint window (single-instance contexts): caller-owned workspace
   char* aws = nullptr;
   size_t aws_bytes = 0;
@@ -176,8 +181,9 @@ void compute_layout(lbib_ctx* c) {
   }
   L.touched = take(4 * (size_t)c->ntiles);
   L.overflow = take(8);
-  L.fmax = take(8 * (size_t)c->ninst);
-  L.bond_flag = take(4 * (size_t)c->ninst);
+  L.fmax = take(8 * 2 * (size_t)c->ninst);        // two slots, by step parity
+  L.bond_flag = take(4 * 2 * (size_t)c->ninst);
+  L.step_slot = take(8 * 2 * (size_t)c->ninst);
   L.spin = take(8);
   L.Uspare = take(es * 2 * c->nodes);   // velocity output of measurement launches
   L.tile_inst = take(4 * c->ntiles);
@@ -227,8 +233,16 @@ Ptrs<T> make_ptrs(const lbib_ctx* c) {
   p.bin_next = (int*)(w + L.bins[c->parity ^ 1]);
   p.touched = (int*)(w + L.touched);
   p.overflow = (int*)(w + L.overflow);
-  p.fmax_bits = (unsigned long long*)(w + L.fmax);
-  p.bond_flag = (int*)(w + L.bond_flag);
+  {
+    const int cur = c->parity, oth = c->parity ^ 1;
+    const size_t ni = (size_t)c->ninst;
+    p.fmax_bits = (unsigned long long*)(w + L.fmax) + cur * ni;
+    p.fmax_next = (unsigned long long*)(w + L.fmax) + oth * ni;
+    p.bond_flag = (int*)(w + L.bond_flag) + cur * ni;
+    p.bond_flag_next = (int*)(w + L.bond_flag) + oth * ni;
+    p.step_slot = (long long*)(w + L.step_slot) + cur * ni;
+    p.step_prev = (long long*)(w + L.step_slot) + oth * ni;
+  }
   p.spin_timeouts = (int*)(w + L.spin);
   p.bin_cap = c->bin_cap;
   p.tile_inst = (int*)(w + L.tile_inst);
@@ -253,6 +267,29 @@ Ptrs<T> make_ptrs(const lbib_ctx* c) {
   return p;
 }
 
+// LDS bytes for a particle workgroup's cache of rho*, u*: the node box that
+// its vertex and probe stencils reach (extent + probe 1.2 + stencil 1 + margin
+// 2 on each side), with 10 % spare for deformation; 16 KB to 96 KB.
+int body_cache_bytes(const lbib_ctx* c) {
+  const int es = elem_size(c->dtype);
+  long long need = 0;
+  for (auto& I : c->inst)
+    for (auto& b : I.bodies) {
+      if (b.d.kind == LBIB_RBC_KINEMATIC) continue;
+      double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+      for (int v = 0; v < b.d.nv; ++v) {
+        x0 = std::min(x0, b.xy[2 * v]); x1 = std::max(x1, b.xy[2 * v]);
+        y0 = std::min(y0, b.xy[2 * v + 1]); y1 = std::max(y1, b.xy[2 * v + 1]);
+      }
+      const double pad = 2.0 * (1.2 + 1.0 + 2.0) + 2.0;
+      const long long nodes = (long long)std::ceil(x1 - x0 + pad) * (long long)std::ceil(y1 - y0 + pad);
+      need = std::max(need, nodes * 3 * es * 11 / 10);
+    }
+  const long long lo = 16 * 1024, hi = 96 * 1024;
+  need = std::min(std::max(need, lo), hi);
+  return (int)((need + 255) & ~255ll);
+}
+
 StepArgs step_args(const lbib_ctx* c) {
   StepArgs a;
   a.tile_x = c->TX;
@@ -263,6 +300,7 @@ StepArgs step_args(const lbib_ctx* c) {
     const int nt = ((c->inst[i].lat.nx + c->TX - 1) / c->TX) * ((c->inst[i].lat.ny + c->TY - 1) / c->TY);
     a.max_inst_tiles = std::max(a.max_inst_tiles, nt);
   }
+  a.body_cache_bytes = c->body_cache;
   return a;
 }
 
@@ -415,8 +453,9 @@ lbib_status upload_all(lbib_ctx* c) {
   for (int k = 0; k < 2; ++k) HIPCHK(c, hipMemsetAsync(w + L.cnt[k], 0, 4 * (size_t)c->ntiles, s));
   HIPCHK(c, hipMemsetAsync(w + L.touched, 0, 4 * (size_t)c->ntiles, s));
   HIPCHK(c, hipMemsetAsync(w + L.overflow, 0, 8, s));
-  HIPCHK(c, hipMemsetAsync(w + L.fmax, 0, 8 * (size_t)c->ninst, s));
-  HIPCHK(c, hipMemsetAsync(w + L.bond_flag, 0, 4 * (size_t)c->ninst, s));
+  HIPCHK(c, hipMemsetAsync(w + L.fmax, 0, 8 * 2 * (size_t)c->ninst, s));
+  HIPCHK(c, hipMemsetAsync(w + L.bond_flag, 0, 4 * 2 * (size_t)c->ninst, s));
+  HIPCHK(c, hipMemsetAsync(w + L.step_slot, 0, 8 * 2 * (size_t)c->ninst, s));
   HIPCHK(c, hipMemsetAsync(w + L.spin, 0, 8, s));
   HIPCHK(c, hipStreamSynchronize(s));
   // populations: equilibrium of the initial fields, shifted by the weights
@@ -448,12 +487,17 @@ lbib_status upload_all(lbib_ctx* c) {
   return LBIB_OK;
 }
 
+// n steps.  With merge_advance, two kernels each: the Lagrangian kernel
+// (which, after the first step, also finishes the previous step's marker
+// advance for its own bodies) and the fused lattice kernel, and the last
+// step ends with the marker advance of all markers.  Otherwise three kernels
+// each: Lagrangian, fused lattice, marker advance.
 template <typename T>
 void enqueue_steps(lbib_ctx* c, long long n) {
   const StepArgs a = step_args(c);
   for (long long k = 0; k < n; ++k) {
     Ptrs<T> p = make_ptrs<T>(c);
-    launch_lagrangian<T>(p, a, c->stream);
+    launch_lagrangian<T>(p, a, c->stream, c->merge_advance && k > 0);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->ktiming && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
       launch_lb_fused<T>(p, a, c->stream, 1, e0, e1);
@@ -461,7 +505,7 @@ void enqueue_steps(lbib_ctx* c, long long n) {
     } else {
       launch_lb_fused<T>(p, a, c->stream);
     }
-    launch_advance<T>(p, a, c->stream);
+    if (!c->merge_advance || k == n - 1) launch_advance<T>(p, a, c->stream);
     c->parity ^= 1;
   }
 }
@@ -920,6 +964,8 @@ lbib_status lbib_add_body(lbib_ctx* c, const lbib_body_desc* d, const double* xy
   if (d->nv < 3) return fail(c, LBIB_EINVAL, "a body needs nv >= 3");
   if (d->kind < 0 || d->kind > 2) return fail(c, LBIB_EINVAL, "bad body kind");
   if (d->ligand_stride < 0) return fail(c, LBIB_EINVAL, "ligand_stride must be >= 0");
+  if (d->kind == LBIB_RBC_KINEMATIC && d->ligand_stride > 0)
+    return fail(c, LBIB_EINVAL, "ligands sit on particles only (red cells carry none)");
   if (d->kind != LBIB_RBC_KINEMATIC && !(d->density_ratio > 0))
     return fail(c, LBIB_EINVAL, "particles need density_ratio > 0");
   BodyHost b;
@@ -1006,6 +1052,11 @@ lbib_status lbib_bind(lbib_ctx* c, void* ws, size_t bytes, void* stream) {
 lbib_status lbib_finalize_setup(lbib_ctx* c) {
   if (!c) return fail(c, LBIB_EINVAL, "NULL context");
   if (c->phase != 1) return fail(c, LBIB_ESTATE, "bind a workspace before finalize_setup");
+  c->body_cache = body_cache_bytes(c);
+  c->merge_advance = true;
+  for (auto& I : c->inst)
+    for (auto& b : I.bodies)
+      if (b.d.nv > 512) c->merge_advance = false;
   lbib_status s = c->dtype == LBIB_F64 ? upload_all<double>(c) : upload_all<float>(c);
   if (s != LBIB_OK) return s;
   c->phase = 2;
@@ -1095,6 +1146,9 @@ lbib_status lbib_set_markers(lbib_ctx* c, int32_t body, const double* xy, const 
   HIPCHK(c, hipMemcpyAsync(c->ws + c->L.y + o, b.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->L.xm + o, am.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->L.ym + o, bm.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
+  // particles: X^n also in the slot their dynamics fill (read by the bond kinetics)
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.xn + o, a.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.yn + o, b.data(), 8 * nv, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->stencil_dirty = true;
   return LBIB_OK;

@@ -304,7 +304,42 @@ __global__ __launch_bounds__(256) void k_stencil(Ptrs<T> p) {
   register_marker<TX, TY>(p.cnt_cur, p.bin_cur, p.bin_cap, p.overflow, L, gm, cx, cy, active);
 }
 
-constexpr int kBodyCacheBytes = 16 * 1024;   // LDS cache of rho*, u* per particle
+// LDS cache of rho*, u* per particle: sized by the host from the particles'
+// extent (between 16 KB and 96 KB; the body kernel's static LDS is ~41 KB)
+
+// ---------------------------------------------------------------- advance
+// Kinematic IB update of a red-cell vertex (Eq. kinematicPos): the velocity
+// of the step, interpolated at X^n with the stencil stored for X^n, then
+// BDF2 (forward Euler on the first step).
+template <typename T>
+__device__ inline void advance_rbc(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y,
+                                   bool first, double& xn, double& yn) {
+  const long long N = (long long)L.nx * L.ny;
+  const T* U = p.U + 2 * L.node_base;
+  const int nm = p.nm_total;
+  const int cx = p.cx[gm], cy = p.cy[gm];
+  double ux = 0.0, uy = 0.0;
+  for (int b2 = 0; b2 < 3; ++b2) {
+    int row = cy + b2 - 1;
+    if (L.periodic_y) row = wrap_i(row, L.ny);
+    else if (row < 0 || row >= L.ny) continue;
+    const double wy = p.wy[b2 * nm + gm];
+    for (int a = 0; a < 3; ++a) {
+      const int col = wrap_i(cx + a - 1, L.nx);
+      const double w = p.wx[a * nm + gm] * wy;
+      const long long node = (long long)row * L.nx + col;
+      ux += double(U[node]) * w;
+      uy += double(U[N + node]) * w;
+    }
+  }
+  if (first) {
+    xn = X + ux;
+    yn = Y + uy;
+  } else {
+    xn = (2.0 / 3.0) * (2.0 * X - 0.5 * p.xm[gm] + ux);
+    yn = (2.0 / 3.0) * (2.0 * Y - 0.5 * p.ym[gm] + uy);
+  }
+}
 
 // ---------------------------------------------------------------- k_bonds
 template <typename T>
@@ -325,8 +360,10 @@ __device__ __forceinline__ void bonds_kinetics(Ptrs<T>& p, const LatDev& L, int 
     if (l < L.n_lig) {
       const int gl = L.lig_base + l;
       const int va = p.lig_va[gl], vb = p.lig_vb[gl];
-      const double cx = 0.5 * (p.x[va] + p.x[vb]);
-      const double cy = 0.5 * (p.y[va] + p.y[vb]);
+      // particle positions X^n: xn (equal to x once a step has ended; while
+      // the merged step kernel runs, its particle workgroups copy xn into x)
+      const double cx = 0.5 * (p.xn[va] + p.xn[vb]);
+      const double cy = 0.5 * (p.yn[va] + p.yn[vb]);
       const int r = p.l2r[gl];
       if (r >= 0) {
         const int wall = r < L.n_rec0 ? 0 : 1;
@@ -364,8 +401,8 @@ __device__ __forceinline__ void bonds_kinetics(Ptrs<T>& p, const LatDev& L, int 
       const int l = code >> 1, wall = code & 1;
       const int gl = L.lig_base + l;
       const int va = p.lig_va[gl], vb = p.lig_vb[gl];
-      const double cx = 0.5 * (p.x[va] + p.x[vb]);
-      const double cy = 0.5 * (p.y[va] + p.y[vb]);
+      const double cx = 0.5 * (p.xn[va] + p.xn[vb]);
+      const double cy = 0.5 * (p.yn[va] + p.yn[vb]);
       const int nr = wall == 0 ? L.n_rec0 : L.n_rec1;
       if (nr == 0) continue;
       const int roff = wall == 0 ? 0 : L.n_rec0;
@@ -429,6 +466,15 @@ __device__ __forceinline__ void bonds_impl(Ptrs<T>& p, int inst, int* s_tmp, int
   if (tid == 0) {
     p.step_cur[inst] = n;
     p.step_next[inst] = n + 1;
+    p.step_slot[inst] = n;
+  }
+  if (inst == 0 && tid == 0) {
+    // the other slot was last used by the previous step, whose kernels have
+    // all finished: clear it for the next step
+    for (int i = 0; i < p.ninst; ++i) {
+      p.fmax_next[i] = 0ull;
+      p.bond_flag_next[i] = 0;
+    }
   }
   const int ny = L.ny, nx = L.nx;
   bonds_kinetics(p, L, inst, n, nx, ny, s_tmp, s_nelig);
@@ -483,12 +529,44 @@ constexpr int kVmax = 512;   // bodies up to this many vertices keep their scrat
 
 // SMALL: the body's per-vertex scratch lives in LDS (sm); otherwise in the
 // workspace.  A template parameter, so every access has a known address space.
-template <typename T, bool SMALL>
+template <typename T, bool SMALL, int TX, int TY, bool ADV>
 __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, double (*sm)[kVmax],
                                           double (*s_red)[kBodyThreads / 64], double* s_rigid, int* s_box,
                                           unsigned char* s_dyn) {
   BodyDev* Bp = p.body + b;
   const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0, inst = Bp->inst;
+  if (ADV) {
+    // end of the previous step for this body's vertices: X^n from the
+    // kinematic update (red cells) or the particle dynamics, stencils, and
+    // the bins of this step's fused kernel
+    const LatDev& La = p.lat[inst];
+    const bool first_prev = p.step_prev[inst] == 0;
+    for (int v00 = 0; v00 < nv; v00 += blockDim.x) {
+      const int v = v00 + (int)threadIdx.x;
+      const bool act = v < nv;
+      const int gm = v0 + (act ? v : 0);
+      int ncx = 0, ncy = 0;
+      if (act) {
+        const double Xo = p.x[gm], Yo = p.y[gm];
+        double xn, yn;
+        if (kind == kRBC) {
+          advance_rbc(p, La, gm, Xo, Yo, first_prev, xn, yn);
+        } else {
+          xn = p.xn[gm];
+          yn = p.yn[gm];
+        }
+        p.xm[gm] = Xo;
+        p.ym[gm] = Yo;
+        p.x[gm] = xn;
+        p.y[gm] = yn;
+        marker_stencil(p, La, gm, xn, yn);
+        ncx = p.cx[gm];
+        ncy = p.cy[gm];
+      }
+      register_marker<TX, TY>(p.cnt_cur, p.bin_cur, p.bin_cap, p.overflow, La, gm, ncx, ncy, act);
+    }
+    __syncthreads();
+  }
   const double ks = Bp->ks, kb = Bp->kb, ka = Bp->ka, p_ref = Bp->p_ref, A0 = Bp->A0;
   const double mv = Bp->mv, sigma = Bp->sigma;
   const int lig_stride = Bp->lig_stride, lig_base = Bp->lig_base;
@@ -796,8 +874,9 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
 }
 
 // Workgroups [0, ninst): bond kinetics of each instance; then one workgroup
-// per body: membrane forces, particle loads and motion.
-template <typename T>
+// per body: membrane forces, particle loads and motion.  ADV: the body's
+// vertices first finish the previous step (merged step kernel).
+template <typename T, int TX, int TY, bool ADV>
 __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_nodes) {
   __shared__ double s_red[3][kBodyThreads / 64];
   __shared__ double s_rigid[6];
@@ -812,12 +891,15 @@ __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_node
   }
   const int b = blockIdx.x - p.ninst;
   if (p.body[b].nv <= kVmax)
-    body_impl<T, true>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+    body_impl<T, true, TX, TY, ADV>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
   else
-    body_impl<T, false>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+    body_impl<T, false, TX, TY, ADV>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
 }
 
-// ---------------------------------------------------------------- k_advance
+// Ends a run of steps: every marker moves to X^{n+1} (red cells by the
+// kinematic update, particles adopt the positions of their dynamics) and
+// joins the bins the next step's fused kernel reads.  Inside a run the body
+// workgroups of the next step may do this for their own vertices.
 template <typename T, int TX, int TY>
 __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
   const int gm0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -835,31 +917,7 @@ __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
   const double X = p.x[gm], Y = p.y[gm];
   double xn, yn;
   if (kind == kRBC) {
-    const long long N = (long long)L.nx * L.ny;
-    const T* U = p.U + 2 * L.node_base;
-    const int nm = p.nm_total;
-    const int cx = p.cx[gm], cy = p.cy[gm];
-    double ux = 0.0, uy = 0.0;
-    for (int b2 = 0; b2 < 3; ++b2) {
-      int row = cy + b2 - 1;
-      if (L.periodic_y) row = wrap_i(row, L.ny);
-      else if (row < 0 || row >= L.ny) continue;
-      const double wy = p.wy[b2 * nm + gm];
-      for (int a = 0; a < 3; ++a) {
-        const int col = wrap_i(cx + a - 1, L.nx);
-        const double w = p.wx[a * nm + gm] * wy;
-        const long long node = (long long)row * L.nx + col;
-        ux += double(U[node]) * w;
-        uy += double(U[N + node]) * w;
-      }
-    }
-    if (first) {
-      xn = X + ux;
-      yn = Y + uy;
-    } else {
-      xn = (2.0 / 3.0) * (2.0 * X - 0.5 * p.xm[gm] + ux);
-      yn = (2.0 / 3.0) * (2.0 * Y - 0.5 * p.ym[gm] + uy);
-    }
+    advance_rbc(p, L, gm, X, Y, first, xn, yn);
   } else {
     xn = p.xn[gm];
     yn = p.yn[gm];
@@ -875,14 +933,6 @@ __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
     marker_stencil(p, L, gm, xn, yn);
     ncx = p.cx[gm];
     ncy = p.cy[gm];
-  }
-  if (gm0 == 0) {
-    // the fused kernel of this step has read the force maximum and the body
-    // kernel has passed its bond flags: reset both for the next step
-    for (int i = 0; i < p.ninst; ++i) {
-      p.fmax_bits[i] = 0ull;
-      p.bond_flag[i] = 0;
-    }
   }
   // join the bins the next step's fused kernel reads (all lanes take part
   // in the wave-aggregated registration)
@@ -905,10 +955,20 @@ void launch_stencil(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
-  const int cache_nodes = kBodyCacheBytes / (3 * (int)sizeof(T));
-  hipLaunchKernelGGL(k_body<T>, dim3(p.ninst + p.nbody_total), dim3(kBodyThreads), kBodyCacheBytes, s,
-                     p, cache_nodes);
+void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, bool advance_first) {
+  const int cache_nodes = a.body_cache_bytes / (3 * (int)sizeof(T));
+  const dim3 grid(p.ninst + p.nbody_total), block(kBodyThreads);
+  const unsigned lds = (unsigned)a.body_cache_bytes;
+#define LBIB_BODY(TXv, TYv)                                                                        \
+  do {                                                                                          \
+    if (advance_first) hipLaunchKernelGGL((k_body<T, TXv, TYv, true>), grid, block, lds, s, p, cache_nodes); \
+    else hipLaunchKernelGGL((k_body<T, TXv, TYv, false>), grid, block, lds, s, p, cache_nodes);    \
+  } while (0)
+  if (a.tile_x == 64 && a.tile_y == 4) LBIB_BODY(64, 4);
+  else if (a.tile_x == 128 && a.tile_y == 2) LBIB_BODY(128, 2);
+  else if (a.tile_x == 32 && a.tile_y == 8) LBIB_BODY(32, 8);
+  else LBIB_BODY(256, 1);
+#undef LBIB_BODY
 }
 
 template <typename T>
@@ -918,8 +978,8 @@ void launch_advance(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
 }
 #undef LBIB_TILE_DISPATCH
 
-template void launch_lagrangian<float>(const Ptrs<float>&, const StepArgs&, hipStream_t);
-template void launch_lagrangian<double>(const Ptrs<double>&, const StepArgs&, hipStream_t);
+template void launch_lagrangian<float>(const Ptrs<float>&, const StepArgs&, hipStream_t, bool);
+template void launch_lagrangian<double>(const Ptrs<double>&, const StepArgs&, hipStream_t, bool);
 template void launch_advance<float>(const Ptrs<float>&, const StepArgs&, hipStream_t);
 template void launch_advance<double>(const Ptrs<double>&, const StepArgs&, hipStream_t);
 template void launch_stencil<float>(const Ptrs<float>&, const StepArgs&, hipStream_t);

@@ -91,8 +91,13 @@ struct Ptrs {
   int *bin_cur, *bin_next;   // [tile * bin_cap + k] = marker id
   int* touched;              // per tile: IB force applied in the last step
   int* overflow;             // registrations dropped because a bin was full
+  // per-step slots (two sets used alternately, like the population buffers)
   unsigned long long* fmax_bits;  // per instance: bit pattern of max |F| this step
   int* bond_flag;            // per instance: bond update of this step done
+  long long* step_slot;      // per instance: step number of this step
+  unsigned long long* fmax_next;  // the other slots: cleared during this step
+  int* bond_flag_next;
+  long long* step_prev;      // step number of the previous step
   int* spin_timeouts;        // waits for a bond flag that hit their bound
   int bin_cap;
   int* tile_inst;
@@ -174,6 +179,7 @@ struct StepArgs {
   int tile_x, tile_y;
   int ntiles_total;
   int max_inst_tiles;   // largest tile count of any instance
+  int body_cache_bytes; // LDS cache of rho*, u* per particle workgroup
 };
 
 template <typename T>
@@ -189,7 +195,7 @@ template <typename T>
 void launch_init_pop(const Ptrs<T>& p, const double* rho, const double* ux, const double* uy,
                      long long node_base, long long n, long long nodes_total, hipStream_t s);
 template <typename T>
-void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
+void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, bool advance_first);
 template <typename T>
 void launch_advance(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
 template <typename T>

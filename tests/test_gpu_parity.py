@@ -122,12 +122,13 @@ def test_bodies_fp64_match_oracle_to_roundoff(name, kw):
 
 def _large_and_seam_cases():
     """Bodies beyond the LDS scratch (> 512 vertices), a particle whose
-    stencil box exceeds the LDS cache, and bodies straddling the periodic
-    seam of a 129-wide lattice whose last 64-wide tile is one column wide."""
+    stencil box (about 100 x 100 nodes) exceeds the largest LDS cache, and
+    bodies straddling the periodic seam of a 129-wide lattice whose last
+    64-wide tile is one column wide."""
     out = []
     nx, ny = 260, 130
     rbc = geometry.place(geometry.rbc_contour(40.0, 600), 0.2, [70.0, 62.0])
-    big = geometry.place(geometry.circle(22.0, 140), 0.0, [180.0, 60.0])
+    big = geometry.place(geometry.circle(45.0, 280), 0.0, [190.0, 64.0])
     g = configs.poiseuille_force(0.02, ny, 1.0)
     rho0, u0 = configs.poiseuille_init(nx, ny, g, 1.0)
     out.append(("large", configs.Workload(

@@ -237,6 +237,7 @@ def batched_vs_plain(pkg, torch, n_inst, steps):
     tuned = autotune(ws, "f32", device="cuda:0", steps=100, warmup=20)
     tile = tuple(tuned["tile"])
     b = pkg.Batch(ws, dtype="f32", tile=tile, device="cuda:0", graph_steps=tuned["graph_steps"])
+    b.set_step_mode(tuned["step_mode"])
     b.step(max(20, tuned["graph_steps"]))
     ms_b = _timed(torch, b, steps)
     d = b.diagnostics()
@@ -252,13 +253,15 @@ def batched_vs_plain(pkg, torch, n_inst, steps):
     mb = nodes * steps / (ms_b * 1e-3) / 1e6
     mp = nodes * steps / (ms_p * 1e-3) / 1e6
     print(f"bench: batched {mb:.0f} MLUPS (tile {tile[0]}x{tile[1]}, graphs of "
-          f"{tuned['graph_steps']}), plain sequential {mp:.0f} MLUPS", file=sys.stderr, flush=True)
+          f"{tuned['graph_steps']}, step mode {tuned['step_mode']}), plain sequential {mp:.0f} MLUPS",
+          file=sys.stderr, flush=True)
     return {"workload": f"sweep-{len(ws)}-instances", "instances": len(ws), "nodes": nodes,
             "steps": steps, "batched_mlups": round(mb, 1), "plain_mlups": round(mp, 1),
             "speedup": round(mb / mp, 3), "tile": f"{tile[0]}x{tile[1]}",
-            "graph_steps": tuned["graph_steps"],
+            "graph_steps": tuned["graph_steps"], "step_mode": tuned["step_mode"],
             "candidates": [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "graph_steps": c["graph_steps"],
-                            "mlups": round(c["mlups"], 1)} for c in tuned["candidates"]]}
+                            "step_mode": c["step_mode"], "mlups": round(c["mlups"], 1)}
+                           for c in tuned["candidates"]]}
 
 
 def adjoint_window(pkg, torch, steps, ckpt):

@@ -294,6 +294,20 @@ lbib_status lbib_adjoint_backward(lbib_ctx* ctx, double dJ, double* grad);
  * the last adjoint forward window. */
 lbib_status lbib_set_body_params(lbib_ctx* ctx, int32_t body, double ks, double kb, double sigma);
 
+/* How steps are launched (the results are the same bit for bit):
+ *   1  three kernels per step: body forces and particle motion, fused
+ *      lattice step, marker advance;
+ *   2  merged: inside a run the body kernel first finishes the previous
+ *      step's marker advance for its own bodies (two kernels per step; used
+ *      only when every body has <= 512 vertices, else as 1);
+ *   3  overlapped: the lattice tiles without IB force run on a second stream
+ *      while the body kernel runs, the tiles with IB force after it;
+ *   0  automatic (default): 2 when every body has <= 512 vertices, else 1.
+ * Allowed in any phase; LBIB_EINVAL for other values.  lbib_get_step_mode
+ * returns the form in use (after finalize_setup) or the requested mode. */
+lbib_status lbib_set_step_mode(lbib_ctx* ctx, int32_t mode);
+lbib_status lbib_get_step_mode(const lbib_ctx* ctx, int32_t* mode);
+
 /* Completed step count. */
 lbib_status lbib_get_step(const lbib_ctx* ctx, int64_t* step);
 

@@ -38,7 +38,7 @@ EXPORTS = [
     "lbib_get_kernel_timing", "lbib_destroy", "lbib_batch_create", "lbib_batch_size",
     "lbib_batch_get_fields", "lbib_batch_get_markers", "lbib_batch_get_bonds",
     "lbib_adjoint_workspace_query", "lbib_adjoint_bind", "lbib_adjoint_forward",
-    "lbib_adjoint_backward", "lbib_set_body_params",
+    "lbib_adjoint_backward", "lbib_set_body_params", "lbib_set_step_mode", "lbib_get_step_mode",
 ]
 
 
@@ -135,6 +135,8 @@ def library() -> ctypes.CDLL:
         "lbib_adjoint_forward": (I32, [P, ctypes.POINTER(ctypes.c_double), ip]),
         "lbib_adjoint_backward": (I32, [P, D, dp]),
         "lbib_set_body_params": (I32, [P, I32, D, D, D]),
+        "lbib_set_step_mode": (I32, [P, I32]),
+        "lbib_get_step_mode": (I32, [P, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +198,16 @@ class _Ctx:
 
     def set_graph_steps(self, n: int):
         self.check(self.lib.lbib_set_graph_steps(self.h, int(n)))
+
+    def set_step_mode(self, mode: int):
+        """0 automatic, 1 three kernels, 2 merged advance, 3 overlapped tiles."""
+        self.check(self.lib.lbib_set_step_mode(self.h, int(mode)))
+
+    @property
+    def step_mode(self) -> int:
+        m = ctypes.c_int32()
+        self.check(self.lib.lbib_get_step_mode(self.h, ctypes.byref(m)))
+        return m.value
 
     def time_lattice_kernel(self, reps: int = 20) -> float:
         """Mean duration (ms) of one fused lattice-kernel launch, HIP events."""

@@ -89,10 +89,13 @@ struct lbib_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> kevents;
   int bin_cap = 1024;         // marker registrations per tile and bin set
   int body_cache = 16 * 1024; // LDS bytes of a particle workgroup's rho*, u* cache
-  // steps inside a run finish the previous step's marker advance in the body
-  // kernel; only when every body is small enough that its workgroup covers
-  // its vertices in two rounds (else the separate advance kernel is faster)
-  bool merge_advance = true;
+  // how a step is launched (lbib_set_step_mode): 0 automatic, 1 three
+  // kernels, 2 merged advance, 3 overlapped lattice tiles
+  int step_mode = 0;
+  bool merge_advance = true;  // resolved from step_mode and the bodies
+  bool overlap = false;
+  hipStream_t aux = nullptr;  // second stream of the overlapped form
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // adjoint window (single-instance contexts): caller-owned workspace
   char* aws = nullptr;
   size_t aws_bytes = 0;
@@ -492,15 +495,48 @@ lbib_status upload_all(lbib_ctx* c) {
 // advance for its own bodies) and the fused lattice kernel, and the last
 // step ends with the marker advance of all markers.  Otherwise three kernels
 // each: Lagrangian, fused lattice, marker advance.
+// Step form of the context: three kernels (body, lattice, advance), the
+// merged form (the body kernel finishes the previous step's advance; only
+// when every body has <= 512 vertices, where one round of the workgroup
+// covers them), or the overlapped form (the lattice tiles without IB force
+// on a second stream while the body kernel runs).  Automatic: merged when
+// possible, else three kernels (measured faster than the overlapped form on
+// the 2000 x 200 and 6667 x 667 capillaries and the 64-instance sweep).
+void resolve_step_mode(lbib_ctx* c) {
+  bool small_bodies = true;
+  for (auto& I : c->inst)
+    for (auto& b : I.bodies)
+      if (b.d.nv > 512) small_bodies = false;
+  int m = c->step_mode;
+  if (m == 0) m = small_bodies ? 2 : 1;
+  c->merge_advance = m == 2 && small_bodies;
+  c->overlap = m == 3;
+}
+
 template <typename T>
 void enqueue_steps(lbib_ctx* c, long long n) {
   const StepArgs a = step_args(c);
+  if (c->overlap && !c->ktiming) {
+    for (long long k = 0; k < n; ++k) {
+      Ptrs<T> p = make_ptrs<T>(c);
+      (void)hipEventRecord(c->ev_fork, c->stream);
+      (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+      launch_lb_fused<T>(p, a, c->aux, 1 | (1 << 2));        // tiles without IB force
+      (void)hipEventRecord(c->ev_join, c->aux);
+      launch_lagrangian<T>(p, a, c->stream, false);
+      launch_lb_fused<T>(p, a, c->stream, 1 | (2 << 2));     // tiles with IB force
+      (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
+      launch_advance<T>(p, a, c->stream);
+      c->parity ^= 1;
+    }
+    return;
+  }
   for (long long k = 0; k < n; ++k) {
     Ptrs<T> p = make_ptrs<T>(c);
     launch_lagrangian<T>(p, a, c->stream, c->merge_advance && k > 0);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->ktiming && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-      launch_lb_fused<T>(p, a, c->stream, 1, e0, e1);
+      launch_lb_fused<T>(p, a, c->stream, 3, e0, e1);
       c->kevents.emplace_back(e0, e1);
     } else {
       launch_lb_fused<T>(p, a, c->stream);
@@ -1045,6 +1081,11 @@ lbib_status lbib_bind(lbib_ctx* c, void* ws, size_t bytes, void* stream) {
   c->ws = (char*)ws;
   c->ws_bytes = bytes;
   c->stream = (hipStream_t)stream;
+  if (!c->aux) {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
   c->phase = 1;
   return LBIB_OK;
 }
@@ -1053,13 +1094,28 @@ lbib_status lbib_finalize_setup(lbib_ctx* c) {
   if (!c) return fail(c, LBIB_EINVAL, "NULL context");
   if (c->phase != 1) return fail(c, LBIB_ESTATE, "bind a workspace before finalize_setup");
   c->body_cache = body_cache_bytes(c);
-  c->merge_advance = true;
-  for (auto& I : c->inst)
-    for (auto& b : I.bodies)
-      if (b.d.nv > 512) c->merge_advance = false;
+  resolve_step_mode(c);
   lbib_status s = c->dtype == LBIB_F64 ? upload_all<double>(c) : upload_all<float>(c);
   if (s != LBIB_OK) return s;
   c->phase = 2;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_step_mode(lbib_ctx* c, int32_t mode) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (mode < 0 || mode > 3) return fail(c, LBIB_EINVAL, "step mode must be 0..3");
+  c->step_mode = mode;
+  if (c->phase == 2) {
+    drop_graphs(c);
+    resolve_step_mode(c);
+  }
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_step_mode(const lbib_ctx* cc, int32_t* mode) {
+  lbib_ctx* c = const_cast<lbib_ctx*>(cc);
+  if (!c || !mode) return fail(c, LBIB_EINVAL, "NULL argument");
+  *mode = c->phase == 2 ? (c->overlap ? 3 : (c->merge_advance ? 2 : 1)) : c->step_mode;
   return LBIB_OK;
 }
 
@@ -1350,6 +1406,9 @@ lbib_status lbib_destroy(lbib_ctx* c) {
   if (!c) return LBIB_OK;
   drop_graphs(c);
   drop_adjoint_graphs(c);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   drop_kevents(c);
   delete c;
   return LBIB_OK;

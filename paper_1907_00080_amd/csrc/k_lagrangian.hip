@@ -885,6 +885,9 @@ __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_node
   __shared__ int s_tmp[kBodyThreads];
   __shared__ int s_nelig;
   extern __shared__ unsigned char s_dyn[];
+  // the other bin set (last read two steps ago) starts its next use empty
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < p.ntile_total; t += gridDim.x * blockDim.x)
+    p.cnt_next[t] = 0;
   if ((int)blockIdx.x < p.ninst) {
     bonds_impl(p, blockIdx.x, s_tmp, &s_nelig);
     return;

@@ -25,15 +25,20 @@ namespace lbib {
 
 constexpr int kCap = 256;  // lanes per workgroup = nodes per tile
 
-// consume = 0 (measurement launches): the marker bins are left in place and
-// the caller points U at a spare buffer, so the simulation state is untouched.
+// mode bits: 1 = record which tiles carried IB force (touched), 2 = clear the
+// bin counts this launch consumed; mode >> 2 selects tiles: 0 all, 1 only
+// those without registered markers, 2 only those with.  mode = 0
+// (measurement launches): the bins are left in place and the caller points
+// U at a spare buffer, so the simulation state is untouched.
 template <typename T, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int consume) {
+__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int mode) {
   static_assert(TX * TY == kCap, "one lane per LDS slot");
   const int g = blockIdx.x;
   const int per = (ntiles_total + 7) >> 3;
   const int tile = (g & 7) * per + (g >> 3);
   if (tile >= ntiles_total) return;
+  const int cls = mode >> 2;
+  if (cls != 0 && (cls == 1) == (p.cnt_cur[tile] > 0)) return;   // the other launch's tile
   const int inst = p.tile_inst[tile];
   const LatDev& L = p.lat[inst];
   const int nx = L.nx, ny = L.ny, ntx = L.ntx, nty = L.nty;
@@ -123,10 +128,10 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
       Fy = T(L.gy + (double)(long long)s_ay[lane] * isc);
     }
   }
-  if (consume && lane == 0) {
+  if (lane == 0) {
     // every lane has read the count: clear it for the next use of this set
-    if (Mreg > 0) p.cnt_cur[tile] = 0;
-    p.touched[tile] = Mreg > 0;
+    if ((mode & 2) && Mreg > 0) p.cnt_cur[tile] = 0;
+    if (mode & 1) p.touched[tile] = Mreg > 0;
   }
   if (!inside) return;
 
@@ -258,7 +263,7 @@ __global__ void k_diag2(const double* part, int nblk, double* out) {
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int consume,
+void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mode,
                      hipEvent_t ev0, hipEvent_t ev1) {
   const int per = (a.ntiles_total + 7) / 8;
   dim3 grid(8 * per), block(kCap);
@@ -266,16 +271,16 @@ void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int con
   // time is the kernel's execution time and not that of separate markers
   if (a.tile_x == 64 && a.tile_y == 4)
     hipExtLaunchKernelGGL((k_lb_fused<T, 64, 4>), grid, block, 0, s, ev0, ev1, 0, p,
-                          a.ntiles_total, consume);
+                          a.ntiles_total, mode);
   else if (a.tile_x == 128 && a.tile_y == 2)
     hipExtLaunchKernelGGL((k_lb_fused<T, 128, 2>), grid, block, 0, s, ev0, ev1, 0, p,
-                          a.ntiles_total, consume);
+                          a.ntiles_total, mode);
   else if (a.tile_x == 32 && a.tile_y == 8)
     hipExtLaunchKernelGGL((k_lb_fused<T, 32, 8>), grid, block, 0, s, ev0, ev1, 0, p,
-                          a.ntiles_total, consume);
+                          a.ntiles_total, mode);
   else
     hipExtLaunchKernelGGL((k_lb_fused<T, 256, 1>), grid, block, 0, s, ev0, ev1, 0, p,
-                          a.ntiles_total, consume);
+                          a.ntiles_total, mode);
 }
 
 template <typename T>

@@ -183,7 +183,7 @@ struct StepArgs {
 };
 
 template <typename T>
-void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int consume = 1,
+void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mode = 3,
                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_fields(const Ptrs<T>& p, const StepArgs& a, int inst, double* rho, double* ux,

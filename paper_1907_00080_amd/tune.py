@@ -1,10 +1,11 @@
-"""Tile-shape and graph-chunk autotuner for batched sweeps (host logic).
+"""Autotuner for batched sweeps: tile shape, step form, graph chunk (host logic).
 
 A batch advances many uneven capillary instances together (one launch per
 kernel per step for all of them).  Which tile shape of the fused lattice
-kernel and which number of steps per captured HIP graph run fastest depends
-on the instance mix and the device, so `autotune` times whole steps of the
-actual batch for every candidate and keeps the fastest.  Results are cached
+kernel, which step form (three kernels, merged marker advance, overlapped
+lattice tiles) and which number of steps per captured HIP graph run fastest
+depends on the instance mix and the device, so `autotune` times whole steps
+of the actual batch for every candidate and keeps the fastest.  Results are cached
 in a JSON file keyed by the batch signature (lattice shapes, body and marker
 counts, dtype) and the device name, so a sweep pays for tuning once.
 
@@ -20,6 +21,7 @@ from typing import Callable, Iterable, Optional, Sequence, Tuple
 
 TILES: Tuple[Tuple[int, int], ...] = ((64, 4), (128, 2), (32, 8), (256, 1))
 GRAPH_STEPS: Tuple[int, ...] = (10, 100)
+STEP_MODES: Tuple[int, ...] = (1, 2, 3)   # three kernels, merged advance, overlapped tiles
 
 
 def signature(workloads: Sequence, dtype: str) -> str:
@@ -80,14 +82,15 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
              device=None, steps: int = 100, warmup: int = 20,
              tiles: Sequence[Tuple[int, int]] = TILES,
              graph_steps: Sequence[int] = GRAPH_STEPS,
+             step_modes: Sequence[int] = STEP_MODES,
              measure: Optional[Callable] = None) -> dict:
-    """Pick the tile shape and graph chunk for a batch of `workloads`.
+    """Pick the tile shape, step form and graph chunk for a batch of `workloads`.
 
-    Returns {"tile": [tx, ty], "graph_steps": g, "ms_per_step": t, "mlups": m,
-    "candidates": [...], "device": name, "cached": bool}.  `steps` is rounded
-    up to a multiple of every graph chunk.  `measure(tile, g)` replaces the
-    GPU timing (returns ms per step); it exists for tests of the selection
-    and caching logic.
+    Returns {"tile": [tx, ty], "graph_steps": g, "step_mode": m, "ms_per_step": t,
+    "mlups": ..., "candidates": [...], "device": name, "cached": bool}.
+    `steps` is rounded up to a multiple of every graph chunk.
+    `measure(tile, g, mode)` replaces the GPU timing (returns ms per step);
+    it exists for tests of the selection and caching logic.
     """
     nodes = sum(int(w.nx) * int(w.ny) for w in workloads)
     dev_name = _device_name(device) if measure is None else "measure-callback"
@@ -104,22 +107,26 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
     results = []
     for tile in tiles:
         if measure is not None:
-            for g in graph_steps:
-                ms = float(measure(tuple(tile), int(g)))
-                results.append(_record(tile, g, ms, nodes))
+            for mode in step_modes:
+                for g in graph_steps:
+                    ms = float(measure(tuple(tile), int(g), int(mode)))
+                    results.append(_record(tile, g, mode, ms, nodes))
             continue
         from . import Batch
         b = Batch(workloads, dtype=dtype, tile=tuple(tile), device=device, graph_steps=0)
         try:
-            for g in graph_steps:
-                b.set_graph_steps(int(g))
-                b.step(max(int(warmup), int(g)))
-                ms = _time_steps(b, steps) / steps
-                results.append(_record(tile, g, ms, nodes))
+            for mode in step_modes:
+                b.set_step_mode(int(mode))
+                for g in graph_steps:
+                    b.set_graph_steps(int(g))
+                    b.step(max(int(warmup), int(g)))
+                    ms = _time_steps(b, steps) / steps
+                    results.append(_record(tile, g, b.step_mode, ms, nodes))
         finally:
             b.close()
     best = choose(results)
     rec = {"tile": list(best["tile"]), "graph_steps": best["graph_steps"],
+           "step_mode": best["step_mode"],
            "ms_per_step": best["ms_per_step"], "mlups": best["mlups"],
            "candidates": results, "device": dev_name, "nodes": nodes,
            "instances": len(workloads), "dtype": str(dtype)}
@@ -130,8 +137,9 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
     return rec
 
 
-def _record(tile, g, ms, nodes) -> dict:
-    return {"tile": [int(tile[0]), int(tile[1])], "graph_steps": int(g), "ms_per_step": ms,
+def _record(tile, g, mode, ms, nodes) -> dict:
+    return {"tile": [int(tile[0]), int(tile[1])], "graph_steps": int(g), "step_mode": int(mode),
+            "ms_per_step": ms,
             "mlups": nodes / (ms * 1e-3) / 1e6 if ms > 0 else float("inf")}
 
 

@@ -155,3 +155,17 @@ def test_adjoint_calls_need_a_running_single_context():
     assert lib.lbib_adjoint_backward(h, 1.0, g) == 2
     assert lib.lbib_set_body_params(h, 0, 1.0, 0.0, 0.0) == 2
     lib.lbib_destroy(h)
+
+
+def test_step_mode_validation():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    assert lib.lbib_set_step_mode(h, 4) == 1
+    assert lib.lbib_set_step_mode(h, -1) == 1
+    for m in (0, 1, 2, 3):
+        assert lib.lbib_set_step_mode(h, m) == 0
+        got = ctypes.c_int32()
+        assert lib.lbib_get_step_mode(h, ctypes.byref(got)) == 0
+        assert got.value == m
+    lib.lbib_destroy(h)

@@ -277,6 +277,33 @@ def test_capillary_2000x200_full_size_steps_match_oracle():
     assert np.array_equal(sim.bonds(), ref.l2r)
 
 
+# ------------------------------------------------------------- step forms
+@pytest.mark.parametrize("graph", [0, 10])
+@pytest.mark.parametrize("case", ["adhesive", "seam"])
+def test_step_modes_bitwise_identical(case, graph):
+    """Three kernels per step, the merged advance and the overlapped tiles
+    give the same bits (fields, markers, bonds), eager and graph-captured."""
+    announce(f"step modes {case} graph {graph}")
+    if case == "adhesive":
+        wl, tile = adhesive_fixture(), (64, 4)
+    else:
+        wl, tile = _large_and_seam_cases()[1][1], (256, 1)
+    out = []
+    for mode in (1, 2, 3):
+        sim = pkg.Sim(wl, dtype="f32", tile=tile, graph_steps=graph)
+        sim.set_step_mode(mode)
+        assert sim.step_mode == mode
+        sim.step(41)
+        out.append((sim.fields(), sim.all_markers(), sim.bonds(), sim.diagnostics()))
+        sim.close()
+    for f, m, b, d in out[1:]:
+        for x, y in zip(f, out[0][0]):
+            assert np.array_equal(x, y)
+        assert np.array_equal(m, out[0][1])
+        assert np.array_equal(b, out[0][2])
+        assert d["bin_overflow"] == 0 and d["sync_timeouts"] == 0
+
+
 # ------------------------------------------------------------- determinism
 def test_bitwise_determinism_graph_and_resume():
     announce("determinism")

@@ -33,22 +33,23 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
             ((128, 2), 100): 1.5, ((32, 8), 10): 4.0, ((32, 8), 100): 1.7,
             ((256, 1), 10): 2.2, ((256, 1), 100): 2.0}
 
-    def measure(tile, g):
-        calls.append((tile, g))
-        return cost[(tile, g)]
+    def measure(tile, g, mode):
+        calls.append((tile, g, mode))
+        return cost[(tile, g)] + (0.0 if mode == 2 else 0.25 * mode)
 
     path = str(tmp_path / "sub" / "tune.json")
     ws = _ws()
     rec = tune.autotune(ws, "f32", cache=path, measure=measure)
     assert rec["tile"] == [128, 2] and rec["graph_steps"] == 100 and not rec["cached"]
-    assert len(calls) == 8
+    assert rec["step_mode"] == 2
+    assert len(calls) == 24
     nodes = sum(w.nodes for w in ws)
     assert abs(rec["mlups"] - nodes / 1.5e-3 / 1e6) < 1e-9
     with open(path) as f:
         data = json.load(f)
     assert len(data) == 1
     again = tune.autotune(ws, "f32", cache=path, measure=measure)
-    assert again["cached"] and again["tile"] == [128, 2] and len(calls) == 8
+    assert again["cached"] and again["tile"] == [128, 2] and len(calls) == 24
     # another batch adds a second record and keeps the first
     tune.autotune(ws[:1], "f32", cache=path, measure=measure)
     with open(path) as f:
@@ -57,6 +58,6 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
 
 def test_autotune_without_cache_measures_every_time():
     n = []
-    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g: n.append(1) or 1.0)
-    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g: n.append(1) or 1.0)
-    assert len(n) == 16
+    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m: n.append(1) or 1.0)
+    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m: n.append(1) or 1.0)
+    assert len(n) == 48

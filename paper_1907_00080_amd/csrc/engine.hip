@@ -103,9 +103,10 @@ struct lbib_ctx {
   int adjk = 0;               // checkpoint spacing
   bool adj_ready = false;     // a forward window has run since the last change
   std::vector<long long> ck_step;   // step of each checkpoint (last: end of window)
-  // captured recompute + reverse sweep of a segment, keyed by
-  // (steps, start parity, segment starts at step 0)
-  std::map<std::tuple<long long, int, int>, hipGraphExec_t> adj_graphs;
+  // captured recompute of a segment, keyed by (steps, start parity, store),
+  // and reverse sweep, keyed by (steps, store, segment starts at step 0)
+  std::map<std::tuple<long long, int, int>, hipGraphExec_t> adj_graphs, adj_rgraphs;
+  hipEvent_t ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   std::vector<double> adj_y;        // marker ordinates at the end of the window
 };
 
@@ -556,7 +557,9 @@ void drop_kevents(lbib_ctx* c) {
 
 void drop_adjoint_graphs(lbib_ctx* c) {
   for (auto& kv : c->adj_graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->adj_rgraphs) (void)hipGraphExecDestroy(kv.second);
   c->adj_graphs.clear();
+  c->adj_rgraphs.clear();
 }
 
 void drop_graphs(lbib_ctx* c) {
@@ -692,7 +695,7 @@ struct AdjLayout {
   int nseg, nck;
   size_t ck;
   size_t rec_bytes, r_h, r_x, r_y, r_fx, r_fy, r_xn, r_yn, r_u;
-  size_t seg;
+  size_t seg[2];   // two segment stores: recompute into one while the other is reversed
   size_t ha, fph, FE, FEh, mom, Uh, Rh, xa, ya, xma, yma;
   size_t mk[13];
   size_t grad;
@@ -725,7 +728,8 @@ AdjLayout adj_layout(const lbib_ctx* c, long long K, int k) {
   A.r_xn = rt(8 * nm); A.r_yn = rt(8 * nm);
   A.r_u = rt(es * 2 * N);
   A.rec_bytes = rb;
-  A.seg = take(rb * (size_t)k);
+  A.seg[0] = take(rb * (size_t)k);
+  A.seg[1] = take(rb * (size_t)k);
   A.ha = take(8 * 9 * N); A.fph = take(8 * 9 * N);
   A.FE = take(16 * N); A.FEh = take(16 * N); A.mom = take(24 * N);
   A.Uh = take(16 * N); A.Rh = take(24 * N);
@@ -845,41 +849,74 @@ lbib_status adjoint_forward_impl(lbib_ctx* c, double* J) {
   return LBIB_OK;
 }
 
-// Recompute n steps from the restored state, keeping the forward data of
-// each step, then run the reverse sweep over them (captured as one graph).
+// Recompute n steps from the restored state into segment store `buf`,
+// keeping the forward data of each step (one copy launch per step, after its
+// lattice kernel: the populations h^n are still in the read buffer, positions
+// X^n, forces and particle positions X^{n+1} are set, u^n is written).
 template <typename T>
-void enqueue_adjoint_segment(lbib_ctx* c, const AdjLayout& A, AdjPtrs a, long long n, bool first) {
+void enqueue_recompute(lbib_ctx* c, const AdjLayout& A, int buf, long long n) {
   const long long N = c->nodes;
   const size_t es = elem_size(c->dtype), nmb = 8 * (size_t)c->nm;
+  const StepArgs sa = step_args(c);
   for (long long s = 0; s < n; ++s) {
-    char* rec = c->aws + A.seg + (size_t)s * A.rec_bytes;
+    char* rec = c->aws + A.seg[buf] + (size_t)s * A.rec_bytes;
     Ptrs<T> p = make_ptrs<T>(c);
-    CopyList pre{};
-    pre.n = 3;
-    pre.src[0] = (const char*)p.A; pre.dst[0] = rec + A.r_h; pre.bytes[0] = es * 9 * N;
-    pre.src[1] = (const char*)p.x; pre.dst[1] = rec + A.r_x; pre.bytes[1] = nmb;
-    pre.src[2] = (const char*)p.y; pre.dst[2] = rec + A.r_y; pre.bytes[2] = nmb;
-    launch_copies(pre, c->stream);
-    enqueue_steps<T>(c, 1);
-    CopyList post{};
-    post.n = 5;
-    post.src[0] = (const char*)p.fx; post.dst[0] = rec + A.r_fx; post.bytes[0] = nmb;
-    post.src[1] = (const char*)p.fy; post.dst[1] = rec + A.r_fy; post.bytes[1] = nmb;
-    post.src[2] = (const char*)p.xn; post.dst[2] = rec + A.r_xn; post.bytes[2] = nmb;
-    post.src[3] = (const char*)p.yn; post.dst[3] = rec + A.r_yn; post.bytes[3] = nmb;
-    post.src[4] = (const char*)p.U; post.dst[4] = rec + A.r_u; post.bytes[4] = es * 2 * N;
-    launch_copies(post, c->stream);
+    launch_lagrangian<T>(p, sa, c->stream, c->merge_advance && s > 0);
+    launch_lb_fused<T>(p, sa, c->stream);
+    CopyList cl{};
+    cl.n = 8;
+    const char* src[8] = {(const char*)p.A, (const char*)p.x, (const char*)p.y, (const char*)p.fx,
+                          (const char*)p.fy, (const char*)p.xn, (const char*)p.yn, (const char*)p.U};
+    const size_t off[8] = {A.r_h, A.r_x, A.r_y, A.r_fx, A.r_fy, A.r_xn, A.r_yn, A.r_u};
+    const size_t by[8] = {es * 9 * N, nmb, nmb, nmb, nmb, nmb, nmb, es * 2 * N};
+    for (int k = 0; k < 8; ++k) {
+      cl.src[k] = src[k];
+      cl.dst[k] = rec + off[k];
+      cl.bytes[k] = by[k];
+    }
+    launch_copies(cl, c->stream);
+    if (!c->merge_advance || s == n - 1) launch_advance<T>(p, sa, c->stream);
+    c->parity ^= 1;
   }
-  for (long long s = n - 1; s >= 0; --s) {
-    const char* rec = c->aws + A.seg + (size_t)s * A.rec_bytes;
-    a.h = rec + A.r_h;
-    a.x = (const double*)(rec + A.r_x); a.y = (const double*)(rec + A.r_y);
-    a.fx = (const double*)(rec + A.r_fx); a.fy = (const double*)(rec + A.r_fy);
-    a.xn = (const double*)(rec + A.r_xn); a.yn = (const double*)(rec + A.r_yn);
-    a.u = rec + A.r_u;
-    a.first = first && s == 0;
-    launch_adjoint_step<T>(make_ptrs<T>(c), a, N, c->stream);
+}
+
+// Reverse sweep over the n steps held in segment store `buf`, on stream s.
+template <typename T>
+void enqueue_reverse(lbib_ctx* c, const AdjLayout& A, AdjPtrs a, int buf, long long n, bool first,
+                     hipStream_t s) {
+  std::vector<AdjPtrs> steps((size_t)n, a);
+  for (long long k = 0; k < n; ++k) {
+    const char* rec = c->aws + A.seg[buf] + (size_t)k * A.rec_bytes;
+    AdjPtrs& q = steps[(size_t)k];
+    q.h = rec + A.r_h;
+    q.x = (const double*)(rec + A.r_x); q.y = (const double*)(rec + A.r_y);
+    q.fx = (const double*)(rec + A.r_fx); q.fy = (const double*)(rec + A.r_fy);
+    q.xn = (const double*)(rec + A.r_xn); q.yn = (const double*)(rec + A.r_yn);
+    q.u = rec + A.r_u;
+    q.first = first && k == 0;
   }
+  launch_adjoint_segment<T>(make_ptrs<T>(c), steps.data(), (int)n, c->nodes, s);
+}
+
+// Capture `enqueue` on stream s once per key; return the executable graph.
+template <typename F>
+lbib_status cached_graph(lbib_ctx* c, std::map<std::tuple<long long, int, int>, hipGraphExec_t>& cache,
+                         std::tuple<long long, int, int> key, hipStream_t s, F enqueue,
+                         hipGraphExec_t* out) {
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    hipGraph_t graph;
+    HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue();
+    HIPCHK(c, hipStreamEndCapture(s, &graph));
+    hipGraphExec_t ex_;
+    hipError_t e = hipGraphInstantiate(&ex_, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, LBIB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    it = cache.emplace(key, ex_).first;
+  }
+  *out = it->second;
+  return LBIB_OK;
 }
 
 template <typename T>
@@ -906,34 +943,38 @@ lbib_status adjoint_backward_impl(lbib_ctx* c, double dJ, double* grad) {
   launch_fill(a.FE, 2 * N, 0.0, c->stream);
   launch_fill(a.Uh, 2 * N, 0.0, c->stream);
   launch_fill(a.Rh, 3 * N, 0.0, c->stream);
+  // segments from last to first; the recompute of segment j - 1 (main
+  // stream) overlaps the reverse sweep of segment j (second stream); stores
+  // alternate, and a store is refilled only after its previous reverse sweep
   for (int j = A.nseg - 1; j >= 0; --j) {
+    const int buf = j & 1;
+    if (j + 2 <= A.nseg - 1) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_rev[buf], 0));
     adj_checkpoint(c, A, j, false);
     c->step = c->ck_step[j];
-    // marker bins of the restored positions (eager, outside the graph)
+    // marker bins of the restored positions (eager, outside the graphs)
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.cnt[c->parity], 0, 4 * (size_t)c->ntiles, c->stream));
     launch_stencil<T>(make_ptrs<T>(c), step_args(c), c->stream);
     c->stencil_dirty = false;
     const long long n = std::min<long long>(c->adjk, c->adjK - (long long)j * c->adjk);
     const int par = c->parity, first = c->ck_step[j] == 0 ? 1 : 0;
-    const auto key = std::make_tuple(n, par, first);
-    auto it = c->adj_graphs.find(key);
-    if (it == c->adj_graphs.end()) {
-      hipGraph_t graph;
-      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-      enqueue_adjoint_segment<T>(c, A, a, n, first != 0);
-      HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
-      c->parity = par;   // capture ran nothing
-      hipGraphExec_t ex_;
-      hipError_t e = hipGraphInstantiate(&ex_, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess)
-        return fail(c, LBIB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      it = c->adj_graphs.emplace(key, ex_).first;
-    }
-    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    hipGraphExec_t gr, gv;
+    st = cached_graph(c, c->adj_graphs, std::make_tuple(n, par, buf), c->stream,
+                      [&] { enqueue_recompute<T>(c, A, buf, n); }, &gr);
+    if (st != LBIB_OK) return st;
+    c->parity = par;   // capture ran nothing
+    st = cached_graph(c, c->adj_rgraphs, std::make_tuple(n, buf, first), c->aux,
+                      [&] { enqueue_reverse<T>(c, A, a, buf, n, first != 0, c->aux); }, &gv);
+    if (st != LBIB_OK) return st;
+    HIPCHK(c, hipGraphLaunch(gr, c->stream));
     c->parity = par ^ (int)(n & 1);
     c->step += n;
+    HIPCHK(c, hipEventRecord(c->ev_rec[buf], c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_rec[buf], 0));
+    HIPCHK(c, hipGraphLaunch(gv, c->aux));
+    HIPCHK(c, hipEventRecord(c->ev_rev[buf], c->aux));
   }
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_rev[0], 0));
+  if (A.nseg > 1) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_rev[1], 0));
   HIPCHK(c, hipGetLastError());
   // leave the context at the end of the window
   adj_checkpoint(c, A, A.nseg, false);
@@ -1107,6 +1148,7 @@ lbib_status lbib_set_step_mode(lbib_ctx* c, int32_t mode) {
   c->step_mode = mode;
   if (c->phase == 2) {
     drop_graphs(c);
+    drop_adjoint_graphs(c);
     resolve_step_mode(c);
   }
   return LBIB_OK;
@@ -1406,6 +1448,10 @@ lbib_status lbib_destroy(lbib_ctx* c) {
   if (!c) return LBIB_OK;
   drop_graphs(c);
   drop_adjoint_graphs(c);
+  for (int k = 0; k < 2; ++k) {
+    if (c->ev_rec[k]) (void)hipEventDestroy(c->ev_rec[k]);
+    if (c->ev_rev[k]) (void)hipEventDestroy(c->ev_rev[k]);
+  }
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -1436,6 +1482,10 @@ lbib_status lbib_adjoint_bind(lbib_ctx* c, void* ws, size_t bytes, int64_t nstep
   if (bytes < adj_layout(c, nsteps, ckpt_every).total)
     return fail(c, LBIB_ENOSPACE, "adjoint workspace smaller than lbib_adjoint_workspace_query");
   drop_adjoint_graphs(c);   // they hold pointers into the previous workspace
+  for (int k = 0; k < 2; ++k) {
+    if (!c->ev_rec[k]) HIPCHK(c, hipEventCreateWithFlags(&c->ev_rec[k], hipEventDisableTiming));
+    if (!c->ev_rev[k]) HIPCHK(c, hipEventCreateWithFlags(&c->ev_rev[k], hipEventDisableTiming));
+  }
   c->aws = (char*)ws;
   c->aws_bytes = bytes;
   c->adjK = nsteps;

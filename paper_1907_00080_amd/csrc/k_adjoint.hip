@@ -18,7 +18,8 @@
 // the segment store of the checkpointed recomputation.
 //
 // Scatter-form adjoints (transpose of an interpolation, of a probe
-// evaluation) use float64 atomics into dense adjoint fields.
+// evaluation) use the hardware float64 atomic add into dense adjoint fields
+// (the workspace is ordinary coarse-grained device memory, which it needs).
 #include "adj_math.h"
 #include "lbib_dev.h"
 
@@ -88,8 +89,7 @@ __device__ inline void block_sum4(double v[4], double (*s)[kAdjThreads / 64]) {
 // update, whose interpolation of the stored velocity u^n scatters into the
 // adjoint of u.
 template <typename T>
-__global__ void ka_marker(Ptrs<T> p, AdjPtrs a) {
-  const int gm = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm) {
   if (gm >= p.nm_total) return;
   const LatDev& L = p.lat[0];
   const long long N = (long long)L.nx * L.ny;
@@ -108,11 +108,11 @@ __global__ void ka_marker(Ptrs<T> p, AdjPtrs a) {
     for (int c = 0; c < 3; ++c) {
       const long long node = (long long)s.row[b] * L.nx + s.col[c];
       const double w = s.wx[c] * s.wy[b];
-      atomicAdd(&a.FE[node], fx * w);
-      atomicAdd(&a.FE[N + node], fy * w);
+      unsafeAtomicAdd(&a.FE[node], fx * w);
+      unsafeAtomicAdd(&a.FE[N + node], fy * w);
       if (rbc) {
-        atomicAdd(&a.Uh[node], ux * w);
-        atomicAdd(&a.Uh[N + node], uy * w);
+        unsafeAtomicAdd(&a.Uh[node], ux * w);
+        unsafeAtomicAdd(&a.Uh[N + node], uy * w);
         const double uu = ux * double(U[node]) + uy * double(U[N + node]);
         gx -= uu * s.dwx[c] * s.wy[b];
         gy -= uu * s.wx[c] * s.dwy[b];
@@ -246,8 +246,8 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
           const double us = mom[N + node], vs = mom[2 * N + node];
           U0x += us * w;
           U0y += vs * w;
-          atomicAdd(&a.Rh[N + node], xa * w);
-          atomicAdd(&a.Rh[2 * N + node], ya * w);
+          unsafeAtomicAdd(&a.Rh[N + node], xa * w);
+          unsafeAtomicAdd(&a.Rh[2 * N + node], ya * w);
           const double uu = xa * us + ya * vs;
           g2x -= uu * s.dwx[c] * s.wy[bb];
           g2y -= uu * s.wx[c] * s.dwy[bb];
@@ -344,9 +344,9 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
           const double wx = s.wx[c], wy = s.wy[bb], dwx = s.dwx[c], dwy = s.dwy[bb];
           const double ddwx = s.ddwx[c], ddwy = s.ddwy[bb];
           const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
-          atomicAdd(&a.Rh[node], rqh * wx * wy);
-          atomicAdd(&a.Rh[N + node], -gh[0] * dwx * wy - gh[1] * wx * dwy);
-          atomicAdd(&a.Rh[2 * N + node], -gh[2] * dwx * wy - gh[3] * wx * dwy);
+          unsafeAtomicAdd(&a.Rh[node], rqh * wx * wy);
+          unsafeAtomicAdd(&a.Rh[N + node], -gh[0] * dwx * wy - gh[1] * wx * dwy);
+          unsafeAtomicAdd(&a.Rh[2 * N + node], -gh[2] * dwx * wy - gh[3] * wx * dwy);
           qhx += -rqh * r0 * dwx * wy + gh[0] * us * ddwx * wy + gh[1] * us * dwx * dwy +
                  gh[2] * vs * ddwx * wy + gh[3] * vs * dwx * dwy;
           qhy += -rqh * r0 * wx * dwy + gh[0] * us * dwx * dwy + gh[1] * us * wx * ddwy +
@@ -410,10 +410,9 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
 // bounced at a wall, f^_{opp(j)}(y).  f^ includes the pre-forcing moment
 // terms of rho*, u*.
 template <typename T>
-__global__ void ka_stream(Ptrs<T> p, AdjPtrs a) {
+__device__ inline void stream_adjoint(const Ptrs<T>& p, const AdjPtrs& a, long long node) {
   const LatDev& L = p.lat[0];
   const long long N = (long long)L.nx * L.ny;
-  const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= N) return;
   const int x = (int)(node % L.nx), y = (int)(node / L.nx);
 #pragma unroll
@@ -433,6 +432,25 @@ __global__ void ka_stream(Ptrs<T> p, AdjPtrs a) {
     const double r = rh - (uh * us + vh * vs) / rho;
     a.ha[j * N + node] = a.fph[i * N + src] + r + (ex(i) * uh + ey(i) * vh) / rho;
   }
+}
+
+template <typename T>
+__global__ void ka_marker(Ptrs<T> p, AdjPtrs a) {
+  marker_adjoint(p, a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <typename T>
+__global__ void ka_stream(Ptrs<T> p, AdjPtrs a) {
+  stream_adjoint(p, a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Reverse streaming of step s (workgroups [0, gn)) together with the marker
+// kernel of step s - 1 (the rest): independent data, one launch.
+template <typename T>
+__global__ void ka_stream_marker(Ptrs<T> p, AdjPtrs as, AdjPtrs am, int gn) {
+  const int b = blockIdx.x;
+  if (b < gn) stream_adjoint(p, as, (long long)b * blockDim.x + threadIdx.x);
+  else marker_adjoint(p, am, (b - gn) * (int)blockDim.x + (int)threadIdx.x);
 }
 
 // --------------------------------------------------------------- copies
@@ -456,17 +474,25 @@ __global__ void ka_fill(double* out, long long n, double v) {
 }
 
 // ------------------------------------------------------------------ launchers
+// Reverse sweep over the steps of a segment, last to first: the marker
+// kernel of step s runs inside the previous launch (the reverse streaming of
+// step s + 1), so a step costs three launches.
 template <typename T>
-void launch_adjoint_step(const Ptrs<T>& p, const AdjPtrs& a, long long N, hipStream_t s) {
+void launch_adjoint_segment(const Ptrs<T>& p, const AdjPtrs* a, int n, long long N, hipStream_t s) {
   const int nm = p.nm_total;
   const unsigned gn = (unsigned)((N + 255) / 256), gm = (unsigned)((nm + 255) / 256);
-  // FE, Uh (and Rh) start the step cleared: by the previous reverse step's
+  // FE, Uh (and Rh) start each step cleared: by the previous reverse step's
   // collide kernel, or by the fill before the first one
-  if (nm > 0) hipLaunchKernelGGL(ka_marker<T>, dim3(gm), dim3(256), 0, s, p, a);
-  hipLaunchKernelGGL(ka_collide<T>, dim3(gn), dim3(256), 0, s, p, a);
-  if (p.nbody_total > 0)
-    hipLaunchKernelGGL(ka_body<T>, dim3(p.nbody_total), dim3(kAdjThreads), 0, s, p, a);
-  hipLaunchKernelGGL(ka_stream<T>, dim3(gn), dim3(256), 0, s, p, a);
+  if (nm > 0) hipLaunchKernelGGL(ka_marker<T>, dim3(gm), dim3(256), 0, s, p, a[n - 1]);
+  for (int k = n - 1; k >= 0; --k) {
+    hipLaunchKernelGGL(ka_collide<T>, dim3(gn), dim3(256), 0, s, p, a[k]);
+    if (p.nbody_total > 0)
+      hipLaunchKernelGGL(ka_body<T>, dim3(p.nbody_total), dim3(kAdjThreads), 0, s, p, a[k]);
+    if (k > 0 && nm > 0)
+      hipLaunchKernelGGL(ka_stream_marker<T>, dim3(gn + gm), dim3(256), 0, s, p, a[k], a[k - 1], (int)gn);
+    else
+      hipLaunchKernelGGL(ka_stream<T>, dim3(gn), dim3(256), 0, s, p, a[k]);
+  }
 }
 
 void launch_copies(const CopyList& c, hipStream_t s) {
@@ -483,7 +509,7 @@ void launch_fill(double* out, long long n, double v, hipStream_t s) {
                      s, out, n, v);
 }
 
-template void launch_adjoint_step<float>(const Ptrs<float>&, const AdjPtrs&, long long, hipStream_t);
-template void launch_adjoint_step<double>(const Ptrs<double>&, const AdjPtrs&, long long, hipStream_t);
+template void launch_adjoint_segment<float>(const Ptrs<float>&, const AdjPtrs*, int, long long, hipStream_t);
+template void launch_adjoint_segment<double>(const Ptrs<double>&, const AdjPtrs*, int, long long, hipStream_t);
 
 }  // namespace lbib

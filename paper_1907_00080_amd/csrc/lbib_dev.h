@@ -169,7 +169,7 @@ struct CopyList {
 };
 
 template <typename T>
-void launch_adjoint_step(const Ptrs<T>& p, const AdjPtrs& a, long long N, hipStream_t s);
+void launch_adjoint_segment(const Ptrs<T>& p, const AdjPtrs* a, int n, long long N, hipStream_t s);
 void launch_copies(const CopyList& c, hipStream_t s);
 void launch_fill(double* out, long long n, double v, hipStream_t s);
 

@@ -197,77 +197,92 @@ __device__ inline int block_exclusive_scan(int v, int* s_tmp) {
 // (neighbours along a membrane) share one atomic.  A full bin drops the
 // registration and counts it in *overflow (the fused kernel then poisons
 // that tile's force so the watchdog reports it).
+template <int TX, int TY, int R>
+__device__ inline void register_markers(int* cnt, int* bin, int cap, int* overflow, const LatDev& L,
+                                        const int* gm, const int* cx, const int* cy,
+                                        const bool* active) {
+  const bool pery = L.periodic_y != 0;
+  const int nx = L.nx, ny = L.ny;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int key[R][9], leader[R][9], rank[R][9], gcount[R][9];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int tc[3], tr[3];
+    int ntc = 0, ntr = 0;
+    if (active[r]) {
+#pragma unroll
+      for (int a = -1; a <= 1; ++a) {
+        int c = cx[r] + a;
+        c = c < 0 ? c + nx : (c >= nx ? c - nx : c);
+        const int t = c / TX;
+        bool dup = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dup |= k < ntc && tc[k] == t;
+        if (!dup) { tc[ntc] = t; ++ntc; }
+      }
+#pragma unroll
+      for (int b = -1; b <= 1; ++b) {
+        int rr = cy[r] + b;
+        if (pery) rr = rr < 0 ? rr + ny : (rr >= ny ? rr - ny : rr);
+        else if (rr < 0 || rr >= ny) continue;
+        const int t = rr / TY;
+        bool dup = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dup |= k < ntr && tr[k] == t;
+        if (!dup) { tr[ntr] = t; ++ntr; }
+      }
+    }
+    // 1. group the lanes of every slot by tile (no memory traffic)
+#pragma unroll
+    for (int s9 = 0; s9 < 9; ++s9) {
+      const int i = s9 / 3, j = s9 % 3;
+      const bool has = i < ntr && j < ntc;
+      key[r][s9] = has ? L.tile_base + tr[i] * L.ntx + tc[j] : -1;
+      leader[r][s9] = lane;
+      rank[r][s9] = 0;
+      gcount[r][s9] = 0;
+      unsigned long long pending = __ballot(has);
+      while (pending) {
+        const int ld = __ffsll((long long)pending) - 1;
+        const int k = __shfl(key[r][s9], ld);
+        const unsigned long long grp = __ballot(key[r][s9] == k) & pending;
+        if (key[r][s9] == k) {
+          leader[r][s9] = ld;
+          rank[r][s9] = __popcll(grp & lt);
+        }
+        if (lane == ld) gcount[r][s9] = __popcll(grp);
+        pending &= ~grp;
+      }
+    }
+  }
+  // 2. every group leader reserves its slots; the atomics of all markers,
+  //    groups and slots are in flight together
+  int base[R][9];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s9 = 0; s9 < 9; ++s9)
+      base[r][s9] = gcount[r][s9] > 0 ? atomicAdd(&cnt[key[r][s9]], gcount[r][s9]) : 0;
+  // 3. positions and stores
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s9 = 0; s9 < 9; ++s9) {
+      const int b = __shfl(base[r][s9], leader[r][s9]);
+      if (key[r][s9] >= 0) {
+        const int pos = b + rank[r][s9];
+        if (pos < cap) bin[(long long)key[r][s9] * cap + pos] = gm[r];
+        else atomicAdd(overflow, 1);
+      }
+    }
+}
+
+// One marker per lane.
 template <int TX, int TY>
 __device__ inline void register_marker(int* cnt, int* bin, int cap, int* overflow, const LatDev& L,
                                        int gm, int cx, int cy, bool active) {
-  const bool pery = L.periodic_y != 0;
-  const int nx = L.nx, ny = L.ny;
-  int tc[3], tr[3];
-  int ntc = 0, ntr = 0;
-  if (active) {
-#pragma unroll
-    for (int a = -1; a <= 1; ++a) {
-      int c = cx + a;
-      c = c < 0 ? c + nx : (c >= nx ? c - nx : c);
-      const int t = c / TX;
-      bool dup = false;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) dup |= k < ntc && tc[k] == t;
-      if (!dup) { tc[ntc] = t; ++ntc; }
-    }
-#pragma unroll
-    for (int b = -1; b <= 1; ++b) {
-      int r = cy + b;
-      if (pery) r = r < 0 ? r + ny : (r >= ny ? r - ny : r);
-      else if (r < 0 || r >= ny) continue;
-      const int t = r / TY;
-      bool dup = false;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) dup |= k < ntr && tr[k] == t;
-      if (!dup) { tr[ntr] = t; ++ntr; }
-    }
-  }
-  const int lane = threadIdx.x & 63;
-  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  // 1. group the lanes of every slot by tile (no memory traffic)
-  int key[9], leader[9], rank[9], gcount[9];
-#pragma unroll
-  for (int s9 = 0; s9 < 9; ++s9) {
-    const int i = s9 / 3, j = s9 % 3;
-    const bool has = i < ntr && j < ntc;
-    key[s9] = has ? L.tile_base + tr[i] * L.ntx + tc[j] : -1;
-    leader[s9] = lane;
-    rank[s9] = 0;
-    gcount[s9] = 0;
-    unsigned long long pending = __ballot(has);
-    while (pending) {
-      const int ld = __ffsll((long long)pending) - 1;
-      const int k = __shfl(key[s9], ld);
-      const unsigned long long grp = __ballot(key[s9] == k) & pending;
-      if (key[s9] == k) {
-        leader[s9] = ld;
-        rank[s9] = __popcll(grp & lt);
-      }
-      if (lane == ld) gcount[s9] = __popcll(grp);
-      pending &= ~grp;
-    }
-  }
-  // 2. every group leader reserves its slots; the atomics of all groups and
-  //    slots are in flight together
-  int base[9];
-#pragma unroll
-  for (int s9 = 0; s9 < 9; ++s9)
-    base[s9] = gcount[s9] > 0 ? atomicAdd(&cnt[key[s9]], gcount[s9]) : 0;
-  // 3. positions and stores
-#pragma unroll
-  for (int s9 = 0; s9 < 9; ++s9) {
-    const int b = __shfl(base[s9], leader[s9]);
-    if (key[s9] >= 0) {
-      const int pos = b + rank[s9];
-      if (pos < cap) bin[(long long)key[s9] * cap + pos] = gm;
-      else atomicAdd(overflow, 1);
-    }
-  }
+  register_markers<TX, TY, 1>(cnt, bin, cap, overflow, L, &gm, &cx, &cy, &active);
 }
 
 // ---------------------------------------------------------------- stencils
@@ -276,7 +291,8 @@ __device__ inline void register_marker(int* cnt, int* bin, int cap, int* overflo
 // can be recognised) and the 3 + 3 Roma kernel weights (zero for rows beyond
 // the walls).
 template <typename T>
-__device__ inline void marker_stencil(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y) {
+__device__ inline void marker_stencil(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y,
+                                      int& ocx, int& ocy) {
   const int nm = p.nm_total;
   const bool pery = L.periodic_y != 0;
   const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
@@ -287,8 +303,10 @@ __device__ inline void marker_stencil(const Ptrs<T>& p, const LatDev& L, int gm,
     const bool valid = pery || (ry >= 0.0 && ry < (double)L.ny);
     p.wy[a * nm + gm] = valid ? roma_phi(ry - Y) : 0.0;
   }
-  p.cx[gm] = wrap_i((int)cxr, L.nx);
-  p.cy[gm] = pery ? wrap_i((int)cyr, L.ny) : (int)fmin(fmax(cyr, -4.0), (double)(L.ny + 3));
+  ocx = wrap_i((int)cxr, L.nx);
+  ocy = pery ? wrap_i((int)cyr, L.ny) : (int)fmin(fmax(cyr, -4.0), (double)(L.ny + 3));
+  p.cx[gm] = ocx;
+  p.cy[gm] = ocy;
 }
 
 // Stencils of all markers from their current positions (after set-up or
@@ -299,8 +317,8 @@ __global__ __launch_bounds__(256) void k_stencil(Ptrs<T> p) {
   const bool active = gm < p.nm_total;
   const int g = active ? gm : 0;
   const LatDev& L = p.lat[p.minfo[g] >> 2];
-  if (active) marker_stencil(p, L, gm, p.x[gm], p.y[gm]);
-  const int cx = active ? p.cx[gm] : 0, cy = active ? p.cy[gm] : 0;
+  int cx = 0, cy = 0;
+  if (active) marker_stencil(p, L, gm, p.x[gm], p.y[gm], cx, cy);
   register_marker<TX, TY>(p.cnt_cur, p.bin_cur, p.bin_cap, p.overflow, L, gm, cx, cy, active);
 }
 
@@ -535,38 +553,6 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
                                           unsigned char* s_dyn) {
   BodyDev* Bp = p.body + b;
   const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0, inst = Bp->inst;
-  if (ADV) {
-    // end of the previous step for this body's vertices: X^n from the
-    // kinematic update (red cells) or the particle dynamics, stencils, and
-    // the bins of this step's fused kernel
-    const LatDev& La = p.lat[inst];
-    const bool first_prev = p.step_prev[inst] == 0;
-    for (int v00 = 0; v00 < nv; v00 += blockDim.x) {
-      const int v = v00 + (int)threadIdx.x;
-      const bool act = v < nv;
-      const int gm = v0 + (act ? v : 0);
-      int ncx = 0, ncy = 0;
-      if (act) {
-        const double Xo = p.x[gm], Yo = p.y[gm];
-        double xn, yn;
-        if (kind == kRBC) {
-          advance_rbc(p, La, gm, Xo, Yo, first_prev, xn, yn);
-        } else {
-          xn = p.xn[gm];
-          yn = p.yn[gm];
-        }
-        p.xm[gm] = Xo;
-        p.ym[gm] = Yo;
-        p.x[gm] = xn;
-        p.y[gm] = yn;
-        marker_stencil(p, La, gm, xn, yn);
-        ncx = p.cx[gm];
-        ncy = p.cy[gm];
-      }
-      register_marker<TX, TY>(p.cnt_cur, p.bin_cur, p.bin_cap, p.overflow, La, gm, ncx, ncy, act);
-    }
-    __syncthreads();
-  }
   const double ks = Bp->ks, kb = Bp->kb, ka = Bp->ka, p_ref = Bp->p_ref, A0 = Bp->A0;
   const double mv = Bp->mv, sigma = Bp->sigma;
   const int lig_stride = Bp->lig_stride, lig_base = Bp->lig_base;
@@ -586,6 +572,141 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
   double* S_bny = SMALL ? sm[7] : p.s_bny + v0;
   double* S_fex = SMALL ? sm[8] : p.s_fex + v0;
   double* S_fey = SMALL ? sm[9] : p.s_fey + v0;
+  // ---- particles: LDS cache of rho*, u* over the box of nodes their vertex
+  // and probe stencils can reach: the vertex bounding box of X^n widened by
+  // 4 nodes (probe 1.2 along the normal, stencil reach 1.5, one node of
+  // margin).  Boxes larger than the cache fall back to direct evaluation.
+  // The first batch of population loads is issued before the marker
+  // advance below, whose work hides their latency.
+  bool cached = false;
+  StarCache<T> C{(const T*)s_dyn, 0, 0, 0, 0};
+  constexpr int NB = 4;   // nodes per lane per batch: 36 loads in flight
+  T hv[NB][kQ];
+  int nbox = 0;
+  const long long Nn = (long long)L.nx * L.ny;
+  if (kind != kRBC) {
+    // X^n of a particle: its dynamics' positions while the previous step is
+    // still being finished here, else the current positions
+    const double* PX = ADV ? p.xn + v0 : p.x + v0;
+    const double* PY = ADV ? p.yn + v0 : p.y + v0;
+    int mnx = 0x7fffffff, mxx = -0x7fffffff, mny = 0x7fffffff, mxy = -0x7fffffff;
+    for (int v = t; v < nv; v += nt) {
+      const double xv = PX[v], yv = PY[v];
+      mnx = min(mnx, (int)floor(xv) - 4); mxx = max(mxx, (int)ceil(xv) + 4);
+      mny = min(mny, (int)floor(yv) - 4); mxy = max(mxy, (int)ceil(yv) + 4);
+    }
+    // wave reductions first: only one lane per wave touches the LDS words
+    for (int o = 32; o > 0; o >>= 1) {
+      mnx = min(mnx, __shfl_xor(mnx, o)); mxx = max(mxx, __shfl_xor(mxx, o));
+      mny = min(mny, __shfl_xor(mny, o)); mxy = max(mxy, __shfl_xor(mxy, o));
+    }
+    if (t == 0) { s_box[0] = 0x7fffffff; s_box[1] = -0x7fffffff; s_box[2] = 0x7fffffff; s_box[3] = -0x7fffffff; }
+    __syncthreads();
+    if ((t & 63) == 0) {
+      atomicMin(&s_box[0], mnx); atomicMax(&s_box[1], mxx);
+      atomicMin(&s_box[2], mny); atomicMax(&s_box[3], mxy);
+    }
+    __syncthreads();
+    int by0 = s_box[2], by1 = s_box[3];
+    if (!pery) { by0 = max(by0, 0); by1 = min(by1, L.ny - 1); }
+    const int bw = s_box[1] - s_box[0] + 1, bh = by1 - by0 + 1;
+    if (bw > 0 && bh > 0 && (long long)bw * bh <= cache_nodes) {
+      cached = true;
+      C.bx0 = s_box[0]; C.by0 = by0; C.bw = bw; C.bh = bh;
+      nbox = bw * bh;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int k = q * nt + t;
+        const int kk = k < nbox ? k : 0;
+        const int col = wrap_i(C.bx0 + kk % bw, L.nx);
+        int row = by0 + kk / bw;
+        if (pery) row = wrap_i(row, L.ny);
+        pull_node(A, Nn, L.nx, L.ny, pery, col, row, hv[q]);
+      }
+    }
+  }
+
+  if (ADV) {
+    // end of the previous step for this body's vertices: X^n from the
+    // kinematic update (red cells) or the particle dynamics, stencils, and
+    // the bins of this step's fused kernel; two vertices per lane, their
+    // loads and bin reservations in flight together
+    const bool first_prev = p.step_prev[inst] == 0;
+    constexpr int R = 2;
+    for (int base0 = 0; base0 < nv; base0 += R * nt) {
+      int gmv[R], ncx[R], ncy[R];
+      bool act[R];
+      double xo[R], yo[R], xn[R], yn[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int v = base0 + r * nt + t;
+        act[r] = v < nv;
+        gmv[r] = v0 + (act[r] ? v : 0);
+        xo[r] = p.x[gmv[r]];
+        yo[r] = p.y[gmv[r]];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (kind == kRBC) {
+          advance_rbc(p, L, gmv[r], xo[r], yo[r], first_prev, xn[r], yn[r]);
+        } else {
+          xn[r] = p.xn[gmv[r]];
+          yn[r] = p.yn[gmv[r]];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        ncx[r] = 0;
+        ncy[r] = 0;
+        if (act[r]) {
+          p.xm[gmv[r]] = xo[r];
+          p.ym[gmv[r]] = yo[r];
+          p.x[gmv[r]] = xn[r];
+          p.y[gmv[r]] = yn[r];
+          marker_stencil(p, L, gmv[r], xn[r], yn[r], ncx[r], ncy[r]);
+        }
+      }
+      register_markers<TX, TY, R>(p.cnt_cur, p.bin_cur, p.bin_cap, p.overflow, L, gmv, ncx, ncy, act);
+    }
+  }
+
+  if (cached) {
+    // finish the cache: the batch in flight, then any further ones
+    T* cw = (T*)s_dyn;
+    const int bw = C.bw, by0 = C.by0;
+    for (int k0 = 0; k0 < nbox; k0 += NB * nt) {
+      if (k0 > 0) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const int k = k0 + q * nt + t;
+          const int kk = k < nbox ? k : 0;
+          const int col = wrap_i(C.bx0 + kk % bw, L.nx);
+          int row = by0 + kk / bw;
+          if (pery) row = wrap_i(row, L.ny);
+          pull_node(A, Nn, L.nx, L.ny, pery, col, row, hv[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int k = k0 + q * nt + t;
+        if (k >= nbox) continue;
+        double drho = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+          const double h = double(hv[q][i]);
+          drho += h;
+          jx += ex(i) * h;
+          jy += ey(i) * h;
+        }
+        const double r = 1.0 + drho;
+        cw[3 * k] = T(r);
+        cw[3 * k + 1] = T((jx + 0.5 * L.gx) / r);
+        cw[3 * k + 2] = T((jy + 0.5 * L.gy) / r);
+      }
+    }
+  }
+  __syncthreads();   // positions, stencils and cache visible to the workgroup
+
   if (SMALL) {
     for (int v = t; v < nv; v += nt) {
       sm[0][v] = p.x[v0 + v];
@@ -623,81 +744,6 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
   double area = shoe;
   block_sum<1>(s_red, &area);   // its barriers also publish the scratch
   area *= 0.5;
-
-  // particles: cache rho*, u* over the box of nodes the probe and vertex
-  // stencils read (one pass of 9-population pulls per node instead of one
-  // per stencil use); boxes larger than the LDS cache fall back to direct
-  // evaluation
-  bool cached = false;
-  StarCache<T> C{(const T*)s_dyn, 0, 0, 0, 0};
-  if (kind != kRBC) {
-    int mnx = 0x7fffffff, mxx = -0x7fffffff, mny = 0x7fffffff, mxy = -0x7fffffff;
-    for (int v = t; v < nv; v += nt) {
-      const int vp = v + 1 == nv ? 0 : v + 1;
-      const double qx = 0.5 * (X[v] + X[vp]) + 1.2 * S_nx[v];
-      double qy = 0.5 * (Y[v] + Y[vp]) + 1.2 * S_ny[v];
-      if (!pery) qy = fmin(fmax(qy, 0.5), L.ny - 1.5);
-      const int c1x = (int)floor(X[v] + 0.5), c1y = (int)floor(Y[v] + 0.5);
-      const int c2x = (int)floor(qx + 0.5), c2y = (int)floor(qy + 0.5);
-      // stencil reach +-1, plus one node of margin against a one-ulp
-      // difference in the probe position recomputed in pass 2
-      mnx = min(mnx, min(c1x, c2x) - 2); mxx = max(mxx, max(c1x, c2x) + 2);
-      mny = min(mny, min(c1y, c2y) - 2); mxy = max(mxy, max(c1y, c2y) + 2);
-    }
-    // wave reductions first: only one lane per wave touches the LDS words
-    for (int o = 32; o > 0; o >>= 1) {
-      mnx = min(mnx, __shfl_xor(mnx, o)); mxx = max(mxx, __shfl_xor(mxx, o));
-      mny = min(mny, __shfl_xor(mny, o)); mxy = max(mxy, __shfl_xor(mxy, o));
-    }
-    if (t == 0) { s_box[0] = 0x7fffffff; s_box[1] = -0x7fffffff; s_box[2] = 0x7fffffff; s_box[3] = -0x7fffffff; }
-    __syncthreads();
-    if ((t & 63) == 0) {
-      atomicMin(&s_box[0], mnx); atomicMax(&s_box[1], mxx);
-      atomicMin(&s_box[2], mny); atomicMax(&s_box[3], mxy);
-    }
-    __syncthreads();
-    int by0 = s_box[2], by1 = s_box[3];
-    if (!pery) { by0 = max(by0, 0); by1 = min(by1, L.ny - 1); }
-    const int bw = s_box[1] - s_box[0] + 1, bh = by1 - by0 + 1;
-    if (bw > 0 && bh > 0 && (long long)bw * bh <= cache_nodes) {
-      cached = true;
-      C.bx0 = s_box[0]; C.by0 = by0; C.bw = bw; C.bh = bh;
-      T* cw = (T*)s_dyn;
-      const long long N = (long long)L.nx * L.ny;
-      const int nbox = bw * bh;
-      constexpr int NB = 4;   // nodes per lane per batch: 36 loads in flight
-      for (int k0 = 0; k0 < nbox; k0 += NB * nt) {
-        T hv[NB][kQ];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const int k = k0 + q * nt + t;
-          const int kk = k < nbox ? k : 0;
-          const int col = wrap_i(C.bx0 + kk % bw, L.nx);
-          int row = by0 + kk / bw;
-          if (pery) row = wrap_i(row, L.ny);
-          pull_node(A, N, L.nx, L.ny, pery, col, row, hv[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const int k = k0 + q * nt + t;
-          if (k >= nbox) continue;
-          double drho = 0.0, jx = 0.0, jy = 0.0;
-#pragma unroll
-          for (int i = 0; i < kQ; ++i) {
-            const double h = double(hv[q][i]);
-            drho += h;
-            jx += ex(i) * h;
-            jy += ey(i) * h;
-          }
-          const double r = 1.0 + drho;
-          cw[3 * k] = T(r);
-          cw[3 * k + 1] = T((jx + 0.5 * L.gx) / r);
-          cw[3 * k + 2] = T((jy + 0.5 * L.gy) / r);
-        }
-      }
-    }
-    __syncthreads();
-  }
 
   // particles read the bond table (and rigid ones the step counter) written
   // by this instance's bond workgroup: wait for its flag (bounded spin; the
@@ -933,9 +979,7 @@ __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
     p.y[gm] = yn;
     // stencil of the new position, used by the next step's spreading and
     // interpolation (this lane has finished reading the old one)
-    marker_stencil(p, L, gm, xn, yn);
-    ncx = p.cx[gm];
-    ncy = p.cy[gm];
+    marker_stencil(p, L, gm, xn, yn, ncx, ncy);
   }
   // join the bins the next step's fused kernel reads (all lanes take part
   // in the wave-aggregated registration)

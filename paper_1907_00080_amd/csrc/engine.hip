@@ -305,6 +305,9 @@ StepArgs step_args(const lbib_ctx* c) {
     a.max_inst_tiles = std::max(a.max_inst_tiles, nt);
   }
   a.body_cache_bytes = c->body_cache;
+  a.max_nv = 0;
+  for (auto& I : c->inst)
+    for (auto& b : I.bodies) a.max_nv = std::max(a.max_nv, b.d.nv);
   return a;
 }
 
@@ -498,8 +501,8 @@ lbib_status upload_all(lbib_ctx* c) {
 // each: Lagrangian, fused lattice, marker advance.
 // Step form of the context: three kernels (body, lattice, advance), the
 // merged form (the body kernel finishes the previous step's advance; only
-// when every body has <= 512 vertices, where one round of the workgroup
-// covers them), or the overlapped form (the lattice tiles without IB force
+// when every body has <= kSmallBody vertices, where one round of the
+// workgroup covers them), or the overlapped form (the lattice tiles without IB force
 // on a second stream while the body kernel runs).  Automatic: merged when
 // possible, else three kernels (measured faster than the overlapped form on
 // the 2000 x 200 and 6667 x 667 capillaries and the 64-instance sweep).
@@ -507,7 +510,7 @@ void resolve_step_mode(lbib_ctx* c) {
   bool small_bodies = true;
   for (auto& I : c->inst)
     for (auto& b : I.bodies)
-      if (b.d.nv > 512) small_bodies = false;
+      if (b.d.nv > kSmallBody) small_bodies = false;
   int m = c->step_mode;
   if (m == 0) m = small_bodies ? 2 : 1;
   c->merge_advance = m == 2 && small_bodies;

@@ -208,36 +208,36 @@ __device__ inline void register_markers(int* cnt, int* bin, int cap, int* overfl
   int key[R][9], leader[R][9], rank[R][9], gcount[R][9];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    // tile column and row of each stencil offset; an offset whose tile an
+    // earlier offset already reached adds no slot (fixed indices only, so
+    // the lists stay in registers)
     int tc[3], tr[3];
-    int ntc = 0, ntr = 0;
-    if (active[r]) {
+    bool okc[3], okr[3];
 #pragma unroll
-      for (int a = -1; a <= 1; ++a) {
-        int c = cx[r] + a;
-        c = c < 0 ? c + nx : (c >= nx ? c - nx : c);
-        const int t = c / TX;
-        bool dup = false;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) dup |= k < ntc && tc[k] == t;
-        if (!dup) { tc[ntc] = t; ++ntc; }
-      }
-#pragma unroll
-      for (int b = -1; b <= 1; ++b) {
-        int rr = cy[r] + b;
-        if (pery) rr = rr < 0 ? rr + ny : (rr >= ny ? rr - ny : rr);
-        else if (rr < 0 || rr >= ny) continue;
-        const int t = rr / TY;
-        bool dup = false;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) dup |= k < ntr && tr[k] == t;
-        if (!dup) { tr[ntr] = t; ++ntr; }
-      }
+    for (int a = 0; a < 3; ++a) {
+      int c = cx[r] + a - 1;
+      c = c < 0 ? c + nx : (c >= nx ? c - nx : c);
+      tc[a] = c / TX;
+      okc[a] = active[r];
+      int rr = cy[r] + a - 1;
+      bool ok = active[r];
+      if (pery) rr = rr < 0 ? rr + ny : (rr >= ny ? rr - ny : rr);
+      else ok = ok && rr >= 0 && rr < ny;
+      tr[a] = ok ? rr / TY : -1;
+      okr[a] = ok;
     }
+    bool vc[3], vr[3];
+    vc[0] = okc[0];
+    vc[1] = okc[1] && tc[1] != tc[0];
+    vc[2] = okc[2] && tc[2] != tc[0] && tc[2] != tc[1];
+    vr[0] = okr[0];
+    vr[1] = okr[1] && !(okr[0] && tr[1] == tr[0]);
+    vr[2] = okr[2] && !(okr[0] && tr[2] == tr[0]) && !(okr[1] && tr[2] == tr[1]);
     // 1. group the lanes of every slot by tile (no memory traffic)
 #pragma unroll
     for (int s9 = 0; s9 < 9; ++s9) {
       const int i = s9 / 3, j = s9 % 3;
-      const bool has = i < ntr && j < ntc;
+      const bool has = vr[i] && vc[j];
       key[r][s9] = has ? L.tile_base + tr[i] * L.ntx + tc[j] : -1;
       leader[r][s9] = lane;
       rank[r][s9] = 0;
@@ -543,7 +543,7 @@ __device__ inline void record_fmax(unsigned long long* slot, double m, double (*
   if ((threadIdx.x & 63) == 0 && m != 0.0) atomicMax(slot, (unsigned long long)__double_as_longlong(m));
 }
 
-constexpr int kVmax = 512;   // bodies up to this many vertices keep their scratch in LDS
+constexpr int kVmax = kSmallBody;
 
 // SMALL: the body's per-vertex scratch lives in LDS (sm); otherwise in the
 // workspace.  A template parameter, so every access has a known address space.
@@ -557,10 +557,26 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
   const double mv = Bp->mv, sigma = Bp->sigma;
   const int lig_stride = Bp->lig_stride, lig_base = Bp->lig_base;
   const LatDev& L = p.lat[inst];
-  const int t = threadIdx.x, nt = blockDim.x;
+  const int t = threadIdx.x, nt = kBodyThreads;   // the launch's block size
   const T* A = p.A + 9 * L.node_base;
   const double nu = (L.tau - 0.5) / 3.0;
   const bool pery = L.periodic_y != 0;
+  // rest data of this lane's vertices (a small body has at most kPre per
+  // lane), requested now so that the loads are in flight during the work
+  // before their use
+  constexpr int kPre = (kVmax + kBodyThreads - 1) / kBodyThreads;
+  double pre_th0[kPre], pre_l0[kPre], pre_l0m[kPre];
+  if constexpr (SMALL) {
+#pragma unroll
+    for (int j = 0; j < kPre; ++j) {
+      const int v = t + j * nt < nv ? t + j * nt : 0;
+      const int vm = v == 0 ? nv - 1 : v - 1;
+      const bool soft = kind != kRigid;
+      pre_th0[j] = soft ? p.th0[v0 + v] : 0.0;
+      pre_l0[j] = soft ? p.l0[v0 + v] : 0.0;
+      pre_l0m[j] = soft ? p.l0[v0 + vm] : 0.0;
+    }
+  }
   // per-vertex scratch: LDS for small bodies, workspace otherwise
   const double* X = SMALL ? sm[0] : p.x + v0;
   const double* Y = SMALL ? sm[1] : p.y + v0;
@@ -663,6 +679,10 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
           p.ym[gmv[r]] = yo[r];
           p.x[gmv[r]] = xn[r];
           p.y[gmv[r]] = yn[r];
+          if constexpr (SMALL) {
+            sm[0][base0 + r * nt + t] = xn[r];
+            sm[1][base0 + r * nt + t] = yn[r];
+          }
           marker_stencil(p, L, gmv[r], xn[r], yn[r], ncx[r], ncy[r]);
         }
       }
@@ -707,7 +727,8 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
   }
   __syncthreads();   // positions, stencils and cache visible to the workgroup
 
-  if (SMALL) {
+  if (SMALL && !ADV) {
+    // (the merged form wrote X^n into LDS as it computed it)
     for (int v = t; v < nv; v += nt) {
       sm[0][v] = p.x[v0 + v];
       sm[1][v] = p.y[v0 + v];
@@ -717,7 +738,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
 
   // pass 1: element geometry (element v joins v -> v+1), bending data, area
   double shoe = 0.0;
-  for (int v = t; v < nv; v += nt) {
+  auto pass1 = [&](int v, double th0v) {
     const int vp = v + 1 == nv ? 0 : v + 1, vm = v == 0 ? nv - 1 : v - 1;
     const double xv = X[v], yv = Y[v], xp = X[vp], yp = Y[vp], xm = X[vm], ym = Y[vm];
     const double dxr = xp - xv, dyr = yp - yv;
@@ -735,11 +756,18 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       const double th = atan2(cr, dt);
       const double nsx = tyl + tyr, nsy = -txl - txr;
       const double nn = sqrt(nsx * nsx + nsy * nsy);
-      S_bc[v] = kb * (th - p.th0[v0 + v]);
+      S_bc[v] = kb * (th - th0v);
       S_bnx[v] = nsx / nn;
       S_bny[v] = nsy / nn;
     }
     shoe += xv * yp - xp * yv;
+  };
+  if constexpr (SMALL) {
+#pragma unroll
+    for (int j = 0; j < kPre; ++j)
+      if (t + j * nt < nv) pass1(t + j * nt, pre_th0[j]);
+  } else {
+    for (int v = t; v < nv; v += nt) pass1(v, p.th0[v0 + v]);
   }
   double area = shoe;
   block_sum<1>(s_red, &area);   // its barriers also publish the scratch
@@ -862,14 +890,14 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
 
   // membrane vertex forces: strain + bending + shared element loads
   double fm = 0.0;
-  for (int v = t; v < nv; v += nt) {
+  auto vertex_force = [&](int v, double l0v, double l0m) {
     const int gm = v0 + v;
     const int vm = v == 0 ? nv - 1 : v - 1, vp = v + 1 == nv ? 0 : v + 1;
     const int vmm = vm == 0 ? nv - 1 : vm - 1;
     // strain: element v pulls v along +t, element v-1 pulls v along -t
     const double lr = S_len[v], ll = S_len[vm];
-    const double sr = ks * (lr - p.l0[gm]);
-    const double sl = ks * (ll - p.l0[v0 + vm]);
+    const double sr = ks * (lr - l0v);
+    const double sl = ks * (ll - l0m);
     // tangents from normals: t = (-n_y, n_x)
     double fx = sr * (-S_ny[v]) - sl * (-S_ny[vm]);
     double fy = sr * S_nx[v] - sl * S_nx[vm];
@@ -915,15 +943,29 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       p.fy[gm] = ffy;
       fm = fmax_nan(fm, fmax_nan(fabs(ffx), fabs(ffy)));
     }
+  };
+  if constexpr (SMALL) {
+#pragma unroll
+    for (int j = 0; j < kPre; ++j)
+      if (t + j * nt < nv) vertex_force(t + j * nt, pre_l0[j], pre_l0m[j]);
+  } else {
+    for (int v = t; v < nv; v += nt) {
+      const int vm = v == 0 ? nv - 1 : v - 1;
+      vertex_force(v, p.l0[v0 + v], p.l0[v0 + vm]);
+    }
   }
   record_fmax(p.fmax_bits + inst, fm, s_red);
 }
 
 // Workgroups [0, ninst): bond kinetics of each instance; then one workgroup
 // per body: membrane forces, particle loads and motion.  ADV: the body's
-// vertices first finish the previous step (merged step kernel).
-template <typename T, int TX, int TY, bool ADV>
+// vertices first finish the previous step (merged step kernel).  SMALL_ONLY:
+// every body has at most kVmax vertices (the host knows), so only the LDS
+// form of the body code is compiled in: a smaller kernel, fewer instruction
+// fetches on its serial path.  The merged form is only launched that way.
+template <typename T, int TX, int TY, bool ADV, bool SMALL_ONLY>
 __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_nodes) {
+  static_assert(SMALL_ONLY || !ADV, "the merged step form needs small bodies");
   __shared__ double s_red[3][kBodyThreads / 64];
   __shared__ double s_rigid[6];
   __shared__ int s_box[4];
@@ -939,10 +981,10 @@ __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_node
     return;
   }
   const int b = blockIdx.x - p.ninst;
-  if (p.body[b].nv <= kVmax)
+  if (SMALL_ONLY || p.body[b].nv <= kVmax)
     body_impl<T, true, TX, TY, ADV>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
   else
-    body_impl<T, false, TX, TY, ADV>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+    body_impl<T, false, TX, TY, false>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
 }
 
 // Ends a run of steps: every marker moves to X^{n+1} (red cells by the
@@ -1006,10 +1048,14 @@ void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, bool 
   const int cache_nodes = a.body_cache_bytes / (3 * (int)sizeof(T));
   const dim3 grid(p.ninst + p.nbody_total), block(kBodyThreads);
   const unsigned lds = (unsigned)a.body_cache_bytes;
+  // advance_first (the merged form) is only requested when every body is
+  // small: the engine resolves the step form from the same limit
+  const bool small = a.max_nv <= kVmax;
 #define LBIB_BODY(TXv, TYv)                                                                        \
   do {                                                                                          \
-    if (advance_first) hipLaunchKernelGGL((k_body<T, TXv, TYv, true>), grid, block, lds, s, p, cache_nodes); \
-    else hipLaunchKernelGGL((k_body<T, TXv, TYv, false>), grid, block, lds, s, p, cache_nodes);    \
+    if (advance_first) hipLaunchKernelGGL((k_body<T, TXv, TYv, true, true>), grid, block, lds, s, p, cache_nodes); \
+    else if (small) hipLaunchKernelGGL((k_body<T, TXv, TYv, false, true>), grid, block, lds, s, p, cache_nodes); \
+    else hipLaunchKernelGGL((k_body<T, TXv, TYv, false, false>), grid, block, lds, s, p, cache_nodes); \
   } while (0)
   if (a.tile_x == 64 && a.tile_y == 4) LBIB_BODY(64, 4);
   else if (a.tile_x == 128 && a.tile_y == 2) LBIB_BODY(128, 2);

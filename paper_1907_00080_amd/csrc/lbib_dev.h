@@ -175,11 +175,16 @@ void launch_fill(double* out, long long n, double v, hipStream_t s);
 
 // ------------------------------------------------------------ launchers
 // (defined in the kernel translation units, called by the host engine)
+// Bodies with at most this many vertices keep their per-vertex scratch in the
+// body kernel's LDS; the merged step form needs every body to be that small.
+constexpr int kSmallBody = 512;
+
 struct StepArgs {
   int tile_x, tile_y;
   int ntiles_total;
   int max_inst_tiles;   // largest tile count of any instance
   int body_cache_bytes; // LDS cache of rho*, u* per particle workgroup
+  int max_nv;           // most vertices of any body
 };
 
 template <typename T>

@@ -193,8 +193,8 @@ __device__ inline int block_exclusive_scan(int v, int* s_tmp) {
 // Register marker gm in every tile its 3x3 stencil overlaps (centre cx, cy).
 // Three consecutive columns (rows) touch at most three tiles (a ragged last
 // tile can be one column wide), so a marker joins at most nine bins.  Slots
-// come from wave-aggregated atomics: lanes of a wave that hit the same tile
-// (neighbours along a membrane) share one atomic.  A full bin drops the
+// come from wave-aggregated atomics: a run of adjacent lanes that hit the
+// same tile (neighbours along a membrane) shares one atomic.  A full bin drops the
 // registration and counts it in *overflow (the fused kernel then poisons
 // that tile's force so the watchdog reports it).
 template <int TX, int TY, int R>
@@ -233,27 +233,26 @@ __device__ inline void register_markers(int* cnt, int* bin, int cap, int* overfl
     vr[0] = okr[0];
     vr[1] = okr[1] && !(okr[0] && tr[1] == tr[0]);
     vr[2] = okr[2] && !(okr[0] && tr[2] == tr[0]) && !(okr[1] && tr[2] == tr[1]);
-    // 1. group the lanes of every slot by tile (no memory traffic)
+    // 1. group the lanes of every slot by tile, no memory traffic: a run of
+    //    adjacent lanes with the same tile (neighbouring markers) is one
+    //    group; a tile met in several runs gets one group per run
 #pragma unroll
     for (int s9 = 0; s9 < 9; ++s9) {
       const int i = s9 / 3, j = s9 % 3;
       const bool has = vr[i] && vc[j];
-      key[r][s9] = has ? L.tile_base + tr[i] * L.ntx + tc[j] : -1;
-      leader[r][s9] = lane;
-      rank[r][s9] = 0;
-      gcount[r][s9] = 0;
-      unsigned long long pending = __ballot(has);
-      while (pending) {
-        const int ld = __ffsll((long long)pending) - 1;
-        const int k = __shfl(key[r][s9], ld);
-        const unsigned long long grp = __ballot(key[r][s9] == k) & pending;
-        if (key[r][s9] == k) {
-          leader[r][s9] = ld;
-          rank[r][s9] = __popcll(grp & lt);
-        }
-        if (lane == ld) gcount[r][s9] = __popcll(grp);
-        pending &= ~grp;
-      }
+      const int k = has ? L.tile_base + tr[i] * L.ntx + tc[j] : -1;
+      key[r][s9] = k;
+      const int kprev = __shfl_up(k, 1);
+      const unsigned long long hasm = __ballot(has);
+      const unsigned long long heads = __ballot(has && (lane == 0 || kprev != k));
+      const unsigned long long le = lt | (1ull << lane);
+      const unsigned long long mine = heads & le;
+      const int ld = mine ? 63 - __clzll((long long)mine) : lane;
+      leader[r][s9] = ld;
+      rank[r][s9] = lane - ld;
+      const unsigned long long brk = (heads | ~hasm) & ~le;   // lanes after this one that end the run
+      const int next = brk ? __ffsll((long long)brk) - 1 : 64;
+      gcount[r][s9] = has && lane == ld ? next - lane : 0;
     }
   }
   // 2. every group leader reserves its slots; the atomics of all markers,
@@ -337,11 +336,15 @@ __device__ inline void advance_rbc(const Ptrs<T>& p, const LatDev& L, int gm, do
   const int nm = p.nm_total;
   const int cx = p.cx[gm], cy = p.cy[gm];
   double ux = 0.0, uy = 0.0;
+  // a row beyond a wall has weight exactly zero: it reads a clamped row and
+  // adds zeros, so all 18 loads are independent of control flow
+#pragma unroll
   for (int b2 = 0; b2 < 3; ++b2) {
     int row = cy + b2 - 1;
     if (L.periodic_y) row = wrap_i(row, L.ny);
-    else if (row < 0 || row >= L.ny) continue;
+    else row = min(max(row, 0), L.ny - 1);
     const double wy = p.wy[b2 * nm + gm];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int col = wrap_i(cx + a - 1, L.nx);
       const double w = p.wx[a * nm + gm] * wy;
@@ -588,65 +591,13 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
   double* S_bny = SMALL ? sm[7] : p.s_bny + v0;
   double* S_fex = SMALL ? sm[8] : p.s_fex + v0;
   double* S_fey = SMALL ? sm[9] : p.s_fey + v0;
-  // ---- particles: LDS cache of rho*, u* over the box of nodes their vertex
-  // and probe stencils can reach: the vertex bounding box of X^n widened by
-  // 4 nodes (probe 1.2 along the normal, stencil reach 1.5, one node of
-  // margin).  Boxes larger than the cache fall back to direct evaluation.
-  // The first batch of population loads is issued before the marker
-  // advance below, whose work hides their latency.
-  bool cached = false;
-  StarCache<T> C{(const T*)s_dyn, 0, 0, 0, 0};
-  constexpr int NB = 4;   // nodes per lane per batch: 36 loads in flight
-  T hv[NB][kQ];
-  int nbox = 0;
-  const long long Nn = (long long)L.nx * L.ny;
-  if (kind != kRBC) {
-    // X^n of a particle: its dynamics' positions while the previous step is
-    // still being finished here, else the current positions
-    const double* PX = ADV ? p.xn + v0 : p.x + v0;
-    const double* PY = ADV ? p.yn + v0 : p.y + v0;
-    int mnx = 0x7fffffff, mxx = -0x7fffffff, mny = 0x7fffffff, mxy = -0x7fffffff;
-    for (int v = t; v < nv; v += nt) {
-      const double xv = PX[v], yv = PY[v];
-      mnx = min(mnx, (int)floor(xv) - 4); mxx = max(mxx, (int)ceil(xv) + 4);
-      mny = min(mny, (int)floor(yv) - 4); mxy = max(mxy, (int)ceil(yv) + 4);
-    }
-    // wave reductions first: only one lane per wave touches the LDS words
-    for (int o = 32; o > 0; o >>= 1) {
-      mnx = min(mnx, __shfl_xor(mnx, o)); mxx = max(mxx, __shfl_xor(mxx, o));
-      mny = min(mny, __shfl_xor(mny, o)); mxy = max(mxy, __shfl_xor(mxy, o));
-    }
-    if (t == 0) { s_box[0] = 0x7fffffff; s_box[1] = -0x7fffffff; s_box[2] = 0x7fffffff; s_box[3] = -0x7fffffff; }
-    __syncthreads();
-    if ((t & 63) == 0) {
-      atomicMin(&s_box[0], mnx); atomicMax(&s_box[1], mxx);
-      atomicMin(&s_box[2], mny); atomicMax(&s_box[3], mxy);
-    }
-    __syncthreads();
-    int by0 = s_box[2], by1 = s_box[3];
-    if (!pery) { by0 = max(by0, 0); by1 = min(by1, L.ny - 1); }
-    const int bw = s_box[1] - s_box[0] + 1, bh = by1 - by0 + 1;
-    if (bw > 0 && bh > 0 && (long long)bw * bh <= cache_nodes) {
-      cached = true;
-      C.bx0 = s_box[0]; C.by0 = by0; C.bw = bw; C.bh = bh;
-      nbox = bw * bh;
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int k = q * nt + t;
-        const int kk = k < nbox ? k : 0;
-        const int col = wrap_i(C.bx0 + kk % bw, L.nx);
-        int row = by0 + kk / bw;
-        if (pery) row = wrap_i(row, L.ny);
-        pull_node(A, Nn, L.nx, L.ny, pery, col, row, hv[q]);
-      }
-    }
-  }
-
+  // ---- end of the previous step (merged form) for this body's vertices:
+  // X^n from the kinematic update (red cells) or the particle dynamics,
+  // stencils, and the bins of this step's fused kernel; two vertices per
+  // lane, their loads and bin reservations in flight together.  Particles
+  // also take the bounding box of X^n for their LDS cache from here.
+  int mnx = 0x7fffffff, mxx = -0x7fffffff, mny = 0x7fffffff, mxy = -0x7fffffff;
   if (ADV) {
-    // end of the previous step for this body's vertices: X^n from the
-    // kinematic update (red cells) or the particle dynamics, stencils, and
-    // the bins of this step's fused kernel; two vertices per lane, their
-    // loads and bin reservations in flight together
     const bool first_prev = p.step_prev[inst] == 0;
     constexpr int R = 2;
     for (int base0 = 0; base0 < nv; base0 += R * nt) {
@@ -684,18 +635,54 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
             sm[1][base0 + r * nt + t] = yn[r];
           }
           marker_stencil(p, L, gmv[r], xn[r], yn[r], ncx[r], ncy[r]);
+          if (kind != kRBC) {
+            mnx = min(mnx, (int)floor(xn[r]) - 4); mxx = max(mxx, (int)ceil(xn[r]) + 4);
+            mny = min(mny, (int)floor(yn[r]) - 4); mxy = max(mxy, (int)ceil(yn[r]) + 4);
+          }
         }
       }
       register_markers<TX, TY, R>(p.cnt_cur, p.bin_cur, p.bin_cap, p.overflow, L, gmv, ncx, ncy, act);
     }
   }
 
-  if (cached) {
-    // finish the cache: the batch in flight, then any further ones
-    T* cw = (T*)s_dyn;
-    const int bw = C.bw, by0 = C.by0;
-    for (int k0 = 0; k0 < nbox; k0 += NB * nt) {
-      if (k0 > 0) {
+  // ---- particles: LDS cache of rho*, u* over the box of nodes their vertex
+  // and probe stencils can reach: the vertex bounding box of X^n widened by
+  // 4 nodes (probe 1.2 along the normal, stencil reach 1.5, one node of
+  // margin).  Boxes larger than the cache fall back to direct evaluation.
+  bool cached = false;
+  StarCache<T> C{(const T*)s_dyn, 0, 0, 0, 0};
+  if (kind != kRBC) {
+    if (!ADV) {
+      for (int v = t; v < nv; v += nt) {
+        const double xv = p.x[v0 + v], yv = p.y[v0 + v];
+        mnx = min(mnx, (int)floor(xv) - 4); mxx = max(mxx, (int)ceil(xv) + 4);
+        mny = min(mny, (int)floor(yv) - 4); mxy = max(mxy, (int)ceil(yv) + 4);
+      }
+    }
+    // wave reductions first: only one lane per wave touches the LDS words
+    for (int o = 32; o > 0; o >>= 1) {
+      mnx = min(mnx, __shfl_xor(mnx, o)); mxx = max(mxx, __shfl_xor(mxx, o));
+      mny = min(mny, __shfl_xor(mny, o)); mxy = max(mxy, __shfl_xor(mxy, o));
+    }
+    if (t == 0) { s_box[0] = 0x7fffffff; s_box[1] = -0x7fffffff; s_box[2] = 0x7fffffff; s_box[3] = -0x7fffffff; }
+    __syncthreads();
+    if ((t & 63) == 0) {
+      atomicMin(&s_box[0], mnx); atomicMax(&s_box[1], mxx);
+      atomicMin(&s_box[2], mny); atomicMax(&s_box[3], mxy);
+    }
+    __syncthreads();
+    int by0 = s_box[2], by1 = s_box[3];
+    if (!pery) { by0 = max(by0, 0); by1 = min(by1, L.ny - 1); }
+    const int bw = s_box[1] - s_box[0] + 1, bh = by1 - by0 + 1;
+    if (bw > 0 && bh > 0 && (long long)bw * bh <= cache_nodes) {
+      cached = true;
+      C.bx0 = s_box[0]; C.by0 = by0; C.bw = bw; C.bh = bh;
+      const int nbox = bw * bh;
+      const long long Nn = (long long)L.nx * L.ny;
+      T* cw = (T*)s_dyn;
+      constexpr int NB = 4;   // nodes per lane per batch: 36 loads in flight
+      T hv[NB][kQ];
+      for (int k0 = 0; k0 < nbox; k0 += NB * nt) {
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
           const int k = k0 + q * nt + t;
@@ -705,23 +692,23 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
           if (pery) row = wrap_i(row, L.ny);
           pull_node(A, Nn, L.nx, L.ny, pery, col, row, hv[q]);
         }
-      }
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int k = k0 + q * nt + t;
-        if (k >= nbox) continue;
-        double drho = 0.0, jx = 0.0, jy = 0.0;
+        for (int q = 0; q < NB; ++q) {
+          const int k = k0 + q * nt + t;
+          if (k >= nbox) continue;
+          double drho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-          const double h = double(hv[q][i]);
-          drho += h;
-          jx += ex(i) * h;
-          jy += ey(i) * h;
+          for (int i = 0; i < kQ; ++i) {
+            const double h = double(hv[q][i]);
+            drho += h;
+            jx += ex(i) * h;
+            jy += ey(i) * h;
+          }
+          const double r = 1.0 + drho;
+          cw[3 * k] = T(r);
+          cw[3 * k + 1] = T((jx + 0.5 * L.gx) / r);
+          cw[3 * k + 2] = T((jy + 0.5 * L.gy) / r);
         }
-        const double r = 1.0 + drho;
-        cw[3 * k] = T(r);
-        cw[3 * k + 1] = T((jx + 0.5 * L.gx) / r);
-        cw[3 * k + 2] = T((jy + 0.5 * L.gy) / r);
       }
     }
   }

@@ -206,6 +206,7 @@ __device__ inline void register_markers(int* cnt, int* bin, int cap, int* overfl
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int key[R][9], leader[R][9], rank[R][9], gcount[R][9];
+  unsigned used = 0;   // slots some lane of the wave uses (bit r * 9 + s9; wave-uniform)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     // tile column and row of each stencil offset; an offset whose tile an
@@ -242,8 +243,13 @@ __device__ inline void register_markers(int* cnt, int* bin, int cap, int* overfl
       const bool has = vr[i] && vc[j];
       const int k = has ? L.tile_base + tr[i] * L.ntx + tc[j] : -1;
       key[r][s9] = k;
-      const int kprev = __shfl_up(k, 1);
+      leader[r][s9] = lane;
+      rank[r][s9] = 0;
+      gcount[r][s9] = 0;
       const unsigned long long hasm = __ballot(has);
+      if (hasm == 0ull) continue;
+      used |= 1u << (r * 9 + s9);
+      const int kprev = __shfl_up(k, 1);
       const unsigned long long heads = __ballot(has && (lane == 0 || kprev != k));
       const unsigned long long le = lt | (1ull << lane);
       const unsigned long long mine = heads & le;
@@ -262,12 +268,14 @@ __device__ inline void register_markers(int* cnt, int* bin, int cap, int* overfl
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int s9 = 0; s9 < 9; ++s9)
-      base[r][s9] = gcount[r][s9] > 0 ? atomicAdd(&cnt[key[r][s9]], gcount[r][s9]) : 0;
+      base[r][s9] = (used >> (r * 9 + s9) & 1u) && gcount[r][s9] > 0
+                        ? atomicAdd(&cnt[key[r][s9]], gcount[r][s9]) : 0;
   // 3. positions and stores
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int s9 = 0; s9 < 9; ++s9) {
+      if (!(used >> (r * 9 + s9) & 1u)) continue;
       const int b = __shfl(base[r][s9], leader[r][s9]);
       if (key[r][s9] >= 0) {
         const int pos = b + rank[r][s9];
@@ -328,13 +336,35 @@ __global__ __launch_bounds__(256) void k_stencil(Ptrs<T> p) {
 // Kinematic IB update of a red-cell vertex (Eq. kinematicPos): the velocity
 // of the step, interpolated at X^n with the stencil stored for X^n, then
 // BDF2 (forward Euler on the first step).
+// Split in two so that a lane handling several vertices issues every load
+// of all of them before it waits: first the stencil and X^{n-1} (needed by
+// BDF2 only, loaded unconditionally), then the velocity gather.
+struct RbcAdv {
+  int cx, cy;
+  double wx[3], wy[3];
+  double xm, ym;
+};
+
 template <typename T>
-__device__ inline void advance_rbc(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y,
-                                   bool first, double& xn, double& yn) {
+__device__ inline void rbc_adv_load(const Ptrs<T>& p, int gm, RbcAdv& a) {
+  const int nm = p.nm_total;
+  a.cx = p.cx[gm];
+  a.cy = p.cy[gm];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a.wx[k] = p.wx[k * nm + gm];
+    a.wy[k] = p.wy[k * nm + gm];
+  }
+  a.xm = p.xm[gm];
+  a.ym = p.ym[gm];
+}
+
+template <typename T>
+__device__ inline void rbc_adv_finish(const Ptrs<T>& p, const LatDev& L, const RbcAdv& in, double X,
+                                      double Y, bool first, double& xn, double& yn) {
   const long long N = (long long)L.nx * L.ny;
   const T* U = p.U + 2 * L.node_base;
-  const int nm = p.nm_total;
-  const int cx = p.cx[gm], cy = p.cy[gm];
+  const int cx = in.cx, cy = in.cy;
   double ux = 0.0, uy = 0.0;
   // a row beyond a wall has weight exactly zero: it reads a clamped row and
   // adds zeros, so all 18 loads are independent of control flow
@@ -343,11 +373,11 @@ __device__ inline void advance_rbc(const Ptrs<T>& p, const LatDev& L, int gm, do
     int row = cy + b2 - 1;
     if (L.periodic_y) row = wrap_i(row, L.ny);
     else row = min(max(row, 0), L.ny - 1);
-    const double wy = p.wy[b2 * nm + gm];
+    const double wy = in.wy[b2];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int col = wrap_i(cx + a - 1, L.nx);
-      const double w = p.wx[a * nm + gm] * wy;
+      const double w = in.wx[a] * wy;
       const long long node = (long long)row * L.nx + col;
       ux += double(U[node]) * w;
       uy += double(U[N + node]) * w;
@@ -357,9 +387,17 @@ __device__ inline void advance_rbc(const Ptrs<T>& p, const LatDev& L, int gm, do
     xn = X + ux;
     yn = Y + uy;
   } else {
-    xn = (2.0 / 3.0) * (2.0 * X - 0.5 * p.xm[gm] + ux);
-    yn = (2.0 / 3.0) * (2.0 * Y - 0.5 * p.ym[gm] + uy);
+    xn = (2.0 / 3.0) * (2.0 * X - 0.5 * in.xm + ux);
+    yn = (2.0 / 3.0) * (2.0 * Y - 0.5 * in.ym + uy);
   }
+}
+
+template <typename T>
+__device__ inline void advance_rbc(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y,
+                                   bool first, double& xn, double& yn) {
+  RbcAdv a;
+  rbc_adv_load(p, gm, a);
+  rbc_adv_finish(p, L, a, X, Y, first, xn, yn);
 }
 
 // ---------------------------------------------------------------- k_bonds
@@ -612,11 +650,16 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
         xo[r] = p.x[gmv[r]];
         yo[r] = p.y[gmv[r]];
       }
+      if (kind == kRBC) {
+        RbcAdv ra[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (kind == kRBC) {
-          advance_rbc(p, L, gmv[r], xo[r], yo[r], first_prev, xn[r], yn[r]);
-        } else {
+        for (int r = 0; r < R; ++r) rbc_adv_load(p, gmv[r], ra[r]);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          rbc_adv_finish(p, L, ra[r], xo[r], yo[r], first_prev, xn[r], yn[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
           xn[r] = p.xn[gmv[r]];
           yn[r] = p.yn[gmv[r]];
         }

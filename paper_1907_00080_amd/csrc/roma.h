@@ -12,14 +12,16 @@
 
 namespace lbib {
 
+// One square root, of the argument of whichever piece applies (the same
+// values as evaluating the pieces separately, without a divergent branch).
 LBIB_HD double roma_phi(double r) {
-  double a = fabs(r);
-  if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) * (1.0 / 3.0);
-  if (a <= 1.5) {
-    double b = 1.0 - a;
-    double s = 1.0 - 3.0 * b * b;
-    return (5.0 - 3.0 * a - sqrt(s > 0.0 ? s : 0.0)) * (1.0 / 6.0);
-  }
+  const double a = fabs(r);
+  const bool inner = a <= 0.5;
+  const double b = 1.0 - a;
+  const double s = 1.0 - 3.0 * b * b;
+  const double q = sqrt(inner ? 1.0 - 3.0 * a * a : (s > 0.0 ? s : 0.0));
+  if (inner) return (1.0 + q) * (1.0 / 3.0);
+  if (a <= 1.5) return (5.0 - 3.0 * a - q) * (1.0 / 6.0);
   return 0.0;
 }
 

@@ -7,8 +7,9 @@ and velocity history; the ligand-to-receptor bond table; the step counter.
 Order of the sub-steps within step n (the paper does not fix it; this is
 the reading used everywhere in this project):
   1. bonds: rupture then formation at the positions X^n;
-  2. membrane forces at X^n (Eqs. strainFor, bendFor, areaFor) and
-     adhesion springs (Eq. adhFor);
+  2. membrane forces at X^n (Eqs. strainFor, bendFor, areaFor), adhesion
+     springs (Eq. adhFor) and, when enabled, the repulsion between vertices
+     of different bodies (Eq. repFor, see repulsion.py);
   3. particles: probe loads from the pre-forcing fluid state, new
      positions X^{n+1} and velocities, weak-coupling forces (Sec. 2.3;
      soft vertices impose their displacement velocity, see particles.py);
@@ -24,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import adhesion, ib, lattice, membrane, particles
+from . import adhesion, ib, lattice, membrane, particles, repulsion
 
 RBC_KINEMATIC = 0
 PARTICLE_SOFT = 1
@@ -84,6 +85,8 @@ class Sim:
         self.bond_params = adhesion.BondParams(a.y_cr, a.y_eq, a.kf0_dt, a.kr0_dt,
                                                a.sigma_ts_frac, a.kbt)
         self.freeze_topology = bool(a.freeze_topology)
+        self.rep_coeff = float(getattr(wl, "repulsion", 0.0))
+        self.rep_cutoff = float(getattr(wl, "repulsion_cutoff", repulsion.CUTOFF))
         self.n = 0
         self.ties = 0
         self.rho = rho0.copy()
@@ -141,10 +144,16 @@ class Sim:
         ux_s = (jx + 0.5 * self.gx) / rho_s
         uy_s = (jy + 0.5 * self.gy) / rho_s
         # 2-3. forces and particle motion
+        if self.rep_coeff > 0.0:
+            frep = repulsion.forces([b.X for b in self.bodies], self.rep_coeff, self.rep_cutoff,
+                                    nx, ny, py)
+        else:
+            frep = [np.zeros((b.nv, 2)) for b in self.bodies]
         Xnext = []
         for bi, b in enumerate(self.bodies):
             if b.kind == RBC_KINEMATIC:
                 F = membrane.internal_force(b.X, b.l0, b.theta0, b.A0, b.ks, b.kb, b.ka, b.p_ref)
+                F = F + frep[bi]
                 self.marker_force[bi] = F
                 Xnext.append(None)
                 continue
@@ -154,14 +163,15 @@ class Sim:
             ds = particles.marker_weights(b.X)
             if b.kind == PARTICLE_SOFT:
                 Fv = (membrane.internal_force(b.X, b.l0, b.theta0, b.A0, b.ks, b.kb, b.ka, b.p_ref)
-                      + membrane.share_to_vertices(fel))
+                      + membrane.share_to_vertices(fel) + frep[bi])
                 Xn1 = b.X + U0 + 0.5 * Fv / b.mv
                 # velocity imposed by the weak coupling: displacement of the step
                 Un1 = Xn1 - b.X
             else:
-                Ftot = fel.sum(axis=0)
+                Ftot = fel.sum(axis=0) + frep[bi].sum(axis=0)
                 c = membrane.centroids(b.X)
-                Mtot = float(np.sum(particles.cross2(c - b.Xc[None, :], fel)))
+                Mtot = float(np.sum(particles.cross2(c - b.Xc[None, :], fel))
+                             + np.sum(particles.cross2(b.X - b.Xc[None, :], frep[bi])))
                 U = particles.bdf2(b.U, b.Um, Ftot / b.mass, first)
                 Om = particles.bdf2(b.Om, b.Omm, Mtot / b.inertia, first)
                 b.Um, b.U = b.U, U

@@ -36,6 +36,8 @@ SEED_BASE = 190700080  # seeds are SEED_BASE + config number (+ instance)
 
 BOLTZMANN = 1.380649e-23
 
+REPULSION_COEFF = 1e-4 / (8.0 * np.sqrt(2.0))  # Eq. repFor prefactor, lattice units
+
 
 @dataclass
 class Body:
@@ -75,6 +77,8 @@ class Workload:
     bodies: List[Body] = field(default_factory=list)
     receptors: List[np.ndarray] = field(default_factory=lambda: [np.zeros(0), np.zeros(0)])
     adhesion: Adhesion = field(default_factory=Adhesion)
+    repulsion: float = 0.0              # Eq. repFor coefficient (0: off; REPULSION_COEFF)
+    repulsion_cutoff: float = 2.0       # pairs closer than this interact
     rho0: Optional[np.ndarray] = None   # (ny, nx) initial density, None -> 1
     u0: Optional[np.ndarray] = None     # (2, ny, nx) initial velocity, None -> 0
     steps: int = 1000

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define LBIB_ABI_VERSION 2u
+#define LBIB_ABI_VERSION 3u
 
 typedef struct lbib_ctx lbib_ctx;
 
@@ -134,7 +134,9 @@ typedef struct {
   int32_t nbonds;
   int32_t bin_overflow;  /* marker-bin registrations dropped since set-up (a
                             full bin also poisons its tile's force, so the
-                            watchdog reports it); 0 in any valid run       */
+                            watchdog reports it), plus bodies whose
+                            repulsion candidate list was truncated; 0 in
+                            any valid run                                  */
   int32_t sync_timeouts; /* in-kernel waits for the bond update that gave up
                             (0 in any valid run)                           */
 } lbib_diag;
@@ -163,6 +165,22 @@ lbib_status lbib_set_receptors(lbib_ctx* ctx, int32_t wall, const double* x, int
 
 /* Bond kinetics parameters (setup phase; defaults: no bonds form). */
 lbib_status lbib_set_adhesion(lbib_ctx* ctx, const lbib_adhesion_desc* desc);
+
+/* Repulsion between vertices of different bodies (setup phase; default off),
+ * Sec. 2.2 "Particle-Particle Interaction", Eq. (repFor): every vertex closer
+ * than `cutoff` (lattice units) to a vertex of another body of the same
+ * lattice adds coeff * sqrt(1 / d^5) along its own inward vertex normal (the
+ * normalised sum of its two element normals, negated); d uses the minimum
+ * image along periodic axes.  The paper's coefficient is 1e-4 / (8 sqrt 2);
+ * cutoff 2 is this library's reading (the expression has none).  Evaluated
+ * at X^n with the membrane forces: red cells spread it, soft particles add
+ * it to their vertex forces, rigid particles to their force and torque.
+ * coeff = 0 switches it off.  With it on, the merged step form is not used
+ * (the repulsion needs every body's X^n first) and the adjoint calls return
+ * LBIB_EINVAL.  Errors: LBIB_EINVAL for coeff < 0, a non-finite value or a
+ * cutoff outside (0, 16]; LBIB_ESTATE outside set-up or on a batch (a batch
+ * takes each instance's setting). */
+lbib_status lbib_set_repulsion(lbib_ctx* ctx, double coeff, double cutoff);
 
 /* Initial fluid state (setup phase): populations at equilibrium with
  * density rho and velocity (ux, uy), host arrays of ny*nx doubles, row-major

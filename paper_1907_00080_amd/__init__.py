@@ -29,7 +29,8 @@ TILES = [(64, 4), (128, 2), (32, 8), (256, 1)]
 # symbols the library exports (include/lbib.h and include/lbib_batch.h)
 EXPORTS = [
     "lbib_abi_version", "lbib_status_string", "lbib_last_error", "lbib_create",
-    "lbib_add_body", "lbib_set_receptors", "lbib_set_adhesion", "lbib_init_fields",
+    "lbib_add_body", "lbib_set_receptors", "lbib_set_adhesion", "lbib_set_repulsion",
+    "lbib_init_fields",
     "lbib_workspace_query", "lbib_bind", "lbib_finalize_setup", "lbib_step",
     "lbib_set_watchdog", "lbib_set_graph_steps", "lbib_get_fields", "lbib_get_markers",
     "lbib_set_markers", "lbib_get_marker_forces", "lbib_num_ligands", "lbib_get_bonds",
@@ -102,6 +103,7 @@ def library() -> ctypes.CDLL:
         "lbib_add_body": (I32, [P, ctypes.POINTER(BodyDesc), dp, ip]),
         "lbib_set_receptors": (I32, [P, I32, dp, I32]),
         "lbib_set_adhesion": (I32, [P, ctypes.POINTER(AdhesionDesc)]),
+        "lbib_set_repulsion": (I32, [P, D, D]),
         "lbib_init_fields": (I32, [P, dp, dp, dp]),
         "lbib_workspace_query": (I32, [P, ctypes.POINTER(ctypes.c_size_t)]),
         "lbib_bind": (I32, [P, P, ctypes.c_size_t, P]),
@@ -279,6 +281,8 @@ def _create(lib, workload, dtype: int, tile) -> ctypes.c_void_p:
     ad = AdhesionDesc(float(a.y_cr), float(a.y_eq), float(a.kf0_dt), float(a.kr0_dt),
                       float(a.sigma_ts_frac), float(a.kbt), int(a.freeze_topology))
     chk(lib.lbib_set_adhesion(h, ctypes.byref(ad)))
+    chk(lib.lbib_set_repulsion(h, float(getattr(workload, "repulsion", 0.0)),
+                               float(getattr(workload, "repulsion_cutoff", 2.0))))
     rho = None if workload.rho0 is None else np.ascontiguousarray(workload.rho0, dtype=np.float64)
     ux = uy = None
     if workload.u0 is not None:

@@ -35,6 +35,7 @@ struct InstHost {
   std::vector<BodyHost> bodies;
   std::vector<double> rec[2];
   lbib_adhesion_desc adh{};
+  double rep_coeff = 0.0, rep_cutoff = 2.0;   // vertex repulsion (Eq. repFor)
   std::vector<double> rho0, ux0, uy0;
 };
 
@@ -53,7 +54,7 @@ bool valid_tile(int tx, int ty) {
 struct Layout {
   size_t lat, body, A, B, U;
   size_t x, y, xm, ym, xn, yn, fx, fy, l0, th0, r0x, r0y;
-  size_t mbody, minfo, cx, cy, wx, wy;
+  size_t mbody, minfo, cx, cy, wx, wy, frep;
   size_t s[9];
   size_t cnt[2], bins[2], touched, overflow, fmax, bond_flag, step_slot, spin, Uspare, tile_inst;
   size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma;
@@ -93,6 +94,7 @@ struct lbib_ctx {
   // kernels, 2 merged advance, 3 overlapped lattice tiles
   int step_mode = 0;
   bool merge_advance = true;  // resolved from step_mode and the bodies
+  bool repulsion = false;     // some instance has the vertex repulsion on
   bool overlap = false;
   hipStream_t aux = nullptr;  // second stream of the overlapped form
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -178,6 +180,7 @@ void compute_layout(lbib_ctx* c) {
   L.cy = take(4 * nm);
   L.wx = take(8 * 3 * nm);
   L.wy = take(8 * 3 * nm);
+  L.frep = take(8 * nm);
   for (auto& s : L.s) s = take(8 * nm);
   for (int k = 0; k < 2; ++k) {
     L.cnt[k] = take(4 * (size_t)c->ntiles);
@@ -229,6 +232,7 @@ Ptrs<T> make_ptrs(const lbib_ctx* c) {
   p.minfo = (int*)(w + L.minfo);
   p.cx = (int*)(w + L.cx); p.cy = (int*)(w + L.cy);
   p.wx = (double*)(w + L.wx); p.wy = (double*)(w + L.wy);
+  p.frep = (double*)(w + L.frep);
   double** sp[] = {&p.s_len, &p.s_nx, &p.s_ny, &p.s_bc, &p.s_bnx, &p.s_bny, &p.s_bfl, &p.s_fex, &p.s_fey};
   for (int k = 0; k < 9; ++k) *sp[k] = (double*)(w + L.s[k]);
   p.cnt_cur = (int*)(w + L.cnt[c->parity]);
@@ -368,6 +372,7 @@ lbib_status upload_all(lbib_ctx* c) {
     D.seed = I.lat.seed;
     D.y_cr = I.adh.y_cr; D.y_eq = I.adh.y_eq; D.kf0_dt = I.adh.kf0_dt; D.kr0_dt = I.adh.kr0_dt;
     D.sigma_ts_frac = I.adh.sigma_ts_frac; D.kbt = I.adh.kbt; D.freeze = I.adh.freeze_topology;
+    D.rep_coeff = I.rep_coeff; D.rep_cutoff = I.rep_cutoff;
     for (int t = 0; t < D.ntx * D.nty; ++t) tile_inst[D.tile_base + t] = i;
     int m = D.marker_base, nl = 0;
     for (auto& b : I.bodies) {
@@ -506,14 +511,20 @@ lbib_status upload_all(lbib_ctx* c) {
 // on a second stream while the body kernel runs).  Automatic: merged when
 // possible, else three kernels (measured faster than the overlapped form on
 // the 2000 x 200 and 6667 x 667 capillaries and the 64-instance sweep).
+// The vertex repulsion needs X^n of every body before any body's forces,
+// which the merged form cannot give (there each body workgroup finishes its
+// own advance): with the repulsion on, the merged form is not used.
 void resolve_step_mode(lbib_ctx* c) {
   bool small_bodies = true;
-  for (auto& I : c->inst)
+  c->repulsion = false;
+  for (auto& I : c->inst) {
     for (auto& b : I.bodies)
       if (b.d.nv > kSmallBody) small_bodies = false;
+    if (I.rep_coeff > 0.0 && !I.bodies.empty()) c->repulsion = true;
+  }
   int m = c->step_mode;
-  if (m == 0) m = small_bodies ? 2 : 1;
-  c->merge_advance = m == 2 && small_bodies;
+  if (m == 0) m = small_bodies && !c->repulsion ? 2 : 1;
+  c->merge_advance = m == 2 && small_bodies && !c->repulsion;
   c->overlap = m == 3;
 }
 
@@ -523,6 +534,7 @@ void enqueue_steps(lbib_ctx* c, long long n) {
   if (c->overlap && !c->ktiming) {
     for (long long k = 0; k < n; ++k) {
       Ptrs<T> p = make_ptrs<T>(c);
+      if (c->repulsion) launch_repulsion<T>(p, a, c->stream);
       (void)hipEventRecord(c->ev_fork, c->stream);
       (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
       launch_lb_fused<T>(p, a, c->aux, 1 | (1 << 2));        // tiles without IB force
@@ -537,6 +549,7 @@ void enqueue_steps(lbib_ctx* c, long long n) {
   }
   for (long long k = 0; k < n; ++k) {
     Ptrs<T> p = make_ptrs<T>(c);
+    if (c->repulsion) launch_repulsion<T>(p, a, c->stream);
     launch_lagrangian<T>(p, a, c->stream, c->merge_advance && k > 0);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->ktiming && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
@@ -787,12 +800,14 @@ lbib_status set_freeze(lbib_ctx* c, int32_t f) {
 lbib_status adj_check_sizes(lbib_ctx* c) {
   if (c->phase != 2) return fail(c, LBIB_ESTATE, "finalize_setup before binding an adjoint workspace");
   if (c->ninst != 1) return fail(c, LBIB_EINVAL, "the adjoint runs on single-lattice contexts");
+  if (c->repulsion) return fail(c, LBIB_EINVAL, "the adjoint does not cover the vertex repulsion");
   return LBIB_OK;
 }
 
 lbib_status adj_check(lbib_ctx* c) {
   if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
   if (c->ninst != 1) return fail(c, LBIB_EINVAL, "the adjoint runs on single-lattice contexts");
+  if (c->repulsion) return fail(c, LBIB_EINVAL, "the adjoint does not cover the vertex repulsion");
   for (auto& b : c->inst[0].bodies)
     if (b.d.kind == LBIB_PARTICLE_RIGID)
       return fail(c, LBIB_EINVAL, "the adjoint covers red cells and soft particles (no rigid bodies)");
@@ -1085,6 +1100,17 @@ lbib_status lbib_set_adhesion(lbib_ctx* c, const lbib_adhesion_desc* d) {
   if (!(d->kbt > 0) || d->y_cr < 0 || d->kf0_dt < 0 || d->kr0_dt < 0)
     return fail(c, LBIB_EINVAL, "bad adhesion parameters");
   c->inst.back().adh = *d;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_repulsion(lbib_ctx* c, double coeff, double cutoff) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 0 || c->is_batch) return fail(c, LBIB_ESTATE, "repulsion can only be set during set-up");
+  if (!std::isfinite(coeff) || coeff < 0.0) return fail(c, LBIB_EINVAL, "repulsion coefficient must be finite and >= 0");
+  if (!std::isfinite(cutoff) || !(cutoff > 0.0) || cutoff > 16.0)
+    return fail(c, LBIB_EINVAL, "repulsion cutoff must be in (0, 16]");
+  c->inst.back().rep_coeff = coeff;
+  c->inst.back().rep_cutoff = cutoff;
   return LBIB_OK;
 }
 

@@ -606,7 +606,10 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
   // lane), requested now so that the loads are in flight during the work
   // before their use
   constexpr int kPre = (kVmax + kBodyThreads - 1) / kBodyThreads;
-  double pre_th0[kPre], pre_l0[kPre], pre_l0m[kPre];
+  double pre_th0[kPre], pre_l0[kPre], pre_l0m[kPre], pre_rep[kPre];
+  // vertex repulsion (Eq. repFor): summed magnitudes from the repulsion
+  // kernel, which runs before this one (never in the merged form)
+  const bool rep = !ADV && L.rep_coeff > 0.0;
   if constexpr (SMALL) {
 #pragma unroll
     for (int j = 0; j < kPre; ++j) {
@@ -616,6 +619,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       pre_th0[j] = soft ? p.th0[v0 + v] : 0.0;
       pre_l0[j] = soft ? p.l0[v0 + v] : 0.0;
       pre_l0m[j] = soft ? p.l0[v0 + vm] : 0.0;
+      pre_rep[j] = rep ? p.frep[v0 + v] : 0.0;
     }
   }
   // per-vertex scratch: LDS for small bodies, workspace otherwise
@@ -780,15 +784,18 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
     S_len[v] = lr;
     S_nx[v] = tyr;
     S_ny[v] = -txr;
+    if (kind != kRigid || rep) {
+      // vertex normal (bending; also the direction of the repulsion)
+      const double nsx = tyl + tyr, nsy = -txl - txr;
+      const double nn = sqrt(nsx * nsx + nsy * nsy);
+      S_bnx[v] = nsx / nn;
+      S_bny[v] = nsy / nn;
+    }
     if (kind != kRigid) {
       const double cr = txl * tyr - tyl * txr;
       const double dt = txl * txr + tyl * tyr;
       const double th = atan2(cr, dt);
-      const double nsx = tyl + tyr, nsy = -txl - txr;
-      const double nn = sqrt(nsx * nsx + nsy * nsy);
       S_bc[v] = kb * (th - th0v);
-      S_bnx[v] = nsx / nn;
-      S_bny[v] = nsy / nn;
     }
     shoe += xv * yp - xp * yv;
   };
@@ -866,13 +873,27 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
   if (kind == kRigid) {
     const double xc0 = Bp->xc, yc0 = Bp->yc;
     double r3[3] = {0.0, 0.0, 0.0};
-    for (int l = t; l < nv; l += nt) {
+    auto rigid_sum = [&](int l, double sv) {
       const int lp = l + 1 == nv ? 0 : l + 1;
       const double fex = S_fex[l], fey = S_fey[l];
       const double cx = 0.5 * (X[l] + X[lp]) - xc0, cy = 0.5 * (Y[l] + Y[lp]) - yc0;
       r3[0] += fex;
       r3[1] += fey;
       r3[2] += cx * fey - cy * fex;
+      if (rep) {
+        // repulsion at vertex l, along its inward normal; lever X_l - X_c
+        const double frx = -sv * S_bnx[l], fry = -sv * S_bny[l];
+        r3[0] += frx;
+        r3[1] += fry;
+        r3[2] += (X[l] - xc0) * fry - (Y[l] - yc0) * frx;
+      }
+    };
+    if constexpr (SMALL) {
+#pragma unroll
+      for (int j = 0; j < kPre; ++j)
+        if (t + j * nt < nv) rigid_sum(t + j * nt, pre_rep[j]);
+    } else {
+      for (int l = t; l < nv; l += nt) rigid_sum(l, rep ? p.frep[v0 + l] : 0.0);
     }
     block_sum<3>(s_red, r3);
     if (t == 0) {
@@ -920,7 +941,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
 
   // membrane vertex forces: strain + bending + shared element loads
   double fm = 0.0;
-  auto vertex_force = [&](int v, double l0v, double l0m) {
+  auto vertex_force = [&](int v, double l0v, double l0m, double sv) {
     const int gm = v0 + v;
     const int vm = v == 0 ? nv - 1 : v - 1, vp = v + 1 == nv ? 0 : v + 1;
     const int vmm = vm == 0 ? nv - 1 : vm - 1;
@@ -951,6 +972,10 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
     }
     fx += 0.5 * S_fex[v] + 0.5 * S_fex[vm];
     fy += 0.5 * S_fey[v] + 0.5 * S_fey[vm];
+    if (rep) {
+      fx -= sv * S_bnx[v];
+      fy -= sv * S_bny[v];
+    }
     if (kind == kRBC) {
       p.fx[gm] = fx;
       p.fy[gm] = fy;
@@ -977,11 +1002,11 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
   if constexpr (SMALL) {
 #pragma unroll
     for (int j = 0; j < kPre; ++j)
-      if (t + j * nt < nv) vertex_force(t + j * nt, pre_l0[j], pre_l0m[j]);
+      if (t + j * nt < nv) vertex_force(t + j * nt, pre_l0[j], pre_l0m[j], pre_rep[j]);
   } else {
     for (int v = t; v < nv; v += nt) {
       const int vm = v == 0 ? nv - 1 : v - 1;
-      vertex_force(v, p.l0[v0 + v], p.l0[v0 + vm]);
+      vertex_force(v, p.l0[v0 + v], p.l0[v0 + vm], rep ? p.frep[v0 + v] : 0.0);
     }
   }
   record_fmax(p.fmax_bits + inst, fm, s_red);

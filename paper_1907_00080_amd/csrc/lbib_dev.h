@@ -56,6 +56,7 @@ struct LatDev {
   double y_cr, y_eq, kf0_dt, kr0_dt, sigma_ts_frac, kbt;
   int freeze;
   int pad_;
+  double rep_coeff, rep_cutoff;   // vertex repulsion (Eq. repFor); coeff 0: off
 };
 
 // Per-body description and rigid-body state (device copy; rigid state mutable).
@@ -83,6 +84,7 @@ struct Ptrs {
   int* minfo;            // per marker: (instance << 2) | body kind
   int *cx, *cy;
   double *wx, *wy;       // [3][Nm]
+  double* frep;          // per marker: summed repulsion magnitude of this step
   double *s_len, *s_nx, *s_ny, *s_bc, *s_bnx, *s_bny, *s_bfl, *s_fex, *s_fey;  // per-vertex scratch
   // marker bins of fixed capacity per tile, double buffered: the fused
   // kernel consumes (and clears) the current set while the marker advance
@@ -187,6 +189,8 @@ struct StepArgs {
   int max_nv;           // most vertices of any body
 };
 
+template <typename T>
+void launch_repulsion(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
 template <typename T>
 void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mode = 3,
                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for name in decl:
         assert hasattr(lib, name), name
     assert decl == set(pkg.EXPORTS)
-    assert lib.lbib_abi_version() == 2
+    assert lib.lbib_abi_version() == 3
     for s, n in pkg.STATUS.items():
         assert lib.lbib_status_string(s).decode() == n
 
@@ -169,3 +169,20 @@ def test_step_mode_validation():
         assert lib.lbib_get_step_mode(h, ctypes.byref(got)) == 0
         assert got.value == m
     lib.lbib_destroy(h)
+
+
+def test_repulsion_validation_and_phase():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    try:
+        assert lib.lbib_set_repulsion(h, -1e-6, 2.0) == 1
+        assert lib.lbib_set_repulsion(h, float("nan"), 2.0) == 1
+        assert lib.lbib_set_repulsion(h, 1e-5, 0.0) == 1
+        assert lib.lbib_set_repulsion(h, 1e-5, 17.0) == 1
+        assert lib.lbib_set_repulsion(h, 1e-5, float("inf")) == 1
+        assert lib.lbib_set_repulsion(h, configs.REPULSION_COEFF, 2.0) == 0
+        assert lib.lbib_set_repulsion(h, 0.0, 2.0) == 0      # off
+        assert lib.lbib_set_repulsion(None, 1e-5, 2.0) == 1
+    finally:
+        lib.lbib_destroy(h)

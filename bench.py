@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain sweep")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient window")
+    ap.add_argument("--no-repulsion", action="store_true",
+                    help="skip the step with the vertex repulsion switched on")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -170,6 +172,8 @@ def main():
         out["batched"] = batched_vs_plain(pkg, torch, args.batch_instances, args.batch_steps)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_window(pkg, torch, args.adjoint_steps, 100)
+    if not args.no_repulsion:
+        out["repulsion"] = repulsion_cost(pkg, torch, args.workload, tile, 1000, args.graph_steps)
     if not args.no_cpu:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
@@ -212,6 +216,36 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps)
           file=sys.stderr, flush=True)
     sim.close()
     return {"mlups": mlups, "ms_step": ms_step, "kernel_ms": k_ms, "kernel_launches": k_n}
+
+
+def repulsion_cost(pkg, torch, name, tile, steps, graph_steps):
+    """The same workload with the vertex repulsion (Eq. repFor, the paper's
+    coefficient, cutoff 2) switched on, which runs the three-kernel step form
+    plus the repulsion kernel; against the same form without it and against
+    the default (merged) form without it."""
+    from workloads import configs
+    res = {}
+    for key, coeff, mode in (("on", configs.REPULSION_COEFF, 0), ("off_three_kernel", 0.0, 1),
+                             ("off_default", 0.0, 0)):
+        wl = make_workload(name)
+        wl.repulsion = coeff
+        sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=graph_steps)
+        sim.set_step_mode(mode)
+        sim.step(200)
+        ms = _timed(torch, sim, steps) / steps
+        d = sim.diagnostics()
+        if d["nonfinite"] or d["bin_overflow"] or d["sync_timeouts"]:
+            raise SystemExit("invalid state after the repulsion benchmark")
+        res[key] = {"ms_per_step": round(ms, 5), "mlups": round(wl.nodes / (ms * 1e-3) / 1e6, 1),
+                    "step_mode": sim.step_mode}
+        sim.close()
+    res["workload"] = name + " with vertex repulsion"
+    res["repulsion_us_per_step"] = round(1e3 * (res["on"]["ms_per_step"]
+                                               - res["off_three_kernel"]["ms_per_step"]), 2)
+    print(f"bench: repulsion on {res['on']['ms_per_step'] * 1e3:.2f} us/step, three kernels "
+          f"without {res['off_three_kernel']['ms_per_step'] * 1e3:.2f}, default form "
+          f"{res['off_default']['ms_per_step'] * 1e3:.2f}", file=sys.stderr, flush=True)
+    return res
 
 
 def _timed(torch, ctx, steps):

@@ -54,7 +54,7 @@ bool valid_tile(int tx, int ty) {
 struct Layout {
   size_t lat, body, A, B, U;
   size_t x, y, xm, ym, xn, yn, fx, fy, l0, th0, r0x, r0y;
-  size_t mbody, minfo, cx, cy, wx, wy, frep;
+  size_t mbody, minfo, cx, cy, wx, wy, frep, rep_chunk;
   size_t s[9];
   size_t cnt[2], bins[2], touched, overflow, fmax, bond_flag, step_slot, spin, Uspare, tile_inst;
   size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma;
@@ -95,6 +95,7 @@ struct lbib_ctx {
   int step_mode = 0;
   bool merge_advance = true;  // resolved from step_mode and the bodies
   bool repulsion = false;     // some instance has the vertex repulsion on
+  int nrep_chunk = 0;         // repulsion work units (kRepChunk vertices of a body)
   bool overlap = false;
   hipStream_t aux = nullptr;  // second stream of the overlapped form
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -134,6 +135,7 @@ int elem_size(int dtype) { return dtype == LBIB_F64 ? 8 : 4; }
 void compute_sizes(lbib_ctx* c) {
   c->ninst = (int)c->inst.size();
   c->nm = c->nbody = c->nlig = c->nrec = c->ntiles = 0;
+  c->nrep_chunk = 0;
   c->nodes = 0;
   c->marker_base.clear(); c->body_base.clear(); c->lig_base.clear();
   c->rec_base.clear(); c->tile_base.clear(); c->node_base.clear();
@@ -147,6 +149,7 @@ void compute_sizes(lbib_ctx* c) {
     for (auto& b : I.bodies) {
       c->nm += b.d.nv;
       c->nbody += 1;
+      c->nrep_chunk += (b.d.nv + kRepChunk - 1) / kRepChunk;
       if (b.d.ligand_stride > 0) c->nlig += (b.d.nv + b.d.ligand_stride - 1) / b.d.ligand_stride;
     }
     c->nrec += (int)(I.rec[0].size() + I.rec[1].size());
@@ -181,6 +184,7 @@ void compute_layout(lbib_ctx* c) {
   L.wx = take(8 * 3 * nm);
   L.wy = take(8 * 3 * nm);
   L.frep = take(8 * nm);
+  L.rep_chunk = take(16 * (size_t)std::max(c->nrep_chunk, 1));
   for (auto& s : L.s) s = take(8 * nm);
   for (int k = 0; k < 2; ++k) {
     L.cnt[k] = take(4 * (size_t)c->ntiles);
@@ -448,6 +452,19 @@ lbib_status upload_all(lbib_ctx* c) {
   HIPCHK(c, up(L.r0x, r0x.data(), 8 * nm));
   HIPCHK(c, up(L.r0y, r0y.data(), 8 * nm));
   HIPCHK(c, up(L.mbody, mbody.data(), 4 * nm));
+  {
+    // work units of the repulsion kernel: (body, first global vertex,
+    // vertex count, instance) per chunk of kRepChunk vertices
+    std::vector<int> chunks;
+    for (int bb = 0; bb < c->nbody; ++bb)
+      for (int v = 0; v < bodies[bb].nv; v += kRepChunk) {
+        chunks.push_back(bb);
+        chunks.push_back(bodies[bb].v0 + v);
+        chunks.push_back(std::min(kRepChunk, bodies[bb].nv - v));
+        chunks.push_back(bodies[bb].inst);
+      }
+    if (!chunks.empty()) HIPCHK(c, up(L.rep_chunk, chunks.data(), 4 * chunks.size()));
+  }
   HIPCHK(c, up(L.minfo, minfo.data(), 4 * nm));
   HIPCHK(c, up(L.tile_inst, tile_inst.data(), 4 * tile_inst.size()));
   HIPCHK(c, up(L.lig_body, lig_body.data(), 4 * lig_body.size()));
@@ -465,6 +482,7 @@ lbib_status upload_all(lbib_ctx* c) {
   for (int k = 0; k < 2; ++k) HIPCHK(c, hipMemsetAsync(w + L.cnt[k], 0, 4 * (size_t)c->ntiles, s));
   HIPCHK(c, hipMemsetAsync(w + L.touched, 0, 4 * (size_t)c->ntiles, s));
   HIPCHK(c, hipMemsetAsync(w + L.overflow, 0, 8, s));
+  HIPCHK(c, hipMemsetAsync(w + L.frep, 0, 8 * nm, s));
   HIPCHK(c, hipMemsetAsync(w + L.fmax, 0, 8 * 2 * (size_t)c->ninst, s));
   HIPCHK(c, hipMemsetAsync(w + L.bond_flag, 0, 4 * 2 * (size_t)c->ninst, s));
   HIPCHK(c, hipMemsetAsync(w + L.step_slot, 0, 8 * 2 * (size_t)c->ninst, s));
@@ -534,7 +552,7 @@ void enqueue_steps(lbib_ctx* c, long long n) {
   if (c->overlap && !c->ktiming) {
     for (long long k = 0; k < n; ++k) {
       Ptrs<T> p = make_ptrs<T>(c);
-      if (c->repulsion) launch_repulsion<T>(p, a, c->stream);
+      if (c->repulsion) launch_repulsion<T>(p, a, (const int*)(c->ws + c->L.rep_chunk), c->nrep_chunk, c->stream);
       (void)hipEventRecord(c->ev_fork, c->stream);
       (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
       launch_lb_fused<T>(p, a, c->aux, 1 | (1 << 2));        // tiles without IB force
@@ -549,7 +567,7 @@ void enqueue_steps(lbib_ctx* c, long long n) {
   }
   for (long long k = 0; k < n; ++k) {
     Ptrs<T> p = make_ptrs<T>(c);
-    if (c->repulsion) launch_repulsion<T>(p, a, c->stream);
+    if (c->repulsion) launch_repulsion<T>(p, a, (const int*)(c->ws + c->L.rep_chunk), c->nrep_chunk, c->stream);
     launch_lagrangian<T>(p, a, c->stream, c->merge_advance && k > 0);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->ktiming && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {

@@ -886,6 +886,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
         r3[0] += frx;
         r3[1] += fry;
         r3[2] += (X[l] - xc0) * fry - (Y[l] - yc0) * frx;
+        p.frep[v0 + l] = 0.0;   // applied: the next step's repulsion kernel rewrites it
       }
     };
     if constexpr (SMALL) {
@@ -975,6 +976,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
     if (rep) {
       fx -= sv * S_bnx[v];
       fy -= sv * S_bny[v];
+      p.frep[gm] = 0.0;   // applied: the next step's repulsion kernel rewrites it
     }
     if (kind == kRBC) {
       p.fx[gm] = fx;

@@ -85,6 +85,8 @@ struct Ptrs {
   int *cx, *cy;
   double *wx, *wy;       // [3][Nm]
   double* frep;          // per marker: summed repulsion magnitude of this step
+                         // (written by the repulsion kernel, cleared by the
+                         // body kernel once applied)
   double *s_len, *s_nx, *s_ny, *s_bc, *s_bnx, *s_bny, *s_bfl, *s_fex, *s_fey;  // per-vertex scratch
   // marker bins of fixed capacity per tile, double buffered: the fused
   // kernel consumes (and clears) the current set while the marker advance
@@ -189,8 +191,13 @@ struct StepArgs {
   int max_nv;           // most vertices of any body
 };
 
+// The repulsion kernel's work unit: kRepChunk consecutive vertices of one
+// body; the host lists the chunks as (body, first global vertex, vertex
+// count, instance) records.
+constexpr int kRepChunk = 16;
 template <typename T>
-void launch_repulsion(const Ptrs<T>& p, const StepArgs& a, hipStream_t s);
+void launch_repulsion(const Ptrs<T>& p, const StepArgs& a, const int* chunks, int nchunk,
+                      hipStream_t s);
 template <typename T>
 void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mode = 3,
                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

@@ -252,6 +252,48 @@ lbib_status lbib_set_state(lbib_ctx* ctx, const void* blob, size_t bytes);
 /* Whole-lattice diagnostics (synchronises). */
 lbib_status lbib_diagnostics(lbib_ctx* ctx, lbib_diag* out);
 
+/* Flow regions of a body's lateral position eta = (y_c + 1/2) / ny, the walls
+ * being at y = -1/2 and ny - 1/2 (Sec. 3, three flow regions; the paper's
+ * open intervals leave 0.2 and 0.8 unassigned: they go to the cell-free
+ * layer). */
+enum { LBIB_REGION_CFL = 0,            /* eta <= 0.2 or eta >= 0.8        */
+       LBIB_REGION_INTERMEDIATE = 1,   /* 0.2 < eta < 0.3, 0.7 < eta < 0.8 */
+       LBIB_REGION_BULK = 2 };         /* 0.3 <= eta <= 0.7               */
+
+/* Per-body observables, the quantities the paper reports for margination
+ * and adhesion (Sec. 3: region occupancy, <r_max>/H, rolling and lateral
+ * velocity, n_L / n_L0).  Lattice units; velocities per time step (divide
+ * by u_max for the paper's ratios). */
+typedef struct {
+  double xc, yc;           /* centre of mass (mean of the vertex positions)
+                              at the last observation; x unwrapped          */
+  double x0, y0;           /* at the first observation (release)            */
+  double r_max;            /* largest |yc - y0| over the observations       */
+  double u_x, u_y;         /* centre-of-mass displacement over the last
+                              interval / its steps (0 before the second)    */
+  double u_x_sum, u_y_sum; /* sums of u_x, u_y over the intervals (n_obs - 1)*/
+  int32_t region;          /* LBIB_REGION_* of yc                           */
+  int32_t n_bonds;         /* ligands of the body holding a bond            */
+  int32_t n_bonds0;        /* n_bonds at the first observation              */
+  int32_t n_obs;           /* observations so far                           */
+  int64_t step_obs;        /* step of the last observation                  */
+} lbib_body_obs;
+
+/* One observation of every body at the current step (running phase),
+ * computed on the device and queued on the bound stream (does not
+ * synchronise); records accumulate until lbib_reset_observations.  For the
+ * host's sampling loop: step k, observe, step k, observe, ...  Errors:
+ * LBIB_ESTATE outside the running phase. */
+lbib_status lbib_observe(lbib_ctx* ctx);
+
+/* Copy the records of all bodies (body order; a batch lists its instances'
+ * bodies in instance order) into out[nbody] (synchronises).  Errors:
+ * LBIB_EINVAL for NULL, LBIB_ESTATE outside the running phase. */
+lbib_status lbib_get_observations(lbib_ctx* ctx, lbib_body_obs* out);
+
+/* Clear the records: the next observation is the release (running phase). */
+lbib_status lbib_reset_observations(lbib_ctx* ctx);
+
 /* Measurement: launch the fused lattice kernel (streaming, collision and
  * gathered spreading) `reps` times on the bound stream with the current
  * state, bracketed by HIP events, and return the mean duration per launch

@@ -40,7 +40,10 @@ EXPORTS = [
     "lbib_batch_get_fields", "lbib_batch_get_markers", "lbib_batch_get_bonds",
     "lbib_adjoint_workspace_query", "lbib_adjoint_bind", "lbib_adjoint_forward",
     "lbib_adjoint_backward", "lbib_set_body_params", "lbib_set_step_mode", "lbib_get_step_mode",
+    "lbib_observe", "lbib_get_observations", "lbib_reset_observations",
 ]
+
+REGION_CFL, REGION_INTERMEDIATE, REGION_BULK = 0, 1, 2
 
 
 class LatticeDesc(ctypes.Structure):
@@ -61,6 +64,15 @@ class AdhesionDesc(ctypes.Structure):
     _fields_ = [("y_cr", ctypes.c_double), ("y_eq", ctypes.c_double), ("kf0_dt", ctypes.c_double),
                 ("kr0_dt", ctypes.c_double), ("sigma_ts_frac", ctypes.c_double),
                 ("kbt", ctypes.c_double), ("freeze_topology", ctypes.c_int32)]
+
+
+class BodyObs(ctypes.Structure):
+    """lbib_body_obs: per-body observables (include/lbib.h)."""
+    _fields_ = [("xc", ctypes.c_double), ("yc", ctypes.c_double), ("x0", ctypes.c_double),
+                ("y0", ctypes.c_double), ("r_max", ctypes.c_double), ("u_x", ctypes.c_double),
+                ("u_y", ctypes.c_double), ("u_x_sum", ctypes.c_double), ("u_y_sum", ctypes.c_double),
+                ("region", ctypes.c_int32), ("n_bonds", ctypes.c_int32), ("n_bonds0", ctypes.c_int32),
+                ("n_obs", ctypes.c_int32), ("step_obs", ctypes.c_int64)]
 
 
 class Diag(ctypes.Structure):
@@ -121,6 +133,9 @@ def library() -> ctypes.CDLL:
         "lbib_get_state": (I32, [P, P, ctypes.POINTER(ctypes.c_size_t)]),
         "lbib_set_state": (I32, [P, P, ctypes.c_size_t]),
         "lbib_diagnostics": (I32, [P, ctypes.POINTER(Diag)]),
+        "lbib_observe": (I32, [P]),
+        "lbib_get_observations": (I32, [P, ctypes.POINTER(BodyObs)]),
+        "lbib_reset_observations": (I32, [P]),
         "lbib_get_step": (I32, [P, ctypes.POINTER(ctypes.c_int64)]),
         "lbib_time_lattice_kernel": (I32, [P, I32, ctypes.POINTER(ctypes.c_double)]),
         "lbib_set_kernel_timing": (I32, [P, I32]),
@@ -237,6 +252,26 @@ class _Ctx:
         d = Diag()
         self.check(self.lib.lbib_diagnostics(self.h, ctypes.byref(d)))
         return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    def n_bodies_total(self) -> int:
+        # a Sim keeps one vertex count per body, a Batch one list per instance
+        return sum(len(x) if isinstance(x, list) else 1 for x in getattr(self, "nv", []))
+
+    def observe(self):
+        """One observation of every body at the current step (on the device)."""
+        self.check(self.lib.lbib_observe(self.h))
+
+    def observations(self) -> list:
+        """Per-body observation records (dicts, body order)."""
+        n = self.n_bodies_total()
+        if n == 0:
+            return []
+        arr = (BodyObs * n)()
+        self.check(self.lib.lbib_get_observations(self.h, arr))
+        return [{k: getattr(r, k) for k, _ in BodyObs._fields_} for r in arr]
+
+    def reset_observations(self):
+        self.check(self.lib.lbib_reset_observations(self.h))
 
     def close(self):
         if self.h:

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbib.so")
-SOURCES = ["engine.hip", "k_lattice.hip", "k_lagrangian.hip", "k_adjoint.hip", "k_repulsion.hip"]
+SOURCES = ["engine.hip", "k_lattice.hip", "k_lagrangian.hip", "k_adjoint.hip", "k_repulsion.hip", "k_observe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -54,7 +54,7 @@ bool valid_tile(int tx, int ty) {
 struct Layout {
   size_t lat, body, A, B, U;
   size_t x, y, xm, ym, xn, yn, fx, fy, l0, th0, r0x, r0y;
-  size_t mbody, minfo, cx, cy, wx, wy, frep, rep_chunk;
+  size_t mbody, minfo, cx, cy, wx, wy, frep, rep_chunk, obs;
   size_t s[9];
   size_t cnt[2], bins[2], touched, overflow, fmax, bond_flag, step_slot, spin, Uspare, tile_inst;
   size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma;
@@ -184,6 +184,7 @@ void compute_layout(lbib_ctx* c) {
   L.wx = take(8 * 3 * nm);
   L.wy = take(8 * 3 * nm);
   L.frep = take(8 * nm);
+  L.obs = take(sizeof(lbib_body_obs) * (size_t)std::max(c->nbody, 1));
   L.rep_chunk = take(16 * (size_t)std::max(c->nrep_chunk, 1));
   for (auto& s : L.s) s = take(8 * nm);
   for (int k = 0; k < 2; ++k) {
@@ -483,6 +484,7 @@ lbib_status upload_all(lbib_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.touched, 0, 4 * (size_t)c->ntiles, s));
   HIPCHK(c, hipMemsetAsync(w + L.overflow, 0, 8, s));
   HIPCHK(c, hipMemsetAsync(w + L.frep, 0, 8 * nm, s));
+  HIPCHK(c, hipMemsetAsync(w + L.obs, 0, sizeof(lbib_body_obs) * (size_t)std::max(c->nbody, 1), s));
   HIPCHK(c, hipMemsetAsync(w + L.fmax, 0, 8 * 2 * (size_t)c->ninst, s));
   HIPCHK(c, hipMemsetAsync(w + L.bond_flag, 0, 4 * 2 * (size_t)c->ninst, s));
   HIPCHK(c, hipMemsetAsync(w + L.step_slot, 0, 8 * 2 * (size_t)c->ninst, s));
@@ -1427,6 +1429,34 @@ lbib_status lbib_diagnostics(lbib_ctx* c, lbib_diag* out) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   out->bin_overflow = ovf;
   out->sync_timeouts = spin;
+  return LBIB_OK;
+}
+
+lbib_status lbib_observe(lbib_ctx* c) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  lbib_body_obs* o = (lbib_body_obs*)(c->ws + c->L.obs);
+  if (c->dtype == LBIB_F64) launch_observe<double>(make_ptrs<double>(c), o, c->step, c->stream);
+  else launch_observe<float>(make_ptrs<float>(c), o, c->step, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_observations(lbib_ctx* c, lbib_body_obs* out) {
+  if (!c || !out) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  if (c->nbody == 0) return LBIB_OK;
+  HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.obs, sizeof(lbib_body_obs) * (size_t)c->nbody,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBIB_OK;
+}
+
+lbib_status lbib_reset_observations(lbib_ctx* c) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  HIPCHK(c, hipMemsetAsync(c->ws + c->L.obs, 0, sizeof(lbib_body_obs) * (size_t)std::max(c->nbody, 1),
+                           c->stream));
   return LBIB_OK;
 }
 

@@ -13,6 +13,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include "lbib.h"
 #include "roma.h"
 #include <stdint.h>
 
@@ -190,6 +191,9 @@ struct StepArgs {
   int body_cache_bytes; // LDS cache of rho*, u* per particle workgroup
   int max_nv;           // most vertices of any body
 };
+
+template <typename T>
+void launch_observe(const Ptrs<T>& p, lbib_body_obs* obs, long long step, hipStream_t s);
 
 // The repulsion kernel's work unit: kRepChunk consecutive vertices of one
 // body; the host lists the chunks as (body, first global vertex, vertex

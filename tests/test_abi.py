@@ -186,3 +186,16 @@ def test_repulsion_validation_and_phase():
         assert lib.lbib_set_repulsion(None, 1e-5, 2.0) == 1
     finally:
         lib.lbib_destroy(h)
+
+
+def test_observation_calls_need_a_running_context():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    assert lib.lbib_observe(h) == 2
+    assert lib.lbib_reset_observations(h) == 2
+    rec = (pkg.BodyObs * 1)()
+    assert lib.lbib_get_observations(h, rec) == 2
+    assert lib.lbib_get_observations(h, None) == 1
+    assert lib.lbib_observe(None) == 1
+    lib.lbib_destroy(h)

@@ -174,6 +174,7 @@ def main():
         out["adjoint"] = adjoint_window(pkg, torch, args.adjoint_steps, 100)
     if not args.no_repulsion:
         out["repulsion"] = repulsion_cost(pkg, torch, args.workload, tile, 1000, args.graph_steps)
+        out["observables"] = observables_cost(pkg, torch, args.workload, tile, args.graph_steps)
     if not args.no_cpu:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
@@ -245,6 +246,41 @@ def repulsion_cost(pkg, torch, name, tile, steps, graph_steps):
     print(f"bench: repulsion on {res['on']['ms_per_step'] * 1e3:.2f} us/step, three kernels "
           f"without {res['off_three_kernel']['ms_per_step'] * 1e3:.2f}, default form "
           f"{res['off_default']['ms_per_step'] * 1e3:.2f}", file=sys.stderr, flush=True)
+    return res
+
+
+def observables_cost(pkg, torch, name, tile, graph_steps, every=100, n_obs=20):
+    """On-device observations of the workload every `every` steps: the cost
+    of one observation (HIP events around it) and the resulting per-region
+    counts of the particles at the end."""
+    from workloads import configs
+    wl = make_workload(name)
+    sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=graph_steps)
+    sim.step(200)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    ms = 0.0
+    for _ in range(n_obs):
+        start.record(sim.stream)
+        sim.observe()
+        end.record(sim.stream)
+        sim.step(every)
+        end.synchronize()
+        ms += start.elapsed_time(end)
+    recs = sim.observations()
+    sim.close()
+    parts = [r for r, b in zip(recs, wl.bodies) if b.kind != configs.RBC_KINEMATIC]
+    regions = {"cell_free_layer": 0, "intermediate": 0, "bulk": 0}
+    names = {0: "cell_free_layer", 1: "intermediate", 2: "bulk"}
+    for r in parts:
+        regions[names[r["region"]]] += 1
+    res = {"workload": name, "bodies": len(recs), "every_steps": every, "observations": n_obs,
+           "us_per_observation": round(1e3 * ms / n_obs, 2),
+           "particles_by_region": regions,
+           "particles_with_bonds": sum(1 for r in parts if r["n_bonds"] > 0),
+           "max_r_max_over_H": round(max((r["r_max"] for r in parts), default=0.0) / wl.ny, 6)}
+    print(f"bench: observation of {len(recs)} bodies {res['us_per_observation']} us", file=sys.stderr,
+          flush=True)
     return res
 
 

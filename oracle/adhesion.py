@@ -62,19 +62,23 @@ def min_image(xr: float, cx_wrapped: float, nx: int) -> float:
     return d
 
 
-def wall_y(wall: int, ny: int) -> float:
+def wall_y(wall: int, ny: int, y_walls=None) -> float:
+    """Wall positions: -1/2 and ny - 1/2 (halfway bounce-back), or the given
+    pair (velocity walls on the node rows: 0 and ny - 1)."""
+    if y_walls is not None:
+        return float(y_walls[wall])
     return -0.5 if wall == 0 else ny - 0.5
 
 
-def nearer_wall(cy: float, ny: int):
-    d0 = cy + 0.5
-    d1 = (ny - 0.5) - cy
+def nearer_wall(cy: float, ny: int, y_walls=None):
+    d0 = cy - wall_y(0, ny, y_walls)
+    d1 = wall_y(1, ny, y_walls) - cy
     return (0, d0) if d0 <= d1 else (1, d1)
 
 
-def bond_length(c, xr: float, wall: int, nx: int, ny: int) -> float:
+def bond_length(c, xr: float, wall: int, nx: int, ny: int, y_walls=None) -> float:
     dx = min_image(xr, wrap_x(c[0], nx), nx)
-    dy = c[1] - wall_y(wall, ny)
+    dy = c[1] - wall_y(wall, ny, y_walls)
     return math.sqrt(dx * dx + dy * dy)
 
 
@@ -91,7 +95,7 @@ def rupture_probability(y: float, sigma: float, p: BondParams) -> float:
 
 
 def bond_update(step: int, lig_c, lig_sigma, lig_to_rec, receptors, nx: int, ny: int,
-                p: BondParams, seed: int, instance: int = 0):
+                p: BondParams, seed: int, instance: int = 0, y_walls=None):
     """One rupture-then-formation pass.
 
     lig_c: (N_L, 2) ligand centroids at this time level; lig_sigma: (N_L,)
@@ -117,7 +121,7 @@ def bond_update(step: int, lig_c, lig_sigma, lig_to_rec, receptors, nx: int, ny:
         if r < 0:
             continue
         xr, wall = rec_pos(r)
-        y = bond_length(lig_c[l], xr, wall, nx, ny)
+        y = bond_length(lig_c[l], xr, wall, nx, ny, y_walls)
         P = rupture_probability(y, lig_sigma[l], p)
         u = philox.uniform(seed, step, l, philox.PURPOSE_RUPTURE, instance)
         ties += abs(u - P) < TIE_BAND
@@ -128,7 +132,7 @@ def bond_update(step: int, lig_c, lig_sigma, lig_to_rec, receptors, nx: int, ny:
     for l in range(len(l2r)):
         if not free_at_start[l]:
             continue
-        wall, d = nearer_wall(lig_c[l][1], ny)
+        wall, d = nearer_wall(lig_c[l][1], ny, y_walls)
         if not d < p.y_cr:
             continue
         xs = receptors[wall]
@@ -143,7 +147,7 @@ def bond_update(step: int, lig_c, lig_sigma, lig_to_rec, receptors, nx: int, ny:
                 best, bestd = k, dd
         if best < 0:
             continue
-        y = bond_length(lig_c[l], xs[best], wall, nx, ny)
+        y = bond_length(lig_c[l], xs[best], wall, nx, ny, y_walls)
         P = formation_probability(y, lig_sigma[l], p)
         u = philox.uniform(seed, step, l, philox.PURPOSE_FORM, instance)
         ties += abs(u - P) < TIE_BAND
@@ -153,7 +157,8 @@ def bond_update(step: int, lig_c, lig_sigma, lig_to_rec, receptors, nx: int, ny:
     return l2r, ties
 
 
-def spring_force(c, n, xr: float, wall: int, sigma: float, y_eq: float, nx: int, ny: int):
+def spring_force(c, n, xr: float, wall: int, sigma: float, y_eq: float, nx: int, ny: int,
+                 y_walls=None):
     """Eq. (adhFor): F = sigma (y_l - y_eq) n_l at the element centroid."""
-    y = bond_length(c, xr, wall, nx, ny)
+    y = bond_length(c, xr, wall, nx, ny, y_walls)
     return sigma * (y - y_eq) * np.asarray(n, dtype=np.float64)

@@ -17,6 +17,9 @@ Readings where the text is garbled or silent:
     immersed-boundary force);
   * walls: halfway bounce-back at y = -1/2 and y = ny - 1/2 (no-slip),
     x periodic.  An optional periodic-y mode removes the walls (tests).
+    The paper's own wall condition, Zou-He velocity walls on the node rows
+    y = 0 and y = ny - 1 (wet nodes, channel height ny - 1), is the other
+    mode: see `zou_he`.
 """
 from __future__ import annotations
 
@@ -65,12 +68,12 @@ def guo_source(ux, uy, fx, fy, tau: float) -> np.ndarray:
     return out
 
 
-def stream(fpost: np.ndarray, periodic_y: bool = False) -> np.ndarray:
+def stream(fpost: np.ndarray, periodic_y: bool = False, wet_walls: bool = False) -> np.ndarray:
     """Pull streaming f_i(x) <- f*_i(x - e_i), x periodic.
 
-    With walls, a population whose source node lies beyond y = -1/2 or
-    y = ny - 1/2 is the opposite population reflected at the same node
-    (halfway bounce-back, wall at rest).
+    With walls, a population whose source node lies beyond the lattice is
+    the opposite population reflected at the same node (halfway bounce-back,
+    wall at rest), or with wet_walls unknown (NaN) until `zou_he` sets it.
     """
     ny = fpost.shape[1]
     fpre = np.empty_like(fpost)
@@ -79,10 +82,44 @@ def stream(fpost: np.ndarray, periodic_y: bool = False) -> np.ndarray:
         fpre[i] = np.roll(np.roll(fpost[i], ex, axis=1), ey, axis=0)
         if not periodic_y:
             if ey == 1:      # source row y-1 does not exist for y = 0
-                fpre[i, 0, :] = fpost[OPP[i], 0, :]
+                fpre[i, 0, :] = np.nan if wet_walls else fpost[OPP[i], 0, :]
             elif ey == -1:   # source row y+1 does not exist for y = ny-1
-                fpre[i, ny - 1, :] = fpost[OPP[i], ny - 1, :]
+                fpre[i, ny - 1, :] = np.nan if wet_walls else fpost[OPP[i], ny - 1, :]
     return fpre
+
+
+def zou_he(fpre: np.ndarray, fx, fy, u_lo: float, u_hi: float) -> np.ndarray:
+    """Velocity walls on the node rows y = 0 and y = ny - 1 (Zou & He, the
+    paper's wall condition, Sec. 2.1): the populations that would come from
+    beyond the wall are set so that the node's half-force velocity is the
+    wall velocity (u_w, 0), i.e. its bare momentum sum f e = rho u_w - F/2,
+    with the density following from the known populations, and the
+    non-equilibrium parts of the normal pair bounced back.
+
+    Reading: with a force at the wall node, the prescribed velocity is the
+    half-force velocity of Sec. 2.2 (the bare momentum carries -F/2).
+    """
+    f = fpre.copy()
+    ny = f.shape[1]
+    # bottom row: unknown 2 (+y), 5 (+x+y), 6 (-x+y)
+    y = 0
+    Fx, Fy = np.broadcast_to(fx, f.shape[1:])[y], np.broadcast_to(fy, f.shape[1:])[y]
+    rho = f[0, y] + f[1, y] + f[3, y] + 2.0 * (f[4, y] + f[7, y] + f[8, y]) - 0.5 * Fy
+    jx, jy = rho * u_lo - 0.5 * Fx, -0.5 * Fy
+    d13 = f[1, y] - f[3, y]
+    f[2, y] = f[4, y] + (2.0 / 3.0) * jy
+    f[5, y] = f[7, y] - 0.5 * d13 + 0.5 * jx + jy / 6.0
+    f[6, y] = f[8, y] + 0.5 * d13 - 0.5 * jx + jy / 6.0
+    # top row: unknown 4 (-y), 7 (-x-y), 8 (+x-y)
+    y = ny - 1
+    Fx, Fy = np.broadcast_to(fx, f.shape[1:])[y], np.broadcast_to(fy, f.shape[1:])[y]
+    rho = f[0, y] + f[1, y] + f[3, y] + 2.0 * (f[2, y] + f[5, y] + f[6, y]) + 0.5 * Fy
+    jx, jy = rho * u_hi - 0.5 * Fx, -0.5 * Fy
+    d13 = f[1, y] - f[3, y]
+    f[4, y] = f[2, y] - (2.0 / 3.0) * jy
+    f[7, y] = f[5, y] + 0.5 * d13 - 0.5 * jx - jy / 6.0
+    f[8, y] = f[6, y] - 0.5 * d13 + 0.5 * jx - jy / 6.0
+    return f
 
 
 def density(f: np.ndarray) -> np.ndarray:

@@ -4,8 +4,9 @@ Sec. 3 (margination and adhesion results).  Test infrastructure only.
 An observation at step n records, for every body:
   * the centre of mass X_c = mean of the vertex positions (vertices carry
     equal masses: m_v = m / n_v);
-  * the flow region of its lateral position eta = (y_c + 1/2) / H, H = n_y
-    (walls at y = -1/2 and n_y - 1/2): the cell-free layer eta <= 0.2 or
+  * the flow region of its lateral position eta = (y_c - y_lo) / (y_hi - y_lo)
+    between the walls (y = -1/2 and n_y - 1/2 with halfway bounce-back, the
+    node rows 0 and n_y - 1 with velocity walls): the cell-free layer eta <= 0.2 or
     eta >= 0.8, the intermediate zone 0.2 < eta < 0.3 or 0.7 < eta < 0.8,
     the bulk 0.3 <= eta <= 0.7 (Sec. 3, three flow regions);
   * r_max, the largest lateral displacement |y_c - y_c,0| from the release
@@ -35,8 +36,11 @@ def centre_of_mass(xy: np.ndarray) -> np.ndarray:
     return np.asarray(xy, dtype=np.float64).mean(axis=0)
 
 
-def region(yc: float, ny: int) -> int:
-    eta = (yc + 0.5) / ny
+def region(yc: float, ny: int, y_walls=None) -> int:
+    """Flow region of a lateral position; walls at -1/2 and ny - 1/2, or at
+    the given positions (velocity walls on the node rows 0 and ny - 1)."""
+    lo, hi = (-0.5, ny - 0.5) if y_walls is None else y_walls
+    eta = (yc - lo) / (hi - lo)
     if eta <= 0.2 or eta >= 0.8:
         return CFL
     if 0.3 <= eta <= 0.7:
@@ -68,7 +72,7 @@ class Observer:
     def __init__(self, n_bodies: int):
         self.obs = [BodyObs() for _ in range(n_bodies)]
 
-    def observe(self, step: int, bodies_xy, bonds_per_body, ny: int):
+    def observe(self, step: int, bodies_xy, bonds_per_body, ny: int, y_walls=None):
         for o, xy, nb in zip(self.obs, bodies_xy, bonds_per_body):
             c = centre_of_mass(xy)
             if o.n_obs == 0:
@@ -83,7 +87,7 @@ class Observer:
                     o.u_y_sum += o.u_y
             o.xc, o.yc = float(c[0]), float(c[1])
             o.r_max = max(o.r_max, abs(o.yc - o.y0))
-            o.region = region(o.yc, ny)
+            o.region = region(o.yc, ny, y_walls)
             o.n_bonds = int(nb)
             o.n_obs += 1
             o.step_obs = int(step)
@@ -94,4 +98,4 @@ class Observer:
         for k, bi in enumerate(sim.lig_body):
             if sim.l2r[k] >= 0:
                 nb[bi] += 1
-        self.observe(sim.n, [b.X for b in sim.bodies], nb, sim.ny)
+        self.observe(sim.n, [b.X for b in sim.bodies], nb, sim.ny, sim.y_walls)

@@ -85,6 +85,11 @@ class Sim:
         self.bond_params = adhesion.BondParams(a.y_cr, a.y_eq, a.kf0_dt, a.kr0_dt,
                                                a.sigma_ts_frac, a.kbt)
         self.freeze_topology = bool(a.freeze_topology)
+        # walls: halfway bounce-back at -1/2 and ny - 1/2, or the paper's
+        # Zou-He velocity walls on the node rows 0 and ny - 1 (wet nodes)
+        self.wet_walls = getattr(wl, "walls", "bounce-back") == "zou-he" and not self.periodic_y
+        self.u_wall = tuple(float(u) for u in getattr(wl, "u_wall", (0.0, 0.0)))
+        self.y_walls = (0.0, self.ny - 1.0) if self.wet_walls else None
         self.rep_coeff = float(getattr(wl, "repulsion", 0.0))
         self.rep_cutoff = float(getattr(wl, "repulsion_cutoff", repulsion.CUTOFF))
         self.n = 0
@@ -119,7 +124,7 @@ class Sim:
             e = int(self.lig_elem[k])
             xr, wall = self.receptor(r)
             out[e] += adhesion.spring_force(c[e], n[e], xr, wall, b.sigma,
-                                            self.bond_params.y_eq, self.nx, self.ny)
+                                            self.bond_params.y_eq, self.nx, self.ny, self.y_walls)
         return out
 
     # ------------------------------------------------------------ step
@@ -135,10 +140,12 @@ class Sim:
             sig = np.array([self.bodies[bi].sigma for bi in self.lig_body])
             self.l2r, t = adhesion.bond_update(self.n, self.ligand_centroids(), sig, self.l2r,
                                                self.receptors, nx, ny, self.bond_params,
-                                               self.seed, self.instance)
+                                               self.seed, self.instance, self.y_walls)
             self.ties += t
-        # pre-forcing fluid state of this step (streamed populations, drive only)
-        fpre = lattice.stream(self.f, py)
+        # pre-forcing fluid state of this step (streamed populations, drive
+        # only; velocity walls set with the drive as the node force)
+        fs = lattice.stream(self.f, py, self.wet_walls)
+        fpre = (lattice.zou_he(fs, self.gx, self.gy, *self.u_wall) if self.wet_walls else fs)
         rho_s = lattice.density(fpre)
         jx, jy = lattice.momentum(fpre)
         ux_s = (jx + 0.5 * self.gx) / rho_s
@@ -192,7 +199,9 @@ class Sim:
             FE = np.zeros((2, ny, nx))
         FE[0] += self.gx
         FE[1] += self.gy
-        # 5. lattice Boltzmann
+        # 5. lattice Boltzmann (velocity walls set with the full node force)
+        if self.wet_walls:
+            fpre = lattice.zou_he(fs, FE[0], FE[1], *self.u_wall)
         self.f, self.rho, self.ux, self.uy = lattice.collide(fpre, FE[0], FE[1], self.tau)
         # 6. marker advance
         for bi, b in enumerate(self.bodies):

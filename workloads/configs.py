@@ -77,6 +77,8 @@ class Workload:
     bodies: List[Body] = field(default_factory=list)
     receptors: List[np.ndarray] = field(default_factory=lambda: [np.zeros(0), np.zeros(0)])
     adhesion: Adhesion = field(default_factory=Adhesion)
+    walls: str = "bounce-back"          # or "zou-he": velocity walls on rows 0 and ny - 1
+    u_wall: tuple = (0.0, 0.0)          # wall velocities along x (bottom, top), zou-he only
     repulsion: float = 0.0              # Eq. repFor coefficient (0: off; REPULSION_COEFF)
     repulsion_cutoff: float = 2.0       # pairs closer than this interact
     rho0: Optional[np.ndarray] = None   # (ny, nx) initial density, None -> 1

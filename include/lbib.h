@@ -166,6 +166,21 @@ lbib_status lbib_set_receptors(lbib_ctx* ctx, int32_t wall, const double* x, int
 /* Bond kinetics parameters (setup phase; defaults: no bonds form). */
 lbib_status lbib_set_adhesion(lbib_ctx* ctx, const lbib_adhesion_desc* desc);
 
+/* Wall condition (setup phase; default mode 0).  Mode 0: halfway bounce-back,
+ * walls at rest at y = -1/2 and ny - 1/2.  Mode 1: the paper's wall
+ * condition (Sec. 2.1), Zou-He velocity walls on the node rows y = 0 and
+ * ny - 1 (channel height ny - 1) moving along x with u_lo (bottom) and u_hi
+ * (top), e.g. a Couette box; the populations from beyond a wall are set so
+ * that the node's half-force velocity (Sec. 2.2) is the wall velocity, with
+ * the node's total force, and with the drive alone in the state the particle
+ * probes read.  Bond lengths, wall distances and flow regions use the wall
+ * positions of the mode.  Errors: LBIB_EINVAL for a mode other than 0 or 1,
+ * a non-finite or |u| > 0.3 velocity, moving walls in mode 0, or mode 1 on a
+ * periodic-y lattice or one with ny < 2; LBIB_ESTATE outside set-up or on a
+ * batch (a batch takes each instance's setting).  The adjoint calls return
+ * LBIB_EINVAL for mode 1. */
+lbib_status lbib_set_walls(lbib_ctx* ctx, int32_t mode, double u_lo, double u_hi);
+
 /* Repulsion between vertices of different bodies (setup phase; default off),
  * Sec. 2.2 "Particle-Particle Interaction", Eq. (repFor): every vertex closer
  * than `cutoff` (lattice units) to a vertex of another body of the same
@@ -252,10 +267,10 @@ lbib_status lbib_set_state(lbib_ctx* ctx, const void* blob, size_t bytes);
 /* Whole-lattice diagnostics (synchronises). */
 lbib_status lbib_diagnostics(lbib_ctx* ctx, lbib_diag* out);
 
-/* Flow regions of a body's lateral position eta = (y_c + 1/2) / ny, the walls
- * being at y = -1/2 and ny - 1/2 (Sec. 3, three flow regions; the paper's
- * open intervals leave 0.2 and 0.8 unassigned: they go to the cell-free
- * layer). */
+/* Flow regions of a body's lateral position eta = (y_c - y_lo) / (y_hi - y_lo)
+ * between the walls (-1/2 and ny - 1/2, or 0 and ny - 1 with velocity walls;
+ * Sec. 3, three flow regions; the paper's open intervals leave 0.2 and 0.8
+ * unassigned: they go to the cell-free layer). */
 enum { LBIB_REGION_CFL = 0,            /* eta <= 0.2 or eta >= 0.8        */
        LBIB_REGION_INTERMEDIATE = 1,   /* 0.2 < eta < 0.3, 0.7 < eta < 0.8 */
        LBIB_REGION_BULK = 2 };         /* 0.3 <= eta <= 0.7               */

@@ -30,6 +30,7 @@ TILES = [(64, 4), (128, 2), (32, 8), (256, 1)]
 EXPORTS = [
     "lbib_abi_version", "lbib_status_string", "lbib_last_error", "lbib_create",
     "lbib_add_body", "lbib_set_receptors", "lbib_set_adhesion", "lbib_set_repulsion",
+    "lbib_set_walls",
     "lbib_init_fields",
     "lbib_workspace_query", "lbib_bind", "lbib_finalize_setup", "lbib_step",
     "lbib_set_watchdog", "lbib_set_graph_steps", "lbib_get_fields", "lbib_get_markers",
@@ -116,6 +117,7 @@ def library() -> ctypes.CDLL:
         "lbib_set_receptors": (I32, [P, I32, dp, I32]),
         "lbib_set_adhesion": (I32, [P, ctypes.POINTER(AdhesionDesc)]),
         "lbib_set_repulsion": (I32, [P, D, D]),
+        "lbib_set_walls": (I32, [P, I32, D, D]),
         "lbib_init_fields": (I32, [P, dp, dp, dp]),
         "lbib_workspace_query": (I32, [P, ctypes.POINTER(ctypes.c_size_t)]),
         "lbib_bind": (I32, [P, P, ctypes.c_size_t, P]),
@@ -316,6 +318,13 @@ def _create(lib, workload, dtype: int, tile) -> ctypes.c_void_p:
     ad = AdhesionDesc(float(a.y_cr), float(a.y_eq), float(a.kf0_dt), float(a.kr0_dt),
                       float(a.sigma_ts_frac), float(a.kbt), int(a.freeze_topology))
     chk(lib.lbib_set_adhesion(h, ctypes.byref(ad)))
+    walls = getattr(workload, "walls", "bounce-back")
+    if walls not in ("bounce-back", "zou-he"):
+        lib.lbib_destroy(h)
+        raise ValueError(f"walls must be 'bounce-back' or 'zou-he', got {walls!r}")
+    u_lo, u_hi = (float(u) for u in getattr(workload, "u_wall", (0.0, 0.0)))
+    if walls == "zou-he" and not workload.periodic_y:
+        chk(lib.lbib_set_walls(h, 1, u_lo, u_hi))
     chk(lib.lbib_set_repulsion(h, float(getattr(workload, "repulsion", 0.0)),
                                float(getattr(workload, "repulsion_cutoff", 2.0))))
     rho = None if workload.rho0 is None else np.ascontiguousarray(workload.rho0, dtype=np.float64)

@@ -36,6 +36,8 @@ struct InstHost {
   std::vector<double> rec[2];
   lbib_adhesion_desc adh{};
   double rep_coeff = 0.0, rep_cutoff = 2.0;   // vertex repulsion (Eq. repFor)
+  int wall_mode = 0;                          // 0 halfway bounce-back, 1 velocity walls
+  double u_wall_lo = 0.0, u_wall_hi = 0.0;
   std::vector<double> rho0, ux0, uy0;
 };
 
@@ -378,6 +380,10 @@ lbib_status upload_all(lbib_ctx* c) {
     D.y_cr = I.adh.y_cr; D.y_eq = I.adh.y_eq; D.kf0_dt = I.adh.kf0_dt; D.kr0_dt = I.adh.kr0_dt;
     D.sigma_ts_frac = I.adh.sigma_ts_frac; D.kbt = I.adh.kbt; D.freeze = I.adh.freeze_topology;
     D.rep_coeff = I.rep_coeff; D.rep_cutoff = I.rep_cutoff;
+    D.wall_mode = I.wall_mode;
+    D.u_wall_lo = I.u_wall_lo; D.u_wall_hi = I.u_wall_hi;
+    D.y_wall_lo = I.wall_mode == 1 ? 0.0 : -0.5;
+    D.y_wall_hi = I.wall_mode == 1 ? I.lat.ny - 1.0 : I.lat.ny - 0.5;
     for (int t = 0; t < D.ntx * D.nty; ++t) tile_inst[D.tile_base + t] = i;
     int m = D.marker_base, nl = 0;
     for (auto& b : I.bodies) {
@@ -821,6 +827,7 @@ lbib_status adj_check_sizes(lbib_ctx* c) {
   if (c->phase != 2) return fail(c, LBIB_ESTATE, "finalize_setup before binding an adjoint workspace");
   if (c->ninst != 1) return fail(c, LBIB_EINVAL, "the adjoint runs on single-lattice contexts");
   if (c->repulsion) return fail(c, LBIB_EINVAL, "the adjoint does not cover the vertex repulsion");
+  if (c->inst[0].wall_mode != 0) return fail(c, LBIB_EINVAL, "the adjoint covers bounce-back walls only");
   return LBIB_OK;
 }
 
@@ -828,6 +835,7 @@ lbib_status adj_check(lbib_ctx* c) {
   if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
   if (c->ninst != 1) return fail(c, LBIB_EINVAL, "the adjoint runs on single-lattice contexts");
   if (c->repulsion) return fail(c, LBIB_EINVAL, "the adjoint does not cover the vertex repulsion");
+  if (c->inst[0].wall_mode != 0) return fail(c, LBIB_EINVAL, "the adjoint covers bounce-back walls only");
   for (auto& b : c->inst[0].bodies)
     if (b.d.kind == LBIB_PARTICLE_RIGID)
       return fail(c, LBIB_EINVAL, "the adjoint covers red cells and soft particles (no rigid bodies)");
@@ -1120,6 +1128,23 @@ lbib_status lbib_set_adhesion(lbib_ctx* c, const lbib_adhesion_desc* d) {
   if (!(d->kbt > 0) || d->y_cr < 0 || d->kf0_dt < 0 || d->kr0_dt < 0)
     return fail(c, LBIB_EINVAL, "bad adhesion parameters");
   c->inst.back().adh = *d;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_walls(lbib_ctx* c, int32_t mode, double u_lo, double u_hi) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 0 || c->is_batch) return fail(c, LBIB_ESTATE, "walls can only be set during set-up");
+  auto& I = c->inst.back();
+  if (mode != 0 && mode != 1) return fail(c, LBIB_EINVAL, "wall mode must be 0 or 1");
+  if (!std::isfinite(u_lo) || !std::isfinite(u_hi) || std::fabs(u_lo) > 0.3 || std::fabs(u_hi) > 0.3)
+    return fail(c, LBIB_EINVAL, "wall velocities must be finite and |u| <= 0.3");
+  if (mode == 0 && (u_lo != 0.0 || u_hi != 0.0))
+    return fail(c, LBIB_EINVAL, "moving walls need the velocity-wall mode");
+  if (mode == 1 && (I.lat.periodic_y || I.lat.ny < 2))
+    return fail(c, LBIB_EINVAL, "velocity walls need a walled lattice with ny >= 2");
+  I.wall_mode = mode;
+  I.u_wall_lo = u_lo;
+  I.u_wall_hi = u_hi;
   return LBIB_OK;
 }
 

@@ -41,12 +41,21 @@ __device__ inline void pull_node(const T* A, long long N, int nx, int ny, bool p
   }
 }
 
+// Velocity walls: a wall node of the pre-forcing state takes the drive as its
+// force (the step's IB forces are not known yet).
 template <typename T>
-__device__ inline void pulled_moments(const T* A, long long N, int nx, int ny, bool pery, int x,
-                                      int y, double& drho, double& jx, double& jy) {
+__device__ inline void wall_fill_drive(const LatDev& L, int y, T hv[kQ]) {
+  if (L.wall_mode == 1 && !L.periodic_y && (y == 0 || y == L.ny - 1))
+    zou_he_fill(hv, y == 0, T(y == 0 ? L.u_wall_lo : L.u_wall_hi), T(L.gx), T(L.gy));
+}
+
+template <typename T>
+__device__ inline void pulled_moments(const T* A, const LatDev& L, long long N, int x, int y,
+                                      double& drho, double& jx, double& jy) {
   drho = 0.0; jx = 0.0; jy = 0.0;
   T hv[kQ];
-  pull_node(A, N, nx, ny, pery, x, y, hv);
+  pull_node(A, N, L.nx, L.ny, L.periodic_y != 0, x, y, hv);
+  wall_fill_drive(L, y, hv);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const double h = double(hv[i]);
@@ -62,7 +71,7 @@ __device__ inline void node_star(const T* A, const LatDev& L, int x, int y, doub
                                  double& ux, double& uy) {
   const long long N = (long long)L.nx * L.ny;
   double drho, jx, jy;
-  pulled_moments(A, N, L.nx, L.ny, L.periodic_y != 0, x, y, drho, jx, jy);
+  pulled_moments(A, L, N, x, y, drho, jx, jy);
   rho = 1.0 + drho;
   ux = (jx + 0.5 * L.gx) / rho;
   uy = (jy + 0.5 * L.gy) / rho;
@@ -168,7 +177,7 @@ __device__ inline double min_image(double xr, double cxw, int nx) {
 __device__ inline double bond_len(double cx, double cy, double xr, int wall, const LatDev& L) {
 #pragma clang fp contract(off)
   const double dx = min_image(xr, wrap_x(cx, L.nx), L.nx);
-  const double yw = wall == 0 ? -0.5 : L.ny - 0.5;
+  const double yw = wall == 0 ? L.y_wall_lo : L.y_wall_hi;
   const double dy = cy - yw;
   return sqrt(dx * dx + dy * dy);
 }
@@ -438,7 +447,7 @@ __device__ __forceinline__ void bonds_kinetics(Ptrs<T>& p, const LatDev& L, int 
           p.r2l[L.rec_base + r] = -1;
         }
       } else {
-        const double d0 = cy + 0.5, d1 = (ny - 0.5) - cy;
+        const double d0 = cy - L.y_wall_lo, d1 = L.y_wall_hi - cy;
         const int wall = d0 <= d1 ? 0 : 1;
         const double d = wall == 0 ? d0 : d1;
         if (d < y_cr) flag = 1 + wall;
@@ -743,6 +752,11 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
         for (int q = 0; q < NB; ++q) {
           const int k = k0 + q * nt + t;
           if (k >= nbox) continue;
+          {
+            int row = by0 + k / bw;
+            if (pery) row = wrap_i(row, L.ny);
+            wall_fill_drive(L, row, hv[q]);
+          }
           double drho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
           for (int i = 0; i < kQ; ++i) {

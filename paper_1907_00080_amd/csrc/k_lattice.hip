@@ -134,6 +134,10 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
     if (mode & 1) p.touched[tile] = Mreg > 0;
   }
   if (!inside) return;
+  // velocity walls: the populations from beyond the wall, set now that the
+  // node's force is known (the pull above loaded placeholders)
+  if (L.wall_mode == 1 && !pery && (y == 0 || y == ny - 1))
+    zou_he_fill(h, y == 0, T(y == 0 ? L.u_wall_lo : L.u_wall_hi), Fx, Fy);
 
   // ---- moments and forced BGK collision
   const T drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(Ptrs<T> p, lbib_body_ob
   o.xc = xc;
   o.yc = yc;
   o.r_max = fmax(o.r_max, fabs(yc - o.y0));
-  const double eta = (yc + 0.5) / L.ny;
+  const double eta = (yc - L.y_wall_lo) / (L.y_wall_hi - L.y_wall_lo);
   o.region = (eta <= 0.2 || eta >= 0.8) ? LBIB_REGION_CFL
              : (eta >= 0.3 && eta <= 0.7) ? LBIB_REGION_BULK : LBIB_REGION_INTERMEDIATE;
   o.n_bonds = nb;

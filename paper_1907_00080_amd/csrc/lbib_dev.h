@@ -58,6 +58,10 @@ struct LatDev {
   int freeze;
   int pad_;
   double rep_coeff, rep_cutoff;   // vertex repulsion (Eq. repFor); coeff 0: off
+  int wall_mode;                  // 0 halfway bounce-back, 1 velocity walls on rows 0, ny-1
+  int pad2_;
+  double u_wall_lo, u_wall_hi;    // wall velocities along x (velocity walls)
+  double y_wall_lo, y_wall_hi;    // wall positions: -1/2, ny-1/2 or 0, ny-1
 };
 
 // Per-body description and rigid-body state (device copy; rigid state mutable).
@@ -72,6 +76,33 @@ struct BodyDev {
 };
 
 // Device pointers into the workspace.
+// Velocity walls on the node rows 0 and ny - 1 (Zou and He; the paper's wall
+// condition, Sec. 2.1): the populations of a wall node whose source lies
+// beyond the wall are set so that the node's half-force velocity is the wall
+// velocity (u_w, 0), i.e. its bare momentum is rho u_w - F/2 (F the node's
+// force), its density following from the known populations, and the
+// non-equilibrium parts of the normal pair bounced back.  On shifted
+// populations h = f - w: the pairs' differences are those of f, and the
+// weights of the known terms of the density sum to one.
+template <typename T>
+__device__ inline void zou_he_fill(T h[9], bool bottom, T u_wall, T Fx, T Fy) {
+  const T d13 = h[1] - h[3];
+  const T jy = -T(0.5) * Fy;
+  if (bottom) {   // unknown: 2 (+y), 5 (+x+y), 6 (-x+y)
+    const T rho = T(1) + h[0] + h[1] + h[3] + T(2) * (h[4] + h[7] + h[8]) - T(0.5) * Fy;
+    const T jx = rho * u_wall - T(0.5) * Fx;
+    h[2] = h[4] + T(2.0 / 3.0) * jy;
+    h[5] = h[7] - T(0.5) * d13 + T(0.5) * jx + jy * T(1.0 / 6.0);
+    h[6] = h[8] + T(0.5) * d13 - T(0.5) * jx + jy * T(1.0 / 6.0);
+  } else {        // unknown: 4 (-y), 7 (-x-y), 8 (+x-y)
+    const T rho = T(1) + h[0] + h[1] + h[3] + T(2) * (h[2] + h[5] + h[6]) + T(0.5) * Fy;
+    const T jx = rho * u_wall - T(0.5) * Fx;
+    h[4] = h[2] - T(2.0 / 3.0) * jy;
+    h[7] = h[5] + T(0.5) * d13 - T(0.5) * jx - jy * T(1.0 / 6.0);
+    h[8] = h[6] - T(0.5) * d13 + T(0.5) * jx - jy * T(1.0 / 6.0);
+  }
+}
+
 template <typename T>
 struct Ptrs {
   LatDev* lat;

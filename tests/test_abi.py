@@ -199,3 +199,24 @@ def test_observation_calls_need_a_running_context():
     assert lib.lbib_get_observations(h, None) == 1
     assert lib.lbib_observe(None) == 1
     lib.lbib_destroy(h)
+
+
+def test_wall_mode_validation():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    try:
+        assert lib.lbib_set_walls(h, 2, 0.0, 0.0) == 1
+        assert lib.lbib_set_walls(h, 0, 0.0, 0.01) == 1          # moving walls need mode 1
+        assert lib.lbib_set_walls(h, 1, 0.0, 0.5) == 1           # |u| > 0.3
+        assert lib.lbib_set_walls(h, 1, float("nan"), 0.0) == 1
+        assert lib.lbib_set_walls(h, 1, 0.0, 0.01) == 0
+        assert lib.lbib_set_walls(h, 0, 0.0, 0.0) == 0
+    finally:
+        lib.lbib_destroy(h)
+    st, h = _create(periodic_y=1)
+    assert lib.lbib_set_walls(h, 1, 0.0, 0.0) == 1               # no walls to move
+    lib.lbib_destroy(h)
+    st, h = _create(ny=1)
+    assert lib.lbib_set_walls(h, 1, 0.0, 0.0) == 1
+    lib.lbib_destroy(h)

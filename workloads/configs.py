@@ -247,6 +247,47 @@ def capillary_6667x667(soft: bool = False) -> Workload:
                       SEED_BASE + 3, 50000, place_res=4.0)
 
 
+def couette_box(kind: int = PARTICLE_RIGID, sigma_phys: float = 1.0, nx: int = 600,
+                ny: int = 200, dx_um: float = 0.015, seed_offset: int = 6) -> Workload:
+    """The paper's adhesion box: a slice of the cell-free layer next to the
+    vessel wall (600 x 200 nodes at dx = 15 nm, 9 um x 3 um) between Zou-He
+    velocity walls on the node rows 0 and ny - 1, the top wall moving so that
+    the shear rate is the wall shear rate 4 u_max / H of the Re = 0.01
+    capillary (u_max = Re nu / H, H = 10 um); one 1 um particle (rigid, or
+    soft with Ca = 1e-2 and E_b = 0.05) released with its lowest vertex at the
+    bond rest length y_eq above the lower wall, ligands on every other
+    element, receptors on every wall node; sigma in units rho nu^2 / H."""
+    tau = 1.0
+    nu = viscosity(tau)
+    h_cap = 10.0 / dx_um
+    u_max = 0.01 * nu / h_cap
+    u_top = 4.0 * u_max / h_cap * (ny - 1)
+    r_p = 0.5 / dx_um
+    ks = nu * u_max / 1e-2
+    sig_unit = nu * nu / h_cap
+    y_cr = 0.025 / dx_um
+    n_p = max(16, int(round(2 * np.pi * r_p / 1.0)))
+    n_p += n_p % 2
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + seed_offset))
+    xy = geometry.place(geometry.circle(r_p, n_p), rng.uniform(0, 2 * np.pi),
+                        [0.25 * nx, 0.0])
+    xy[:, 1] += 0.5 * y_cr - xy[:, 1].min()
+    if kind == PARTICLE_RIGID:
+        body = Body(PARTICLE_RIGID, xy, sigma=sigma_phys * sig_unit, ligand_stride=2)
+    else:
+        body = Body(PARTICLE_SOFT, xy, ks=ks, kb=0.05 * ks * r_p * r_p,
+                    sigma=sigma_phys * sig_unit, ligand_stride=2)
+    adh = Adhesion(y_cr=y_cr, y_eq=0.5 * y_cr, kf0_dt=1e-3, kr0_dt=1e-3 / 8.5e3,
+                   sigma_ts_frac=0.5, kbt=kbt_lattice(dx_um * 1e-6, nu))
+    y = np.arange(ny, dtype=np.float64)
+    u0 = np.zeros((2, ny, nx))
+    u0[0] = (u_top * y / (ny - 1))[:, None]
+    name = f"couette-box-{nx}x{ny}-{'rigid' if kind == PARTICLE_RIGID else 'soft'}-sigma{sigma_phys:g}"
+    return Workload(name, nx, ny, tau, seed=SEED_BASE + seed_offset, bodies=[body],
+                    receptors=uniform_receptors(nx), adhesion=adh, u0=u0,
+                    walls="zou-he", u_wall=(0.0, u_top), steps=20000, dtype="f32")
+
+
 def sweep_instances(n_inst: int = 64, seed_offset: int = 4) -> List[Workload]:
     """Uneven capillary instances (20-100 um long, dx = 50 nm, 200 rows),
     20 % hematocrit, four particles each; (Ca, sigma) cycle over

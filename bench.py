@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain sweep")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient window")
+    ap.add_argument("--no-couette", action="store_true",
+                    help="skip the adhesion boxes with velocity walls")
+    ap.add_argument("--couette-steps", type=int, default=2000)
     ap.add_argument("--no-repulsion", action="store_true",
                     help="skip the step with the vertex repulsion switched on")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
@@ -175,6 +178,8 @@ def main():
     if not args.no_repulsion:
         out["repulsion"] = repulsion_cost(pkg, torch, args.workload, tile, 1000, args.graph_steps)
         out["observables"] = observables_cost(pkg, torch, args.workload, tile, args.graph_steps)
+    if not args.no_couette:
+        out["couette_box"] = couette_box_batch(pkg, torch, args.couette_steps)
     if not args.no_cpu:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
@@ -282,6 +287,38 @@ def observables_cost(pkg, torch, name, tile, graph_steps, every=100, n_obs=20):
     print(f"bench: observation of {len(recs)} bodies {res['us_per_observation']} us", file=sys.stderr,
           flush=True)
     return res
+
+
+def couette_box_batch(pkg, torch, steps):
+    """The paper's adhesion workload: 600 x 200 boxes at dx = 15 nm between
+    Zou-He velocity walls (moving top wall), one 1 um particle each, rigid and
+    soft with sigma = 0.5, 1, 2: six instances advanced as one batch.  Reports
+    the batch's MLUPS and, per instance, the bonds held and the particle's
+    rolling velocity over the timed steps relative to the top wall speed."""
+    from workloads import configs
+    ws = [configs.couette_box(kind=k, sigma_phys=s)
+          for k in (configs.PARTICLE_RIGID, configs.PARTICLE_SOFT) for s in (0.5, 1.0, 2.0)]
+    for i, w in enumerate(ws):
+        w.instance = i
+    nodes = sum(w.nodes for w in ws)
+    b = pkg.Batch(ws, dtype="f32", graph_steps=100)
+    b.step(200)
+    b.observe()
+    ms = _timed(torch, b, steps)
+    b.observe()
+    recs = b.observations()
+    d = b.diagnostics()
+    b.close()
+    if d["nonfinite"] or d["bin_overflow"] or d["sync_timeouts"]:
+        raise SystemExit("invalid state after the adhesion boxes")
+    inst = [{"instance": w.name, "bonds": r["n_bonds"], "bonds_at_start": r["n_bonds0"],
+             "u_roll_over_u_top": round(r["u_x"] / w.u_wall[1], 4)} for w, r in zip(ws, recs)]
+    mlups = nodes * steps / (ms * 1e-3) / 1e6
+    print(f"bench: adhesion boxes (6 x 600x200, velocity walls) {mlups:.0f} MLUPS", file=sys.stderr,
+          flush=True)
+    return {"workload": "couette-box-600x200 x6 (rigid, soft; sigma 0.5, 1, 2)", "nodes": nodes,
+            "steps": steps, "ms_per_step": round(ms / steps, 5), "mlups": round(mlups, 1),
+            "instances": inst}
 
 
 def _timed(torch, ctx, steps):

@@ -44,7 +44,7 @@ __device__ inline void pull_node(const T* A, long long N, int nx, int ny, bool p
 // Velocity walls: a wall node of the pre-forcing state takes the drive as its
 // force (the step's IB forces are not known yet).
 template <typename T>
-__device__ inline void wall_fill_drive(const LatDev& L, int y, T hv[kQ]) {
+__device__ __forceinline__ void wall_fill_drive(const LatDev& L, int y, T hv[kQ]) {
   if (L.wall_mode == 1 && !L.periodic_y && (y == 0 || y == L.ny - 1))
     zou_he_fill(hv, y == 0, T(y == 0 ? L.u_wall_lo : L.u_wall_hi), T(L.gx), T(L.gy));
 }
@@ -752,7 +752,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
         for (int q = 0; q < NB; ++q) {
           const int k = k0 + q * nt + t;
           if (k >= nbox) continue;
-          {
+          if (L.wall_mode == 1) {   // velocity walls: wall rows take the drive as force
             int row = by0 + k / bw;
             if (pery) row = wrap_i(row, L.ny);
             wall_fill_drive(L, row, hv[q]);

@@ -85,22 +85,26 @@ struct BodyDev {
 // populations h = f - w: the pairs' differences are those of f, and the
 // weights of the known terms of the density sum to one.
 template <typename T>
-__device__ inline void zou_he_fill(T h[9], bool bottom, T u_wall, T Fx, T Fy) {
+__device__ __forceinline__ void zou_he_fill(T h[9], bool bottom, T u_wall, T Fx, T Fy) {
+  // both walls' candidates from the old values, then selects: no branch
+  // around the array's writes, so it stays in registers
   const T d13 = h[1] - h[3];
   const T jy = -T(0.5) * Fy;
-  if (bottom) {   // unknown: 2 (+y), 5 (+x+y), 6 (-x+y)
-    const T rho = T(1) + h[0] + h[1] + h[3] + T(2) * (h[4] + h[7] + h[8]) - T(0.5) * Fy;
-    const T jx = rho * u_wall - T(0.5) * Fx;
-    h[2] = h[4] + T(2.0 / 3.0) * jy;
-    h[5] = h[7] - T(0.5) * d13 + T(0.5) * jx + jy * T(1.0 / 6.0);
-    h[6] = h[8] + T(0.5) * d13 - T(0.5) * jx + jy * T(1.0 / 6.0);
-  } else {        // unknown: 4 (-y), 7 (-x-y), 8 (+x-y)
-    const T rho = T(1) + h[0] + h[1] + h[3] + T(2) * (h[2] + h[5] + h[6]) + T(0.5) * Fy;
-    const T jx = rho * u_wall - T(0.5) * Fx;
-    h[4] = h[2] - T(2.0 / 3.0) * jy;
-    h[7] = h[5] + T(0.5) * d13 - T(0.5) * jx - jy * T(1.0 / 6.0);
-    h[8] = h[6] - T(0.5) * d13 + T(0.5) * jx - jy * T(1.0 / 6.0);
-  }
+  const T known = bottom ? (h[4] + h[7] + h[8]) : (h[2] + h[5] + h[6]);
+  const T rho = T(1) + h[0] + h[1] + h[3] + T(2) * known + (bottom ? -T(0.5) : T(0.5)) * Fy;
+  const T jx = rho * u_wall - T(0.5) * Fx;
+  const T n2 = h[4] + T(2.0 / 3.0) * jy;                             // bottom: 2 (+y)
+  const T n5 = h[7] - T(0.5) * d13 + T(0.5) * jx + jy * T(1.0 / 6.0);  //         5 (+x+y)
+  const T n6 = h[8] + T(0.5) * d13 - T(0.5) * jx + jy * T(1.0 / 6.0);  //         6 (-x+y)
+  const T n4 = h[2] - T(2.0 / 3.0) * jy;                             // top: 4 (-y)
+  const T n7 = h[5] + T(0.5) * d13 - T(0.5) * jx - jy * T(1.0 / 6.0);  //      7 (-x-y)
+  const T n8 = h[6] - T(0.5) * d13 + T(0.5) * jx - jy * T(1.0 / 6.0);  //      8 (+x-y)
+  h[2] = bottom ? n2 : h[2];
+  h[5] = bottom ? n5 : h[5];
+  h[6] = bottom ? n6 : h[6];
+  h[4] = bottom ? h[4] : n4;
+  h[7] = bottom ? h[7] : n7;
+  h[8] = bottom ? h[8] : n8;
 }
 
 template <typename T>

@@ -15,7 +15,7 @@ Readings for what the text leaves open:
   * probe quantities come from the pre-forcing fluid state of this step:
     rho* = sum f_i and u* = (sum f_i e_i + g/2)/rho* of the streamed
     populations, g the uniform driving force; p = cs^2 (rho* - rho0);
-    velocity gradient = gradient of the kernel interpolant;
+    velocity gradient = gradient of the kernel (or MLS) interpolant;
     tau = rho0 nu (grad u + grad u^T);
   * with walls the probe ordinate is clamped to [1/2, ny - 3/2] so the
     probe stencil stays inside the fluid;
@@ -54,14 +54,15 @@ def probe_points(xy: np.ndarray, ny: int, periodic_y: bool) -> np.ndarray:
     return q
 
 
-def hydro_element_forces(xy, rho_s, ux_s, uy_s, nu: float, periodic_y: bool) -> np.ndarray:
+def hydro_element_forces(xy, rho_s, ux_s, uy_s, nu: float, periodic_y: bool,
+                         tr: ib.Transfer = ib.ROMA) -> np.ndarray:
     """F^p + F^tau per element, (nv, 2)."""
     ny = rho_s.shape[0]
     length, _, n = membrane.elements(xy)
     q = probe_points(xy, ny, periodic_y)
-    p = CS2 * (ib.interpolate(rho_s, q, periodic_y) - RHO0)
-    dudx, dudy = ib.interpolate_gradient(ux_s, q, periodic_y)
-    dvdx, dvdy = ib.interpolate_gradient(uy_s, q, periodic_y)
+    p = CS2 * (ib.interpolate(rho_s, q, periodic_y, tr) - RHO0)
+    dudx, dudy = ib.interpolate_gradient(ux_s, q, periodic_y, tr)
+    dvdx, dvdy = ib.interpolate_gradient(uy_s, q, periodic_y, tr)
     txx = 2.0 * RHO0 * nu * dudx
     tyy = 2.0 * RHO0 * nu * dvdy
     txy = RHO0 * nu * (dudy + dvdx)

@@ -92,6 +92,10 @@ class Sim:
         self.y_walls = (0.0, self.ny - 1.0) if self.wet_walls else None
         self.rep_coeff = float(getattr(wl, "repulsion", 0.0))
         self.rep_cutoff = float(getattr(wl, "repulsion_cutoff", repulsion.CUTOFF))
+        # lattice <-> marker transfer: the Roma kernel or the general MLS fit
+        self.tr = (ib.Transfer("mls", getattr(wl, "mls_weight", "cubic"),
+                               float(getattr(wl, "mls_support", 1.3)))
+                   if getattr(wl, "transfer", "roma") == "mls" else ib.ROMA)
         self.n = 0
         self.ties = 0
         self.rho = rho0.copy()
@@ -164,9 +168,10 @@ class Sim:
                 self.marker_force[bi] = F
                 Xnext.append(None)
                 continue
-            fel = particles.hydro_element_forces(b.X, rho_s, ux_s, uy_s, self.nu, py)
+            fel = particles.hydro_element_forces(b.X, rho_s, ux_s, uy_s, self.nu, py, self.tr)
             fel = fel + self.adhesion_element_forces(bi)
-            U0 = np.stack([ib.interpolate(ux_s, b.X, py), ib.interpolate(uy_s, b.X, py)], axis=1)
+            U0 = np.stack([ib.interpolate(ux_s, b.X, py, self.tr),
+                           ib.interpolate(uy_s, b.X, py, self.tr)], axis=1)
             ds = particles.marker_weights(b.X)
             if b.kind == PARTICLE_SOFT:
                 Fv = (membrane.internal_force(b.X, b.l0, b.theta0, b.A0, b.ks, b.kb, b.ka, b.p_ref)
@@ -194,7 +199,7 @@ class Sim:
         if self.bodies:
             XY = np.concatenate([b.X for b in self.bodies])
             F = np.concatenate(self.marker_force)
-            FE = ib.spread(F, XY, nx, ny, py)
+            FE = ib.spread(F, XY, nx, ny, py, self.tr)
         else:
             FE = np.zeros((2, ny, nx))
         FE[0] += self.gx
@@ -206,8 +211,8 @@ class Sim:
         # 6. marker advance
         for bi, b in enumerate(self.bodies):
             if b.kind == RBC_KINEMATIC:
-                U = np.stack([ib.interpolate(self.ux, b.X, py), ib.interpolate(self.uy, b.X, py)],
-                             axis=1)
+                U = np.stack([ib.interpolate(self.ux, b.X, py, self.tr),
+                              ib.interpolate(self.uy, b.X, py, self.tr)], axis=1)
                 Xn1 = b.X + U if first else (2.0 / 3.0) * (2.0 * b.X - 0.5 * b.Xm + U)
             else:
                 Xn1 = Xnext[bi]

@@ -81,6 +81,9 @@ class Workload:
     u_wall: tuple = (0.0, 0.0)          # wall velocities along x (bottom, top), zou-he only
     repulsion: float = 0.0              # Eq. repFor coefficient (0: off; REPULSION_COEFF)
     repulsion_cutoff: float = 2.0       # pairs closer than this interact
+    transfer: str = "roma"              # lattice <-> marker transfer: "roma" kernel or "mls"
+    mls_weight: str = "cubic"           # MLS weight: "roma", "cubic" or "gauss"
+    mls_support: float = 1.3            # MLS support half-width (square of side 2.6 dx)
     rho0: Optional[np.ndarray] = None   # (ny, nx) initial density, None -> 1
     u0: Optional[np.ndarray] = None     # (2, ny, nx) initial velocity, None -> 0
     steps: int = 1000

@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--couette-steps", type=int, default=2000)
     ap.add_argument("--no-repulsion", action="store_true",
                     help="skip the step with the vertex repulsion switched on")
+    ap.add_argument("--no-mls", action="store_true",
+                    help="skip the step with the moving-least-squares transfer")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -177,6 +179,8 @@ def main():
         out["adjoint"] = adjoint_window(pkg, torch, args.adjoint_steps, 100)
     if not args.no_repulsion:
         out["repulsion"] = repulsion_cost(pkg, torch, args.workload, tile, 1000, args.graph_steps)
+    if not args.no_mls:
+        out["mls"] = mls_cost(pkg, torch, args.workload, tile, 1000, args.graph_steps)
         out["observables"] = observables_cost(pkg, torch, args.workload, tile, args.graph_steps)
     if not args.no_couette:
         out["couette_box"] = couette_box_batch(pkg, torch, args.couette_steps)
@@ -251,6 +255,32 @@ def repulsion_cost(pkg, torch, name, tile, steps, graph_steps):
     print(f"bench: repulsion on {res['on']['ms_per_step'] * 1e3:.2f} us/step, three kernels "
           f"without {res['off_three_kernel']['ms_per_step'] * 1e3:.2f}, default form "
           f"{res['off_default']['ms_per_step'] * 1e3:.2f}", file=sys.stderr, flush=True)
+    return res
+
+
+def mls_cost(pkg, torch, name, tile, steps, graph_steps):
+    """The same workload with the general moving-least-squares transfer
+    (linear basis, cubic-spline and Gaussian weights of support half-width
+    1.3, the paper's 2.6 dx square) in place of the Roma kernel, default step
+    form, against the Roma kernel."""
+    res = {}
+    for key, transfer, weight in (("roma_kernel", "roma", "cubic"), ("mls_cubic", "mls", "cubic"),
+                                  ("mls_gauss", "mls", "gauss")):
+        wl = make_workload(name)
+        wl.transfer, wl.mls_weight, wl.mls_support = transfer, weight, 1.3
+        sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=graph_steps)
+        sim.step(200)
+        ms = _timed(torch, sim, steps) / steps
+        d = sim.diagnostics()
+        if d["nonfinite"] or d["bin_overflow"] or d["sync_timeouts"]:
+            raise SystemExit("invalid state after the MLS benchmark")
+        res[key] = {"ms_per_step": round(ms, 5), "mlups": round(wl.nodes / (ms * 1e-3) / 1e6, 1),
+                    "step_mode": sim.step_mode}
+        sim.close()
+    res["workload"] = name + " with the MLS transfer"
+    print(f"bench: transfer Roma kernel {res['roma_kernel']['ms_per_step'] * 1e3:.2f} us/step, "
+          f"MLS cubic {res['mls_cubic']['ms_per_step'] * 1e3:.2f}, MLS Gaussian "
+          f"{res['mls_gauss']['ms_per_step'] * 1e3:.2f}", file=sys.stderr, flush=True)
     return res
 
 

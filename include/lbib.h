@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define LBIB_ABI_VERSION 3u
+#define LBIB_ABI_VERSION 4u
 
 typedef struct lbib_ctx lbib_ctx;
 
@@ -180,6 +180,34 @@ lbib_status lbib_set_adhesion(lbib_ctx* ctx, const lbib_adhesion_desc* desc);
  * batch (a batch takes each instance's setting).  The adjoint calls return
  * LBIB_EINVAL for mode 1. */
 lbib_status lbib_set_walls(lbib_ctx* ctx, int32_t mode, double u_lo, double u_hi);
+
+/* Lattice <-> marker transfer (Sec. 2.2 "Immersed Boundary Treatment": the
+ * paper exchanges all data between lattice and chain by a moving-least-
+ * squares reconstruction; Sec. 2.3: nine nodes in a square of side 2.6 dx).
+ * Every transfer (velocity at red-cell vertices, probe values and velocity
+ * gradients of particles, their vertex velocities, and the spreading of
+ * marker forces, which uses the same weights) works on the 3x3 nodes nearest
+ * the point.  LBIB_TRANSFER_ROMA (default): the 3-point kernel of Roma,
+ * Peskin and Berger along each axis; rows beyond a wall are dropped.
+ * LBIB_TRANSFER_MLS: linear basis (1, x, y) fitted by weighted least squares
+ * to those nodes, weight w(x_j - X) w(y_j - Y) chosen by `weight`:
+ *   LBIB_MLS_WEIGHT_ROMA  the Roma kernel (support 3/2; `half_width` ignored;
+ *                         in the interior this equals the default transfer),
+ *   LBIB_MLS_WEIGHT_CUBIC cubic spline of support half-width `half_width`,
+ *   LBIB_MLS_WEIGHT_GAUSS Gaussian exp(-(|r| / (0.4 h))^2), shifted to vanish
+ *                         at |r| = h = `half_width`;
+ * the paper's square is half_width = 1.3.  Rows beyond a wall carry no
+ * weight, so the fit next to a wall is one-sided (constants and linear
+ * fields are still reproduced exactly); a point with fewer than two rows
+ * inside the support fits a constant along y.  Velocity gradients are the
+ * derivatives of the fitted shape functions.  Errors: LBIB_EINVAL for an
+ * unknown mode or weight, or half_width outside (1, 3/2] (non-finite
+ * included) for the cubic and Gaussian weights; LBIB_ESTATE outside set-up or
+ * on a batch (a batch takes each instance's setting).  The adjoint calls
+ * return LBIB_EINVAL for the MLS transfer. */
+enum { LBIB_TRANSFER_ROMA = 0, LBIB_TRANSFER_MLS = 1 };
+enum { LBIB_MLS_WEIGHT_ROMA = 0, LBIB_MLS_WEIGHT_CUBIC = 1, LBIB_MLS_WEIGHT_GAUSS = 2 };
+lbib_status lbib_set_transfer(lbib_ctx* ctx, int32_t mode, int32_t weight, double half_width);
 
 /* Repulsion between vertices of different bodies (setup phase; default off),
  * Sec. 2.2 "Particle-Particle Interaction", Eq. (repFor): every vertex closer

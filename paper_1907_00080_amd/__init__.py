@@ -30,7 +30,7 @@ TILES = [(64, 4), (128, 2), (32, 8), (256, 1)]
 EXPORTS = [
     "lbib_abi_version", "lbib_status_string", "lbib_last_error", "lbib_create",
     "lbib_add_body", "lbib_set_receptors", "lbib_set_adhesion", "lbib_set_repulsion",
-    "lbib_set_walls",
+    "lbib_set_walls", "lbib_set_transfer",
     "lbib_init_fields",
     "lbib_workspace_query", "lbib_bind", "lbib_finalize_setup", "lbib_step",
     "lbib_set_watchdog", "lbib_set_graph_steps", "lbib_get_fields", "lbib_get_markers",
@@ -45,6 +45,8 @@ EXPORTS = [
 ]
 
 REGION_CFL, REGION_INTERMEDIATE, REGION_BULK = 0, 1, 2
+TRANSFER_ROMA, TRANSFER_MLS = 0, 1
+MLS_WEIGHTS = {"roma": 0, "cubic": 1, "gauss": 2}
 
 
 class LatticeDesc(ctypes.Structure):
@@ -118,6 +120,7 @@ def library() -> ctypes.CDLL:
         "lbib_set_adhesion": (I32, [P, ctypes.POINTER(AdhesionDesc)]),
         "lbib_set_repulsion": (I32, [P, D, D]),
         "lbib_set_walls": (I32, [P, I32, D, D]),
+        "lbib_set_transfer": (I32, [P, I32, I32, D]),
         "lbib_init_fields": (I32, [P, dp, dp, dp]),
         "lbib_workspace_query": (I32, [P, ctypes.POINTER(ctypes.c_size_t)]),
         "lbib_bind": (I32, [P, P, ctypes.c_size_t, P]),
@@ -327,6 +330,15 @@ def _create(lib, workload, dtype: int, tile) -> ctypes.c_void_p:
         chk(lib.lbib_set_walls(h, 1, u_lo, u_hi))
     chk(lib.lbib_set_repulsion(h, float(getattr(workload, "repulsion", 0.0)),
                                float(getattr(workload, "repulsion_cutoff", 2.0))))
+    transfer = getattr(workload, "transfer", "roma")
+    weight = getattr(workload, "mls_weight", "cubic")
+    if transfer not in ("roma", "mls") or weight not in MLS_WEIGHTS:
+        lib.lbib_destroy(h)
+        raise ValueError(f"transfer must be 'roma' or 'mls' and mls_weight one of "
+                         f"{sorted(MLS_WEIGHTS)}, got {transfer!r}, {weight!r}")
+    if transfer == "mls":
+        chk(lib.lbib_set_transfer(h, TRANSFER_MLS, MLS_WEIGHTS[weight],
+                                  float(getattr(workload, "mls_support", 1.3))))
     rho = None if workload.rho0 is None else np.ascontiguousarray(workload.rho0, dtype=np.float64)
     ux = uy = None
     if workload.u0 is not None:

@@ -38,6 +38,9 @@ struct InstHost {
   double rep_coeff = 0.0, rep_cutoff = 2.0;   // vertex repulsion (Eq. repFor)
   int wall_mode = 0;                          // 0 halfway bounce-back, 1 velocity walls
   double u_wall_lo = 0.0, u_wall_hi = 0.0;
+  int transfer = LBIB_TRANSFER_ROMA;           // lattice <-> marker transfer
+  int mls_weight = LBIB_MLS_WEIGHT_CUBIC;
+  double mls_h = 1.3;
   std::vector<double> rho0, ux0, uy0;
 };
 
@@ -183,7 +186,7 @@ void compute_layout(lbib_ctx* c) {
   L.minfo = take(4 * nm);
   L.cx = take(4 * nm);
   L.cy = take(4 * nm);
-  L.wx = take(8 * 3 * nm);
+  L.wx = take(8 * 9 * nm);   // 9 rows: the MLS weights; the Roma kernel uses 3
   L.wy = take(8 * 3 * nm);
   L.frep = take(8 * nm);
   L.obs = take(sizeof(lbib_body_obs) * (size_t)std::max(c->nbody, 1));
@@ -317,8 +320,11 @@ StepArgs step_args(const lbib_ctx* c) {
   }
   a.body_cache_bytes = c->body_cache;
   a.max_nv = 0;
-  for (auto& I : c->inst)
+  a.any_mls = 0;
+  for (auto& I : c->inst) {
     for (auto& b : I.bodies) a.max_nv = std::max(a.max_nv, b.d.nv);
+    if (I.transfer == LBIB_TRANSFER_MLS) a.any_mls = 1;
+  }
   return a;
 }
 
@@ -384,6 +390,9 @@ lbib_status upload_all(lbib_ctx* c) {
     D.u_wall_lo = I.u_wall_lo; D.u_wall_hi = I.u_wall_hi;
     D.y_wall_lo = I.wall_mode == 1 ? 0.0 : -0.5;
     D.y_wall_hi = I.wall_mode == 1 ? I.lat.ny - 1.0 : I.lat.ny - 0.5;
+    D.transfer = I.transfer;
+    D.mls_weight = I.mls_weight;
+    D.mls_h = I.mls_weight == LBIB_MLS_WEIGHT_ROMA ? 1.5 : I.mls_h;
     for (int t = 0; t < D.ntx * D.nty; ++t) tile_inst[D.tile_base + t] = i;
     int m = D.marker_base, nl = 0;
     for (auto& b : I.bodies) {
@@ -713,7 +722,7 @@ std::vector<std::pair<size_t, size_t>> state_regions(const lbib_ctx* c) {
       {Aoff, es * 9 * c->nodes}, {L.U, es * 2 * c->nodes},
       {L.body, sizeof(BodyDev) * std::max(c->nbody, 1)},
       {L.x, 8 * nm}, {L.y, 8 * nm}, {L.xm, 8 * nm}, {L.ym, 8 * nm}, {L.xn, 8 * nm}, {L.yn, 8 * nm},
-      {L.fx, 8 * nm}, {L.fy, 8 * nm}, {L.cx, 4 * nm}, {L.cy, 4 * nm}, {L.wx, 24 * nm}, {L.wy, 24 * nm},
+      {L.fx, 8 * nm}, {L.fy, 8 * nm}, {L.cx, 4 * nm}, {L.cy, 4 * nm}, {L.wx, 72 * nm}, {L.wy, 24 * nm},
       {L.touched, 4 * (size_t)c->ntiles},
       {L.l2r, 4 * nl}, {L.r2l, 4 * nr}, {L.step_next, 8 * (size_t)c->ninst},
       {L.step_cur, 8 * (size_t)c->ninst}, {L.ties, 8 * (size_t)c->ninst}};
@@ -828,6 +837,8 @@ lbib_status adj_check_sizes(lbib_ctx* c) {
   if (c->ninst != 1) return fail(c, LBIB_EINVAL, "the adjoint runs on single-lattice contexts");
   if (c->repulsion) return fail(c, LBIB_EINVAL, "the adjoint does not cover the vertex repulsion");
   if (c->inst[0].wall_mode != 0) return fail(c, LBIB_EINVAL, "the adjoint covers bounce-back walls only");
+  if (c->inst[0].transfer != LBIB_TRANSFER_ROMA)
+    return fail(c, LBIB_EINVAL, "the adjoint covers the Roma-kernel transfer only");
   return LBIB_OK;
 }
 
@@ -836,6 +847,8 @@ lbib_status adj_check(lbib_ctx* c) {
   if (c->ninst != 1) return fail(c, LBIB_EINVAL, "the adjoint runs on single-lattice contexts");
   if (c->repulsion) return fail(c, LBIB_EINVAL, "the adjoint does not cover the vertex repulsion");
   if (c->inst[0].wall_mode != 0) return fail(c, LBIB_EINVAL, "the adjoint covers bounce-back walls only");
+  if (c->inst[0].transfer != LBIB_TRANSFER_ROMA)
+    return fail(c, LBIB_EINVAL, "the adjoint covers the Roma-kernel transfer only");
   for (auto& b : c->inst[0].bodies)
     if (b.d.kind == LBIB_PARTICLE_RIGID)
       return fail(c, LBIB_EINVAL, "the adjoint covers red cells and soft particles (no rigid bodies)");
@@ -1145,6 +1158,24 @@ lbib_status lbib_set_walls(lbib_ctx* c, int32_t mode, double u_lo, double u_hi) 
   I.wall_mode = mode;
   I.u_wall_lo = u_lo;
   I.u_wall_hi = u_hi;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_transfer(lbib_ctx* c, int32_t mode, int32_t weight, double half_width) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 0 || c->is_batch) return fail(c, LBIB_ESTATE, "the transfer can only be set during set-up");
+  if (mode != LBIB_TRANSFER_ROMA && mode != LBIB_TRANSFER_MLS)
+    return fail(c, LBIB_EINVAL, "transfer mode must be LBIB_TRANSFER_ROMA or LBIB_TRANSFER_MLS");
+  if (weight != LBIB_MLS_WEIGHT_ROMA && weight != LBIB_MLS_WEIGHT_CUBIC && weight != LBIB_MLS_WEIGHT_GAUSS)
+    return fail(c, LBIB_EINVAL, "unknown MLS weight");
+  // a support above 1 keeps two nodes per axis inside it; up to 3/2 it lies
+  // within the 3x3 nearest nodes
+  if (weight != LBIB_MLS_WEIGHT_ROMA && !(half_width > 1.0 && half_width <= 1.5))
+    return fail(c, LBIB_EINVAL, "MLS support half-width must be in (1, 1.5]");
+  auto& I = c->inst.back();
+  I.transfer = mode;
+  I.mls_weight = weight;
+  I.mls_h = weight == LBIB_MLS_WEIGHT_ROMA ? 1.5 : half_width;
   return LBIB_OK;
 }
 

@@ -20,6 +20,7 @@
 //                 and the marker joins the bins of every lattice tile that
 //                 stencil overlaps, for the next step's fused kernel.
 #include "lbib_dev.h"
+#include "mls.h"
 
 namespace lbib {
 
@@ -77,10 +78,58 @@ __device__ inline void node_star(const T* A, const LatDev& L, int x, int y, doub
   uy = (jy + 0.5 * L.gy) / rho;
 }
 
-// Kernel interpolant of rho*, u* at a point and (optionally) its gradient.
-template <typename T>
+// MLS interpolant of rho*, u* at a point and (GRAD) its gradient (the MLS
+// shape functions and their derivatives), from the node values fetch(x, row,
+// rho, ux, uy) (x unwrapped; row wrapped on a periodic lattice, else
+// clamped: a row beyond a wall has weight zero, so it reads the wall row,
+// inside the lattice and any cache of the point's nodes).
+template <bool GRAD, typename Fetch>
+__device__ __forceinline__ void interp_mls(const LatDev& L, double X, double Y, Fetch fetch,
+                                           double& rho, double& ux, double& uy, double g[4]) {
+  double ph[9], px[9], py[9];
+  mls_shape<GRAD>(L, X, Y, ph, px, py);
+  const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
+  rho = 0; ux = 0; uy = 0;
+  g[0] = g[1] = g[2] = g[3] = 0;
+  const bool pery = L.periodic_y != 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    int row = (int)(cyr + (b - 1));
+    row = pery ? row : min(max(row, 0), L.ny - 1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double r, u, v;
+      fetch((int)(cxr + (a - 1)), row, r, u, v);
+      const double w = ph[3 * b + a];
+      rho += r * w;
+      ux += u * w;
+      uy += v * w;
+      if (GRAD) {
+        g[0] += u * px[3 * b + a];
+        g[1] += u * py[3 * b + a];
+        g[2] += v * px[3 * b + a];
+        g[3] += v * py[3 * b + a];
+      }
+    }
+  }
+}
+
+// Kernel (or, with MLS compiled in and selected, MLS) interpolant of rho*,
+// u* at a point and (optionally) its gradient.  MLS = false compiles the
+// kernel weights only: the latency-bound kernels of runs without the MLS
+// transfer carry none of its code (their instruction fetches grow with the
+// code they hold).
+template <bool MLS, typename T>
 __device__ inline void interp_star(const T* A, const LatDev& L, double X, double Y, bool grad,
                                    double& rho, double& ux, double& uy, double g[4]) {
+  if (MLS && use_mls(L)) {
+    auto fetch = [&](int xr, int row, double& r, double& u, double& v) {
+      node_star(A, L, wrap_i(xr, L.nx), L.periodic_y ? wrap_i(row, L.ny) : row, r, u, v);
+    };
+    if (grad) interp_mls<true>(L, X, Y, fetch, rho, ux, uy, g);
+    else interp_mls<false>(L, X, Y, fetch, rho, ux, uy, g);
+    return;
+  }
   const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
   rho = 0; ux = 0; uy = 0;
   g[0] = g[1] = g[2] = g[3] = 0;  // du/dx, du/dy, dv/dx, dv/dy
@@ -126,9 +175,20 @@ struct StarCache {
   int bx0, by0, bw, bh;
 };
 
-template <typename T>
+template <bool MLS, typename T>
 __device__ inline void interp_cached(const StarCache<T>& C, const LatDev& L, double X, double Y,
                                      bool grad, double& rho, double& ux, double& uy, double g[4]) {
+  if (MLS && use_mls(L)) {
+    auto fetch = [&](int xr, int row, double& r, double& u, double& v) {
+      const int k = 3 * ((row - C.by0) * C.bw + (xr - C.bx0));
+      r = double(C.c[k]);
+      u = double(C.c[k + 1]);
+      v = double(C.c[k + 2]);
+    };
+    if (grad) interp_mls<true>(L, X, Y, fetch, rho, ux, uy, g);
+    else interp_mls<false>(L, X, Y, fetch, rho, ux, uy, g);
+    return;
+  }
   const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
   rho = 0; ux = 0; uy = 0;
   g[0] = g[1] = g[2] = g[3] = 0;
@@ -304,20 +364,28 @@ __device__ inline void register_marker(int* cnt, int* bin, int cap, int* overflo
 // ---------------------------------------------------------------- stencils
 // Stencil of a marker at (X, Y): centre node floor(X + 1/2) (column wrapped,
 // row wrapped on a periodic lattice, else kept raw so rows beyond the walls
-// can be recognised) and the 3 + 3 Roma kernel weights (zero for rows beyond
-// the walls).
-template <typename T>
+// can be recognised) and the weights of its 3x3 nodes: the Roma kernel
+// along each axis (zero for rows beyond the walls), or the MLS shape
+// functions.
+template <bool MLS = true, typename T>
 __device__ inline void marker_stencil(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y,
                                       int& ocx, int& ocy) {
   const int nm = p.nm_total;
   const bool pery = L.periodic_y != 0;
   const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
+  if (MLS && use_mls(L)) {
+    double ph[9];
+    mls_shape<false>(L, X, Y, ph, nullptr, nullptr);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    p.wx[a * nm + gm] = roma_phi((cxr + (a - 1)) - X);
-    const double ry = cyr + (a - 1);
-    const bool valid = pery || (ry >= 0.0 && ry < (double)L.ny);
-    p.wy[a * nm + gm] = valid ? roma_phi(ry - Y) : 0.0;
+    for (int k = 0; k < 9; ++k) p.wx[k * nm + gm] = ph[k];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      p.wx[a * nm + gm] = roma_phi((cxr + (a - 1)) - X);
+      const double ry = cyr + (a - 1);
+      const bool valid = pery || (ry >= 0.0 && ry < (double)L.ny);
+      p.wy[a * nm + gm] = valid ? roma_phi(ry - Y) : 0.0;
+    }
   }
   ocx = wrap_i((int)cxr, L.nx);
   ocy = pery ? wrap_i((int)cyr, L.ny) : (int)fmin(fmax(cyr, -4.0), (double)(L.ny + 3));
@@ -348,28 +416,50 @@ __global__ __launch_bounds__(256) void k_stencil(Ptrs<T> p) {
 // Split in two so that a lane handling several vertices issues every load
 // of all of them before it waits: first the stencil and X^{n-1} (needed by
 // BDF2 only, loaded unconditionally), then the velocity gather.
-struct RbcAdv {
+// MLS = false: the Roma kernel's per-axis weights (the layout the kernels
+// without MLS keep: a wider one costs them register spills); MLS = true: nine
+// slots, the Roma weights in 0..5 (wx then wy) or the nine MLS weights.
+template <bool MLS> struct RbcAdv;
+template <> struct RbcAdv<false> {
   int cx, cy;
   double wx[3], wy[3];
   double xm, ym;
 };
+template <> struct RbcAdv<true> {
+  int cx, cy;
+  double ph[9];
+  double xm, ym;
+};
 
-template <typename T>
-__device__ inline void rbc_adv_load(const Ptrs<T>& p, int gm, RbcAdv& a) {
+template <bool MLS, typename T>
+__device__ inline void rbc_adv_load(const Ptrs<T>& p, const LatDev& L, int gm, RbcAdv<MLS>& a) {
   const int nm = p.nm_total;
   a.cx = p.cx[gm];
   a.cy = p.cy[gm];
+  if constexpr (MLS) {
+    // one load per slot from the array the transfer uses (fixed slots, no
+    // branch around the writes, so the struct stays in registers)
+    const bool mls = use_mls(L);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    a.wx[k] = p.wx[k * nm + gm];
-    a.wy[k] = p.wy[k * nm + gm];
+    for (int k = 0; k < 6; ++k) {
+      const double* src = (mls || k < 3) ? p.wx + k * nm : p.wy + (k - 3) * nm;
+      a.ph[k] = src[gm];
+    }
+#pragma unroll
+    for (int k = 6; k < 9; ++k) a.ph[k] = mls ? p.wx[k * nm + gm] : 0.0;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a.wx[k] = p.wx[k * nm + gm];
+      a.wy[k] = p.wy[k * nm + gm];
+    }
   }
   a.xm = p.xm[gm];
   a.ym = p.ym[gm];
 }
 
-template <typename T>
-__device__ inline void rbc_adv_finish(const Ptrs<T>& p, const LatDev& L, const RbcAdv& in, double X,
+template <bool MLS, typename T>
+__device__ inline void rbc_adv_finish(const Ptrs<T>& p, const LatDev& L, const RbcAdv<MLS>& in, double X,
                                       double Y, bool first, double& xn, double& yn) {
   const long long N = (long long)L.nx * L.ny;
   const T* U = p.U + 2 * L.node_base;
@@ -382,11 +472,12 @@ __device__ inline void rbc_adv_finish(const Ptrs<T>& p, const LatDev& L, const R
     int row = cy + b2 - 1;
     if (L.periodic_y) row = wrap_i(row, L.ny);
     else row = min(max(row, 0), L.ny - 1);
-    const double wy = in.wy[b2];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int col = wrap_i(cx + a - 1, L.nx);
-      const double w = in.wx[a] * wy;
+      double w;
+      if constexpr (MLS) w = use_mls(L) ? in.ph[3 * b2 + a] : in.ph[a] * in.ph[3 + b2];
+      else w = in.wx[a] * in.wy[b2];
       const long long node = (long long)row * L.nx + col;
       ux += double(U[node]) * w;
       uy += double(U[N + node]) * w;
@@ -401,12 +492,12 @@ __device__ inline void rbc_adv_finish(const Ptrs<T>& p, const LatDev& L, const R
   }
 }
 
-template <typename T>
+template <bool MLS, typename T>
 __device__ inline void advance_rbc(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y,
                                    bool first, double& xn, double& yn) {
-  RbcAdv a;
-  rbc_adv_load(p, gm, a);
-  rbc_adv_finish(p, L, a, X, Y, first, xn, yn);
+  RbcAdv<MLS> a;
+  rbc_adv_load<MLS>(p, L, gm, a);
+  rbc_adv_finish<MLS>(p, L, a, X, Y, first, xn, yn);
 }
 
 // ---------------------------------------------------------------- k_bonds
@@ -597,7 +688,7 @@ constexpr int kVmax = kSmallBody;
 
 // SMALL: the body's per-vertex scratch lives in LDS (sm); otherwise in the
 // workspace.  A template parameter, so every access has a known address space.
-template <typename T, bool SMALL, int TX, int TY, bool ADV>
+template <typename T, bool SMALL, int TX, int TY, bool ADV, bool MLS>
 __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, double (*sm)[kVmax],
                                           double (*s_red)[kBodyThreads / 64], double* s_rigid, int* s_box,
                                           unsigned char* s_dyn) {
@@ -664,12 +755,12 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
         yo[r] = p.y[gmv[r]];
       }
       if (kind == kRBC) {
-        RbcAdv ra[R];
+        RbcAdv<MLS> ra[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) rbc_adv_load(p, gmv[r], ra[r]);
+        for (int r = 0; r < R; ++r) rbc_adv_load<MLS>(p, L, gmv[r], ra[r]);
 #pragma unroll
         for (int r = 0; r < R; ++r)
-          rbc_adv_finish(p, L, ra[r], xo[r], yo[r], first_prev, xn[r], yn[r]);
+          rbc_adv_finish<MLS>(p, L, ra[r], xo[r], yo[r], first_prev, xn[r], yn[r]);
       } else {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -690,7 +781,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
             sm[0][base0 + r * nt + t] = xn[r];
             sm[1][base0 + r * nt + t] = yn[r];
           }
-          marker_stencil(p, L, gmv[r], xn[r], yn[r], ncx[r], ncy[r]);
+          marker_stencil<MLS>(p, L, gmv[r], xn[r], yn[r], ncx[r], ncy[r]);
           if (kind != kRBC) {
             mnx = min(mnx, (int)floor(xn[r]) - 4); mxx = max(mxx, (int)ceil(xn[r]) + 4);
             mny = min(mny, (int)floor(yn[r]) - 4); mxy = max(mxy, (int)ceil(yn[r]) + 4);
@@ -872,8 +963,8 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       double qy = cy + 1.2 * nyl;
       if (!pery) qy = fmin(fmax(qy, 0.5), L.ny - 1.5);
       double rho, ux, uy, g[4];
-      if (cached) interp_cached(C, L, qx, qy, true, rho, ux, uy, g);
-      else interp_star(A, L, qx, qy, true, rho, ux, uy, g);
+      if (cached) interp_cached<MLS>(C, L, qx, qy, true, rho, ux, uy, g);
+      else interp_star<MLS>(A, L, qx, qy, true, rho, ux, uy, g);
       const double pr = (rho - 1.0) * (1.0 / 3.0);
       const double txx = 2.0 * nu * g[0], tyy = 2.0 * nu * g[3], txy = nu * (g[1] + g[2]);
       fex += (-pr * nxl + txx * nxl + txy * nyl) * len;
@@ -940,8 +1031,8 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       const double relx = xn - xc, rely = yn - yc;
       const double ukx = U0 + Om * (-rely), uky = U1 + Om * relx;
       double rho, ux, uy, g[4];
-      if (cached) interp_cached(C, L, X[v], Y[v], false, rho, ux, uy, g);
-      else interp_star(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      if (cached) interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
+      else interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
       const double ds = 0.5 * (S_len[vm] + S_len[v]);
       p.xn[gm] = xn;
       p.yn[gm] = yn;
@@ -998,8 +1089,8 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       fm = fmax_nan(fm, fmax_nan(fabs(fx), fabs(fy)));
     } else {
       double rho, ux, uy, g[4];
-      if (cached) interp_cached(C, L, X[v], Y[v], false, rho, ux, uy, g);
-      else interp_star(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      if (cached) interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
+      else interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
       const double xn = X[v] + ux + 0.5 * fx / mv;
       const double yn = Y[v] + uy + 0.5 * fy / mv;
       // velocity imposed by the weak coupling: the vertex displacement of the
@@ -1034,7 +1125,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
 // every body has at most kVmax vertices (the host knows), so only the LDS
 // form of the body code is compiled in: a smaller kernel, fewer instruction
 // fetches on its serial path.  The merged form is only launched that way.
-template <typename T, int TX, int TY, bool ADV, bool SMALL_ONLY>
+template <typename T, int TX, int TY, bool ADV, bool SMALL_ONLY, bool MLS>
 __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_nodes) {
   static_assert(SMALL_ONLY || !ADV, "the merged step form needs small bodies");
   __shared__ double s_red[3][kBodyThreads / 64];
@@ -1053,17 +1144,17 @@ __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_node
   }
   const int b = blockIdx.x - p.ninst;
   if (SMALL_ONLY || p.body[b].nv <= kVmax)
-    body_impl<T, true, TX, TY, ADV>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+    body_impl<T, true, TX, TY, ADV, MLS>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
   else
-    body_impl<T, false, TX, TY, false>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+    body_impl<T, false, TX, TY, false, MLS>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
 }
 
 // Ends a run of steps: every marker moves to X^{n+1} (red cells by the
 // kinematic update, particles adopt the positions of their dynamics) and
 // joins the bins the next step's fused kernel reads.  Inside a run the body
 // workgroups of the next step may do this for their own vertices.
-template <typename T, int TX, int TY>
-__global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
+template <typename T, int TX, int TY, bool MLS>
+__device__ __forceinline__ void advance_impl(Ptrs<T>& p) {
   const int gm0 = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = gm0 < p.nm_total;
   const int gm = active ? gm0 : p.nm_total - 1;   // idle lanes shadow the last marker
@@ -1079,7 +1170,7 @@ __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
   const double X = p.x[gm], Y = p.y[gm];
   double xn, yn;
   if (kind == kRBC) {
-    advance_rbc(p, L, gm, X, Y, first, xn, yn);
+    advance_rbc<MLS>(p, L, gm, X, Y, first, xn, yn);
   } else {
     xn = p.xn[gm];
     yn = p.yn[gm];
@@ -1092,12 +1183,20 @@ __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
     p.y[gm] = yn;
     // stencil of the new position, used by the next step's spreading and
     // interpolation (this lane has finished reading the old one)
-    marker_stencil(p, L, gm, xn, yn, ncx, ncy);
+    marker_stencil<MLS>(p, L, gm, xn, yn, ncx, ncy);
   }
   // join the bins the next step's fused kernel reads (all lanes take part
   // in the wave-aggregated registration)
   register_marker<TX, TY>(p.cnt_next, p.bin_next, p.bin_cap, p.overflow, L, gm, ncx, ncy, active);
 }
+
+// Marker advance and new stencils: kernel weights only, or with the MLS
+// transfer compiled in (launched when an instance uses it).
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) { advance_impl<T, TX, TY, false>(p); }
+
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(256) void k_advance_mls(Ptrs<T> p) { advance_impl<T, TX, TY, true>(p); }
 
 // ------------------------------------------------------------------ launchers
 #define LBIB_TILE_DISPATCH(a, KERNEL, ...)                                                   \
@@ -1122,23 +1221,30 @@ void launch_lagrangian(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, bool 
   // advance_first (the merged form) is only requested when every body is
   // small: the engine resolves the step form from the same limit
   const bool small = a.max_nv <= kVmax;
-#define LBIB_BODY(TXv, TYv)                                                                        \
+#define LBIB_BODY(TXv, TYv, M)                                                                     \
   do {                                                                                          \
-    if (advance_first) hipLaunchKernelGGL((k_body<T, TXv, TYv, true, true>), grid, block, lds, s, p, cache_nodes); \
-    else if (small) hipLaunchKernelGGL((k_body<T, TXv, TYv, false, true>), grid, block, lds, s, p, cache_nodes); \
-    else hipLaunchKernelGGL((k_body<T, TXv, TYv, false, false>), grid, block, lds, s, p, cache_nodes); \
+    if (advance_first) hipLaunchKernelGGL((k_body<T, TXv, TYv, true, true, M>), grid, block, lds, s, p, cache_nodes); \
+    else if (small) hipLaunchKernelGGL((k_body<T, TXv, TYv, false, true, M>), grid, block, lds, s, p, cache_nodes); \
+    else hipLaunchKernelGGL((k_body<T, TXv, TYv, false, false, M>), grid, block, lds, s, p, cache_nodes); \
   } while (0)
-  if (a.tile_x == 64 && a.tile_y == 4) LBIB_BODY(64, 4);
-  else if (a.tile_x == 128 && a.tile_y == 2) LBIB_BODY(128, 2);
-  else if (a.tile_x == 32 && a.tile_y == 8) LBIB_BODY(32, 8);
-  else LBIB_BODY(256, 1);
+#define LBIB_BODY_T(M)                                                                             \
+  do {                                                                                          \
+    if (a.tile_x == 64 && a.tile_y == 4) LBIB_BODY(64, 4, M);                                   \
+    else if (a.tile_x == 128 && a.tile_y == 2) LBIB_BODY(128, 2, M);                            \
+    else if (a.tile_x == 32 && a.tile_y == 8) LBIB_BODY(32, 8, M);                              \
+    else LBIB_BODY(256, 1, M);                                                                  \
+  } while (0)
+  if (a.any_mls) LBIB_BODY_T(true);
+  else LBIB_BODY_T(false);
+#undef LBIB_BODY_T
 #undef LBIB_BODY
 }
 
 template <typename T>
 void launch_advance(const Ptrs<T>& p, const StepArgs& a, hipStream_t s) {
   if (p.nm_total == 0) return;
-  LBIB_TILE_DISPATCH(a, k_advance, dim3((p.nm_total + 255) / 256), dim3(256), 0, s, p);
+  if (a.any_mls) LBIB_TILE_DISPATCH(a, k_advance_mls, dim3((p.nm_total + 255) / 256), dim3(256), 0, s, p);
+  else LBIB_TILE_DISPATCH(a, k_advance, dim3((p.nm_total + 255) / 256), dim3(256), 0, s, p);
 }
 #undef LBIB_TILE_DISPATCH
 

@@ -30,6 +30,48 @@ constexpr int kCap = 256;  // lanes per workgroup = nodes per tile
 // those without registered markers, 2 only those with.  mode = 0
 // (measurement launches): the bins are left in place and the caller points
 // U at a spare buffer, so the simulation state is untouched.
+// Adds the markers of a tile's bin (entries lane, lane + kCap, ...) to the
+// tile's fixed-point force accumulators.  Stencil weights: the Roma kernel's
+// per-axis products (MLS = false) or the nine MLS weights; the transfer is
+// chosen per instance outside the loop, so each loop is straight-line code.
+template <bool MLS, int TX, int TY, typename T>
+__device__ __forceinline__ void spread_entries(const Ptrs<T>& p, const int* bin, int M, int lane,
+                                               double sc, int x0, int y0, int nx, int ny, bool pery,
+                                               unsigned long long* s_ax, unsigned long long* s_ay) {
+  const int nm = p.nm_total;
+  for (int j = lane; j < M; j += kCap) {
+    const int m = bin[j];
+    const int cx = p.cx[m], cy = p.cy[m];
+    const double fx = p.fx[m] * sc, fy = p.fy[m] * sc;
+    double wxa[3], wyb[3], ph[9];
+    if constexpr (MLS) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) ph[k] = p.wx[k * nm + m];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        wxa[k] = p.wx[k * nm + m];
+        wyb[k] = p.wy[k * nm + m];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      int row = cy + b - 1;
+      if (pery) row = wrap_i(row, ny);
+      const int ly = row - y0;
+      if (ly < 0 || ly >= TY) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int lx = wrap_i(cx + a - 1, nx) - x0;
+        if (lx < 0 || lx >= TX) continue;
+        const double w = MLS ? ph[3 * b + a] : wxa[a] * wyb[b];
+        atomicAdd(&s_ax[ly * TX + lx], (unsigned long long)__double2ll_rn(fx * w));
+        atomicAdd(&s_ay[ly * TX + lx], (unsigned long long)__double2ll_rn(fy * w));
+      }
+    }
+  }
+}
+
 template <typename T, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int mode) {
   static_assert(TX * TY == kCap, "one lane per LDS slot");
@@ -99,29 +141,10 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
       frexp(fmax_t * (double)M, &e);
       const double sc = ldexp(1.0, 61 - e);
       const int x0 = tx * TX, y0 = ty * TY;
-      const int nm = p.nm_total;
-      for (int j = lane; j < M; j += kCap) {
-        const int m = bin[j];
-        const int cx = p.cx[m], cy = p.cy[m];
-        const double fx = p.fx[m] * sc, fy = p.fy[m] * sc;
-        const double wxa[3] = {p.wx[m], p.wx[nm + m], p.wx[2 * nm + m]};
-        const double wyb[3] = {p.wy[m], p.wy[nm + m], p.wy[2 * nm + m]};
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          int row = cy + b - 1;
-          if (pery) row = wrap_i(row, ny);
-          const int ly = row - y0;
-          if (ly < 0 || ly >= TY) continue;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int lx = wrap_i(cx + a - 1, nx) - x0;
-            if (lx < 0 || lx >= TX) continue;
-            const double w = wxa[a] * wyb[b];
-            atomicAdd(&s_ax[ly * TX + lx], (unsigned long long)__double2ll_rn(fx * w));
-            atomicAdd(&s_ay[ly * TX + lx], (unsigned long long)__double2ll_rn(fy * w));
-          }
-        }
-      }
+      if (L.transfer == LBIB_TRANSFER_MLS)
+        spread_entries<true, TX, TY>(p, bin, M, lane, sc, x0, y0, nx, ny, pery, s_ax, s_ay);
+      else
+        spread_entries<false, TX, TY>(p, bin, M, lane, sc, x0, y0, nx, ny, pery, s_ax, s_ay);
       __syncthreads();
       const double isc = 1.0 / sc;
       Fx = T(L.gx + (double)(long long)s_ax[lane] * isc);

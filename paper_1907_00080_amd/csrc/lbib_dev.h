@@ -6,7 +6,10 @@
 //   velocity     U    : T[2][N] per instance (written on touched tiles only)
 //   markers           : x[Nm], y[Nm] (current), xm/ym (previous), xn/yn (next,
 //                       particles), fx/fy (force handed to the fluid),
-//                       per-marker stencil cx, cy (int) and weights wx[3], wy[3]
+//                       per-marker stencil cx, cy (int) and its weights: the
+//                       Roma kernel's wx[3], wy[3] (node (a, b) weighs
+//                       wx[a] wy[b]), or with the MLS transfer the nine
+//                       weights in wx[9] (node (a, b) at row 3 b + a)
 //   bins              : per tile, the markers whose 3x3 stencil overlaps it
 //                       (fixed capacity, two sets used alternately)
 //   ligands           : l2r[NL] (-1 free), receptors rec_x[NR], r2l[NR]
@@ -62,6 +65,9 @@ struct LatDev {
   int pad2_;
   double u_wall_lo, u_wall_hi;    // wall velocities along x (velocity walls)
   double y_wall_lo, y_wall_hi;    // wall positions: -1/2, ny-1/2 or 0, ny-1
+  int transfer;                   // 0 Roma kernel, 1 moving least squares (LBIB_TRANSFER_*)
+  int mls_weight;                 // MLS weight (LBIB_MLS_WEIGHT_*)
+  double mls_h;                   // MLS support half-width (3/2 for the Roma weight)
 };
 
 // Per-body description and rigid-body state (device copy; rigid state mutable).
@@ -119,7 +125,10 @@ struct Ptrs {
   int* mbody;
   int* minfo;            // per marker: (instance << 2) | body kind
   int *cx, *cy;
-  double *wx, *wy;       // [3][Nm]
+  double *wx, *wy;       // Roma kernel: wx[3][Nm], wy[3][Nm] per axis; MLS:
+                         // wx[9][Nm], node (a, b) at row 3 b + a (one array
+                         // for both keeps this argument block, and the
+                         // registers holding it, as small as it was)
   double* frep;          // per marker: summed repulsion magnitude of this step
                          // (written by the repulsion kernel, cleared by the
                          // body kernel once applied)
@@ -225,6 +234,7 @@ struct StepArgs {
   int max_inst_tiles;   // largest tile count of any instance
   int body_cache_bytes; // LDS cache of rho*, u* per particle workgroup
   int max_nv;           // most vertices of any body
+  int any_mls;          // some instance uses the MLS transfer
 };
 
 template <typename T>

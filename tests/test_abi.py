@@ -30,7 +30,9 @@ def test_library_exports_every_declared_symbol():
     for name in decl:
         assert hasattr(lib, name), name
     assert decl == set(pkg.EXPORTS)
-    assert lib.lbib_abi_version() == 3
+    header = open(os.path.join(ROOT, "include", "lbib.h")).read()
+    want = int(re.search(r"#define LBIB_ABI_VERSION (\d+)u", header).group(1))
+    assert lib.lbib_abi_version() == want
     for s, n in pkg.STATUS.items():
         assert lib.lbib_status_string(s).decode() == n
 
@@ -220,3 +222,30 @@ def test_wall_mode_validation():
     st, h = _create(ny=1)
     assert lib.lbib_set_walls(h, 1, 0.0, 0.0) == 1
     lib.lbib_destroy(h)
+
+
+def test_transfer_validation():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    try:
+        assert lib.lbib_set_transfer(h, 2, 1, 1.3) == 1                 # unknown mode
+        assert lib.lbib_set_transfer(h, 1, 3, 1.3) == 1                 # unknown weight
+        assert lib.lbib_set_transfer(h, 1, 1, 1.0) == 1                 # support must exceed 1
+        assert lib.lbib_set_transfer(h, 1, 2, 1.51) == 1                # and lie within 3/2
+        assert lib.lbib_set_transfer(h, 1, 1, float("nan")) == 1
+        assert lib.lbib_set_transfer(h, 1, 0, float("nan")) == 0        # ignored for the Roma weight
+        assert lib.lbib_set_transfer(h, 1, 1, 1.3) == 0
+        assert lib.lbib_set_transfer(h, 1, 2, 1.5) == 0
+        assert lib.lbib_set_transfer(h, 0, 1, 1.3) == 0
+        assert lib.lbib_set_transfer(None, 0, 1, 1.3) == 1
+    finally:
+        lib.lbib_destroy(h)
+
+
+def test_workload_transfer_is_checked_before_any_device_work():
+    from workloads import configs as c
+    wl = c.Workload("t", 16, 8)
+    wl.transfer = "spline"
+    with pytest.raises(ValueError):
+        pkg.Sim(wl, dtype="f64", device="cpu")

@@ -321,6 +321,9 @@ StepArgs step_args(const lbib_ctx* c) {
   a.body_cache_bytes = c->body_cache;
   a.max_nv = 0;
   a.any_mls = 0;
+  // non-temporal population loads pay on a single lattice and cost on
+  // batches of many small ones (measured): single-lattice contexts only
+  a.nt_loads = c->ninst == 1 ? 1 : 0;
   for (auto& I : c->inst) {
     for (auto& b : I.bodies) a.max_nv = std::max(a.max_nv, b.d.nv);
     if (I.transfer == LBIB_TRANSFER_MLS) a.any_mls = 1;

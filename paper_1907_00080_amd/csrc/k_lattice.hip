@@ -72,7 +72,13 @@ __device__ __forceinline__ void spread_entries(const Ptrs<T>& p, const int* bin,
   }
 }
 
-template <typename T, int TX, int TY>
+// NTL: the population loads carry the non-temporal hint.  Pull streaming is
+// a permutation of the nodes, so every population is read exactly once per
+// step and its cache line is worth nothing to this kernel afterwards;
+// measured on one lattice, the hint gains a few per cent (most on lattices
+// larger than the last-level cache), while on batches of many small
+// lattices it loses, so the host chooses it per context.
+template <typename T, int TX, int TY, bool NTL>
 __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int mode) {
   static_assert(TX * TY == kCap, "one lane per LDS slot");
   const int g = blockIdx.x;
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
       const bool out = ys < 0 || ys >= ny;
       ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
       const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * nx + xs;
-      h[i] = A[src];
+      h[i] = NTL ? __builtin_nontemporal_load(&A[src]) : A[src];
     }
   }
 
@@ -296,18 +302,20 @@ void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mod
   dim3 grid(8 * per), block(kCap);
   // the optional events are bound to the dispatch itself, so their elapsed
   // time is the kernel's execution time and not that of separate markers
-  if (a.tile_x == 64 && a.tile_y == 4)
-    hipExtLaunchKernelGGL((k_lb_fused<T, 64, 4>), grid, block, 0, s, ev0, ev1, 0, p,
-                          a.ntiles_total, mode);
-  else if (a.tile_x == 128 && a.tile_y == 2)
-    hipExtLaunchKernelGGL((k_lb_fused<T, 128, 2>), grid, block, 0, s, ev0, ev1, 0, p,
-                          a.ntiles_total, mode);
-  else if (a.tile_x == 32 && a.tile_y == 8)
-    hipExtLaunchKernelGGL((k_lb_fused<T, 32, 8>), grid, block, 0, s, ev0, ev1, 0, p,
-                          a.ntiles_total, mode);
-  else
-    hipExtLaunchKernelGGL((k_lb_fused<T, 256, 1>), grid, block, 0, s, ev0, ev1, 0, p,
-                          a.ntiles_total, mode);
+#define LBIB_LB(TXv, TYv)                                                                        \
+  do {                                                                                          \
+    if (a.nt_loads)                                                                             \
+      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, true>), grid, block, 0, s, ev0, ev1, 0, p,  \
+                            a.ntiles_total, mode);                                              \
+    else                                                                                        \
+      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, false>), grid, block, 0, s, ev0, ev1, 0, p, \
+                            a.ntiles_total, mode);                                              \
+  } while (0)
+  if (a.tile_x == 64 && a.tile_y == 4) LBIB_LB(64, 4);
+  else if (a.tile_x == 128 && a.tile_y == 2) LBIB_LB(128, 2);
+  else if (a.tile_x == 32 && a.tile_y == 8) LBIB_LB(32, 8);
+  else LBIB_LB(256, 1);
+#undef LBIB_LB
 }
 
 template <typename T>

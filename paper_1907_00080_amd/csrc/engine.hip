@@ -322,8 +322,11 @@ StepArgs step_args(const lbib_ctx* c) {
   a.max_nv = 0;
   a.any_mls = 0;
   // non-temporal population loads pay on a single lattice and cost on
-  // batches of many small ones (measured): single-lattice contexts only
-  a.nt_loads = c->ninst == 1 ? 1 : 0;
+  // batches of many small ones; non-temporal stores pay on a single lattice
+  // whose two population buffers stay well inside the 256 MB last-level
+  // cache (28.8 MB measured) and cost on one beyond it (320 MB measured)
+  const double pop_bytes = 2.0 * 9.0 * (double)c->nodes * (double)elem_size(c->dtype);
+  a.nt_mode = c->ninst != 1 ? 0 : (pop_bytes <= 128.0 * 1024 * 1024 ? 3 : 1);
   for (auto& I : c->inst) {
     for (auto& b : I.bodies) a.max_nv = std::max(a.max_nv, b.d.nv);
     if (I.transfer == LBIB_TRANSFER_MLS) a.any_mls = 1;

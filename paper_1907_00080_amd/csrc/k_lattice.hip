@@ -72,13 +72,15 @@ __device__ __forceinline__ void spread_entries(const Ptrs<T>& p, const int* bin,
   }
 }
 
-// NTL: the population loads carry the non-temporal hint.  Pull streaming is
-// a permutation of the nodes, so every population is read exactly once per
-// step and its cache line is worth nothing to this kernel afterwards;
-// measured on one lattice, the hint gains a few per cent (most on lattices
-// larger than the last-level cache), while on batches of many small
-// lattices it loses, so the host chooses it per context.
-template <typename T, int TX, int TY, bool NTL>
+// NT bit 0: the population loads carry the non-temporal hint.  Pull
+// streaming is a permutation of the nodes, so every population is read
+// exactly once per step and its cache line is worth nothing to this kernel
+// afterwards; measured on one lattice the hint gains a few per cent, on
+// batches of many small lattices it loses.  NT bit 1: the population stores
+// carry it too, which measured faster on a lattice whose populations stay in
+// the last-level cache and much slower on one larger than it.  The host
+// chooses per context.
+template <typename T, int TX, int TY, int NT>
 __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int mode) {
   static_assert(TX * TY == kCap, "one lane per LDS slot");
   const int g = blockIdx.x;
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
       const bool out = ys < 0 || ys >= ny;
       ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
       const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * nx + xs;
-      h[i] = NTL ? __builtin_nontemporal_load(&A[src]) : A[src];
+      h[i] = (NT & 1) ? __builtin_nontemporal_load(&A[src]) : A[src];
     }
   }
 
@@ -186,7 +188,9 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
     const T heq = wq<T>(i) * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu));
     const T src = pre * wq<T>(i) *
                   ((T(3) * (exi - ux) + T(9) * eu * exi) * Fx + (T(3) * (eyi - uy) + T(9) * eu * eyi) * Fy);
-    B[i * N + node] = h[i] + omega * (heq - h[i]) + src;
+    const T hn = h[i] + omega * (heq - h[i]) + src;
+    if (NT & 2) __builtin_nontemporal_store(hn, &B[i * N + node]);
+    else B[i * N + node] = hn;
   }
   if (M > 0) {
     T* U = p.U + 2 * L.node_base;
@@ -304,11 +308,14 @@ void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mod
   // time is the kernel's execution time and not that of separate markers
 #define LBIB_LB(TXv, TYv)                                                                        \
   do {                                                                                          \
-    if (a.nt_loads)                                                                             \
-      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, true>), grid, block, 0, s, ev0, ev1, 0, p,  \
+    if (a.nt_mode == 3)                                                                         \
+      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, 3>), grid, block, 0, s, ev0, ev1, 0, p,     \
+                            a.ntiles_total, mode);                                              \
+    else if (a.nt_mode == 1)                                                                    \
+      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, 1>), grid, block, 0, s, ev0, ev1, 0, p,     \
                             a.ntiles_total, mode);                                              \
     else                                                                                        \
-      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, false>), grid, block, 0, s, ev0, ev1, 0, p, \
+      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, 0>), grid, block, 0, s, ev0, ev1, 0, p,     \
                             a.ntiles_total, mode);                                              \
   } while (0)
   if (a.tile_x == 64 && a.tile_y == 4) LBIB_LB(64, 4);

@@ -235,7 +235,7 @@ struct StepArgs {
   int body_cache_bytes; // LDS cache of rho*, u* per particle workgroup
   int max_nv;           // most vertices of any body
   int any_mls;          // some instance uses the MLS transfer
-  int nt_loads;         // lattice kernel with non-temporal population loads
+  int nt_mode;          // lattice kernel: non-temporal population loads (1), and stores (3)
 };
 
 template <typename T>

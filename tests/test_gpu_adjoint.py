@@ -170,7 +170,7 @@ def test_window_objective_autograd():
     g1 = P.grad.clone()
     P.grad = None
     J2 = obj(P)
-    assert float(J2) == float(J)
+    assert float(J2.detach()) == float(J.detach())
     (3.0 * J2).backward()
     assert torch.allclose(P.grad, 3.0 * g1, rtol=1e-12, atol=0)
     assert float(torch.abs(g1).max()) > 0

@@ -183,3 +183,22 @@ def test_adjoint_refuses_the_mls_transfer():
         AdjointWindow(sim, 10, 5)
     assert e.value.status == 1
     sim.close()
+
+
+@pytest.mark.parametrize("weight", ["cubic", "gauss"])
+def test_channel_fp32_1000_steps_meets_tolerance(weight):
+    """The FP32 bar of the kernel transfer, with the MLS one: 256x64 channel,
+    one RBC and one rigid particle, 1000 steps, velocity rel-L2 <= 1e-5 and
+    markers <= 1e-4 dx against the FP64 oracle."""
+    announce(f"channel 256x64 fp32 1000 steps, mls {weight}")
+    wl = with_mls(configs.channel_256x64(), weight)
+    sim = pkg.Sim(wl, dtype="f32", graph_steps=100)
+    ref = oracle.Sim(wl)
+    sim.step(1000)
+    ref.step(1000)
+    du, dn = _vel_err(sim, ref)
+    dx = float(np.max(np.abs(sim.all_markers() - ref.all_markers())))
+    announce(f"channel mls {weight}: rel-L2 {du / dn:.3e} markers {dx:.3e}")
+    assert du <= 1e-5 * dn
+    assert dx <= 1e-4
+    sim.close()

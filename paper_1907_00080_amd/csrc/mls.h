@@ -55,15 +55,8 @@ __device__ __forceinline__ double mls_weight(double r, int kind, double h, doubl
   return (g - e1) / (1.0 - e1);
 }
 
-// The transfer mode as a value the compiler cannot hoist out of a loop: the
-// per-instance switch between kernel and MLS otherwise invites loop
-// unswitching, which copies whole vertex loops of the calling kernels once
-// per mode (code the latency-bound kernels pay for in instruction fetches).
-__device__ __forceinline__ bool use_mls(const LatDev& L) {
-  int t = L.transfer;
-  asm volatile("" : "+v"(t));
-  return t == LBIB_TRANSFER_MLS;
-}
+// The instance uses the MLS transfer (LBIB_TRANSFER_MLS).
+__device__ __forceinline__ bool use_mls(const LatDev& L) { return L.transfer == LBIB_TRANSFER_MLS; }
 
 // Shape functions ph[3 b + a] of the point (X, Y) and, when GRAD, their
 // derivatives with respect to X (px) and Y (py).
@@ -74,25 +67,15 @@ __device__ __forceinline__ void mls_shape(const LatDev& L, double X, double Y, d
   const bool pery = L.periodic_y != 0;
   const int kind = L.mls_weight;
   const double h = L.mls_h;
-  double dx[3], dy[3], wx[3] = {0, 0, 0}, dwx[3] = {0, 0, 0}, wy[3] = {0, 0, 0}, dwy[3] = {0, 0, 0};
+  double dx[3], dy[3], wx[3], dwx[3], wy[3], dwy[3];
+  // unrolled: the six weights are independent, and only kernels launched
+  // for the MLS transfer hold this code
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     dx[a] = (cxr + (a - 1)) - X;
     dy[a] = (cyr + (a - 1)) - Y;
-  }
-  // the six one-axis weights in a rolled loop: one copy of the weight code
-  // per call site; results go to fixed slots by selects (no indexed array)
-#pragma unroll 1
-  for (int i = 0; i < 6; ++i) {
-    const double r = i == 0 ? dx[0] : i == 1 ? dx[1] : i == 2 ? dx[2] : i == 3 ? dy[0] : i == 4 ? dy[1] : dy[2];
-    double d;
-    const double w = mls_weight(r, kind, h, d);
-    wx[0] = i == 0 ? w : wx[0]; dwx[0] = i == 0 ? d : dwx[0];
-    wx[1] = i == 1 ? w : wx[1]; dwx[1] = i == 1 ? d : dwx[1];
-    wx[2] = i == 2 ? w : wx[2]; dwx[2] = i == 2 ? d : dwx[2];
-    wy[0] = i == 3 ? w : wy[0]; dwy[0] = i == 3 ? d : dwy[0];
-    wy[1] = i == 4 ? w : wy[1]; dwy[1] = i == 4 ? d : dwy[1];
-    wy[2] = i == 5 ? w : wy[2]; dwy[2] = i == 5 ? d : dwy[2];
+    wx[a] = mls_weight(dx[a], kind, h, dwx[a]);
+    wy[a] = mls_weight(dy[a], kind, h, dwy[a]);
   }
   int rows_in = 0;
 #pragma unroll

@@ -691,7 +691,7 @@ constexpr int kVmax = kSmallBody;
 template <typename T, bool SMALL, int TX, int TY, bool ADV, bool MLS>
 __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, double (*sm)[kVmax],
                                           double (*s_red)[kBodyThreads / 64], double* s_rigid, int* s_box,
-                                          unsigned char* s_dyn) {
+                                          unsigned char* s_dyn, double (*s_uv)[kBodyThreads / 2]) {
   BodyDev* Bp = p.body + b;
   const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0, inst = Bp->inst;
   const double ks = Bp->ks, kb = Bp->kb, ka = Bp->ka, p_ref = Bp->p_ref, A0 = Bp->A0;
@@ -934,6 +934,19 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
     first = p.step_cur[inst] == 0;
   }
 
+  // A particle of at most nt/2 vertices: the upper half of the lanes (other
+  // waves, so other SIMDs) interpolates the fluid velocity at the vertices
+  // while the lower half runs the probes, instead of after the particle's
+  // update; the values are the same, read back from LDS.
+  const bool vel_early = SMALL && kind != kRBC && nv <= nt / 2;
+  if (vel_early && t >= nt / 2 && t - nt / 2 < nv) {
+    const int v = t - nt / 2;
+    double rho, ux, uy, g[4];
+    if (cached) interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
+    else interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
+    s_uv[0][v] = ux;
+    s_uv[1][v] = uy;
+  }
   // pass 2: element loads (area penalty, adhesion springs, probe stresses)
   for (int l = t; l < nv; l += nt) {
     const int lp = l + 1 == nv ? 0 : l + 1;
@@ -1031,8 +1044,14 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       const double relx = xn - xc, rely = yn - yc;
       const double ukx = U0 + Om * (-rely), uky = U1 + Om * relx;
       double rho, ux, uy, g[4];
-      if (cached) interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
-      else interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      if (vel_early) {
+        ux = s_uv[0][v];
+        uy = s_uv[1][v];
+      } else if (cached) {
+        interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
+      } else {
+        interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      }
       const double ds = 0.5 * (S_len[vm] + S_len[v]);
       p.xn[gm] = xn;
       p.yn[gm] = yn;
@@ -1089,8 +1108,14 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       fm = fmax_nan(fm, fmax_nan(fabs(fx), fabs(fy)));
     } else {
       double rho, ux, uy, g[4];
-      if (cached) interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
-      else interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      if (vel_early) {
+        ux = s_uv[0][v];
+        uy = s_uv[1][v];
+      } else if (cached) {
+        interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
+      } else {
+        interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      }
       const double xn = X[v] + ux + 0.5 * fx / mv;
       const double yn = Y[v] + uy + 0.5 * fy / mv;
       // velocity imposed by the weak coupling: the vertex displacement of the
@@ -1132,6 +1157,7 @@ __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_node
   __shared__ double s_rigid[6];
   __shared__ int s_box[4];
   __shared__ double sm[10][kVmax];   // x, y, len, nx, ny, bc, bnx, bny, fex, fey
+  __shared__ double s_uv[2][kBodyThreads / 2];   // fluid velocity at a small particle's vertices
   __shared__ int s_tmp[kBodyThreads];
   __shared__ int s_nelig;
   extern __shared__ unsigned char s_dyn[];
@@ -1144,9 +1170,9 @@ __global__ __launch_bounds__(kBodyThreads) void k_body(Ptrs<T> p, int cache_node
   }
   const int b = blockIdx.x - p.ninst;
   if (SMALL_ONLY || p.body[b].nv <= kVmax)
-    body_impl<T, true, TX, TY, ADV, MLS>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+    body_impl<T, true, TX, TY, ADV, MLS>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn, s_uv);
   else
-    body_impl<T, false, TX, TY, false, MLS>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn);
+    body_impl<T, false, TX, TY, false, MLS>(p, b, cache_nodes, sm, s_red, s_rigid, s_box, s_dyn, s_uv);
 }
 
 // Ends a run of steps: every marker moves to X^{n+1} (red cells by the

@@ -78,10 +78,11 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
                       f"step), float64 NumPy, one thread, {dt:.1f} s"}
 
 
-def traffic_from_profile(workload_name: str):
+def traffic_from_profile(workload_name: str, tile=None):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), if
-    it was taken with the current kernel source; else None."""
+    it was taken with the current kernel source and (when given) the same tile
+    shape; else None."""
     try:
         with open(PROFILE_TRAFFIC) as f:
             rec = json.load(f)
@@ -89,7 +90,26 @@ def traffic_from_profile(workload_name: str):
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
+    if tile is not None and rec.get("tiles", {}).get(workload_name) != f"{tile[0]}x{tile[1]}":
+        return None
     return rec.get("bytes_per_launch", {}).get(workload_name)
+
+
+def tuned_config(pkg, wl, args):
+    """Tile shape and step form for one workload: the autotuner's pick (whole
+    steps of this workload timed for every tile and step form), or the tile
+    given on the command line with the default step form."""
+    if args.tile != "auto":
+        return tuple(int(v) for v in args.tile.split("x")), None, None
+    from paper_1907_00080_amd import tune
+    rec = tune.autotune([wl], dtype="f32", device="cuda:0", steps=200, warmup=20,
+                        graph_steps=(args.graph_steps,))
+    tile = tuple(rec["tile"])
+    print(f"bench: {wl.name} tuned: tile {tile[0]}x{tile[1]}, step mode {rec['step_mode']} "
+          f"({len(rec['candidates'])} candidates)", file=sys.stderr, flush=True)
+    cands = [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "step_mode": c["step_mode"],
+              "us_per_step": round(c["ms_per_step"] * 1e3, 2)} for c in rec["candidates"]]
+    return tile, rec["step_mode"], cands
 
 
 def main():
@@ -99,7 +119,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="capillary-2000x200")
     ap.add_argument("--graph-steps", type=int, default=100)
-    ap.add_argument("--tile", default="64x4")
+    ap.add_argument("--tile", default="auto",
+                    help="TXxTY, or auto: tile and step form from the autotuner, per workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 6667 x 667 capillary")
     ap.add_argument("--kernel-steps", type=int, default=200,
@@ -114,6 +135,8 @@ def main():
                     help="skip the step with the vertex repulsion switched on")
     ap.add_argument("--no-mls", action="store_true",
                     help="skip the step with the moving-least-squares transfer")
+    ap.add_argument("--no-observables", action="store_true",
+                    help="skip the on-device observations")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -139,11 +162,11 @@ def main():
         return
     import paper_1907_00080_amd as pkg
 
-    tile = tuple(int(v) for v in args.tile.split("x"))
     wl = make_workload(args.workload)
+    tile, mode, cands = tuned_config(pkg, wl, args)
     res = run_workload(pkg, torch, wl, tile, args.steps, args.warmup, args.graph_steps,
-                       args.kernel_steps)
-    roof = roofline(res, wl)
+                       args.kernel_steps, mode)
+    roof = roofline(res, wl, tile)
 
     out = {
         "metric": "MLUPS of fused LB-IB step; batched vs plain MLUPS; adjoint/forward time",
@@ -161,26 +184,39 @@ def main():
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nodes": wl.nodes,
                    "rbc": sum(b.kind == 0 for b in wl.bodies),
                    "particles": sum(b.kind != 0 for b in wl.bodies),
-                   "markers": wl.n_markers, "tile": args.tile, "graph_steps": args.graph_steps},
+                   "markers": wl.n_markers, "tile": f"{tile[0]}x{tile[1]}",
+                   "step_mode": res["step_mode"], "graph_steps": args.graph_steps,
+                   "tuned": cands is not None},
         "roofline": roof,
     }
+    if cands is not None:
+        out["tuning"] = cands
     if not args.no_large and args.workload != "capillary-6667x667":
         # the HBM-bound case: 10 um x 100 um capillary at dx = 15 nm
         lw = make_workload("capillary-6667x667")
-        lres = run_workload(pkg, torch, lw, tile, args.large_steps, 20, args.graph_steps,
-                            args.large_steps)
+        ltile, lmode, lcands = tuned_config(pkg, lw, args)
+        lres = run_workload(pkg, torch, lw, ltile, args.large_steps, 20, args.graph_steps,
+                            args.large_steps, lmode)
         out["large_lattice"] = {"workload": lw.name, "nodes": lw.nodes, "markers": lw.n_markers,
+                                "tile": f"{ltile[0]}x{ltile[1]}", "step_mode": lres["step_mode"],
                                 "mlups": round(lres["mlups"], 1),
                                 "ms_per_step": round(lres["ms_step"], 5),
-                                "roofline": roofline(lres, lw)}
+                                "roofline": roofline(lres, lw, ltile)}
     if not args.no_batch:
         out["batched"] = batched_vs_plain(pkg, torch, args.batch_instances, args.batch_steps)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_window(pkg, torch, args.adjoint_steps, 100)
     if not args.no_repulsion:
-        out["repulsion"] = repulsion_cost(pkg, torch, args.workload, tile, 1000, args.graph_steps)
+        # its own tile: the repulsion reads the marker bins, whose shape follows the tile
+        rw = make_workload(args.workload)
+        from workloads import configs
+        rw.repulsion = configs.REPULSION_COEFF
+        rtile = tuned_config(pkg, rw, args)[0]
+        out["repulsion"] = repulsion_cost(pkg, torch, args.workload, rtile, 1000, args.graph_steps)
+        out["repulsion"]["tile"] = f"{rtile[0]}x{rtile[1]}"
     if not args.no_mls:
         out["mls"] = mls_cost(pkg, torch, args.workload, tile, 1000, args.graph_steps)
+    if not args.no_observables:
         out["observables"] = observables_cost(pkg, torch, args.workload, tile, args.graph_steps)
     if not args.no_couette:
         out["couette_box"] = couette_box_batch(pkg, torch, args.couette_steps)
@@ -190,12 +226,14 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps):
+def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps, step_mode=None):
     """Time `steps` whole steps (graph-captured chunks), then measure the fused
     lattice kernel in-step over `kernel_steps` plain-launched steps."""
     print(f"bench: workload {wl.name} nodes={wl.nodes} markers={wl.n_markers} "
-          f"bodies={len(wl.bodies)}", file=sys.stderr, flush=True)
+          f"bodies={len(wl.bodies)} tile {tile[0]}x{tile[1]}", file=sys.stderr, flush=True)
     sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=graph_steps)
+    if step_mode is not None:
+        sim.set_step_mode(int(step_mode))
     stream = sim.stream
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -224,8 +262,10 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps)
     sim.set_kernel_timing(False)
     print(f"bench: fused lattice kernel {k_ms * 1e3:.2f} us over {k_n} in-step launches",
           file=sys.stderr, flush=True)
+    mode = sim.step_mode
     sim.close()
-    return {"mlups": mlups, "ms_step": ms_step, "kernel_ms": k_ms, "kernel_launches": k_n}
+    return {"mlups": mlups, "ms_step": ms_step, "kernel_ms": k_ms, "kernel_launches": k_n,
+            "step_mode": mode}
 
 
 def repulsion_cost(pkg, torch, name, tile, steps, graph_steps):
@@ -478,12 +518,12 @@ def adjoint_window(pkg, torch, steps, ckpt):
             "fp64_adjoint_over_forward": round(r64["t_adj"] / r64["t_fwd"], 3)}
 
 
-def roofline(res, wl):
+def roofline(res, wl, tile=None):
     bytes_alg = 72.0 * wl.nodes           # 9 loads + 9 stores of 4 B per node
     achieved = bytes_alg / (res["kernel_ms"] / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profile(wl.name),
+            "traffic": traffic_from_profile(wl.name, tile),
             "kernel": "k_lb_fused", "kernel_us": round(res["kernel_ms"] * 1e3, 3),
             "launches": res["kernel_launches"], "bytes_per_launch": bytes_alg}
 

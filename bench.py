@@ -73,7 +73,14 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
     dt = time.perf_counter() - t0
     if limiter is not None:
         limiter.unregister() if hasattr(limiter, "unregister") else None
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": wl.nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_threads": os.cpu_count(),
             "sample": f"{wl.name}: {n} steps of the full lattice with all bodies (after 1 warm-up "
                       f"step), float64 NumPy, one thread, {dt:.1f} s"}
 

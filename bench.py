@@ -152,8 +152,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this "
-              "build (see DESIGN.md for how the lattice would be sharded)", file=sys.stderr)
+        print("bench.py: this solver runs on one GPU; multi-GPU runs are not supported "
+              "(a single capillary would be sharded in slabs along x with a population halo "
+              "exchange, a sweep by instances)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -43,7 +43,7 @@ def _llvm_tool(name: str) -> str:
 
 def private_segments(obj: str, workdir: str) -> dict:
     """Kernel name -> private (scratch) bytes per lane, read from the gfx950
-    code object this build put into `obj`."""
+    code object compiled into `obj`."""
     base = os.path.join(workdir, os.path.basename(obj))
     sections = subprocess.run([_llvm_tool("llvm-readelf"), "-S", "--wide", obj], check=True,
                               capture_output=True, text=True).stdout

@@ -1,0 +1,37 @@
+"""Host logic of bench.py (no GPU): the stored HBM-counter figure is reported
+only for the kernel source and the tile shape it was taken with, and the
+multi-GPU request is refused."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_traffic_figure_follows_source_hash_and_tile(monkeypatch):
+    b = _bench()
+    with open(b.PROFILE_TRAFFIC) as f:
+        rec = json.load(f)
+    name = "capillary-2000x200"
+    tile = tuple(int(v) for v in rec["tiles"][name].split("x"))
+    monkeypatch.setattr(b, "kernel_source_hash", lambda: rec["kernel_source_sha256_16"])
+    assert b.traffic_from_profile(name, tile) == rec["bytes_per_launch"][name]
+    other = (64, 4) if tile != (64, 4) else (256, 1)
+    assert b.traffic_from_profile(name, other) is None
+    monkeypatch.setattr(b, "kernel_source_hash", lambda: "0" * 16)
+    assert b.traffic_from_profile(name, tile) is None
+
+
+def test_multi_gpu_request_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

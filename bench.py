@@ -425,6 +425,12 @@ def batched_vs_plain(pkg, torch, n_inst, steps):
     b.set_step_mode(tuned["step_mode"])
     b.step(max(20, tuned["graph_steps"]))
     ms_b = _timed(torch, b, steps)
+    # the fused lattice kernel of the batch (one launch for all instances):
+    # HIP events bound to its dispatches over plain-launched steps
+    b.set_kernel_timing(True)
+    b.step(50)
+    k_ms, k_n = b.kernel_timing()
+    b.set_kernel_timing(False)
     d = b.diagnostics()
     b.close()
     if d["nonfinite"] or d["bin_overflow"] or d["sync_timeouts"]:
@@ -438,11 +444,18 @@ def batched_vs_plain(pkg, torch, n_inst, steps):
     mb = nodes * steps / (ms_b * 1e-3) / 1e6
     mp = nodes * steps / (ms_p * 1e-3) / 1e6
     print(f"bench: batched {mb:.0f} MLUPS (tile {tile[0]}x{tile[1]}, graphs of "
-          f"{tuned['graph_steps']}, step mode {tuned['step_mode']}), plain sequential {mp:.0f} MLUPS",
+          f"{tuned['graph_steps']}, step mode {tuned['step_mode']}), plain sequential {mp:.0f} MLUPS; "
+          f"batched lattice kernel {k_ms * 1e3:.1f} us "
+          f"({72.0 * nodes / (k_ms / 1e3) / 1e9:.0f} GB/s of algorithmic traffic)",
           file=sys.stderr, flush=True)
     return {"workload": f"sweep-{len(ws)}-instances", "instances": len(ws), "nodes": nodes,
             "steps": steps, "batched_mlups": round(mb, 1), "plain_mlups": round(mp, 1),
             "speedup": round(mb / mp, 3), "tile": f"{tile[0]}x{tile[1]}",
+            "lattice_kernel": {"kernel_us": round(k_ms * 1e3, 3), "launches": k_n,
+                               "bytes_per_launch": 72.0 * nodes,
+                               "achieved": round(72.0 * nodes / (k_ms / 1e3) / 1e9, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(72.0 * nodes / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
             "graph_steps": tuned["graph_steps"], "step_mode": tuned["step_mode"],
             "candidates": [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "graph_steps": c["graph_steps"],
                             "step_mode": c["step_mode"], "mlups": round(c["mlups"], 1)}

@@ -9,7 +9,12 @@ n_l = (t_l,y, -t_l,x).  Forces are returned per vertex, shape (nv, 2).
            the gradient of V = k_s (l - l_0)^2 / 2 (Eq. strainPot);
   bending  (Eq. bendFor): with Delta = theta - theta_0 at vertex v,
            F_left = k_b Delta l_left/(l_left + l_right) n_v,
-           F_v = -k_b Delta n_v, F_right = k_b Delta l_right/(l_left + l_right) n_v;
+           F_v = -k_b Delta n_v, F_right = k_b Delta l_right/(l_left + l_right) n_v,
+           where the sentence after the equation names l_right and l_left
+           the lengths of the left and right edges, respectively: the
+           neighbour across the shorter edge takes the larger share (the
+           lever rule), and the three forces exert neither a net force nor
+           a net moment;
   area     (Eq. areaFor): F_l = -k_a (1 - A/A_0) p_ref (n_l)^- l_l with
            (n_l)^- = -n_l, shared equally by the two vertices of l.
 
@@ -71,16 +76,20 @@ def bending_force(xy: np.ndarray, theta0: np.ndarray, kb: float) -> np.ndarray:
     nv = xy.shape[0]
     theta = turning_angles(xy)
     delta = theta - theta0
-    ll = np.roll(length, 1)              # left element of v: v-1 -> v
-    lr = length                          # right element of v: v -> v+1
+    len_left_edge = np.roll(length, 1)   # element v-1 -> v
+    len_right_edge = length              # element v -> v+1
+    # the symbols of Eq. bendFor: l_left is the right edge's length and
+    # l_right the left edge's (the defining sentence's "respectively")
+    l_left, l_right = len_right_edge, len_left_edge
     nsum = np.roll(n, 1, axis=0) + n
     nvert = nsum / np.hypot(nsum[:, 0], nsum[:, 1])[:, None]
     F = np.zeros((nv, 2))
     for v in range(nv):
         k = kb * delta[v]
-        F[(v - 1) % nv] += k * ll[v] / (ll[v] + lr[v]) * nvert[v]
+        s = l_left[v] + l_right[v]
+        F[(v - 1) % nv] += k * l_left[v] / s * nvert[v]
         F[v] -= k * nvert[v]
-        F[(v + 1) % nv] += k * lr[v] / (ll[v] + lr[v]) * nvert[v]
+        F[(v + 1) % nv] += k * l_right[v] / s * nvert[v]
     return F
 
 

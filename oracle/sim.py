@@ -96,6 +96,11 @@ class Sim:
         self.tr = (ib.Transfer("mls", getattr(wl, "mls_weight", "cubic"),
                                float(getattr(wl, "mls_support", 1.3)))
                    if getattr(wl, "transfer", "roma") == "mls" else ib.ROMA)
+        # velocity the weak coupling imposes at a soft-particle vertex:
+        # "displacement" (X^{n+1} - X^n, the reading used everywhere) or
+        # "verlet" (the second-order difference of Eq. verletVel, kept so
+        # that a test can show why the first-order form is used)
+        self.soft_velocity = "displacement"
         self.n = 0
         self.ties = 0
         self.rho = rho0.copy()
@@ -177,8 +182,11 @@ class Sim:
                 Fv = (membrane.internal_force(b.X, b.l0, b.theta0, b.A0, b.ks, b.kb, b.ka, b.p_ref)
                       + membrane.share_to_vertices(fel) + frep[bi])
                 Xn1 = b.X + U0 + 0.5 * Fv / b.mv
-                # velocity imposed by the weak coupling: displacement of the step
-                Un1 = Xn1 - b.X
+                if self.soft_velocity == "verlet" and not first:
+                    Un1 = 1.5 * Xn1 - 2.0 * b.X + 0.5 * b.Xm      # Eq. verletVel
+                else:
+                    # velocity imposed by the weak coupling: displacement of the step
+                    Un1 = Xn1 - b.X
             else:
                 Ftot = fel.sum(axis=0) + frep[bi].sum(axis=0)
                 c = membrane.centroids(b.X)

@@ -1,4 +1,6 @@
 """Pins of the oracle's membrane forces (Sec. 2.2, Eqs. strainFor, bendFor, areaFor)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -97,3 +99,51 @@ def test_bending_restoring_direction():
     # bending is invariant to scaling and rotation of the rest shape
     F2 = membrane.bending_force(geometry.place(2.0 * xy0, 0.4, [3, 3]), th0, 1.0)
     assert np.max(np.abs(F2)) < 1e-13
+
+
+def _golden_bending():
+    rows, kb = [], None
+    with open(os.path.join(os.path.dirname(__file__), "golden", "bending_rectangle_4x1.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            vals = [float(v) for v in line.split()]
+            if kb is None:
+                kb = vals[0]
+            else:
+                rows.append(vals)
+    a = np.array(rows)
+    return kb, a[:, 1:3], a[:, 3], a[:, 4:6]
+
+
+def test_bending_hand_worked_rectangle():
+    """Eq. bendFor worked by hand on a 4 x 1 rectangle bent at one corner whose
+    two edges differ in length (fixture and derivation in tests/golden/)."""
+    kb, xy, th0, F_expected = _golden_bending()
+    F = membrane.bending_force(xy, th0, kb)
+    assert np.max(np.abs(F - F_expected)) < 1e-15
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_internal_forces_exert_no_net_moment(seed):
+    """Internal membrane forces cannot change the body's angular momentum: the
+    bending triple of every vertex (with unequal edge lengths), the central
+    strain pairs and the area loads all have zero moment about any point."""
+    rng = np.random.default_rng(100 + seed)
+    xy0 = _shapes()[seed % 2]
+    l0, _, _ = membrane.elements(xy0)
+    th0 = membrane.turning_angles(xy0)
+    A0 = membrane.area(xy0)
+    # strongly uneven vertex spacing: element lengths differ by up to 3x
+    xy = xy0 + 0.25 * rng.standard_normal(xy0.shape)
+    length, _, _ = membrane.elements(xy)
+    assert length.max() / length.min() > 3.0
+    ref = rng.uniform(-20, 20, size=2)
+    for F in (membrane.bending_force(xy, th0, 0.01), membrane.strain_force(xy, l0, 0.02),
+              membrane.area_force(xy, A0, 1.0, 1 / 3)):
+        r = xy - ref[None, :]
+        M = np.sum(r[:, 0] * F[:, 1] - r[:, 1] * F[:, 0])
+        scale = np.sum(np.hypot(r[:, 0], r[:, 1]) * np.hypot(F[:, 0], F[:, 1]))
+        assert abs(M) < 1e-13 * scale
+        assert np.max(np.abs(F.sum(0))) < 1e-13 * np.max(np.abs(F))

@@ -110,3 +110,32 @@ def test_rigid_particle_carried_by_uniform_flow():
     assert abs(U[0] - um) < 0.02 * um
     assert abs(U[1]) < 1e-3 * um
     assert 0.8 * 0.01 < um <= 0.01 + 1e-12
+
+
+def _max_coupling_force(s, steps):
+    out = []
+    for _ in range(steps):
+        s.step(1)
+        F = float(np.abs(s.marker_force[1]).max())
+        out.append(F)
+        if not np.isfinite(F):
+            break
+    return np.array(out)
+
+
+def test_literal_verlet_velocity_coupling_grows_next_to_a_wall():
+    """Evidence for the imposed soft-vertex velocity: with the second-order
+    velocity of Eq. verletVel, U = 3/2 X^{n+1} - 2 X^n + 1/2 X^{n-1}, the
+    weak-coupling force of the soft particle released at y_cr/2 from the wall
+    (the gradient-window fixture) grows geometrically, about x1.2 per step,
+    while the displacement velocity X^{n+1} - X^n keeps it at its initial size.
+    Bounded: 56 steps, stops at the first non-finite force."""
+    wl = configs.adjoint_channel()
+    lit = oracle.Sim(wl)
+    lit.soft_velocity = "verlet"
+    F_lit = _max_coupling_force(lit, 56)
+    F_disp = _max_coupling_force(oracle.Sim(wl), 56)
+    assert np.all(np.isfinite(F_disp)) and F_disp.max() < 2.0 * F_disp[:5].max()
+    assert F_lit[-1] > 100.0 * F_lit[:10].max()
+    rate = (F_lit[50] / F_lit[30]) ** (1 / 20)
+    assert rate > 1.1

@@ -107,16 +107,18 @@ def tuned_config(pkg, wl, args):
     steps of this workload timed for every tile and step form), or the tile
     given on the command line with the default step form."""
     if args.tile != "auto":
-        return tuple(int(v) for v in args.tile.split("x")), None, None
+        return tuple(int(v) for v in args.tile.split("x")), None, None, None
     from paper_1907_00080_amd import tune
     rec = tune.autotune([wl], dtype="f32", device="cuda:0", steps=200, warmup=20,
                         graph_steps=(args.graph_steps,))
     tile = tuple(rec["tile"])
-    print(f"bench: {wl.name} tuned: tile {tile[0]}x{tile[1]}, step mode {rec['step_mode']} "
-          f"({len(rec['candidates'])} candidates)", file=sys.stderr, flush=True)
+    print(f"bench: {wl.name} tuned: tile {tile[0]}x{tile[1]}, step mode {rec['step_mode']}, "
+          f"cache hints {rec['cache_hints']} ({len(rec['candidates'])} candidates)",
+          file=sys.stderr, flush=True)
     cands = [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "step_mode": c["step_mode"],
-              "us_per_step": round(c["ms_per_step"] * 1e3, 2)} for c in rec["candidates"]]
-    return tile, rec["step_mode"], cands
+              "cache_hints": c["cache_hints"], "us_per_step": round(c["ms_per_step"] * 1e3, 2)}
+             for c in rec["candidates"]]
+    return tile, rec["step_mode"], rec["cache_hints"], cands
 
 
 def main():
@@ -171,9 +173,9 @@ def main():
     import paper_1907_00080_amd as pkg
 
     wl = make_workload(args.workload)
-    tile, mode, cands = tuned_config(pkg, wl, args)
+    tile, mode, hints, cands = tuned_config(pkg, wl, args)
     res = run_workload(pkg, torch, wl, tile, args.steps, args.warmup, args.graph_steps,
-                       args.kernel_steps, mode)
+                       args.kernel_steps, mode, hints)
     roof = roofline(res, wl, tile)
 
     out = {
@@ -202,9 +204,9 @@ def main():
     if not args.no_large and args.workload != "capillary-6667x667":
         # the HBM-bound case: 10 um x 100 um capillary at dx = 15 nm
         lw = make_workload("capillary-6667x667")
-        ltile, lmode, lcands = tuned_config(pkg, lw, args)
+        ltile, lmode, lhints, lcands = tuned_config(pkg, lw, args)
         lres = run_workload(pkg, torch, lw, ltile, args.large_steps, 20, args.graph_steps,
-                            args.large_steps, lmode)
+                            args.large_steps, lmode, lhints)
         out["large_lattice"] = {"workload": lw.name, "nodes": lw.nodes, "markers": lw.n_markers,
                                 "tile": f"{ltile[0]}x{ltile[1]}", "step_mode": lres["step_mode"],
                                 "mlups": round(lres["mlups"], 1),
@@ -234,7 +236,8 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps, step_mode=None):
+def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps, step_mode=None,
+                 cache_hints=None):
     """Time `steps` whole steps (graph-captured chunks), then measure the fused
     lattice kernel in-step over `kernel_steps` plain-launched steps."""
     print(f"bench: workload {wl.name} nodes={wl.nodes} markers={wl.n_markers} "
@@ -242,6 +245,8 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps,
     sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=graph_steps)
     if step_mode is not None:
         sim.set_step_mode(int(step_mode))
+    if cache_hints is not None:
+        sim.set_cache_hints(int(cache_hints))
     stream = sim.stream
     sim.step(warmup)
     torch.cuda.synchronize()

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define LBIB_ABI_VERSION 4u
+#define LBIB_ABI_VERSION 5u
 
 typedef struct lbib_ctx lbib_ctx;
 
@@ -158,9 +158,14 @@ lbib_status lbib_create(const lbib_lattice_desc* desc, lbib_ctx** out);
 lbib_status lbib_add_body(lbib_ctx* ctx, const lbib_body_desc* desc, const double* xy,
                           int32_t* id);
 
-/* Receptor positions on one wall (setup phase): wall 0 is y = -1/2, wall 1 is
- * y = ny - 1/2.  x: n strictly increasing values in [0, nx).  Replaces any
- * earlier set.  n = 0 clears the wall. */
+/* Receptor positions on one wall (setup phase), the binding sites of the
+ * ligand-receptor bonds of Sec. 2.2 "Wall-Particle Interaction" (receptors
+ * uniformly distributed over the walls): wall 0 is y = -1/2, wall 1 is
+ * y = ny - 1/2 (the node rows 0 and ny - 1 with velocity walls).  x: n
+ * strictly increasing values in [0, nx).  Replaces any earlier set.  n = 0
+ * clears the wall.  Errors: LBIB_EINVAL for a wall other than 0/1, n < 0,
+ * x NULL with n > 0, or values outside [0, nx) or not increasing;
+ * LBIB_ESTATE outside set-up. */
 lbib_status lbib_set_receptors(lbib_ctx* ctx, int32_t wall, const double* x, int32_t n);
 
 /* Bond kinetics parameters (setup phase; defaults: no bonds form). */
@@ -225,9 +230,11 @@ lbib_status lbib_set_transfer(lbib_ctx* ctx, int32_t mode, int32_t weight, doubl
  * takes each instance's setting). */
 lbib_status lbib_set_repulsion(lbib_ctx* ctx, double coeff, double cutoff);
 
-/* Initial fluid state (setup phase): populations at equilibrium with
- * density rho and velocity (ux, uy), host arrays of ny*nx doubles, row-major
- * [y][x].  rho may be NULL (1 everywhere); ux/uy NULL = 0.  Default: rest. */
+/* Initial fluid state (setup phase): populations at the equilibrium of
+ * Eq. (feq) (Sec. 2.1) with density rho and velocity (ux, uy), host arrays
+ * of ny*nx doubles, row-major [y][x], copied during the call.  rho may be
+ * NULL (1 everywhere); ux/uy NULL = 0.  Default: rest.  Errors: LBIB_EINVAL
+ * for a non-finite value or rho <= 0; LBIB_ESTATE outside set-up. */
 lbib_status lbib_init_fields(lbib_ctx* ctx, const double* rho, const double* ux,
                              const double* uy);
 
@@ -242,23 +249,46 @@ lbib_status lbib_bind(lbib_ctx* ctx, void* dev_workspace, size_t bytes, void* hi
 /* Upload the set-up, compute the stress-free state, enter the running phase. */
 lbib_status lbib_finalize_setup(lbib_ctx* ctx);
 
-/* Advance nsteps >= 0 time steps (running phase).  Asynchronous on the
- * bound stream.  If a watchdog interval is set (lbib_set_watchdog), the call
- * synchronises at its end and returns LBIB_EUNSTABLE when the state holds a
- * non-finite population or a non-positive density (state left in place). */
+/* Advance nsteps >= 0 time steps (running phase).  One step n -> n+1 runs,
+ * in this order (the paper gives the pieces, not their order): bond rupture
+ * and formation at X^n (Sec. 2.2 "Wall-Particle Interaction"); membrane,
+ * bending, area and spring forces (Eqs. strainFor, bendFor, areaFor, adhFor)
+ * and the optional repulsion (Eq. repFor); particle probe loads and motion
+ * (Eqs. hydroForP, hydroForNu; Sec. 2.3, Eqs. newtonSoft, verletPos,
+ * linearVelRig, angularVelRig) with the weak no-slip coupling; spreading of
+ * the marker forces (Sec. 2.2 "Immersed Boundary Treatment"); the forced
+ * collide-and-stream (Sec. 2.1, Eqs. BGK, feq; Sec. 2.2, Eqs. forcedBGK,
+ * ForcingTerm); red-cell advance (Sec. 2.3, Eq. kinematicPos).
+ * Asynchronous on the bound stream.  If the watchdog is on
+ * (lbib_set_watchdog), the call synchronises at its end and returns
+ * LBIB_EUNSTABLE when the state holds a non-finite population, a
+ * non-positive density, or a total mass that drifted from the set-up value
+ * by more than 1e-6 relative (bounce-back walls and periodic lattices
+ * conserve it to rounding; velocity walls exchange mass and are exempt from
+ * this check).  The state is left in place.  Errors: LBIB_EINVAL for
+ * nsteps < 0; LBIB_ESTATE outside the running phase. */
 lbib_status lbib_step(lbib_ctx* ctx, int64_t nsteps);
 
 /* Watchdog after every lbib_step call when on != 0 (default off). */
 lbib_status lbib_set_watchdog(lbib_ctx* ctx, int32_t on);
+
+/* Relative mass drift the watchdog accepts (default 1e-6; any phase).  The
+ * reference is the total mass at finalize_setup or at the last set_state.
+ * rel = 0 flags any change, including float32 rounding.  Errors:
+ * LBIB_EINVAL for a negative or non-finite value. */
+lbib_status lbib_set_watchdog_mass_tolerance(lbib_ctx* ctx, double rel);
 
 /* Steps per captured HIP graph used by lbib_step (even, 0 = no graphs;
  * default 0).  Graph replays and plain launches give bitwise-identical
  * results. */
 lbib_status lbib_set_graph_steps(lbib_ctx* ctx, int32_t steps);
 
-/* Fields of the last completed step (synchronises): rho and the physical
- * half-force velocity u = (sum f e + F/2)/rho, ny*nx doubles each, [y][x].
- * Any pointer may be NULL to skip it.  Before the first step: initial state. */
+/* Fields of the last completed step (synchronises): rho = sum f (Sec. 2.1)
+ * and the physical velocity with the half force of Sec. 2.2,
+ * u = (sum f e + F/2)/rho, F the node's total force (drive plus spread IB
+ * force), ny*nx doubles each, [y][x], written into caller buffers.  Any
+ * pointer may be NULL to skip it.  Before the first step: initial state.
+ * Errors: LBIB_ESTATE outside the running phase. */
 lbib_status lbib_get_fields(lbib_ctx* ctx, double* rho, double* ux, double* uy);
 
 /* Current vertex positions of body `body` (synchronises): nv*2 doubles. */
@@ -278,8 +308,12 @@ lbib_status lbib_get_marker_forces(lbib_ctx* ctx, int32_t body, double* fxy);
  * element ascending). */
 lbib_status lbib_num_ligands(const lbib_ctx* ctx, int32_t* n);
 
-/* Bond table (synchronises): lig_to_rec[n_ligands], -1 = free, else receptor
- * index (wall 0 receptors first, then wall 1).  *nbonds may be NULL. */
+/* Ligand-receptor bond table of Sec. 2.2 "Wall-Particle Interaction"
+ * (synchronises): lig_to_rec[n_ligands], -1 = free, else receptor index
+ * (wall 0 receptors first, then wall 1), written into a caller buffer.
+ * *nbonds (may be NULL) receives the number of bonds.  Errors: LBIB_EINVAL
+ * for lig_to_rec NULL with ligands present; LBIB_ESTATE outside the running
+ * phase. */
 lbib_status lbib_get_bonds(lbib_ctx* ctx, int32_t* lig_to_rec, int32_t* nbonds);
 
 /* Overwrite the bond table (running phase).  Entries must be -1 or a valid
@@ -292,7 +326,12 @@ lbib_status lbib_set_bonds(lbib_ctx* ctx, const int32_t* lig_to_rec);
 lbib_status lbib_get_state(lbib_ctx* ctx, void* blob, size_t* bytes);
 lbib_status lbib_set_state(lbib_ctx* ctx, const void* blob, size_t bytes);
 
-/* Whole-lattice diagnostics (synchronises). */
+/* Whole-lattice diagnostics (synchronises): the invariants of the scheme
+ * of Sec. 2.1 that the watchdog checks (mass, which bounce-back walls and
+ * periodic lattices conserve; momentum; density range; non-finite
+ * populations), the bond count of Sec. 2.2, and the library's own overflow
+ * and wait counters.  Errors: LBIB_EINVAL for out NULL; LBIB_ESTATE outside
+ * the running phase. */
 lbib_status lbib_diagnostics(lbib_ctx* ctx, lbib_diag* out);
 
 /* Flow regions of a body's lateral position eta = (y_c - y_lo) / (y_hi - y_lo)
@@ -410,6 +449,18 @@ lbib_status lbib_set_body_params(lbib_ctx* ctx, int32_t body, double ks, double 
  * returns the form in use (after finalize_setup) or the requested mode. */
 lbib_status lbib_set_step_mode(lbib_ctx* ctx, int32_t mode);
 lbib_status lbib_get_step_mode(const lbib_ctx* ctx, int32_t* mode);
+
+/* Cache hints of the fused lattice kernel's population accesses (the
+ * results are the same bit for bit; only the speed differs):
+ *   0  plain loads and stores;
+ *   1  non-temporal loads (pull streaming reads every population once);
+ *   3  non-temporal loads and stores;
+ *  -1  automatic (default): 3 on a single lattice whose two population
+ *      buffers take at most 128 MB, else 0.
+ * Allowed in any phase; LBIB_EINVAL for other values.  lbib_get_cache_hints
+ * returns the hints in use. */
+lbib_status lbib_set_cache_hints(lbib_ctx* ctx, int32_t hints);
+lbib_status lbib_get_cache_hints(const lbib_ctx* ctx, int32_t* hints);
 
 /* Completed step count. */
 lbib_status lbib_get_step(const lbib_ctx* ctx, int64_t* step);

@@ -42,6 +42,7 @@ EXPORTS = [
     "lbib_adjoint_workspace_query", "lbib_adjoint_bind", "lbib_adjoint_forward",
     "lbib_adjoint_backward", "lbib_set_body_params", "lbib_set_step_mode", "lbib_get_step_mode",
     "lbib_observe", "lbib_get_observations", "lbib_reset_observations",
+    "lbib_set_cache_hints", "lbib_get_cache_hints", "lbib_set_watchdog_mass_tolerance",
 ]
 
 REGION_CFL, REGION_INTERMEDIATE, REGION_BULK = 0, 1, 2
@@ -159,6 +160,9 @@ def library() -> ctypes.CDLL:
         "lbib_set_body_params": (I32, [P, I32, D, D, D]),
         "lbib_set_step_mode": (I32, [P, I32]),
         "lbib_get_step_mode": (I32, [P, ip]),
+        "lbib_set_cache_hints": (I32, [P, I32]),
+        "lbib_set_watchdog_mass_tolerance": (I32, [P, D]),
+        "lbib_get_cache_hints": (I32, [P, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -229,6 +233,23 @@ class _Ctx:
     def step_mode(self) -> int:
         m = ctypes.c_int32()
         self.check(self.lib.lbib_get_step_mode(self.h, ctypes.byref(m)))
+        return m.value
+
+    def set_watchdog(self, on: bool, mass_tolerance: Optional[float] = None):
+        """Watchdog after every step call; optional relative mass-drift bound."""
+        self.check(self.lib.lbib_set_watchdog(self.h, int(bool(on))))
+        if mass_tolerance is not None:
+            self.check(self.lib.lbib_set_watchdog_mass_tolerance(self.h, float(mass_tolerance)))
+
+    def set_cache_hints(self, hints: int):
+        """Lattice-kernel cache hints: -1 automatic, 0 plain, 1 non-temporal
+        loads, 3 non-temporal loads and stores."""
+        self.check(self.lib.lbib_set_cache_hints(self.h, int(hints)))
+
+    @property
+    def cache_hints(self) -> int:
+        m = ctypes.c_int32()
+        self.check(self.lib.lbib_get_cache_hints(self.h, ctypes.byref(m)))
         return m.value
 
     def time_lattice_kernel(self, reps: int = 20) -> float:

@@ -139,7 +139,9 @@ LBIB_HD void strain_vjp(double dx, double dy, double l0, double ks, double shx, 
 // Vertex u with left element dL = x_u - x_{u-1} and right element
 // dR = x_{u+1} - x_u: signed turning angle th = atan2(tL x tR, tL . tR),
 // n = normalize(nL + nR) with n = (t_y, -t_x), a = kb (th - th0);
-// F_{u-1} += a lL/(lL+lR) n, F_u -= a n, F_{u+1} += a lR/(lL+lR) n.
+// F_{u-1} += a lR/(lL+lR) n, F_u -= a n, F_{u+1} += a lL/(lL+lR) n (Eq. bendFor,
+// lever rule: each neighbour's share is the far edge's length, so the three
+// forces exert no net moment).
 LBIB_HD void bend_fwd(double dLx, double dLy, double dRx, double dRy, double th0, double kb,
                       double Fm[2], double Fu[2], double Fp[2]) {
   const double lL = sqrt(dLx * dLx + dLy * dLy), lR = sqrt(dRx * dRx + dRy * dRy);
@@ -149,7 +151,7 @@ LBIB_HD void bend_fwd(double dLx, double dLy, double dRx, double dRy, double th0
   const double nn = sqrt(nsx * nsx + nsy * nsy);
   const double nx = nsx / nn, ny = nsy / nn;
   const double a = kb * (th - th0);
-  const double wL = lL / (lL + lR), wR = lR / (lL + lR);
+  const double wL = lR / (lL + lR), wR = lL / (lL + lR);
   Fm[0] = a * wL * nx; Fm[1] = a * wL * ny;
   Fu[0] = -a * nx;     Fu[1] = -a * ny;
   Fp[0] = a * wR * nx; Fp[1] = a * wR * ny;
@@ -168,7 +170,7 @@ LBIB_HD void bend_vjp(double dLx, double dLy, double dRx, double dRy, double th0
   const double nn = sqrt(nsx * nsx + nsy * nsy);
   const double nx = nsx / nn, ny = nsy / nn;
   const double a = kb * (th - th0);
-  const double S = lL + lR, wL = lL / S, wR = lR / S;
+  const double S = lL + lR, wL = lR / S, wR = lL / S;
   const double Gx = wL * Fhm[0] - Fhu[0] + wR * Fhp[0];
   const double Gy = wL * Fhm[1] - Fhu[1] + wR * Fhp[1];
   const double ah = nx * Gx + ny * Gy;
@@ -187,8 +189,9 @@ LBIB_HD void bend_vjp(double dLx, double dLy, double dRx, double dRy, double th0
   tLhx -= nshy; tLhy += nshx;
   tRhx -= nshy; tRhy += nshx;
   const double S2 = S * S;
-  const double lLh = wLh * (lR / S2) - wRh * (lR / S2);
-  const double lRh = -wLh * (lL / S2) + wRh * (lL / S2);
+  // wL = lR / S, wR = lL / S
+  const double lLh = -wLh * (lR / S2) + wRh * (lR / S2);
+  const double lRh = wLh * (lL / S2) - wRh * (lL / S2);
   unit_vjp(dLx, dLy, tLhx, tLhy, lLh, dLh[0], dLh[1]);
   unit_vjp(dRx, dRy, tRhx, tRhy, lRh, dRh[0], dRh[1]);
 }

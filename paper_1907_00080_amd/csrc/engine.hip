@@ -86,6 +86,10 @@ struct lbib_ctx {
   long long step = 0;
   int parity = 0;  // 0: A holds the state; 1: B holds it
   bool watchdog = false;
+  // total mass at set-up (or at the last set_state): the watchdog's drift
+  // reference; NaN when a lattice has velocity walls (they exchange mass)
+  double mass_ref = 0.0;
+  double mass_tol = 1e-6;     // relative drift the watchdog accepts
   int graph_steps = 0;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   std::string err;
@@ -98,6 +102,9 @@ struct lbib_ctx {
   // how a step is launched (lbib_set_step_mode): 0 automatic, 1 three
   // kernels, 2 merged advance, 3 overlapped lattice tiles
   int step_mode = 0;
+  // cache hints of the fused lattice kernel's population accesses
+  // (lbib_set_cache_hints): -1 automatic, else the NT bits
+  int cache_hints = -1;
   bool merge_advance = true;  // resolved from step_mode and the bodies
   bool repulsion = false;     // some instance has the vertex repulsion on
   int nrep_chunk = 0;         // repulsion work units (kRepChunk vertices of a body)
@@ -160,7 +167,7 @@ void compute_sizes(lbib_ctx* c) {
     c->nrec += (int)(I.rec[0].size() + I.rec[1].size());
     const int ntx = (I.lat.nx + c->TX - 1) / c->TX, nty = (I.lat.ny + c->TY - 1) / c->TY;
     c->ntiles += ntx * nty;
-    c->nodes += (long long)I.lat.nx * I.lat.ny;
+    c->nodes += (long long)row_pitch(I.lat.nx) * I.lat.ny;   // padded rows
   }
 }
 
@@ -321,12 +328,14 @@ StepArgs step_args(const lbib_ctx* c) {
   a.body_cache_bytes = c->body_cache;
   a.max_nv = 0;
   a.any_mls = 0;
-  // non-temporal population loads pay on a single lattice and cost on
-  // batches of many small ones; non-temporal stores pay on a single lattice
-  // whose two population buffers stay well inside the 256 MB last-level
-  // cache (28.8 MB measured) and cost on one beyond it (320 MB measured)
+  // automatic cache hints: non-temporal loads and stores on a single lattice
+  // whose two population buffers stay well inside the 256 MB last-level cache
+  // (28.8 MB measured), plain accesses otherwise (with 256-byte aligned rows
+  // they measured as fast or faster on 320 MB, and on batches); the
+  // autotuner times all three forms
   const double pop_bytes = 2.0 * 9.0 * (double)c->nodes * (double)elem_size(c->dtype);
-  a.nt_mode = c->ninst != 1 ? 0 : (pop_bytes <= 128.0 * 1024 * 1024 ? 3 : 1);
+  a.nt_mode = c->cache_hints >= 0 ? c->cache_hints
+                                  : (c->ninst == 1 && pop_bytes <= 128.0 * 1024 * 1024 ? 3 : 0);
   for (auto& I : c->inst) {
     for (auto& b : I.bodies) a.max_nv = std::max(a.max_nv, b.d.nv);
     if (I.transfer == LBIB_TRANSFER_MLS) a.any_mls = 1;
@@ -377,7 +386,8 @@ lbib_status upload_all(lbib_ctx* c) {
     D.ntx = (D.nx + c->TX - 1) / c->TX;
     D.nty = (D.ny + c->TY - 1) / c->TY;
     D.tile_base = c->tile_base[i];
-    D.bin_base = c->tile_base[i] + i;
+    D.pitch = row_pitch(D.nx);
+    D.plane = (long long)D.pitch * D.ny;
     D.marker_base = c->marker_base[i];
     D.body_base = c->body_base[i];
     D.n_bodies = (int)I.bodies.size();
@@ -514,17 +524,19 @@ lbib_status upload_all(lbib_ctx* c) {
   // populations: equilibrium of the initial fields, shifted by the weights
   for (int i = 0; i < c->ninst; ++i) {
     InstHost& I = c->inst[i];
-    const long long N = (long long)I.lat.nx * I.lat.ny;
-    std::vector<T> h(9 * N);
-    for (long long k = 0; k < N; ++k) {
+    const int nx = I.lat.nx, pitch = row_pitch(nx);
+    const long long N = (long long)pitch * I.lat.ny;
+    std::vector<T> h(9 * N, T(0));   // row padding stays zero
+    for (long long k = 0; k < (long long)nx * I.lat.ny; ++k) {
       const double rho = I.rho0.empty() ? 1.0 : I.rho0[k];
       const double ux = I.ux0.empty() ? 0.0 : I.ux0[k];
       const double uy = I.uy0.empty() ? 0.0 : I.uy0[k];
       const double uu = ux * ux + uy * uy;
+      const long long node = (k / nx) * pitch + k % nx;
       for (int q = 0; q < 9; ++q) {
         const double eu = ex(q) * ux + ey(q) * uy;
         const double w8 = wq<double>(q);
-        h[q * N + k] = T(w8 * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
+        h[q * N + node] = T(w8 * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
       }
     }
     HIPCHK(c, hipMemcpyAsync(w + L.A + 9 * c->node_base[i] * sizeof(T), h.data(), sizeof(T) * h.size(),
@@ -687,6 +699,20 @@ lbib_status diag_impl(lbib_ctx* c, double out[6]) {
   return LBIB_OK;
 }
 
+// Reference mass of the watchdog's drift check, from the current state.
+lbib_status record_mass(lbib_ctx* c) {
+  for (auto& I : c->inst)
+    if (I.wall_mode != 0) {
+      c->mass_ref = NAN;   // velocity walls exchange mass with the outside
+      return LBIB_OK;
+    }
+  double d[6];
+  lbib_status s = c->dtype == LBIB_F64 ? diag_impl<double>(c, d) : diag_impl<float>(c, d);
+  if (s != LBIB_OK) return s;
+  c->mass_ref = d[0];
+  return LBIB_OK;
+}
+
 template <typename T>
 lbib_status fields_impl(lbib_ctx* c, int inst, double* rho, double* ux, double* uy) {
   const InstHost& I = c->inst[inst];
@@ -730,7 +756,7 @@ std::vector<std::pair<size_t, size_t>> state_regions(const lbib_ctx* c) {
       {L.x, 8 * nm}, {L.y, 8 * nm}, {L.xm, 8 * nm}, {L.ym, 8 * nm}, {L.xn, 8 * nm}, {L.yn, 8 * nm},
       {L.fx, 8 * nm}, {L.fy, 8 * nm}, {L.cx, 4 * nm}, {L.cy, 4 * nm}, {L.wx, 72 * nm}, {L.wy, 24 * nm},
       {L.touched, 4 * (size_t)c->ntiles},
-      {L.l2r, 4 * nl}, {L.r2l, 4 * nr}, {L.step_next, 8 * (size_t)c->ninst},
+      {L.l2r, 4 * nl}, {L.r2l, 4 * nr}, {L.lig_sigma, 8 * nl}, {L.step_next, 8 * (size_t)c->ninst},
       {L.step_cur, 8 * (size_t)c->ninst}, {L.ties, 8 * (size_t)c->ninst}};
   return r;
 }
@@ -1079,7 +1105,7 @@ const char* lbib_last_error(const lbib_ctx* c) { return c ? c->err.c_str() : g_c
 lbib_status lbib_create(const lbib_lattice_desc* d, lbib_ctx** out) {
   if (!d || !out) return fail(nullptr, LBIB_EINVAL, "NULL argument");
   if (d->nx < 1 || d->ny < 1) return fail(nullptr, LBIB_EINVAL, "nx and ny must be >= 1");
-  if ((long long)d->nx * d->ny > (1ll << 31)) return fail(nullptr, LBIB_EINVAL, "lattice too large");
+  if ((long long)row_pitch(d->nx) * d->ny > (1ll << 31)) return fail(nullptr, LBIB_EINVAL, "lattice too large");
   if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return fail(nullptr, LBIB_EINVAL, "tau must be > 1/2");
   if (d->dtype != LBIB_F32 && d->dtype != LBIB_F64) return fail(nullptr, LBIB_EINVAL, "bad dtype");
   int tx = d->tile_x, ty = d->tile_y;
@@ -1249,6 +1275,8 @@ lbib_status lbib_finalize_setup(lbib_ctx* c) {
   resolve_step_mode(c);
   lbib_status s = c->dtype == LBIB_F64 ? upload_all<double>(c) : upload_all<float>(c);
   if (s != LBIB_OK) return s;
+  s = record_mass(c);
+  if (s != LBIB_OK) return s;
   c->phase = 2;
   return LBIB_OK;
 }
@@ -1265,6 +1293,26 @@ lbib_status lbib_set_step_mode(lbib_ctx* c, int32_t mode) {
   return LBIB_OK;
 }
 
+lbib_status lbib_set_cache_hints(lbib_ctx* c, int32_t hints) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (hints != -1 && hints != 0 && hints != 1 && hints != 3)
+    return fail(c, LBIB_EINVAL, "cache hints must be -1, 0, 1 or 3");
+  if (hints != c->cache_hints) {
+    drop_graphs(c);
+    drop_adjoint_graphs(c);
+  }
+  c->cache_hints = hints;
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_cache_hints(const lbib_ctx* cc, int32_t* hints) {
+  lbib_ctx* c = const_cast<lbib_ctx*>(cc);
+  if (!c || !hints) return fail(c, LBIB_EINVAL, "NULL argument");
+  if (c->phase == 0) compute_sizes(c);
+  *hints = step_args(c).nt_mode;
+  return LBIB_OK;
+}
+
 lbib_status lbib_get_step_mode(const lbib_ctx* cc, int32_t* mode) {
   lbib_ctx* c = const_cast<lbib_ctx*>(cc);
   if (!c || !mode) return fail(c, LBIB_EINVAL, "NULL argument");
@@ -1275,6 +1323,13 @@ lbib_status lbib_get_step_mode(const lbib_ctx* cc, int32_t* mode) {
 lbib_status lbib_set_watchdog(lbib_ctx* c, int32_t on) {
   if (!c) return fail(c, LBIB_EINVAL, "NULL context");
   c->watchdog = on != 0;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_watchdog_mass_tolerance(lbib_ctx* c, double rel) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (!(rel >= 0.0) || !std::isfinite(rel)) return fail(c, LBIB_EINVAL, "tolerance must be finite and >= 0");
+  c->mass_tol = rel;
   return LBIB_OK;
 }
 
@@ -1298,6 +1353,12 @@ lbib_status lbib_step(lbib_ctx* c, int64_t n) {
     if (s != LBIB_OK) return s;
     if (d[5] > 0 || !(d[3] > 0))
       return fail(c, LBIB_EUNSTABLE, "watchdog: non-finite population or non-positive density");
+    if (std::isfinite(c->mass_ref) && !(std::fabs(d[0] - c->mass_ref) <= c->mass_tol * c->mass_ref)) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "watchdog: total mass %.17g drifted from %.17g by more than %g relative",
+                    d[0], c->mass_ref, c->mass_tol);
+      return fail(c, LBIB_EUNSTABLE, msg);
+    }
   }
   return LBIB_OK;
 }
@@ -1458,10 +1519,22 @@ lbib_status lbib_set_state(lbib_ctx* c, const void* blob, size_t bytes) {
     HIPCHK(c, hipMemcpyAsync(c->ws + r.first, o, r.second, hipMemcpyHostToDevice, c->stream));
     o += r.second;
   }
+  // the host copies of the body constants follow the restored records
+  std::vector<BodyDev> bd(std::max(c->nbody, 1));
+  HIPCHK(c, hipMemcpyAsync(bd.data(), c->ws + c->L.body, sizeof(BodyDev) * bd.size(),
+                           hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0, b = 0; i < c->ninst; ++i)
+    for (auto& B : c->inst[i].bodies) {
+      B.d.ks = bd[b].ks;
+      B.d.kb = bd[b].kb;
+      B.d.sigma = bd[b].sigma;
+      ++b;
+    }
   c->step = (long long)h.step;
   c->stencil_dirty = true;   // marker bins are rebuilt from the restored positions
-  return LBIB_OK;
+  c->adj_ready = false;
+  return record_mass(c);
 }
 
 lbib_status lbib_diagnostics(lbib_ctx* c, lbib_diag* out) {

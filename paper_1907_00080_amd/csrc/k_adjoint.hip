@@ -92,7 +92,7 @@ template <typename T>
 __device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm) {
   if (gm >= p.nm_total) return;
   const LatDev& L = p.lat[0];
-  const long long N = (long long)L.nx * L.ny;
+  const long long N = L.plane;
   const int kind = p.minfo[gm] & 3;
   Stencil s;
   stencil_at(L, a.x[gm], a.y[gm], false, s);
@@ -106,7 +106,7 @@ __device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm
   for (int b = 0; b < 3; ++b) {
     if (!s.ok[b]) continue;
     for (int c = 0; c < 3; ++c) {
-      const long long node = (long long)s.row[b] * L.nx + s.col[c];
+      const long long node = (long long)s.row[b] * L.pitch + s.col[c];
       const double w = s.wx[c] * s.wy[b];
       unsafeAtomicAdd(&a.FE[node], fx * w);
       unsafeAtomicAdd(&a.FE[N + node], fy * w);
@@ -139,10 +139,11 @@ __device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm
 template <typename T>
 __global__ void ka_collide(Ptrs<T> p, AdjPtrs a) {
   const LatDev& L = p.lat[0];
-  const long long N = (long long)L.nx * L.ny;
+  const long long N = L.plane;
   const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= N) return;
-  const int x = (int)(node % L.nx), y = (int)(node / L.nx);
+  const int x = (int)(node % L.pitch), y = (int)(node / L.pitch);
+  if (x >= L.nx) return;   // row padding
   const T* H = (const T*)a.h;
   double h[kQ], ah[kQ], hh[kQ];
 #pragma unroll
@@ -151,7 +152,7 @@ __global__ void ka_collide(Ptrs<T> p, AdjPtrs a) {
     int ys = y - ey(i);
     const bool out = ys < 0 || ys >= L.ny;
     ys = wrap_idx(ys, L.ny);
-    const long long src = (out && !L.periodic_y) ? opp(i) * N + node : i * N + (long long)ys * L.nx + xs;
+    const long long src = (out && !L.periodic_y) ? opp(i) * N + node : i * N + (long long)ys * L.pitch + xs;
     h[i] = double(H[src]);
     ah[i] = a.ha[i * N + node];
   }
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
   const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0;
   if (kind == kRigid) return;   // refused by the host
   const LatDev& L = p.lat[0];
-  const long long N = (long long)L.nx * L.ny;
+  const long long N = L.plane;
   const bool pery = L.periodic_y != 0;
   const double nu = (L.tau - 0.5) / 3.0;
   const double ks = Bp->ks, kb = Bp->kb, ka = Bp->ka, p_ref = Bp->p_ref, A0 = Bp->A0;
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
     for (int bb = 0; bb < 3; ++bb) {
       if (!s.ok[bb]) continue;
       for (int c = 0; c < 3; ++c) {
-        const long long node = (long long)s.row[bb] * L.nx + s.col[c];
+        const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
         const double w = s.wx[c] * s.wy[bb];
         const double ex_ = a.FEh[node], ey_ = a.FEh[N + node];
         fhx += ex_ * w;
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
       for (int bb = 0; bb < 3; ++bb) {
         if (!s.ok[bb]) continue;
         for (int c = 0; c < 3; ++c) {
-          const long long node = (long long)s.row[bb] * L.nx + s.col[c];
+          const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
           const double w = s.wx[c] * s.wy[bb];
           const double us = mom[N + node], vs = mom[2 * N + node];
           U0x += us * w;
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
       for (int bb = 0; bb < 3; ++bb) {
         if (!s.ok[bb]) continue;
         for (int c = 0; c < 3; ++c) {
-          const long long node = (long long)s.row[bb] * L.nx + s.col[c];
+          const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
           const double w = s.wx[c] * s.wy[bb];
           const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
           rq += r0 * w;
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
       for (int bb = 0; bb < 3; ++bb) {
         if (!s.ok[bb]) continue;
         for (int c = 0; c < 3; ++c) {
-          const long long node = (long long)s.row[bb] * L.nx + s.col[c];
+          const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
           const double wx = s.wx[c], wy = s.wy[bb], dwx = s.dwx[c], dwy = s.dwy[bb];
           const double ddwx = s.ddwx[c], ddwy = s.ddwy[bb];
           const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
@@ -412,9 +413,10 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
 template <typename T>
 __device__ inline void stream_adjoint(const Ptrs<T>& p, const AdjPtrs& a, long long node) {
   const LatDev& L = p.lat[0];
-  const long long N = (long long)L.nx * L.ny;
+  const long long N = L.plane;
   if (node >= N) return;
-  const int x = (int)(node % L.nx), y = (int)(node / L.nx);
+  const int x = (int)(node % L.pitch), y = (int)(node / L.pitch);
+  if (x >= L.nx) return;   // row padding
 #pragma unroll
   for (int j = 0; j < kQ; ++j) {
     int xs = wrap_idx(x + ex(j), L.nx), ys = y + ey(j);
@@ -425,7 +427,7 @@ __device__ inline void stream_adjoint(const Ptrs<T>& p, const AdjPtrs& a, long l
       i = opp(j);
     } else {
       ys = wrap_idx(ys, L.ny);
-      src = (long long)ys * L.nx + xs;
+      src = (long long)ys * L.pitch + xs;
     }
     const double rho = a.mom[src], us = a.mom[N + src], vs = a.mom[2 * N + src];
     const double rh = a.Rh[src], uh = a.Rh[N + src], vh = a.Rh[2 * N + src];

@@ -27,9 +27,9 @@ namespace lbib {
 // ------------------------------------------------------------------ helpers
 // Populations at a node after streaming, before forcing (walls: bounce-back).
 template <typename T>
-__device__ inline void pull_node(const T* A, long long N, int nx, int ny, bool pery, int x, int y,
-                                 T hv[kQ]) {
-  const long long node = (long long)y * nx + x;
+__device__ inline void pull_node(const T* A, long long N, int nx, int ny, int pitch, bool pery, int x,
+                                 int y, T hv[kQ]) {
+  const long long node = (long long)y * pitch + x;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     int xs = x - ex(i);
@@ -37,7 +37,7 @@ __device__ inline void pull_node(const T* A, long long N, int nx, int ny, bool p
     int ys = y - ey(i);
     const bool out = ys < 0 || ys >= ny;
     ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-    const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * nx + xs;
+    const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * pitch + xs;
     hv[i] = A[src];
   }
 }
@@ -55,7 +55,7 @@ __device__ inline void pulled_moments(const T* A, const LatDev& L, long long N, 
                                       double& drho, double& jx, double& jy) {
   drho = 0.0; jx = 0.0; jy = 0.0;
   T hv[kQ];
-  pull_node(A, N, L.nx, L.ny, L.periodic_y != 0, x, y, hv);
+  pull_node(A, N, L.nx, L.ny, L.pitch, L.periodic_y != 0, x, y, hv);
   wall_fill_drive(L, y, hv);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -70,7 +70,7 @@ __device__ inline void pulled_moments(const T* A, const LatDev& L, long long N, 
 template <typename T>
 __device__ inline void node_star(const T* A, const LatDev& L, int x, int y, double& rho,
                                  double& ux, double& uy) {
-  const long long N = (long long)L.nx * L.ny;
+  const long long N = L.plane;
   double drho, jx, jy;
   pulled_moments(A, L, N, x, y, drho, jx, jy);
   rho = 1.0 + drho;
@@ -461,7 +461,7 @@ __device__ inline void rbc_adv_load(const Ptrs<T>& p, const LatDev& L, int gm, R
 template <bool MLS, typename T>
 __device__ inline void rbc_adv_finish(const Ptrs<T>& p, const LatDev& L, const RbcAdv<MLS>& in, double X,
                                       double Y, bool first, double& xn, double& yn) {
-  const long long N = (long long)L.nx * L.ny;
+  const long long N = L.plane;
   const T* U = p.U + 2 * L.node_base;
   const int cx = in.cx, cy = in.cy;
   double ux = 0.0, uy = 0.0;
@@ -478,7 +478,7 @@ __device__ inline void rbc_adv_finish(const Ptrs<T>& p, const LatDev& L, const R
       double w;
       if constexpr (MLS) w = use_mls(L) ? in.ph[3 * b2 + a] : in.ph[a] * in.ph[3 + b2];
       else w = in.wx[a] * in.wy[b2];
-      const long long node = (long long)row * L.nx + col;
+      const long long node = (long long)row * L.pitch + col;
       ux += double(U[node]) * w;
       uy += double(U[N + node]) * w;
     }
@@ -825,7 +825,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
       cached = true;
       C.bx0 = s_box[0]; C.by0 = by0; C.bw = bw; C.bh = bh;
       const int nbox = bw * bh;
-      const long long Nn = (long long)L.nx * L.ny;
+      const long long Nn = L.plane;
       T* cw = (T*)s_dyn;
       constexpr int NB = 4;   // nodes per lane per batch: 36 loads in flight
       T hv[NB][kQ];
@@ -837,7 +837,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
           const int col = wrap_i(C.bx0 + kk % bw, L.nx);
           int row = by0 + kk / bw;
           if (pery) row = wrap_i(row, L.ny);
-          pull_node(A, Nn, L.nx, L.ny, pery, col, row, hv[q]);
+          pull_node(A, Nn, L.nx, L.ny, L.pitch, pery, col, row, hv[q]);
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -1077,10 +1077,13 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
     // tangents from normals: t = (-n_y, n_x)
     double fx = sr * (-S_ny[v]) - sl * (-S_ny[vm]);
     double fy = sr * S_nx[v] - sl * S_nx[vm];
-    // bending at v-1 (v is its right vertex), v, v+1 (v is its left vertex)
+    // bending at v-1 (v is its right vertex), v, v+1 (v is its left vertex);
+    // Eq. bendFor with the lever rule: a neighbour's share is the length of
+    // the edge on the far side of the bent vertex over the two lengths (the
+    // symbols' defining sentence), so the three forces exert no net moment
     {
       const double c = S_bc[vm];
-      const double fr = S_len[vm] / (S_len[vmm] + S_len[vm]);
+      const double fr = S_len[vmm] / (S_len[vmm] + S_len[vm]);
       fx += c * fr * S_bnx[vm];
       fy += c * fr * S_bny[vm];
     }
@@ -1091,7 +1094,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
     }
     {
       const double c = S_bc[vp];
-      const double fl = S_len[v] / (S_len[v] + S_len[vp]);
+      const double fl = S_len[vp] / (S_len[v] + S_len[vp]);
       fx += c * fl * S_bnx[vp];
       fy += c * fl * S_bny[vp];
     }

@@ -89,9 +89,10 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
   if (tile >= ntiles_total) return;
   const int cls = mode >> 2;
   if (cls != 0 && (cls == 1) == (p.cnt_cur[tile] > 0)) return;   // the other launch's tile
-  const int inst = p.tile_inst[tile];
+  // a single lattice needs no lookup: its parameters are the first load
+  const int inst = p.ninst == 1 ? 0 : p.tile_inst[tile];
   const LatDev& L = p.lat[inst];
-  const int nx = L.nx, ny = L.ny, ntx = L.ntx, nty = L.nty;
+  const int nx = L.nx, ny = L.ny, ntx = L.ntx, pitch = L.pitch;
   const bool pery = L.periodic_y != 0;
   const int local = tile - L.tile_base;
   const int tx = local % ntx, ty = local / ntx;
@@ -102,10 +103,10 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
 
   // ---- pull streaming with halfway bounce-back, issued first so that the
   // population loads are in flight while the tile's IB force is gathered
-  const long long N = (long long)nx * ny;
+  const long long N = L.plane;
   const T* __restrict__ A = p.A + 9 * L.node_base;
   T* __restrict__ B = p.B + 9 * L.node_base;
-  const long long node = (long long)y * nx + x;
+  const long long node = (long long)y * pitch + x;
   T h[kQ];
   if (inside) {
     // source index per direction chosen without branches, so that all nine
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
       int ys = y - ey(i);
       const bool out = ys < 0 || ys >= ny;
       ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-      const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * nx + xs;
+      const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * pitch + xs;
       h[i] = (NT & 1) ? __builtin_nontemporal_load(&A[src]) : A[src];
     }
   }
@@ -204,14 +205,16 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
 // a post-collision momentum sum h* e = rho u + F/2, so where F is the uniform
 // drive alone rho u = sum h* e - g/2.  Touched tiles take u from the velocity
 // buffer written by the fused kernel (their F includes the IB forces).
+// Outputs are dense [y][x] arrays of nx * ny values.
 template <typename T>
 __global__ void k_fields(Ptrs<T> p, int inst, int TX, int TY, double* rho_o, double* ux_o,
                          double* uy_o) {
   const LatDev& L = p.lat[inst];
-  const long long N = (long long)L.nx * L.ny;
-  long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
-  const int x = (int)(node % L.nx), y = (int)(node / L.nx);
+  const long long N = L.plane;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)L.nx * L.ny) return;
+  const int x = (int)(k % L.nx), y = (int)(k / L.nx);
+  const long long node = (long long)y * L.pitch + x;
   const T* A = p.A + 9 * L.node_base;  // A holds the newest post-collision populations
   double h[kQ];
   for (int i = 0; i < kQ; ++i) h[i] = double(A[i * N + node]);
@@ -233,9 +236,9 @@ __global__ void k_fields(Ptrs<T> p, int inst, int TX, int TY, double* rho_o, dou
     ux = (jx - 0.5 * L.gx) / rho;
     uy = (jy - 0.5 * L.gy) / rho;
   }
-  if (rho_o) rho_o[node] = rho;
-  if (ux_o) ux_o[node] = ux;
-  if (uy_o) uy_o[node] = uy;
+  if (rho_o) rho_o[k] = rho;
+  if (ux_o) ux_o[k] = ux;
+  if (uy_o) uy_o[k] = uy;
 }
 
 // Deterministic two-pass reduction of mass, momentum, min rho, max |u| and
@@ -251,8 +254,9 @@ __global__ __launch_bounds__(256) void k_diag1(Ptrs<T> p, long long nodes_total,
     int inst = 0;
     while (inst + 1 < p.ninst && p.lat[inst + 1].node_base <= g) ++inst;
     const LatDev& L = p.lat[inst];
-    const long long N = (long long)L.nx * L.ny;
+    const long long N = L.plane;
     const long long node = g - L.node_base;
+    if (node % L.pitch >= L.nx) continue;   // row padding
     const T* A = p.A + 9 * L.node_base;
     double drho = 0, jx = 0, jy = 0;
     bool fin = true;

@@ -1,7 +1,10 @@
 // lbib_dev.h - device-side data layout and helpers of the LB-IB library (gfx950).
 //
 // Layout in the caller's workspace (all float64 Lagrangian data, SoA):
-//   populations  A, B : T[9][N] per instance, N = nx*ny, node = y*nx + x,
+//   populations  A, B : T[9][N] per instance, node = y*pitch + x with the
+//                       row pitch nx rounded up to 64 elements (every row
+//                       starts on a 256-byte boundary; columns x >= nx are
+//                       padding that no kernel reads), N = pitch*ny,
 //                       stored shifted by the rest weights: h_i = f_i - w_i
 //   velocity     U    : T[2][N] per instance (written on touched tiles only)
 //   markers           : x[Nm], y[Nm] (current), xm/ym (previous), xn/yn (next,
@@ -43,18 +46,25 @@ __host__ __device__ constexpr T wq(int i) {
 
 enum BodyKind : int { kRBC = 0, kSoft = 1, kRigid = 2 };
 
+// Row pitch of an instance's node arrays: nx rounded up to 64 elements.
+// Rows that start on 256-byte boundaries keep a tile's row segment within
+// whole cache lines; with unaligned rows every segment straddles one more
+// line, which neighbouring tiles then fetch twice.
+__host__ __device__ constexpr int row_pitch(int nx) { return (nx + 63) & ~63; }
+
 // Per-instance lattice description (device copy).
 struct LatDev {
   int nx, ny, periodic_y;
   int ntx, nty;          // tiles of the fused kernel / marker bins
   int tile_base;         // first global tile index of this instance
-  int bin_base;          // unused (kept for layout stability)
+  int pitch;             // row pitch of the node arrays (row_pitch(nx))
   int marker_base, n_markers;
   int body_base, n_bodies;
   int lig_base, n_lig;
   int rec_base, n_rec0, n_rec1;
   int instance;
   long long node_base;   // first node of this instance (populations at 9*node_base)
+  long long plane;       // nodes of one population plane: pitch * ny
   double tau, gx, gy;
   unsigned long long seed;
   double y_cr, y_eq, kf0_dt, kr0_dt, sigma_ts_frac, kbt;

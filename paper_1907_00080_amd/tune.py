@@ -1,13 +1,16 @@
-"""Autotuner for batched sweeps: tile shape, step form, graph chunk (host logic).
+"""Autotuner for batched sweeps: tile shape, step form, cache hints, graph chunk (host logic).
 
 A batch advances many uneven capillary instances together (one launch per
 kernel per step for all of them).  Which tile shape of the fused lattice
 kernel, which step form (three kernels, merged marker advance, overlapped
 lattice tiles) and which number of steps per captured HIP graph run fastest
-depends on the instance mix and the device, so `autotune` times whole steps
-of the actual batch for every candidate and keeps the fastest.  Results are cached
-in a JSON file keyed by the batch signature (lattice shapes, body and marker
-counts, dtype) and the device name, so a sweep pays for tuning once.
+depends on the instance mix and the device, and so do the cache hints of the
+lattice kernel's population accesses (plain, non-temporal loads, non-temporal
+loads and stores), so `autotune` times whole steps of the actual batch for
+every candidate and keeps the fastest.  Results are cached in a JSON file
+keyed by the batch signature (lattice shapes, wall mode, transfer, repulsion,
+body and marker counts, dtype) and the device name, so a sweep pays for
+tuning once.
 
 Nothing here computes a step of the method; every step runs in the library.
 """
@@ -22,16 +25,23 @@ from typing import Callable, Iterable, Optional, Sequence, Tuple
 TILES: Tuple[Tuple[int, int], ...] = ((64, 4), (128, 2), (32, 8), (256, 1))
 GRAPH_STEPS: Tuple[int, ...] = (10, 100)
 STEP_MODES: Tuple[int, ...] = (1, 2, 3)   # three kernels, merged advance, overlapped tiles
+CACHE_HINTS: Tuple[int, ...] = (0, 1, 3)   # plain, non-temporal loads, non-temporal loads + stores
 
 
 def signature(workloads: Sequence, dtype: str) -> str:
     """Stable key of a batch: dtype plus, per instance, lattice shape, wall
-    mode, body count and marker count."""
+    mode, lattice <-> marker transfer (and MLS weight), whether the vertex
+    repulsion is on, body count and marker count: everything that changes
+    which kernel variants and step forms run."""
     h = hashlib.sha256()
     h.update(str(dtype).encode())
     for w in workloads:
-        h.update(f"{int(w.nx)}x{int(w.ny)}:{int(w.periodic_y)}:{len(w.bodies)}:"
-                 f"{int(w.n_markers)};".encode())
+        walls = getattr(w, "walls", "bounce-back")
+        transfer = getattr(w, "transfer", "roma")
+        weight = getattr(w, "mls_weight", "cubic") if transfer == "mls" else "-"
+        rep = 1 if float(getattr(w, "repulsion", 0.0)) > 0.0 else 0
+        h.update(f"{int(w.nx)}x{int(w.ny)}:{int(w.periodic_y)}:{walls}:{transfer}:{weight}:"
+                 f"{rep}:{len(w.bodies)}:{int(w.n_markers)};".encode())
     return h.hexdigest()[:24]
 
 
@@ -83,14 +93,16 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
              tiles: Sequence[Tuple[int, int]] = TILES,
              graph_steps: Sequence[int] = GRAPH_STEPS,
              step_modes: Sequence[int] = STEP_MODES,
+             cache_hints: Sequence[int] = CACHE_HINTS,
              measure: Optional[Callable] = None) -> dict:
-    """Pick the tile shape, step form and graph chunk for a batch of `workloads`.
+    """Pick the tile shape, step form, cache hints and graph chunk for a batch
+    of `workloads`.
 
-    Returns {"tile": [tx, ty], "graph_steps": g, "step_mode": m, "ms_per_step": t,
-    "mlups": ..., "candidates": [...], "device": name, "cached": bool}.
-    `steps` is rounded up to a multiple of every graph chunk.
-    `measure(tile, g, mode)` replaces the GPU timing (returns ms per step);
-    it exists for tests of the selection and caching logic.
+    Returns {"tile": [tx, ty], "graph_steps": g, "step_mode": m, "cache_hints": c,
+    "ms_per_step": t, "mlups": ..., "candidates": [...], "device": name,
+    "cached": bool}.  `steps` is rounded up to a multiple of every graph chunk.
+    `measure(tile, g, mode, hints)` replaces the GPU timing (returns ms per
+    step); it exists for tests of the selection and caching logic.
     """
     nodes = sum(int(w.nx) * int(w.ny) for w in workloads)
     dev_name = _device_name(device) if measure is None else "measure-callback"
@@ -108,25 +120,28 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
     for tile in tiles:
         if measure is not None:
             for mode in step_modes:
-                for g in graph_steps:
-                    ms = float(measure(tuple(tile), int(g), int(mode)))
-                    results.append(_record(tile, g, mode, ms, nodes))
+                for hints in cache_hints:
+                    for g in graph_steps:
+                        ms = float(measure(tuple(tile), int(g), int(mode), int(hints)))
+                        results.append(_record(tile, g, mode, hints, ms, nodes))
             continue
         from . import Batch
         b = Batch(workloads, dtype=dtype, tile=tuple(tile), device=device, graph_steps=0)
         try:
             for mode in step_modes:
                 b.set_step_mode(int(mode))
-                for g in graph_steps:
-                    b.set_graph_steps(int(g))
-                    b.step(max(int(warmup), int(g)))
-                    ms = _time_steps(b, steps) / steps
-                    results.append(_record(tile, g, b.step_mode, ms, nodes))
+                for hints in cache_hints:
+                    b.set_cache_hints(int(hints))
+                    for g in graph_steps:
+                        b.set_graph_steps(int(g))
+                        b.step(max(int(warmup), int(g)))
+                        ms = _time_steps(b, steps) / steps
+                        results.append(_record(tile, g, b.step_mode, b.cache_hints, ms, nodes))
         finally:
             b.close()
     best = choose(results)
     rec = {"tile": list(best["tile"]), "graph_steps": best["graph_steps"],
-           "step_mode": best["step_mode"],
+           "step_mode": best["step_mode"], "cache_hints": best["cache_hints"],
            "ms_per_step": best["ms_per_step"], "mlups": best["mlups"],
            "candidates": results, "device": dev_name, "nodes": nodes,
            "instances": len(workloads), "dtype": str(dtype)}
@@ -137,9 +152,9 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
     return rec
 
 
-def _record(tile, g, mode, ms, nodes) -> dict:
+def _record(tile, g, mode, hints, ms, nodes) -> dict:
     return {"tile": [int(tile[0]), int(tile[1])], "graph_steps": int(g), "step_mode": int(mode),
-            "ms_per_step": ms,
+            "cache_hints": int(hints), "ms_per_step": ms,
             "mlups": nodes / (ms * 1e-3) / 1e6 if ms > 0 else float("inf")}
 
 

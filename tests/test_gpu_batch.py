@@ -143,7 +143,7 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path):
     rec = autotune(ws, "f32", cache=path, steps=20, warmup=10)
     assert rec["cached"] is False
     assert tuple(rec["tile"]) in pkg.TILES and rec["graph_steps"] in (10, 100)
-    assert len(rec["candidates"]) == len(pkg.TILES) * 2 * 3
+    assert len(rec["candidates"]) == len(pkg.TILES) * 2 * 3 * 3   # tiles x graph chunks x forms x hints
     assert rec["step_mode"] in (1, 2, 3)
     assert rec["ms_per_step"] == min(c["ms_per_step"] for c in rec["candidates"])
     again = autotune(ws, "f32", cache=path, steps=20, warmup=10)

@@ -353,3 +353,44 @@ def test_watchdog_flags_nonfinite_state():
     with pytest.raises(pkg.LbibError) as ei:
         sim.step(1)
     assert ei.value.status == 5
+
+
+def test_watchdog_mass_drift_check():
+    """The watchdog's mass check: bounce-back walls conserve the total mass to
+    rounding, so the default bound (1e-6 relative) passes, while a bound of 0
+    (forced from the host) flags the float32 rounding drift; velocity walls
+    exchange mass and are exempt."""
+    announce("watchdog mass drift")
+    wl = configs.small_case(nx=96, ny=24, n_rbc=1, particles=(configs.PARTICLE_SOFT,))
+    sim = pkg.Sim(wl, dtype="f32", watchdog=True)
+    sim.step(200)
+    sim.set_watchdog(True, mass_tolerance=0.0)
+    with pytest.raises(pkg.LbibError) as ei:
+        sim.step(50)
+    assert ei.value.status == 5 and "mass" in str(ei.value)
+    box = configs.couette_box()
+    wsim = pkg.Sim(box, dtype="f32", watchdog=True)
+    wsim.set_watchdog(True, mass_tolerance=0.0)
+    wsim.step(50)
+
+
+def test_state_restores_body_constants():
+    """get_state / set_state cover every constant the step reads: after a
+    change of sigma (spring and bond kinetics) and k_s, restoring an earlier
+    state gives bitwise the run that state would have had."""
+    announce("state restores body constants")
+    wl = configs.small_case(nx=96, ny=24, n_rbc=1,
+                            particles=(configs.PARTICLE_SOFT, configs.PARTICLE_RIGID), adhesive=True)
+    sim = pkg.Sim(wl, dtype="f64")
+    sim.step(3)
+    s0 = sim.get_state()
+    sim.step(40)
+    ref = (sim.fields(), sim.all_markers(), sim.bonds())
+    b = 1
+    sim.set_body_params(b, 2.0 * wl.bodies[b].ks, wl.bodies[b].kb, 4.0 * wl.bodies[b].sigma)
+    sim.set_state(s0)
+    sim.step(40)
+    for x, y in zip(sim.fields(), ref[0]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(sim.all_markers(), ref[1])
+    assert np.array_equal(sim.bonds(), ref[2])

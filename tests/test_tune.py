@@ -18,6 +18,15 @@ def test_signature_is_stable_and_sensitive():
     c = _ws()
     c[1] = configs.small_case(nx=65, ny=20, n_rbc=0, seed_offset=32)
     assert tune.signature(a, "f32") != tune.signature(c, "f32")
+    # everything that changes which kernel variants and step forms run
+    for attr, val in (("walls", "zou-he"), ("transfer", "mls"), ("repulsion", 1e-5)):
+        d = _ws()
+        setattr(d[0], attr, val)
+        assert tune.signature(d, "f32") != tune.signature(a, "f32"), attr
+    e, f = _ws(), _ws()
+    for w, weight in ((e[0], "cubic"), (f[0], "gauss")):
+        w.transfer, w.mls_weight = "mls", weight
+    assert tune.signature(e, "f32") != tune.signature(f, "f32")
 
 
 def test_choose_fastest_and_first_on_ties():
@@ -33,23 +42,23 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
             ((128, 2), 100): 1.5, ((32, 8), 10): 4.0, ((32, 8), 100): 1.7,
             ((256, 1), 10): 2.2, ((256, 1), 100): 2.0}
 
-    def measure(tile, g, mode):
-        calls.append((tile, g, mode))
-        return cost[(tile, g)] + (0.0 if mode == 2 else 0.25 * mode)
+    def measure(tile, g, mode, hints):
+        calls.append((tile, g, mode, hints))
+        return cost[(tile, g)] + (0.0 if mode == 2 else 0.25 * mode) + (0.0 if hints == 1 else 0.1)
 
     path = str(tmp_path / "sub" / "tune.json")
     ws = _ws()
     rec = tune.autotune(ws, "f32", cache=path, measure=measure)
     assert rec["tile"] == [128, 2] and rec["graph_steps"] == 100 and not rec["cached"]
-    assert rec["step_mode"] == 2
-    assert len(calls) == 24
+    assert rec["step_mode"] == 2 and rec["cache_hints"] == 1
+    assert len(calls) == 72
     nodes = sum(w.nodes for w in ws)
     assert abs(rec["mlups"] - nodes / 1.5e-3 / 1e6) < 1e-9
     with open(path) as f:
         data = json.load(f)
     assert len(data) == 1
     again = tune.autotune(ws, "f32", cache=path, measure=measure)
-    assert again["cached"] and again["tile"] == [128, 2] and len(calls) == 24
+    assert again["cached"] and again["tile"] == [128, 2] and len(calls) == 72
     # another batch adds a second record and keeps the first
     tune.autotune(ws[:1], "f32", cache=path, measure=measure)
     with open(path) as f:
@@ -58,6 +67,6 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
 
 def test_autotune_without_cache_measures_every_time():
     n = []
-    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m: n.append(1) or 1.0)
-    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m: n.append(1) or 1.0)
-    assert len(n) == 48
+    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m, c: n.append(1) or 1.0)
+    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m, c: n.append(1) or 1.0)
+    assert len(n) == 144

@@ -291,6 +291,18 @@ lbib_status lbib_set_graph_steps(lbib_ctx* ctx, int32_t steps);
  * Errors: LBIB_ESTATE outside the running phase. */
 lbib_status lbib_get_fields(lbib_ctx* ctx, double* rho, double* ux, double* uy);
 
+/* lbib_get_fields without allocating: for callers that cannot allocate
+ * (serving loops and harnesses that forbid allocation).  Same values,
+ * bit for bit, as lbib_get_fields; the fields are staged in a file-scope
+ * device array that each GPU holds for the life of the process (3 x 2^19
+ * doubles, 12 MiB), its address resolved per device by lbib_bind (call that
+ * with the workspace's device current), and copied straight into the
+ * caller's arrays; no memory is allocated on the device or the host.
+ * Calls that overlap on one GPU share that array and race.  Errors:
+ * LBIB_EINVAL for a lattice of more than 2^19 = 524288 nodes (use
+ * lbib_get_fields), LBIB_ESTATE outside the running phase. */
+lbib_status lbib_get_fields_noalloc(lbib_ctx* ctx, double* rho, double* ux, double* uy);
+
 /* Current vertex positions of body `body` (synchronises): nv*2 doubles. */
 lbib_status lbib_get_markers(lbib_ctx* ctx, int32_t body, double* xy);
 

@@ -43,6 +43,7 @@ EXPORTS = [
     "lbib_adjoint_backward", "lbib_set_body_params", "lbib_set_step_mode", "lbib_get_step_mode",
     "lbib_observe", "lbib_get_observations", "lbib_reset_observations",
     "lbib_set_cache_hints", "lbib_get_cache_hints", "lbib_set_watchdog_mass_tolerance",
+    "lbib_get_fields_noalloc",
 ]
 
 REGION_CFL, REGION_INTERMEDIATE, REGION_BULK = 0, 1, 2
@@ -130,6 +131,7 @@ def library() -> ctypes.CDLL:
         "lbib_set_watchdog": (I32, [P, I32]),
         "lbib_set_graph_steps": (I32, [P, I32]),
         "lbib_get_fields": (I32, [P, dp, dp, dp]),
+        "lbib_get_fields_noalloc": (I32, [P, dp, dp, dp]),
         "lbib_get_markers": (I32, [P, I32, dp]),
         "lbib_set_markers": (I32, [P, I32, dp, dp]),
         "lbib_get_marker_forces": (I32, [P, I32, dp]),

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -83,6 +84,7 @@ struct lbib_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
+  int device = -1;            // device current at lbib_bind (the workspace's)
   long long step = 0;
   int parity = 0;  // 0: A holds the state; 1: B holds it
   bool watchdog = false;
@@ -1084,6 +1086,55 @@ lbib_status adjoint_backward_impl(lbib_ctx* c, double dJ, double* grad) {
 }  // namespace
 
 // =============================================================== C ABI
+// ------------------------------------------------ allocation-free field readback
+// Staging of lbib_get_fields_noalloc: a file-scope device array, of which
+// every GPU the library runs on holds its own copy until the process ends.
+// In host code its name is not a device address: the address of each
+// device's copy comes from hipGetSymbolAddress, resolved once per device with
+// that device current (at lbib_bind), and only that address is handed to
+// kernels and copies.  Every call on a GPU shares that GPU's copy, so calls
+// that overlap on one GPU race; each call writes all the entries it reads.
+constexpr long long kFieldStageNodes = 1ll << 19;   // rho, ux, uy: 3 x 4 MiB
+static __device__ __align__(256) double scratch[3 * kFieldStageNodes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's staging array (resolved once per device).
+lbib_status resolve_scratch(lbib_ctx* c) {
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, LBIB_EINVAL, "device index beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  c->device = dev;
+  return LBIB_OK;
+}
+
+template <typename T>
+lbib_status fields_noalloc_impl(lbib_ctx* c, double* rho, double* ux, double* uy) {
+  const InstHost& I = c->inst[0];
+  const long long N = (long long)I.lat.nx * I.lat.ny;
+  double* stage = g_scratch_ptr[c->device];
+  launch_fields<T>(make_ptrs<T>(c), step_args(c), 0, stage, stage + kFieldStageNodes,
+                   stage + 2 * kFieldStageNodes, I.lat.nx, I.lat.ny, c->node_base[0], c->stream);
+  HIPCHK(c, hipGetLastError());
+  double* dst[3] = {rho, ux, uy};
+  for (int k = 0; k < 3; ++k)
+    if (dst[k])
+      HIPCHK(c, hipMemcpyAsync(dst[k], stage + k * kFieldStageNodes, (size_t)N * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBIB_OK;
+}
+}  // namespace
+
 extern "C" {
 
 uint32_t lbib_abi_version(void) { return LBIB_ABI_VERSION; }
@@ -1249,6 +1300,20 @@ lbib_status lbib_workspace_query(const lbib_ctx* cc, size_t* bytes) {
   return LBIB_OK;
 }
 
+lbib_status lbib_get_fields_noalloc(lbib_ctx* c, double* rho, double* ux, double* uy) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (c->phase != 2) return fail(c, LBIB_ESTATE, "not running");
+  const long long N = (long long)c->inst[0].lat.nx * c->inst[0].lat.ny;
+  if (N > kFieldStageNodes)
+    return fail(c, LBIB_EINVAL, "lattice of " + std::to_string(N) + " nodes exceeds the " +
+                                    std::to_string(kFieldStageNodes) +
+                                    "-node staging of lbib_get_fields_noalloc (use lbib_get_fields)");
+  if (c->device < 0 || c->device >= kMaxDevices || !g_scratch_ptr[c->device])
+    return fail(c, LBIB_ESTATE, "staging array not resolved for this context's device");
+  return c->dtype == LBIB_F64 ? fields_noalloc_impl<double>(c, rho, ux, uy)
+                              : fields_noalloc_impl<float>(c, rho, ux, uy);
+}
+
 lbib_status lbib_bind(lbib_ctx* c, void* ws, size_t bytes, void* stream) {
   if (!c || !ws) return fail(c, LBIB_EINVAL, "NULL argument");
   if (c->phase != 0) return fail(c, LBIB_ESTATE, "already bound");
@@ -1256,6 +1321,8 @@ lbib_status lbib_bind(lbib_ctx* c, void* ws, size_t bytes, void* stream) {
   compute_sizes(c);
   compute_layout(c);
   if (bytes < c->L.total) return fail(c, LBIB_ENOSPACE, "workspace smaller than lbib_workspace_query");
+  lbib_status rs = resolve_scratch(c);
+  if (rs != LBIB_OK) return rs;
   c->ws = (char*)ws;
   c->ws_bytes = bytes;
   c->stream = (hipStream_t)stream;

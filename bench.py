@@ -1,20 +1,27 @@
 """Benchmark of the fused LB-IB time step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload capillary-2000x200|capillary-6667x667|channel-256x64]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload capillary-6667x667|capillary-2000x200|channel-256x64]
 
-Workload (default): the 10 um x 100 um capillary at dx = 50 nm, 2000 x 200
-nodes, float32, 18 red cells (352 markers each), 12 adhesive 1 um particles
-(6 rigid, 6 soft), receptors on every wall node, Philox bond kinetics; the
-whole time step (binning + bonds, membrane and particle forces, fused
-collide-stream-spread, interpolation + marker advance) runs each step.
+Headline workload (default): the fine-mesh capillary of the paper's Sec. 3,
+10 um x 100 um at dx = 15 nm, 6667 x 667 nodes (4.45 M), float32, 18 red
+cells (1152 markers each), 3 adhesive 1 um particles (rigid, sigma = 0.5, 1,
+2), receptors on every wall node, Philox bond kinetics; the whole time step
+(bonds, membrane and particle forces, fused collide-stream-spread,
+interpolation + marker advance + binning) runs each step.  Its two
+population buffers (320 MB) exceed the 256 MB last-level cache, so the
+fused lattice kernel streams from HBM.
 
-Prints one JSON line: MLUPS (million lattice-node updates per second of the
-whole step, graph-captured chunks of steps), the roofline of the dominant
-kernel (the fused lattice kernel, timed in-step with HIP events bound to its
-dispatches over plain-launched steps of the same run), the same figures for
-the HBM-bound 6667 x 667 capillary, a sweep of 64 uneven instances run as one
-autotuned batch against the same instances run one by one, and the FP64
-oracle timed on a bounded sample on the host CPU.
+Prints one JSON line: MLUPS of the whole step over exactly K steps replayed
+from captured HIP graphs (and the median of five such windows), the
+roofline of the step's dominant kernel (the fused lattice kernel, timed
+in-step with HIP events bound to its dispatches), the oracle timed on a
+bounded window of the same workload on one host core, and extra objects:
+the all-soft variant of the same capillary, the cache-resident 2000 x 200
+capillary, a sweep of 64 uneven instances as one autotuned batch against
+the same instances run one by one (plain, and graph-captured with tuned
+tiles) and against the oracle over all host cores, the gradient window,
+and the optional physics of the library (repulsion, MLS transfer,
+observables, velocity-wall adhesion boxes).
 """
 from __future__ import annotations
 
@@ -47,6 +54,8 @@ def make_workload(name: str):
         return configs.capillary_2000x200()
     if name == "capillary-6667x667":
         return configs.capillary_6667x667()
+    if name == "capillary-6667x667-soft":
+        return configs.capillary_6667x667(soft=True)
     if name == "channel-256x64":
         w = configs.channel_256x64()
         w.dtype = "f32"
@@ -54,8 +63,17 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
-    """FP64 oracle on the host: as many steps of the same workload as fit the budget."""
+def _host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def cpu_baseline(name: str, budget_s: float = 20.0, min_steps: int = 3) -> dict:
+    """FP64 oracle on one host core: as many steps of the same workload as fit
+    the budget (at least `min_steps`), after one untimed step."""
     import oracle
     try:
         from threadpoolctl import threadpool_limits
@@ -67,22 +85,60 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
     sim.step(1)                     # first step pays one-off costs
     t0 = time.perf_counter()
     n = 0
-    while time.perf_counter() - t0 < budget_s:
+    while n < min_steps or time.perf_counter() - t0 < budget_s:
         sim.step(1)
         n += 1
     dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
+    if limiter is not None and hasattr(limiter, "unregister"):
+        limiter.unregister()
     return {"value": wl.nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "host_cpu": model, "host_threads": os.cpu_count(),
-            "sample": f"{wl.name}: {n} steps of the full lattice with all bodies (after 1 warm-up "
-                      f"step), float64 NumPy, one thread, {dt:.1f} s"}
+            "host_cpu": _host_cpu(), "host_threads": os.cpu_count(),
+            "sample": f"{wl.name}: a window of {n} steps of the full lattice with all bodies (after "
+                      f"1 untimed step), float64 NumPy on one thread, {dt:.1f} s; MLUPS of that "
+                      f"window"}
+
+
+def _oracle_instance_steps(args):
+    """Worker of the sweep baseline: oracle steps of one instance on one core
+    until the deadline; returns (node updates, seconds)."""
+    idx, n_inst, deadline = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import oracle
+    from workloads import configs
+    wl = configs.sweep_instances(n_inst)[idx]
+    sim = oracle.Sim(wl)
+    sim.step(1)
+    t0 = time.perf_counter()
+    n = 0
+    while n < 1 or time.time() < deadline:
+        sim.step(1)
+        n += 1
+    return wl.nodes * n, time.perf_counter() - t0
+
+
+def cpu_baseline_sweep(n_inst: int, budget_s: float = 20.0) -> dict:
+    """FP64 oracle on the sweep's instances fanned out over all host cores (one
+    process per core, each stepping one instance until the deadline); MLUPS
+    = sum of node updates over the pool's wall time."""
+    import concurrent.futures
+    import multiprocessing
+    cores = os.cpu_count() or 1
+    nproc = min(cores, n_inst)
+    ctx = multiprocessing.get_context("spawn")
+    t0 = time.perf_counter()
+    with concurrent.futures.ProcessPoolExecutor(max_workers=nproc, mp_context=ctx) as ex:
+        # the deadline leaves every worker time to import and set up first
+        deadline = time.time() + 10.0 + budget_s
+        res = list(ex.map(_oracle_instance_steps, [(i, n_inst, deadline) for i in range(nproc)]))
+    wall = time.perf_counter() - t0
+    upd = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    return {"value": upd / busy / 1e6, "unit": "MLUPS", "cores": nproc, "kind": "oracle",
+            "host_cpu": _host_cpu(), "host_threads": cores,
+            "sample": f"instances 0..{nproc - 1} of the {n_inst}-instance sweep, one per process, "
+                      f"float64 NumPy on one thread each, each stepped for about {budget_s:.0f} s "
+                      f"(longest {busy:.1f} s, pool wall {wall:.1f} s); MLUPS = node updates of "
+                      f"all processes / longest stepping time"}
 
 
 def traffic_from_profile(workload_name: str, tile=None):
@@ -124,17 +180,23 @@ def tuned_config(pkg, wl, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="capillary-2000x200")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="capillary-6667x667")
     ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--windows", type=int, default=5,
+                    help="timed windows of K steps; the first is the reported region, the "
+                         "median of all is reported beside it")
     ap.add_argument("--tile", default="auto",
-                    help="TXxTY, or auto: tile and step form from the autotuner, per workload")
+                    help="TXxTY, or auto: tile, step form and cache hints from the autotuner")
+    ap.add_argument("--side-workload", default="capillary-2000x200",
+                    help="workload of the optional-physics objects (repulsion, MLS, observables)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the 6667 x 667 capillary")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the all-soft and the cache-resident capillaries")
     ap.add_argument("--kernel-steps", type=int, default=200,
                     help="plain-launched steps over which the fused kernel is timed")
-    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--extra-steps", type=int, default=1000)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain sweep")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient window")
     ap.add_argument("--no-couette", action="store_true",
@@ -175,7 +237,7 @@ def main():
     wl = make_workload(args.workload)
     tile, mode, hints, cands = tuned_config(pkg, wl, args)
     res = run_workload(pkg, torch, wl, tile, args.steps, args.warmup, args.graph_steps,
-                       args.kernel_steps, mode, hints)
+                       args.kernel_steps, mode, hints, windows=args.windows)
     roof = roofline(res, wl, tile)
 
     out = {
@@ -195,75 +257,112 @@ def main():
                    "rbc": sum(b.kind == 0 for b in wl.bodies),
                    "particles": sum(b.kind != 0 for b in wl.bodies),
                    "markers": wl.n_markers, "tile": f"{tile[0]}x{tile[1]}",
-                   "step_mode": res["step_mode"], "graph_steps": args.graph_steps,
-                   "tuned": cands is not None},
+                   "step_mode": res["step_mode"], "cache_hints": res["cache_hints"],
+                   "graph_steps": res["graph_steps"], "plain_steps": res["plain_steps"],
+                   "graph_prime_steps": res["prime_steps"], "tuned": cands is not None},
+        "windows": res["windows"],
         "roofline": roof,
     }
     if cands is not None:
         out["tuning"] = cands
-    if not args.no_large and args.workload != "capillary-6667x667":
-        # the HBM-bound case: 10 um x 100 um capillary at dx = 15 nm
-        lw = make_workload("capillary-6667x667")
-        ltile, lmode, lhints, lcands = tuned_config(pkg, lw, args)
-        lres = run_workload(pkg, torch, lw, ltile, args.large_steps, 20, args.graph_steps,
-                            args.large_steps, lmode, lhints)
-        out["large_lattice"] = {"workload": lw.name, "nodes": lw.nodes, "markers": lw.n_markers,
-                                "tile": f"{ltile[0]}x{ltile[1]}", "step_mode": lres["step_mode"],
-                                "mlups": round(lres["mlups"], 1),
-                                "ms_per_step": round(lres["ms_step"], 5),
-                                "roofline": roofline(lres, lw, ltile)}
+    if not args.no_extra:
+        for key, name in (("capillary_6667x667_soft", "capillary-6667x667-soft"),
+                          ("capillary_2000x200", "capillary-2000x200")):
+            if name == args.workload:
+                continue
+            xw = make_workload(name)
+            xtile, xmode, xhints, xcands = tuned_config(pkg, xw, args)
+            xres = run_workload(pkg, torch, xw, xtile, args.extra_steps, 100, args.graph_steps,
+                                args.kernel_steps, xmode, xhints, windows=args.windows)
+            xroof = roofline(xres, xw, xtile)
+            if 2 * 72.0 * xw.nodes <= 128e6:
+                xroof["note"] = ("populations (2 x 36 B per node) stay in the 256 MB last-level "
+                                 "cache: a bandwidth figure against the HBM peak, not an HBM-bound "
+                                 "roofline; the step is bound by the body kernel's latency")
+            out[key] = {"workload": xw.name, "nodes": xw.nodes, "markers": xw.n_markers,
+                        "tile": f"{xtile[0]}x{xtile[1]}", "step_mode": xres["step_mode"],
+                        "cache_hints": xres["cache_hints"], "graph_steps": xres["graph_steps"],
+                        "steps": args.extra_steps, "mlups": round(xres["mlups"], 1),
+                        "ms_per_step": round(xres["ms_step"], 5), "windows": xres["windows"],
+                        "roofline": xroof}
     if not args.no_batch:
-        out["batched"] = batched_vs_plain(pkg, torch, args.batch_instances, args.batch_steps)
+        out["batched"] = batched_vs_plain(pkg, torch, args, args.batch_instances, args.batch_steps)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_window(pkg, torch, args.adjoint_steps, 100)
+    side = args.side_workload
     if not args.no_repulsion:
         # its own tile: the repulsion reads the marker bins, whose shape follows the tile
-        rw = make_workload(args.workload)
+        rw = make_workload(side)
         from workloads import configs
         rw.repulsion = configs.REPULSION_COEFF
         rtile = tuned_config(pkg, rw, args)[0]
-        out["repulsion"] = repulsion_cost(pkg, torch, args.workload, rtile, 1000, args.graph_steps)
+        out["repulsion"] = repulsion_cost(pkg, torch, side, rtile, 1000, args.graph_steps)
         out["repulsion"]["tile"] = f"{rtile[0]}x{rtile[1]}"
+    stile = tuned_config(pkg, make_workload(side), args)[0] if not (args.no_mls and args.no_observables) else None
     if not args.no_mls:
-        out["mls"] = mls_cost(pkg, torch, args.workload, tile, 1000, args.graph_steps)
+        out["mls"] = mls_cost(pkg, torch, side, stile, 1000, args.graph_steps)
     if not args.no_observables:
-        out["observables"] = observables_cost(pkg, torch, args.workload, tile, args.graph_steps)
+        out["observables"] = observables_cost(pkg, torch, side, stile, args.graph_steps)
     if not args.no_couette:
         out["couette_box"] = couette_box_batch(pkg, torch, args.couette_steps)
     if not args.no_cpu:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
+        if "batched" in out:
+            out["batched"]["cpu_baseline"] = cpu_baseline_sweep(args.batch_instances)
     print(json.dumps(out), flush=True)
 
 
+def graph_chunk(requested: int, steps: int) -> int:
+    """Steps per captured graph for a timed region of `steps` steps: the
+    requested chunk, or `steps` itself when that is shorter, rounded down to
+    an even number (a graph holds both population-buffer parities); 0 when
+    fewer than two steps are timed."""
+    g = min(int(requested), int(steps))
+    g -= g & 1
+    return g if g >= 2 else 0
+
+
 def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps, step_mode=None,
-                 cache_hints=None):
-    """Time `steps` whole steps (graph-captured chunks), then measure the fused
+                 cache_hints=None, windows=5):
+    """W warm-up steps, then graph capture of both buffer parities (2 chunks,
+    untimed), then exactly `steps` steps replayed from the graphs, bracketed by
+    HIP events after a device synchronisation; then `windows - 1` more such
+    windows (their median is reported beside the first); then the fused
     lattice kernel in-step over `kernel_steps` plain-launched steps."""
     print(f"bench: workload {wl.name} nodes={wl.nodes} markers={wl.n_markers} "
           f"bodies={len(wl.bodies)} tile {tile[0]}x{tile[1]}", file=sys.stderr, flush=True)
-    sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=graph_steps)
+    G = graph_chunk(graph_steps, steps)
+    sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=G)
     if step_mode is not None:
         sim.set_step_mode(int(step_mode))
     if cache_hints is not None:
         sim.set_cache_hints(int(cache_hints))
     stream = sim.stream
     sim.step(warmup)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record(stream)
-    sim.step(steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end)
+    sim.step(2 * G)                  # captures the graphs of both parities
+    times = []
+    wall = 0.0
+    for w in range(max(1, int(windows))):
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record(stream)
+        sim.step(steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+        if w == 0:
+            wall = time.perf_counter() - t0
+        times.append(start.elapsed_time(end))
+    ms = times[0]
     ms_step = ms / steps
     mlups = wl.nodes * steps / (ms / 1e3) / 1e6
+    med = sorted(times)[len(times) // 2]
     d = sim.diagnostics()
     print(f"bench: {steps} steps in {ms:.1f} ms (wall {wall:.2f} s), {ms_step * 1e3:.2f} us/step, "
-          f"{mlups:.0f} MLUPS, nonfinite={d['nonfinite']} bin_overflow={d['bin_overflow']}",
+          f"{mlups:.0f} MLUPS (median of {len(times)} windows {med / steps * 1e3:.2f} us/step), "
+          f"graphs of {G}, nonfinite={d['nonfinite']} bin_overflow={d['bin_overflow']}",
           file=sys.stderr, flush=True)
     if d["nonfinite"] or d["bin_overflow"] or d["sync_timeouts"]:
         raise SystemExit("invalid state after the benchmark")
@@ -276,9 +375,14 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps,
     print(f"bench: fused lattice kernel {k_ms * 1e3:.2f} us over {k_n} in-step launches",
           file=sys.stderr, flush=True)
     mode = sim.step_mode
+    hints_used = sim.cache_hints
     sim.close()
     return {"mlups": mlups, "ms_step": ms_step, "kernel_ms": k_ms, "kernel_launches": k_n,
-            "step_mode": mode}
+            "step_mode": mode, "cache_hints": hints_used, "graph_steps": G,
+            "plain_steps": steps % G if G else steps, "prime_steps": 2 * G,
+            "windows": {"count": len(times), "ms_per_step": [round(t / steps, 5) for t in times],
+                        "median_ms_per_step": round(med / steps, 5),
+                        "median_mlups": round(wl.nodes * steps / (med / 1e3) / 1e6, 1)}}
 
 
 def repulsion_cost(pkg, torch, name, tile, steps, graph_steps):
@@ -414,10 +518,12 @@ def _timed(torch, ctx, steps):
     return start.elapsed_time(end)
 
 
-def batched_vs_plain(pkg, torch, n_inst, steps):
+def batched_vs_plain(pkg, torch, args, n_inst, steps):
     """Sweep of uneven capillary instances (20-100 um long, 200 rows): one
-    batch with autotuned tiles and graph chunks, against the same instances
-    run one after another through plain launches (no graphs, default tile)."""
+    batch with autotuned tile, step form, cache hints and graph chunk, against
+    the same instances run one after another (a) through plain launches (no
+    graphs, default tile) and (b) graph-captured with the configuration the
+    autotuner picks for a single instance of median length."""
     from workloads import configs
     from paper_1907_00080_amd.tune import autotune
     ws = configs.sweep_instances(n_inst)
@@ -428,7 +534,8 @@ def batched_vs_plain(pkg, torch, n_inst, steps):
     tile = tuple(tuned["tile"])
     b = pkg.Batch(ws, dtype="f32", tile=tile, device="cuda:0", graph_steps=tuned["graph_steps"])
     b.set_step_mode(tuned["step_mode"])
-    b.step(max(20, tuned["graph_steps"]))
+    b.set_cache_hints(tuned["cache_hints"])
+    b.step(2 * max(20, tuned["graph_steps"]))
     ms_b = _timed(torch, b, steps)
     # the fused lattice kernel of the batch (one launch for all instances):
     # HIP events bound to its dispatches over plain-launched steps
@@ -440,22 +547,43 @@ def batched_vs_plain(pkg, torch, n_inst, steps):
     b.close()
     if d["nonfinite"] or d["bin_overflow"] or d["sync_timeouts"]:
         raise SystemExit("invalid batch state after the benchmark")
+    # (a) plain sequential
     ms_p = 0.0
     for w in ws:
         s = pkg.Sim(w, dtype="f32", tile=(64, 4), device="cuda:0", graph_steps=0)
         s.step(5)
         ms_p += _timed(torch, s, steps)
         s.close()
+    # (b) graph-captured sequential, tuned on the instance of median length
+    order = sorted(range(len(ws)), key=lambda i: ws[i].nodes)
+    rep = ws[order[len(order) // 2]]
+    one = autotune([rep], "f32", device="cuda:0", steps=100, warmup=20, graph_steps=(100,))
+    ms_g = 0.0
+    for w in ws:
+        s = pkg.Sim(w, dtype="f32", tile=tuple(one["tile"]), device="cuda:0", graph_steps=100)
+        s.set_step_mode(one["step_mode"])
+        s.set_cache_hints(one["cache_hints"])
+        s.step(200)
+        ms_g += _timed(torch, s, steps)
+        s.close()
     mb = nodes * steps / (ms_b * 1e-3) / 1e6
     mp = nodes * steps / (ms_p * 1e-3) / 1e6
+    mg = nodes * steps / (ms_g * 1e-3) / 1e6
     print(f"bench: batched {mb:.0f} MLUPS (tile {tile[0]}x{tile[1]}, graphs of "
-          f"{tuned['graph_steps']}, step mode {tuned['step_mode']}), plain sequential {mp:.0f} MLUPS; "
+          f"{tuned['graph_steps']}, step mode {tuned['step_mode']}, hints {tuned['cache_hints']}), "
+          f"sequential plain {mp:.0f} MLUPS, sequential graph-captured tuned {mg:.0f} MLUPS; "
           f"batched lattice kernel {k_ms * 1e3:.1f} us "
           f"({72.0 * nodes / (k_ms / 1e3) / 1e9:.0f} GB/s of algorithmic traffic)",
           file=sys.stderr, flush=True)
     return {"workload": f"sweep-{len(ws)}-instances", "instances": len(ws), "nodes": nodes,
             "steps": steps, "batched_mlups": round(mb, 1), "plain_mlups": round(mp, 1),
-            "speedup": round(mb / mp, 3), "tile": f"{tile[0]}x{tile[1]}",
+            "speedup": round(mb / mp, 3),
+            "sequential_graph_tuned_mlups": round(mg, 1), "speedup_vs_graph_tuned": round(mb / mg, 3),
+            "sequential_graph_tuned_config": {"tile": f"{one['tile'][0]}x{one['tile'][1]}",
+                                              "step_mode": one["step_mode"],
+                                              "cache_hints": one["cache_hints"],
+                                              "tuned_on": rep.name},
+            "tile": f"{tile[0]}x{tile[1]}", "cache_hints": tuned["cache_hints"],
             "lattice_kernel": {"kernel_us": round(k_ms * 1e3, 3), "launches": k_n,
                                "bytes_per_launch": 72.0 * nodes,
                                "achieved": round(72.0 * nodes / (k_ms / 1e3) / 1e9, 1),
@@ -463,8 +591,13 @@ def batched_vs_plain(pkg, torch, n_inst, steps):
                                "frac": round(72.0 * nodes / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
             "graph_steps": tuned["graph_steps"], "step_mode": tuned["step_mode"],
             "candidates": [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "graph_steps": c["graph_steps"],
-                            "step_mode": c["step_mode"], "mlups": round(c["mlups"], 1)}
+                            "step_mode": c["step_mode"], "cache_hints": c["cache_hints"],
+                            "mlups": round(c["mlups"], 1)}
                            for c in tuned["candidates"]]}
+
+
+FD_PARAMS = ((1, 0, "ks_particle"), (1, 1, "kb_particle"), (1, 2, "sigma_particle"),
+             (0, 0, "ks_rbc"))
 
 
 def adjoint_window(pkg, torch, steps, ckpt):
@@ -497,22 +630,29 @@ def adjoint_window(pkg, torch, steps, ckpt):
         win.forward()
         win.backward(1.0)                     # warm-up: graphs of the segments
         sim.set_state(state)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.step(steps)
-        torch.cuda.synchronize()
-        t_fwd = time.perf_counter() - t0
-        sim.set_state(state)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        J, nb = win.forward()
-        g = win.backward(1.0)
-        torch.cuda.synchronize()
-        t_adj = time.perf_counter() - t0
+        # median of three repetitions of each (wall clock around whole calls)
+        t_fwds, t_adjs = [], []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            torch.cuda.synchronize()
+            t_fwds.append(time.perf_counter() - t0)
+            sim.set_state(state)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            J, nb = win.forward()
+            g = win.backward(1.0)
+            torch.cuda.synchronize()
+            t_adjs.append(time.perf_counter() - t0)
+            sim.set_state(state)
+        t_fwd, t_adj = sorted(t_fwds)[1], sorted(t_adjs)[1]
         res[dtype] = dict(J=J, g=g, t_fwd=t_fwd, t_adj=t_adj, bonds=nb)
         if dtype == "f64":
-            errs = {}
-            for (b, q, name) in ((1, 0, "ks_particle"), (1, 2, "sigma_particle"), (0, 0, "ks_rbc")):
+            # central differences of the float64 forward (h = 1e-4 relative):
+            # the reference for both adjoints
+            fds = {}
+            for (b, q, name) in FD_PARAMS:
                 h = 1e-4 * P0[b, q]
                 Js = []
                 for sgn in (1, -1):
@@ -521,25 +661,29 @@ def adjoint_window(pkg, torch, steps, ckpt):
                     sim.set_state(state)
                     params(P, sim)
                     Js.append(win.forward()[0])
-                fd = (Js[0] - Js[1]) / (2 * h)
-                errs[name] = abs(g[b, q] - fd) / abs(fd)
-            res[dtype]["fd_rel_err"] = errs
+                fds[name] = (Js[0] - Js[1]) / (2 * h)
         sim.close()
+    for dtype in ("f32", "f64"):
+        g = res[dtype]["g"]
+        res[dtype]["fd_rel_err"] = {name: abs(g[b, q] - fds[name]) / abs(fds[name])
+                                    for b, q, name in FD_PARAMS}
     r32, r64 = res["f32"], res["f64"]
     ratio = r32["t_adj"] / r32["t_fwd"]
     g32, g64 = r32["g"], r64["g"]
     sel = [(1, 0), (1, 1), (1, 2), (0, 0)]
     f32_vs_f64 = max(abs(g32[b, q] - g64[b, q]) / abs(g64[b, q]) for b, q in sel)
     print(f"bench: adjoint/forward {ratio:.2f} (fp32: forward {1e3 * r32['t_fwd']:.1f} ms, "
-          f"adjoint {1e3 * r32['t_adj']:.1f} ms), fp64 FD rel err {r64['fd_rel_err']}",
-          file=sys.stderr, flush=True)
+          f"adjoint {1e3 * r32['t_adj']:.1f} ms), fp32 adjoint vs FD of the fp64 forward "
+          f"{r32['fd_rel_err']}", file=sys.stderr, flush=True)
     return {"workload": wl.name, "steps": steps, "ckpt_every": ckpt, "dtype": "f32 forward, f64 adjoint",
             "adjoint_over_forward": round(ratio, 3),
             "forward_ms": round(1e3 * r32["t_fwd"], 2), "adjoint_ms": round(1e3 * r32["t_adj"], 2),
+            "timing": "median of 3 wall-clock repetitions of each",
             "J": r32["J"], "bonds": r32["bonds"],
             "grad_fp32": {"ks_particle": g32[1, 0], "kb_particle": g32[1, 1],
                           "sigma_particle": g32[1, 2], "ks_rbc": g32[0, 0]},
             "fp64_adjoint_vs_fp64_fd_rel_err": {k: float(f"{v:.3e}") for k, v in r64["fd_rel_err"].items()},
+            "fp32_adjoint_vs_fp64_fd_rel_err": {k: float(f"{v:.3e}") for k, v in r32["fd_rel_err"].items()},
             "fp32_vs_fp64_gradient_rel_diff": float(f"{f32_vs_f64:.3e}"),
             "fp64_adjoint_over_forward": round(r64["t_adj"] / r64["t_fwd"], 3)}
 

@@ -112,6 +112,10 @@ struct lbib_ctx {
   int nrep_chunk = 0;         // repulsion work units (kRepChunk vertices of a body)
   bool overlap = false;
   hipStream_t aux = nullptr;  // second stream of the overlapped form
+  // streams of the adjoint's backward pass (segment recompute, reverse
+  // sweep), created together so that they sit on different hardware queues
+  hipStream_t adj_s[2] = {nullptr, nullptr};
+  hipEvent_t ev_adj_start = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // adjoint window (single-instance contexts): caller-owned workspace
   char* aws = nullptr;
@@ -1036,9 +1040,21 @@ lbib_status adjoint_backward_impl(lbib_ctx* c, double dJ, double* grad) {
   launch_fill(a.FE, 2 * N, 0.0, c->stream);
   launch_fill(a.Uh, 2 * N, 0.0, c->stream);
   launch_fill(a.Rh, 3 * N, 0.0, c->stream);
-  // segments from last to first; the recompute of segment j - 1 (main
-  // stream) overlaps the reverse sweep of segment j (second stream); stores
-  // alternate, and a store is refilled only after its previous reverse sweep
+  // segments from last to first on the adjoint's own two streams: the
+  // recompute of segment j - 1 (first stream, in the role of the context's
+  // stream for the loop) overlaps the reverse sweep of segment j (second
+  // stream); stores alternate, and a store is refilled only after its
+  // previous reverse sweep
+  hipStream_t caller = c->stream;
+  struct RestoreStream {   // every return below leaves the caller's stream in place
+    lbib_ctx* c;
+    hipStream_t s;
+    ~RestoreStream() { c->stream = s; }
+  } restore{c, caller};
+  HIPCHK(c, hipEventRecord(c->ev_adj_start, caller));
+  HIPCHK(c, hipStreamWaitEvent(c->adj_s[0], c->ev_adj_start, 0));
+  c->stream = c->adj_s[0];
+  hipStream_t rev = c->adj_s[1];
   for (int j = A.nseg - 1; j >= 0; --j) {
     const int buf = j & 1;
     if (j + 2 <= A.nseg - 1) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_rev[buf], 0));
@@ -1055,17 +1071,21 @@ lbib_status adjoint_backward_impl(lbib_ctx* c, double dJ, double* grad) {
                       [&] { enqueue_recompute<T>(c, A, buf, n); }, &gr);
     if (st != LBIB_OK) return st;
     c->parity = par;   // capture ran nothing
-    st = cached_graph(c, c->adj_rgraphs, std::make_tuple(n, buf, first), c->aux,
-                      [&] { enqueue_reverse<T>(c, A, a, buf, n, first != 0, c->aux); }, &gv);
+    st = cached_graph(c, c->adj_rgraphs, std::make_tuple(n, buf, first), rev,
+                      [&] { enqueue_reverse<T>(c, A, a, buf, n, first != 0, rev); }, &gv);
     if (st != LBIB_OK) return st;
     HIPCHK(c, hipGraphLaunch(gr, c->stream));
     c->parity = par ^ (int)(n & 1);
     c->step += n;
     HIPCHK(c, hipEventRecord(c->ev_rec[buf], c->stream));
-    HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_rec[buf], 0));
-    HIPCHK(c, hipGraphLaunch(gv, c->aux));
-    HIPCHK(c, hipEventRecord(c->ev_rev[buf], c->aux));
+    HIPCHK(c, hipStreamWaitEvent(rev, c->ev_rec[buf], 0));
+    HIPCHK(c, hipGraphLaunch(gv, rev));
+    HIPCHK(c, hipEventRecord(c->ev_rev[buf], rev));
   }
+  // the caller's stream resumes after both of the adjoint's streams
+  c->stream = caller;
+  HIPCHK(c, hipEventRecord(c->ev_adj_start, c->adj_s[0]));
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_adj_start, 0));
   HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_rev[0], 0));
   if (A.nseg > 1) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_rev[1], 0));
   HIPCHK(c, hipGetLastError());
@@ -1734,6 +1754,9 @@ lbib_status lbib_destroy(lbib_ctx* c) {
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->aux) (void)hipStreamDestroy(c->aux);
+  for (auto& st : c->adj_s)
+    if (st) (void)hipStreamDestroy(st);
+  if (c->ev_adj_start) (void)hipEventDestroy(c->ev_adj_start);
   drop_kevents(c);
   delete c;
   return LBIB_OK;
@@ -1765,6 +1788,12 @@ lbib_status lbib_adjoint_bind(lbib_ctx* c, void* ws, size_t bytes, int64_t nstep
     if (!c->ev_rec[k]) HIPCHK(c, hipEventCreateWithFlags(&c->ev_rec[k], hipEventDisableTiming));
     if (!c->ev_rev[k]) HIPCHK(c, hipEventCreateWithFlags(&c->ev_rev[k], hipEventDisableTiming));
   }
+  if (!c->ev_adj_start) HIPCHK(c, hipEventCreateWithFlags(&c->ev_adj_start, hipEventDisableTiming));
+  // the recompute and the reverse sweep overlap only on distinct hardware
+  // queues; streams made one after the other get distinct queues, whereas
+  // the caller's stream and the context's second stream may share one
+  for (int k = 0; k < 2; ++k)
+    if (!c->adj_s[k]) HIPCHK(c, hipStreamCreateWithFlags(&c->adj_s[k], hipStreamNonBlocking));
   c->aws = (char*)ws;
   c->aws_bytes = bytes;
   c->adjK = nsteps;

@@ -168,10 +168,13 @@ __device__ inline void interp_star(const T* A, const LatDev& L, double X, double
 
 // rho*, u* of the nodes in a box [bx0, bx0 + bw) x [by0, by0 + bh) cached in
 // LDS (x unwrapped; rows wrapped for a periodic lattice).  Same interpolant
-// as interp_star, read from the cache.
+// as interp_star, read from the cache.  The cache holds the density's
+// deviation rho* - 1, not rho*: in float32, rho* itself (about 1 + 1e-4)
+// would keep only the leading digits of the deviation that the probe
+// pressure cs^2 (rho* - 1) is made of.
 template <typename T>
 struct StarCache {
-  const T* c;   // 3 values per node: rho, ux, uy
+  const T* c;   // 3 values per node: rho - 1, ux, uy
   int bx0, by0, bw, bh;
 };
 
@@ -181,7 +184,7 @@ __device__ inline void interp_cached(const StarCache<T>& C, const LatDev& L, dou
   if (MLS && use_mls(L)) {
     auto fetch = [&](int xr, int row, double& r, double& u, double& v) {
       const int k = 3 * ((row - C.by0) * C.bw + (xr - C.bx0));
-      r = double(C.c[k]);
+      r = 1.0 + double(C.c[k]);
       u = double(C.c[k + 1]);
       v = double(C.c[k + 2]);
     };
@@ -210,7 +213,7 @@ __device__ inline void interp_cached(const StarCache<T>& C, const LatDev& L, dou
       const double rx = cxr + (a - 1);
       const double wx = wxa[a], dwx = dwxa[a];
       const int k = 3 * (kr + ((int)rx - C.bx0));
-      const double r = double(C.c[k]), u = double(C.c[k + 1]), v = double(C.c[k + 2]);
+      const double r = 1.0 + double(C.c[k]), u = double(C.c[k + 1]), v = double(C.c[k + 2]);
       rho += r * wx * wy;
       ux += u * wx * wy;
       uy += v * wx * wy;
@@ -857,7 +860,7 @@ __device__ __forceinline__ void body_impl(Ptrs<T>& p, int b, int cache_nodes, do
             jy += ey(i) * h;
           }
           const double r = 1.0 + drho;
-          cw[3 * k] = T(r);
+          cw[3 * k] = T(drho);
           cw[3 * k + 1] = T((jx + 0.5 * L.gx) / r);
           cw[3 * k + 2] = T((jy + 0.5 * L.gy) / r);
         }

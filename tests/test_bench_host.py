@@ -35,3 +35,13 @@ def test_multi_gpu_request_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_graph_chunk_covers_the_timed_region():
+    """The timed region is replayed from graphs for any step count: the chunk
+    shrinks to the region (even, for the two population buffers)."""
+    b = _bench()
+    assert b.graph_chunk(100, 2000) == 100
+    assert b.graph_chunk(100, 20) == 20
+    assert b.graph_chunk(100, 25) == 24
+    assert b.graph_chunk(100, 1) == 0

@@ -121,10 +121,9 @@ def test_adjoint_window_2000_matches_oracle_fd():
     J(theta) is strongly non-linear over this window and only C1 (markers
     cross stencil nodes, the kernel's second derivative jumps), so the oracle
     differences reach their plateau only at steps of 1e-4 relative and below;
-    they use 1e-4 and 5e-5.  The float64 adjoint matches them
-    to rel <= 1e-3.  The float32 forward follows a trajectory that differs
-    from the float64 one by rounding, which this window amplifies: its
-    gradient stays within 5 % of the float64 one (about 1 % measured)."""
+    they use 1e-4 and 5e-5.  Both the float64 and the float32 forward give
+    gradients within rel 1e-3 of them for every parameter the window depends
+    on: k_s, k_b and sigma of the particle and k_s of the red cell."""
     wl = configs.adjoint_channel()
     W, k = 2000, 100
     grads = {}
@@ -141,8 +140,8 @@ def test_adjoint_window_2000_matches_oracle_fd():
     Jo = oracle_J(wl, P0, W)
     announce(f"window 2000: J fp64 {J64:.12f} fp32 {J32:.12f} oracle {Jo:.12f}")
     assert abs(J64 - Jo) < 1e-9
-    assert abs(J32 - Jo) < 1e-4
-    for b, q, steps in ((1, 2, (1e-4, 5e-5)), (1, 0, (1e-4,)), (0, 0, (1e-4,))):
+    assert abs(J32 - Jo) < 2e-5
+    for b, q, steps in ((1, 2, (1e-4, 5e-5)), (1, 1, (1e-4,)), (1, 0, (1e-4,)), (0, 0, (1e-4,))):
         rows = []
         for rel in steps:
             h = rel * P0[b, q]
@@ -155,7 +154,7 @@ def test_adjoint_window_2000_matches_oracle_fd():
                  f"oracle fd {rows}")
         assert abs(rows[0] - rows[-1]) <= 1e-3 * abs(fd)
         assert abs(g64[b, q] - fd) <= 1e-3 * abs(fd), (b, q, g64[b, q], fd)
-        assert abs(g32[b, q] - g64[b, q]) <= 5e-2 * abs(g64[b, q]), (b, q, g32[b, q], g64[b, q])
+        assert abs(g32[b, q] - fd) <= 1e-3 * abs(fd), (b, q, g32[b, q], fd)
 
 
 def test_window_objective_autograd():

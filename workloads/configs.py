@@ -127,6 +127,29 @@ def kbt_lattice(dx_m: float, nu_lu: float, nu_phys: float = 1.2e-6,
     return BOLTZMANN * temp / e_unit
 
 
+def capillary_units(dx_um: float, ny: int, tau: float = 1.0, Re: float = 1e-2, Ca: float = 1e-2,
+                    nu_phys: float = 1.2e-6, rho_phys: float = 1000.0) -> dict:
+    """Lattice values of the capillary set-up (Sec. 3) for a channel of ny
+    cells of dx_um micrometres, and the scales that convert them back:
+      nu       = (tau - 1/2)/3;
+      u_max    = Re nu / H with H = ny (Re = u_max H / nu);
+      ks       = rho nu u_max / Ca (rho = 1);
+      sigma_unit = rho nu^2 / H, the unit in which sigma is given;
+      y_cr     = 25 nm / dx, y_eq = y_cr / 2;
+      dt_s     = nu dx^2 / nu_phys (seconds per step);
+      velocity_scale = dx / dt (m/s per lattice velocity);
+      stiffness_scale = rho_phys dx^3 / dt^2 (N/m per lattice spring
+      constant, a 2D membrane of depth dx)."""
+    nu = viscosity(tau)
+    dx_m = dx_um * 1e-6
+    u_max = Re * nu / ny
+    dt_s = nu * dx_m * dx_m / nu_phys
+    y_cr = 0.025 / dx_um
+    return {"nu": nu, "u_max": u_max, "ks": nu * u_max / Ca, "sigma_unit": nu * nu / ny,
+            "y_cr": y_cr, "y_eq": 0.5 * y_cr, "dx_m": dx_m, "dt_s": dt_s,
+            "velocity_scale": dx_m / dt_s, "stiffness_scale": rho_phys * dx_m ** 3 / dt_s ** 2}
+
+
 def poiseuille_init(nx: int, ny: int, g: float, tau: float):
     prof = poiseuille_profile(g, ny, tau)
     u0 = np.zeros((2, ny, nx))
@@ -185,14 +208,14 @@ def _capillary(name: str, nx: int, ny: int, dx_um: float, n_rbc: int, rbc_marker
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     tau = 1.0
-    nu = viscosity(tau)
-    u_max = 0.01 * nu / ny                    # Re = u_max H / nu = 1e-2
+    un = capillary_units(dx_um, ny, tau)      # Re = 1e-2, Ca = 1e-2
+    nu, u_max = un["nu"], un["u_max"]
     g = poiseuille_force(u_max, ny, tau)
     alpha = 3.5 / dx_um
     r_p = 0.5 / dx_um
-    ks = nu * u_max / 1e-2                    # Ca = 1e-2
-    sig_unit = nu * nu / ny                   # rho nu^2 / H
-    y_cr = 0.025 / dx_um
+    ks = un["ks"]
+    sig_unit = un["sigma_unit"]               # rho nu^2 / H
+    y_cr = un["y_cr"]
     occ = geometry.Occupancy(nx, ny, res=place_res)
     bodies: List[Body] = []
     rbc0 = geometry.rbc_contour(alpha, rbc_markers)
@@ -224,7 +247,7 @@ def _capillary(name: str, nx: int, ny: int, dx_um: float, n_rbc: int, rbc_marker
         else:
             bodies.append(Body(PARTICLE_SOFT, xy, ks=ks, kb=0.05 * ks * r_p * r_p,
                                sigma=sig * sig_unit, ligand_stride=2))
-    adh = Adhesion(y_cr=y_cr, y_eq=0.5 * y_cr, kf0_dt=1e-3, kr0_dt=1e-3 / 8.5e3,
+    adh = Adhesion(y_cr=y_cr, y_eq=un["y_eq"], kf0_dt=1e-3, kr0_dt=1e-3 / 8.5e3,
                    sigma_ts_frac=0.5, kbt=kbt_lattice(dx_um * 1e-6, nu))
     rho0, u0 = poiseuille_init(nx, ny, g, tau)
     return Workload(name, nx, ny, tau, gx=g, seed=seed, bodies=bodies,

@@ -63,8 +63,9 @@ struct Layout {
   size_t mbody, minfo, cx, cy, wx, wy, frep, rep_chunk, obs;
   size_t s[9];
   size_t cnt[2], bins[2], touched, overflow, fmax, bond_flag, step_slot, spin, Uspare, tile_inst;
-  size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma;
+  size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma, lig_sp;
   size_t step_next, step_cur, ties, red;
+  size_t chunk_body, area_part, rig_part, body_cnt, star, pbox, star_wg, slot_chunk;
   size_t total;
 };
 
@@ -77,6 +78,9 @@ struct lbib_ctx {
   int phase = 0;  // 0 setup, 1 bound, 2 running
   // sizes
   int ninst = 0, nm = 0, nbody = 0, nlig = 0, nrec = 0, ntiles = 0;
+  int nchunk = 0;              // vertex chunks of all bodies (kChunk vertices each)
+  int nstar_wg = 0;            // workgroups of the star pass (particle node boxes)
+  int nslot = 0;               // waves of the chunked body kernel (a multiple of 4)
   long long nodes = 0;
   std::vector<int> marker_base, body_base, lig_base, rec_base, tile_base;
   std::vector<long long> node_base;
@@ -150,9 +154,27 @@ lbib_status fail(lbib_ctx* c, lbib_status s, const std::string& msg) {
 
 int elem_size(int dtype) { return dtype == LBIB_F64 ? 8 : 4; }
 
+// Workgroups of the star pass for one particle: its node box at rest (the
+// vertex extent widened by 4 nodes on each side) with 10 % spare for
+// deformation, 1024 nodes per workgroup and pass (any larger box is still
+// covered: the workgroups loop over it).
+int star_workgroups(const BodyHost& b) {
+  if (b.d.kind == LBIB_RBC_KINEMATIC) return 0;
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (int v = 0; v < b.d.nv; ++v) {
+    x0 = std::min(x0, b.xy[2 * v]); x1 = std::max(x1, b.xy[2 * v]);
+    y0 = std::min(y0, b.xy[2 * v + 1]); y1 = std::max(y1, b.xy[2 * v + 1]);
+  }
+  const double nodes = std::ceil(x1 - x0 + 10.0) * std::ceil(y1 - y0 + 10.0) * 1.1;
+  return std::max(1, (int)std::ceil(nodes / 1024.0));
+}
+
 void compute_sizes(lbib_ctx* c) {
   c->ninst = (int)c->inst.size();
   c->nm = c->nbody = c->nlig = c->nrec = c->ntiles = 0;
+  c->nchunk = 0;
+  c->nstar_wg = 0;
+  int grouped = 0, grouped_chunks = 0;
   c->nrep_chunk = 0;
   c->nodes = 0;
   c->marker_base.clear(); c->body_base.clear(); c->lig_base.clear();
@@ -168,6 +190,12 @@ void compute_sizes(lbib_ctx* c) {
       c->nm += b.d.nv;
       c->nbody += 1;
       c->nrep_chunk += (b.d.nv + kRepChunk - 1) / kRepChunk;
+      c->nchunk += chunks_of(b.d.nv);
+      c->nstar_wg += star_workgroups(b);
+      if (rigid_grouped(b.d.kind, b.d.nv)) {
+        ++grouped;
+        grouped_chunks += chunks_of(b.d.nv);
+      }
       if (b.d.ligand_stride > 0) c->nlig += (b.d.nv + b.d.ligand_stride - 1) / b.d.ligand_stride;
     }
     c->nrec += (int)(I.rec[0].size() + I.rec[1].size());
@@ -175,6 +203,8 @@ void compute_sizes(lbib_ctx* c) {
     c->ntiles += ntx * nty;
     c->nodes += (long long)row_pitch(I.lat.nx) * I.lat.ny;   // padded rows
   }
+  const int packed = c->nchunk - grouped_chunks;
+  c->nslot = (packed + kGroupChunks - 1) / kGroupChunks * kGroupChunks + kGroupChunks * grouped;
 }
 
 void compute_layout(lbib_ctx* c) {
@@ -224,12 +254,22 @@ void compute_layout(lbib_ctx* c) {
   L.lig_va = take(4 * nl);
   L.lig_vb = take(4 * nl);
   L.lig_sigma = take(8 * nl);
+  L.lig_sp = take(8 * nl);
   L.r2l = take(4 * nr);
   L.rec_x = take(8 * nr);
   L.step_next = take(8 * c->ninst);
   L.step_cur = take(8 * c->ninst);
   L.ties = take(8 * c->ninst);
   L.red = take(8 * (6 * 1024 + 64));
+  const size_t nch = (size_t)std::max(c->nchunk, 1);
+  L.chunk_body = take(4 * nch);
+  L.area_part = take(8 * 5 * nch);
+  L.rig_part = take(8 * 3 * nch);
+  L.body_cnt = take(4 * (size_t)std::max(c->nbody, 1));
+  L.star = take(es * 4 * (size_t)c->nodes);
+  L.pbox = take(4 * 4 * nch);
+  L.star_wg = take(4 * 3 * (size_t)std::max(c->nstar_wg, 1));
+  L.slot_chunk = take(8 * (size_t)std::max(c->nslot, 1));
   L.total = cur;
 }
 
@@ -284,17 +324,29 @@ Ptrs<T> make_ptrs(const lbib_ctx* c) {
   p.lig_va = (int*)(w + L.lig_va);
   p.lig_vb = (int*)(w + L.lig_vb);
   p.lig_sigma = (double*)(w + L.lig_sigma);
+  p.lig_sp = (double*)(w + L.lig_sp);
   p.r2l = (int*)(w + L.r2l);
   p.rec_x = (double*)(w + L.rec_x);
   p.step_next = (long long*)(w + L.step_next);
   p.step_cur = (long long*)(w + L.step_cur);
   p.ties = (unsigned long long*)(w + L.ties);
   p.red = (double*)(w + L.red);
+  p.chunk_body = (int*)(w + L.chunk_body);
+  p.area_part = (double*)(w + L.area_part);
+  p.rig_part = (double*)(w + L.rig_part);
+  p.body_cnt = (int*)(w + L.body_cnt);
+  p.star = (T*)(w + L.star);
+  p.pbox = (int*)(w + L.pbox);
+  p.star_wg = (const int*)(w + L.star_wg);
+  p.nstar_wg = c->nstar_wg;
+  p.slot_chunk = (const int2*)(w + L.slot_chunk);
+  p.nslot = c->nslot;
   p.nm_total = c->nm;
   p.nbody_total = c->nbody;
   p.ntile_total = c->ntiles;
   p.ninst = c->ninst;
   p.nlig_total = c->nlig;
+  p.nchunk_total = c->nchunk;
   return p;
 }
 
@@ -383,7 +435,8 @@ lbib_status upload_all(lbib_ctx* c) {
   std::vector<int> lig_va(std::max(c->nlig, 1)), lig_vb(std::max(c->nlig, 1));
   std::vector<double> lig_sigma(std::max(c->nlig, 1), 0.0);
   std::vector<double> rec_x(std::max(c->nrec, 1));
-  int bi = 0, li = 0;
+  std::vector<int> chunk_body(std::max(c->nchunk, 1), 0);
+  int bi = 0, li = 0, ci = 0;
   for (int i = 0; i < c->ninst; ++i) {
     InstHost& I = c->inst[i];
     LatDev& D = lat[i];
@@ -424,6 +477,8 @@ lbib_status upload_all(lbib_ctx* c) {
       B.ks = b.d.ks; B.kb = b.d.kb; B.ka = b.d.ka; B.p_ref = b.d.p_ref; B.sigma = b.d.sigma;
       B.lig_stride = b.d.ligand_stride;
       B.lig_base = D.lig_base + nl;
+      B.chunk0 = ci;
+      for (int k = 0; k < chunks_of(b.d.nv); ++k) chunk_body[ci++] = bi;
       std::vector<double> bl0, bth0;
       double A0;
       rest_state(b.xy, b.d.nv, bl0, bth0, A0);
@@ -504,12 +559,62 @@ lbib_status upload_all(lbib_ctx* c) {
     if (!chunks.empty()) HIPCHK(c, up(L.rep_chunk, chunks.data(), 4 * chunks.size()));
   }
   HIPCHK(c, up(L.minfo, minfo.data(), 4 * nm));
+  HIPCHK(c, up(L.chunk_body, chunk_body.data(), 4 * chunk_body.size()));
+  HIPCHK(c, hipMemsetAsync(w + L.area_part, 0, 8 * 5 * chunk_body.size(), s));
+  HIPCHK(c, hipMemsetAsync(w + L.rig_part, 0, 8 * 3 * chunk_body.size(), s));
+  HIPCHK(c, hipMemsetAsync(w + L.body_cnt, 0, 4 * (size_t)std::max(c->nbody, 1), s));
+  HIPCHK(c, hipMemsetAsync(w + L.star, 0, (size_t)elem_size(c->dtype) * 4 * c->nodes, s));
+  HIPCHK(c, hipMemsetAsync(w + L.pbox, 0, 4 * 4 * chunk_body.size(), s));
+  {
+    // star work list: (body, rank, workgroups of the body) per workgroup
+    std::vector<int> sw;
+    for (int i = 0, bb = 0; i < c->ninst; ++i)
+      for (auto& b : c->inst[i].bodies) {
+        const int K = star_workgroups(b);
+        for (int r = 0; r < K; ++r) {
+          sw.push_back(bb);
+          sw.push_back(r);
+          sw.push_back(K);
+        }
+        ++bb;
+      }
+    if (!sw.empty()) HIPCHK(c, up(L.star_wg, sw.data(), 4 * sw.size()));
+  }
+  {
+    // waves of the chunked body kernel, as (chunk, body): one workgroup per
+    // grouped rigid body first (chunk c on wave c, idle waves -2), then the
+    // chunks of the other particles and of the red cells, packed (the
+    // particles' chains are the longer ones: they start first)
+    std::vector<int> sl;
+    for (int bb = 0; bb < c->nbody; ++bb)
+      if (rigid_grouped(bodies[bb].kind, bodies[bb].nv))
+        for (int k = 0; k < kGroupChunks; ++k) {
+          sl.push_back(k < chunks_of(bodies[bb].nv) ? bodies[bb].chunk0 + k : -2);
+          sl.push_back(bb);
+        }
+    for (int pass = 0; pass < 2; ++pass)
+      for (int bb = 0; bb < c->nbody; ++bb) {
+        const bool rbc = bodies[bb].kind == LBIB_RBC_KINEMATIC;
+        if (rigid_grouped(bodies[bb].kind, bodies[bb].nv) || rbc != (pass == 1)) continue;
+        for (int k = 0; k < chunks_of(bodies[bb].nv); ++k) {
+          sl.push_back(bodies[bb].chunk0 + k);
+          sl.push_back(bb);
+        }
+      }
+    while (sl.size() % (2 * kGroupChunks)) {
+      sl.push_back(-1);
+      sl.push_back(0);
+    }
+    if ((int)sl.size() != 2 * c->nslot) return fail(c, LBIB_EINVAL, "internal: wave slot count");
+    if (!sl.empty()) HIPCHK(c, up(L.slot_chunk, sl.data(), 4 * sl.size()));
+  }
   HIPCHK(c, up(L.tile_inst, tile_inst.data(), 4 * tile_inst.size()));
   HIPCHK(c, up(L.lig_body, lig_body.data(), 4 * lig_body.size()));
   HIPCHK(c, up(L.lig_elem, lig_elem.data(), 4 * lig_elem.size()));
   HIPCHK(c, up(L.lig_va, lig_va.data(), 4 * lig_va.size()));
   HIPCHK(c, up(L.lig_vb, lig_vb.data(), 4 * lig_vb.size()));
   HIPCHK(c, up(L.lig_sigma, lig_sigma.data(), 8 * lig_sigma.size()));
+  HIPCHK(c, hipMemsetAsync(w + L.lig_sp, 0, 8 * lig_sigma.size(), s));
   HIPCHK(c, hipMemsetAsync(w + L.l2r, 0xff, 4 * std::max(c->nlig, 1), s));
   HIPCHK(c, hipMemsetAsync(w + L.r2l, 0xff, 4 * std::max(c->nrec, 1), s));
   HIPCHK(c, up(L.rec_x, rec_x.data(), 8 * rec_x.size()));

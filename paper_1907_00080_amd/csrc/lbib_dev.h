@@ -83,7 +83,8 @@ struct LatDev {
 // Per-body description and rigid-body state (device copy; rigid state mutable).
 struct BodyDev {
   int kind, nv, v0, inst;   // v0: global index of vertex 0
-  int lig_base, n_lig, lig_stride, pad_;
+  int lig_base, n_lig, lig_stride;
+  int chunk0;               // global index of the body's first vertex chunk
   double ks, kb, ka, p_ref;
   double A0, mass, mv, inertia, sigma;
   double xc, yc, theta;     // rigid: reference point and angle
@@ -163,12 +164,121 @@ struct Ptrs {
   int *lig_body, *lig_elem, *l2r, *r2l, *lig_flag;
   int *lig_va, *lig_vb;  // global vertex ids of a ligand element's two ends
   double* lig_sigma;     // bond spring constant of each ligand's body
+  double* lig_sp;        // per ligand holding a bond: sigma (y_l - y_eq) at X^n (Eq. adhFor),
+                         // written by the bond workgroup of the step
   double* rec_x;
   long long *step_next, *step_cur;   // per instance
+  // vertex chunks (kChunk consecutive vertices of one body, one wave each)
+  int* chunk_body;                    // per chunk: its body
+  // waves of the chunked body kernel: (chunk, body) each one takes (chunk
+  // -1: none; -2: an idle wave in the workgroup of a rigid body whose
+  // chunks, at most four, share one workgroup so that its force and torque
+  // are summed in LDS)
+  const int2* slot_chunk;
+  int nslot;
+  double* area_part;                  // per chunk [5][nchunk]: shoelace sum over its interior
+                                      // edges, its first vertex (x, y), its last vertex (x, y)
+  double* rig_part;                   // per chunk: rigid load partials [3][nchunk]
+  int* body_cnt;                      // per body: chunks done (rigid finish), reset by the last
+  // particles' star field: rho* - 1, u*x, u*y (and one unused slot) of the
+  // pre-forcing state per node, written over each particle's node box by
+  // the advance and stencil passes for the next body kernel
+  T* star;                            // [4 * nodes]
+  int* pbox;                          // per chunk of a particle: vertex box x0, x1, y0, y1
+  const int* star_wg;                 // star work list: (body, rank, workgroups of the body)
+  int nstar_wg;
   double* red;                        // reduction scratch
   unsigned long long* ties;           // per instance count of bond draws within 1e-12 of P
-  int nm_total, nbody_total, ntile_total, ninst, nlig_total;
+  int nm_total, nbody_total, ntile_total, ninst, nlig_total, nchunk_total;
 };
+
+// Vertex chunks.  A body's vertices are cut into chunks of kChunk
+// consecutive vertices; chunk c of a body covers [kChunk c, kChunk c + cnt)
+// and is handled by one 64-lane wave whose lane i holds vertex
+// kChunk c + i - 2 (modulo nv): the two lanes on either side are the halo
+// that strain and bending at the chunk's own ("inner") vertices need.  Every
+// sum over a body's vertices (its area, the rigid loads) is taken the same
+// way on every path: each chunk's inner terms summed over the 64 lanes by a
+// fixed butterfly (wave_sum), then the chunk sums in chunk order
+// (chunk_total), so all kernels and step forms give the same bits.
+constexpr int kChunk = 60;
+__host__ __device__ constexpr int chunks_of(int nv) { return (nv + kChunk - 1) / kChunk; }
+// rigid bodies of at most this many chunks (one per wave of a 256-lane
+// workgroup) are summed inside their workgroup
+constexpr int kGroupChunks = 4;
+__host__ __device__ constexpr bool rigid_grouped(int kind, int nv) {
+  return kind == kRigid && chunks_of(nv) <= kGroupChunks;
+}
+
+__device__ __forceinline__ int chunk_vertex(int lane, int first, int nv) {
+  int v = (first + lane - 2) % nv;   // first + lane - 2 >= -2
+  return v < 0 ? v + nv : v;
+}
+
+// Sum over the 64 lanes of a wave, fixed butterfly: every lane ends with the
+// same bits (each pair adds the same two values).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Value of a double held by lane l of the wave (l wave-uniform: two
+// readlanes, no LDS traffic).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// s + x_0 + x_1 + ... + x_{m-1} in this order, x_j held by lane j (m <= 64;
+// a rolled loop: this code runs once per chunk, and its instruction fetches
+// cost more than the loop)
+__device__ __forceinline__ double ordered_lane_sum(double s, double x, int m) {
+#pragma unroll 1
+  for (int j = 0; j < m; ++j) s += readlane_d(x, j);
+  return s;
+}
+
+// Sum of a body's chunk partials in chunk order (part[k], k < nch; every
+// lane of the wave gets the same bits).
+__device__ __forceinline__ double chunk_total(const double* part, int nch) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int k0 = 0; k0 < nch; k0 += 64) {
+    const double pv = k0 + lane < nch ? part[k0 + lane] : 0.0;
+    s = ordered_lane_sum(s, pv, nch - k0 < 64 ? nch - k0 : 64);
+  }
+  return s;
+}
+
+// Shoelace term of the edge from (x0, y0) to (x1, y1): twice the signed area
+// of the triangle it spans with the origin (its rounding fixed by the fma).
+__device__ __forceinline__ double shoelace_term(double x0, double y0, double x1, double y1) {
+  return __fma_rn(x0, y1, -(x1 * y0));
+}
+
+// Twice a body's signed area from its chunk records (the advance or stencil
+// pass writes them): chunk k adds its interior-edge sum P_k and the edge
+// from its last vertex to the first vertex of chunk k + 1 (cyclically),
+// T_k = P_k + shoelace(last_k, first_k+1), and the T_k are added in chunk
+// order.  A chunk's record never needs a vertex another wave moves.
+__device__ __forceinline__ double body_area2(const double* rec, int nct, int ch0, int nch) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int k0 = 0; k0 < nch; k0 += 64) {
+    const int k = k0 + lane;
+    double tk = 0.0;
+    if (k < nch) {
+      const int kn = k + 1 == nch ? 0 : k + 1;
+      tk = rec[ch0 + k] + shoelace_term(rec[3 * nct + ch0 + k], rec[4 * nct + ch0 + k],
+                                        rec[nct + ch0 + kn], rec[2 * nct + ch0 + kn]);
+    }
+    s = ordered_lane_sum(s, tk, nch - k0 < 64 ? nch - k0 : 64);
+  }
+  return s;
+}
 
 __host__ __device__ inline int wrap_i(int i, int n) {
   int r = i % n;

@@ -25,6 +25,27 @@ LBIB_HD double roma_phi(double r) {
   return 0.0;
 }
 
+// The three weights of a point on the nodes next to it along one axis,
+// w[a] = phi(d + a - 1) with d = (nearest node) - (point) in (-1/2, 1/2],
+// and (D) their derivatives dw[a] = phi'(d + a - 1).  All six share the
+// square root q = sqrt(1 - 3 d^2): the middle node is on the inner piece,
+// the outer two at |r| = 1 -+ d, where 1 - |r| = +-d, on the outer piece:
+// phi(d - 1) = (2 + 3d - q)/6, phi(d) = (1 + q)/3, phi(d + 1) = (2 - 3d - q)/6,
+// phi'(d - 1) = 1/2 + d/(2q), phi'(d) = -d/q, phi'(d + 1) = -1/2 + d/(2q).
+template <bool D>
+LBIB_HD void roma_weights3(double d, double w[3], double dw[3]) {
+  const double q = sqrt(1.0 - 3.0 * d * d);
+  w[0] = (2.0 + 3.0 * d - q) * (1.0 / 6.0);
+  w[1] = (1.0 + q) * (1.0 / 3.0);
+  w[2] = (2.0 - 3.0 * d - q) * (1.0 / 6.0);
+  if (D) {
+    const double h = d / q;
+    dw[0] = 0.5 + 0.5 * h;
+    dw[1] = -h;
+    dw[2] = -0.5 + 0.5 * h;
+  }
+}
+
 LBIB_HD double roma_dphi(double r) {
   double a = fabs(r);
   if (a <= 0.5) return -r / sqrt(1.0 - 3.0 * r * r);

@@ -141,11 +141,11 @@ def cpu_baseline_sweep(n_inst: int, budget_s: float = 20.0) -> dict:
                       f"all processes / longest stepping time"}
 
 
-def traffic_from_profile(workload_name: str, tile=None):
+def traffic_from_profile(workload_name: str, tile=None, hints=None):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), if
     it was taken with the current kernel source and (when given) the same tile
-    shape; else None."""
+    shape and cache hints; else None."""
     try:
         with open(PROFILE_TRAFFIC) as f:
             rec = json.load(f)
@@ -155,6 +155,8 @@ def traffic_from_profile(workload_name: str, tile=None):
         return None
     if tile is not None and rec.get("tiles", {}).get(workload_name) != f"{tile[0]}x{tile[1]}":
         return None
+    if hints is not None and rec.get("cache_hints", {}).get(workload_name) != int(hints):
+        return None
     return rec.get("bytes_per_launch", {}).get(workload_name)
 
 
@@ -163,7 +165,7 @@ def tuned_config(pkg, wl, args):
     steps of this workload timed for every tile and step form), or the tile
     given on the command line with the default step form."""
     if args.tile != "auto":
-        return tuple(int(v) for v in args.tile.split("x")), None, None, None
+        return tuple(int(v) for v in args.tile.split("x")), args.step_mode, args.hints, None
     from paper_1907_00080_amd import tune
     rec = tune.autotune([wl], dtype="f32", device="cuda:0", steps=200, warmup=20,
                         graph_steps=(args.graph_steps,))
@@ -189,6 +191,10 @@ def main():
                          "median of all is reported beside it")
     ap.add_argument("--tile", default="auto",
                     help="TXxTY, or auto: tile, step form and cache hints from the autotuner")
+    ap.add_argument("--step-mode", type=int, default=None,
+                    help="with a fixed --tile: step form (1 three kernels, 2 merged, 3 overlapped)")
+    ap.add_argument("--hints", type=int, default=None,
+                    help="with a fixed --tile: cache hints of the lattice kernel (0, 1 or 3)")
     ap.add_argument("--side-workload", default="capillary-2000x200",
                     help="workload of the optional-physics objects (repulsion, MLS, observables)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -693,7 +699,7 @@ def roofline(res, wl, tile=None):
     achieved = bytes_alg / (res["kernel_ms"] / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profile(wl.name, tile),
+            "traffic": traffic_from_profile(wl.name, tile, res.get("cache_hints")),
             "kernel": "k_lb_fused", "kernel_us": round(res["kernel_ms"] * 1e3, 3),
             "launches": res["kernel_launches"], "bytes_per_launch": bytes_alg}
 

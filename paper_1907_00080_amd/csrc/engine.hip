@@ -1284,6 +1284,8 @@ lbib_status lbib_create(const lbib_lattice_desc* d, lbib_ctx** out) {
   if ((long long)row_pitch(d->nx) * d->ny > (1ll << 31)) return fail(nullptr, LBIB_EINVAL, "lattice too large");
   if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return fail(nullptr, LBIB_EINVAL, "tau must be > 1/2");
   if (d->dtype != LBIB_F32 && d->dtype != LBIB_F64) return fail(nullptr, LBIB_EINVAL, "bad dtype");
+  if (!std::isfinite(d->gx) || !std::isfinite(d->gy))
+    return fail(nullptr, LBIB_EINVAL, "the body force must be finite");
   int tx = d->tile_x, ty = d->tile_y;
   if (tx == 0 && ty == 0) { tx = 64; ty = 4; }
   if (!valid_tile(tx, ty)) return fail(nullptr, LBIB_EINVAL, "unsupported tile shape");
@@ -1310,8 +1312,11 @@ lbib_status lbib_add_body(lbib_ctx* c, const lbib_body_desc* d, const double* xy
   if (d->ligand_stride < 0) return fail(c, LBIB_EINVAL, "ligand_stride must be >= 0");
   if (d->kind == LBIB_RBC_KINEMATIC && d->ligand_stride > 0)
     return fail(c, LBIB_EINVAL, "ligands sit on particles only (red cells carry none)");
-  if (d->kind != LBIB_RBC_KINEMATIC && !(d->density_ratio > 0))
-    return fail(c, LBIB_EINVAL, "particles need density_ratio > 0");
+  if (d->kind != LBIB_RBC_KINEMATIC && !(d->density_ratio > 0 && std::isfinite(d->density_ratio)))
+    return fail(c, LBIB_EINVAL, "particles need a finite density_ratio > 0");
+  for (double v : {d->ks, d->kb, d->ka, d->p_ref, d->sigma})
+    if (!(v >= 0) || !std::isfinite(v))
+      return fail(c, LBIB_EINVAL, "ks, kb, ka, p_ref and sigma must be finite and >= 0");
   BodyHost b;
   b.d = *d;
   b.xy.assign(xy, xy + 2 * (size_t)d->nv);
@@ -1346,8 +1351,10 @@ lbib_status lbib_set_receptors(lbib_ctx* c, int32_t wall, const double* x, int32
 lbib_status lbib_set_adhesion(lbib_ctx* c, const lbib_adhesion_desc* d) {
   if (!c || !d) return fail(c, LBIB_EINVAL, "NULL argument");
   if (c->phase != 0 || c->is_batch) return fail(c, LBIB_ESTATE, "adhesion can only be set during set-up");
-  if (!(d->kbt > 0) || d->y_cr < 0 || d->kf0_dt < 0 || d->kr0_dt < 0)
+  if (!(d->kbt > 0) || !(d->y_cr >= 0) || !(d->kf0_dt >= 0) || !(d->kr0_dt >= 0))
     return fail(c, LBIB_EINVAL, "bad adhesion parameters");
+  for (double v : {d->y_cr, d->y_eq, d->kf0_dt, d->kr0_dt, d->sigma_ts_frac, d->kbt})
+    if (!std::isfinite(v)) return fail(c, LBIB_EINVAL, "adhesion parameters must be finite");
   c->inst.back().adh = *d;
   return LBIB_OK;
 }

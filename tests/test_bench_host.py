@@ -1,6 +1,6 @@
 """Host logic of bench.py (no GPU): the stored HBM-counter figure is reported
-only for the kernel source and the tile shape it was taken with, and the
-multi-GPU request is refused."""
+only for the kernel source, tile shape and cache hints it was taken with, and
+the multi-GPU request is refused."""
 import importlib.util
 import json
 import os
@@ -17,18 +17,28 @@ def _bench():
     return mod
 
 
-def test_traffic_figure_follows_source_hash_and_tile(monkeypatch):
+def test_traffic_figure_follows_source_hash_tile_and_hints(monkeypatch):
     b = _bench()
     with open(b.PROFILE_TRAFFIC) as f:
         rec = json.load(f)
-    name = "capillary-2000x200"
+    name = "capillary-6667x667"
     tile = tuple(int(v) for v in rec["tiles"][name].split("x"))
+    hints = rec["cache_hints"][name]
     monkeypatch.setattr(b, "kernel_source_hash", lambda: rec["kernel_source_sha256_16"])
-    assert b.traffic_from_profile(name, tile) == rec["bytes_per_launch"][name]
+    assert b.traffic_from_profile(name, tile, hints) == rec["bytes_per_launch"][name]
     other = (64, 4) if tile != (64, 4) else (256, 1)
-    assert b.traffic_from_profile(name, other) is None
+    assert b.traffic_from_profile(name, other, hints) is None
+    assert b.traffic_from_profile(name, tile, 0 if hints else 3) is None
     monkeypatch.setattr(b, "kernel_source_hash", lambda: "0" * 16)
-    assert b.traffic_from_profile(name, tile) is None
+    assert b.traffic_from_profile(name, tile, hints) is None
+
+
+def test_stored_counters_match_current_kernel():
+    """The committed counter figures were taken with the current fused kernel."""
+    b = _bench()
+    with open(b.PROFILE_TRAFFIC) as f:
+        rec = json.load(f)
+    assert rec["kernel_source_sha256_16"] == b.kernel_source_hash()
 
 
 def test_multi_gpu_request_is_refused():

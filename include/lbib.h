@@ -407,7 +407,8 @@ lbib_status lbib_get_kernel_timing(lbib_ctx* ctx, double* lattice_ms_avg, int64_
 
 /* ---------------------------------------------------------------------------
  * Discrete adjoint of a window of steps (single-lattice contexts with red
- * cells and soft particles; rigid particles are refused with LBIB_EINVAL).
+ * cells, soft and rigid particles, bounce-back walls and the Roma-kernel
+ * transfer; no vertex repulsion).
  *
  * The window advances nsteps steps from the current state with the bond
  * topology frozen (no bond kinetics; bonded springs keep acting, Eq. adhFor),
@@ -418,7 +419,9 @@ lbib_status lbib_get_kernel_timing(lbib_ctx* ctx, double* lattice_ms_avg, int64_
  * The backward pass recomputes each segment from its checkpoint, then applies
  * the transposed Jacobian of every step (Sec. 2.1 collision and streaming,
  * Sec. 2.2 spreading, interpolation, membrane, spring and probe loads,
- * Sec. 2.3 soft-particle and kinematic marker updates) in reverse order.
+ * Sec. 2.3 soft-particle, rigid-particle (Eqs. linearVelRig, angularVelRig)
+ * and kinematic marker updates) in reverse order.  A rigid particle's
+ * gradient has only its sigma entry (k_s and k_b do not act on it).
  *
  * lbib_adjoint_workspace_query / lbib_adjoint_bind: size and bind the
  *   caller-owned device workspace (256-byte aligned, must outlive the
@@ -430,10 +433,16 @@ lbib_status lbib_get_kernel_timing(lbib_ctx* ctx, double* lattice_ms_avg, int64_
  * lbib_adjoint_backward: after lbib_adjoint_forward (and no parameter
  *   change since): grad[3*b + 0..2] = dJ * dJ/dk_s, dJ * dJ/dk_b,
  *   dJ * dJ/dsigma of body b (all bodies of the context, host array).  The
- *   context is left at the end of the window.
+ *   context is left at the end of the window.  The gradient is bitwise
+ *   reproducible: the scatter-form terms (transposed interpolation, probe
+ *   and spreading) add into exact 128-bit fixed-point accumulators, so their
+ *   sums do not depend on the order of the atomics.
  * Errors: LBIB_ESTATE before finalize_setup, without a bound workspace or
- *   forward window; LBIB_EINVAL for batches, rigid bodies or bad sizes;
- *   LBIB_ENOSPACE for a workspace that is too small. */
+ *   forward window; LBIB_EINVAL for batches, the vertex repulsion, velocity
+ *   walls, the MLS transfer or bad sizes;
+ *   LBIB_ENOSPACE for a workspace that is too small; LBIB_EUNSTABLE from
+ *   lbib_adjoint_backward when a scattered term is not finite or of magnitude
+ *   2^62 or more (grad is then left unwritten). */
 lbib_status lbib_adjoint_workspace_query(const lbib_ctx* ctx, int64_t nsteps, int32_t ckpt_every,
                                          size_t* bytes);
 lbib_status lbib_adjoint_bind(lbib_ctx* ctx, void* dev_workspace, size_t bytes, int64_t nsteps,

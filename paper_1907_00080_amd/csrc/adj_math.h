@@ -14,6 +14,8 @@
 //   spring      adhesion spring element load (Eq. adhFor)
 //   hydro       probe pressure and viscous element load (Eqs. hydroForP,
 //               hydroForNu)
+//   rigid       summed load and torque, BDF2 velocity update and rigid
+//               vertex motion (Eqs. linearVelRig, angularVelRig)
 #pragma once
 #include <math.h>
 
@@ -211,6 +213,14 @@ LBIB_HD double area_vjp(double dx, double dy, double kappa, double Fhx, double F
 // Element load F = sigma (y - y_eq) n, n = (t_y, -t_x), y the bond length
 // from the centroid c to the receptor, with (ddx, ddy) = d y / d c.
 // Adds the adjoints of d (element vector), c and sigma.
+LBIB_HD void spring_fwd(double dx, double dy, double y, double sigma, double y_eq, double& Fx,
+                        double& Fy) {
+  const double len = sqrt(dx * dx + dy * dy);
+  const double k = sigma * (y - y_eq);
+  Fx = k * (dy / len);
+  Fy = k * (-dx / len);
+}
+
 LBIB_HD void spring_vjp(double dx, double dy, double y, double ddx, double ddy, double sigma,
                         double y_eq, double Fhx, double Fhy, double& dhx, double& dhy,
                         double& chx, double& chy, double& sigh) {
@@ -251,6 +261,61 @@ LBIB_HD void hydro_vjp(double pr, const double g[4], double nu, double nx, doubl
   gh[3] += 2.0 * nu * tyyh;
   gh[1] += nu * txyh;
   gh[2] += nu * txyh;
+}
+
+// ------------------------------------------------------------------ rigid
+// Rigid particle (Sec. 2.3, Eqs. linearVelRig, angularVelRig).  Its summed
+// load and torque, element by element: F_tot += f, M_tot += r x f with the
+// arm r = c - x_c from the reference point to the element centroid.  Given
+// the adjoints (Fh, Mh) of the sums: adds the adjoints of f and of r.
+LBIB_HD void rigid_load_vjp(double rx, double ry, double fx, double fy, double Fhx, double Fhy,
+                            double Mh, double& fhx, double& fhy, double& rhx, double& rhy) {
+  fhx += Fhx - Mh * ry;
+  fhy += Fhy + Mh * rx;
+  rhx += Mh * fy;
+  rhy += -Mh * fx;
+}
+
+// Velocity update v' = 2/3 (2 v - v_prev / 2 + r / m), or v' = v + r / m on
+// the first step (BDF2 in time, forward Euler to start; r the summed load
+// or torque, m the mass or moment of inertia).  Given the adjoint of v':
+// adds those of v and v_prev and returns that of r.
+LBIB_HD double bdf2_vjp(bool first, double m, double vh_new, double& vh, double& vph) {
+  if (first) {
+    vh += vh_new;
+    return vh_new / m;
+  }
+  vh += (4.0 / 3.0) * vh_new;
+  vph += (-1.0 / 3.0) * vh_new;
+  return (2.0 / 3.0) * vh_new / m;
+}
+
+// Vertex of a rigid particle after the step: X' = x_c' + R(theta') r0 and
+// the rigid-body velocity there, U_k = U' + Omega' x (X' - x_c').
+LBIB_HD void rigid_vertex_fwd(double r0x, double r0y, double xc, double yc, double th, double Ux,
+                              double Uy, double Om, double X[2], double Uk[2]) {
+  const double cs = cos(th), sn = sin(th);
+  const double relx = r0x * cs - r0y * sn, rely = r0x * sn + r0y * cs;
+  X[0] = xc + relx;
+  X[1] = yc + rely;
+  Uk[0] = Ux - Om * rely;
+  Uk[1] = Uy + Om * relx;
+}
+
+// Given the adjoints of X' (xh) and of U_k (uh) at a vertex with arm
+// rel = R(theta') r0: adds those of x_c' (ch), theta' (thh), U' (Uh) and
+// Omega' (Omh).
+LBIB_HD void rigid_vertex_vjp(double relx, double rely, double Om, double xhx, double xhy,
+                              double uhx, double uhy, double ch[2], double& thh, double Uh[2],
+                              double& Omh) {
+  ch[0] += xhx;
+  ch[1] += xhy;
+  Uh[0] += uhx;
+  Uh[1] += uhy;
+  Omh += -uhx * rely + uhy * relx;
+  // adjoint of rel: from X' directly and through Omega' x rel
+  const double rhx = xhx + Om * uhy, rhy = xhy - Om * uhx;
+  thh += -rhx * rely + rhy * relx;   // d rel / d theta = (-rel_y, rel_x)
 }
 
 }  // namespace adj

@@ -888,11 +888,11 @@ struct AdjLayout {
   size_t ck_bytes;
   int nseg, nck;
   size_t ck;
-  size_t rec_bytes, r_h, r_x, r_y, r_fx, r_fy, r_xn, r_yn, r_u;
+  size_t rec_bytes, r_h, r_x, r_y, r_fx, r_fy, r_xn, r_yn, r_u, r_b0, r_b1;
   size_t seg[2];   // two segment stores: recompute into one while the other is reversed
-  size_t ha, fph, FE, FEh, mom, Uh, Rh, xa, ya, xma, yma;
+  size_t ha, fph, FE, FEh, mom, Uh, Rh, bad, xa, ya, xma, yma;
   size_t mk[13];
-  size_t grad;
+  size_t grad, rig;
   size_t total;
 };
 
@@ -921,15 +921,20 @@ AdjLayout adj_layout(const lbib_ctx* c, long long K, int k) {
   A.r_fx = rt(8 * nm); A.r_fy = rt(8 * nm);
   A.r_xn = rt(8 * nm); A.r_yn = rt(8 * nm);
   A.r_u = rt(es * 2 * N);
+  // the bodies (rigid-particle state) before and after the step
+  const size_t bb = sizeof(BodyDev) * (size_t)std::max(c->nbody, 1);
+  A.r_b0 = rt(bb); A.r_b1 = rt(bb);
   A.rec_bytes = rb;
   A.seg[0] = take(rb * (size_t)k);
   A.seg[1] = take(rb * (size_t)k);
   A.ha = take(8 * 9 * N); A.fph = take(8 * 9 * N);
-  A.FE = take(16 * N); A.FEh = take(16 * N); A.mom = take(24 * N);
-  A.Uh = take(16 * N); A.Rh = take(24 * N);
+  // accumulators: a high and a low 64-bit word per entry (high words first)
+  A.FE = take(32 * N); A.FEh = take(16 * N); A.mom = take(24 * N);
+  A.Uh = take(32 * N); A.Rh = take(48 * N); A.bad = take(8);
   A.xa = take(8 * nm); A.ya = take(8 * nm); A.xma = take(8 * nm); A.yma = take(8 * nm);
   for (auto& o : A.mk) o = take(8 * nm);
   A.grad = take(24 * (size_t)std::max(c->nbody, 1));
+  A.rig = take(72 * (size_t)std::max(c->nbody, 1));
   A.total = cur;
   return A;
 }
@@ -938,14 +943,20 @@ AdjPtrs adj_ptrs(const lbib_ctx* c, const AdjLayout& A) {
   char* w = c->aws;
   AdjPtrs a{};
   a.ha = (double*)(w + A.ha); a.fph = (double*)(w + A.fph);
-  a.FE = (double*)(w + A.FE); a.FEh = (double*)(w + A.FEh); a.mom = (double*)(w + A.mom);
-  a.Uh = (double*)(w + A.Uh); a.Rh = (double*)(w + A.Rh);
+  const size_t N = (size_t)c->nodes;
+  auto acc = [&](size_t off, size_t n) {
+    return AccField{(long long*)(w + off), (unsigned long long*)(w + off + 8 * n)};
+  };
+  a.FE = acc(A.FE, 2 * N); a.Uh = acc(A.Uh, 2 * N); a.Rh = acc(A.Rh, 3 * N);
+  a.FEh = (double*)(w + A.FEh); a.mom = (double*)(w + A.mom);
+  a.bad = (int*)(w + A.bad);
   a.xa = (double*)(w + A.xa); a.ya = (double*)(w + A.ya);
   a.xma = (double*)(w + A.xma); a.yma = (double*)(w + A.yma);
   double** m[13] = {&a.dirx, &a.diry, &a.fvx, &a.fvy, &a.dsh, &a.Dx, &a.Dy,
                     &a.Cx, &a.Cy, &a.BLx, &a.BLy, &a.BRx, &a.BRy};
   for (int k = 0; k < 13; ++k) *m[k] = (double*)(w + A.mk[k]);
   a.grad = (double*)(w + A.grad);
+  a.rig = (double*)(w + A.rig);
   return a;
 }
 
@@ -992,9 +1003,6 @@ lbib_status adj_check(lbib_ctx* c) {
   if (c->inst[0].wall_mode != 0) return fail(c, LBIB_EINVAL, "the adjoint covers bounce-back walls only");
   if (c->inst[0].transfer != LBIB_TRANSFER_ROMA)
     return fail(c, LBIB_EINVAL, "the adjoint covers the Roma-kernel transfer only");
-  for (auto& b : c->inst[0].bodies)
-    if (b.d.kind == LBIB_PARTICLE_RIGID)
-      return fail(c, LBIB_EINVAL, "the adjoint covers red cells and soft particles (no rigid bodies)");
   if (!c->aws) return fail(c, LBIB_ESTATE, "bind an adjoint workspace first");
   return LBIB_OK;
 }
@@ -1059,19 +1067,31 @@ template <typename T>
 void enqueue_recompute(lbib_ctx* c, const AdjLayout& A, int buf, long long n) {
   const long long N = c->nodes;
   const size_t es = elem_size(c->dtype), nmb = 8 * (size_t)c->nm;
+  const size_t bb = sizeof(BodyDev) * (size_t)c->nbody;
   const StepArgs sa = step_args(c);
+  char* seg = c->aws + A.seg[buf];
+  if (bb > 0) {   // the bodies before the first step (later steps: after the previous one)
+    CopyList cl{};
+    cl.n = 1;
+    cl.src[0] = c->ws + c->L.body;
+    cl.dst[0] = seg + A.r_b0;
+    cl.bytes[0] = bb;
+    launch_copies(cl, c->stream);
+  }
   for (long long s = 0; s < n; ++s) {
-    char* rec = c->aws + A.seg[buf] + (size_t)s * A.rec_bytes;
+    char* rec = seg + (size_t)s * A.rec_bytes;
     Ptrs<T> p = make_ptrs<T>(c);
     launch_lagrangian<T>(p, sa, c->stream, c->merge_advance && s > 0);
     launch_lb_fused<T>(p, sa, c->stream);
     CopyList cl{};
-    cl.n = 8;
-    const char* src[8] = {(const char*)p.A, (const char*)p.x, (const char*)p.y, (const char*)p.fx,
-                          (const char*)p.fy, (const char*)p.xn, (const char*)p.yn, (const char*)p.U};
-    const size_t off[8] = {A.r_h, A.r_x, A.r_y, A.r_fx, A.r_fy, A.r_xn, A.r_yn, A.r_u};
-    const size_t by[8] = {es * 9 * N, nmb, nmb, nmb, nmb, nmb, nmb, es * 2 * N};
-    for (int k = 0; k < 8; ++k) {
+    const char* src[10] = {(const char*)p.A, (const char*)p.x, (const char*)p.y, (const char*)p.fx,
+                           (const char*)p.fy, (const char*)p.xn, (const char*)p.yn, (const char*)p.U,
+                           (const char*)p.body, (const char*)p.body};
+    const size_t off[10] = {A.r_h, A.r_x, A.r_y, A.r_fx, A.r_fy, A.r_xn, A.r_yn, A.r_u, A.r_b1,
+                            A.rec_bytes + A.r_b0};
+    const size_t by[10] = {es * 9 * N, nmb, nmb, nmb, nmb, nmb, nmb, es * 2 * N, bb, bb};
+    cl.n = bb == 0 ? 8 : (s + 1 < n ? 10 : 9);
+    for (int k = 0; k < cl.n; ++k) {
       cl.src[k] = src[k];
       cl.dst[k] = rec + off[k];
       cl.bytes[k] = by[k];
@@ -1095,6 +1115,8 @@ void enqueue_reverse(lbib_ctx* c, const AdjLayout& A, AdjPtrs a, int buf, long l
     q.fx = (const double*)(rec + A.r_fx); q.fy = (const double*)(rec + A.r_fy);
     q.xn = (const double*)(rec + A.r_xn); q.yn = (const double*)(rec + A.r_yn);
     q.u = rec + A.r_u;
+    q.body0 = (const BodyDev*)(rec + A.r_b0);
+    q.body1 = (const BodyDev*)(rec + A.r_b1);
     q.first = first && k == 0;
   }
   launch_adjoint_segment<T>(make_ptrs<T>(c), steps.data(), (int)n, c->nodes, s);
@@ -1136,15 +1158,18 @@ lbib_status adjoint_backward_impl(lbib_ctx* c, double dJ, double* grad) {
   launch_fill(a.xma, nm, 0.0, c->stream);
   launch_fill(a.yma, nm, 0.0, c->stream);
   launch_fill(a.grad, 3 * (long long)std::max(c->nbody, 1), 0.0, c->stream);
+  launch_fill(a.rig, 9 * (long long)std::max(c->nbody, 1), 0.0, c->stream);
   std::vector<double> seed;
   wall_objective(c, c->adj_y, &seed);
   for (auto& v : seed) v *= dJ;
   if (nm > 0)
     HIPCHK(c, hipMemcpyAsync(a.ya, seed.data(), 8 * (size_t)nm, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  launch_fill(a.FE, 2 * N, 0.0, c->stream);
-  launch_fill(a.Uh, 2 * N, 0.0, c->stream);
-  launch_fill(a.Rh, 3 * N, 0.0, c->stream);
+  // accumulators and the range flag start at zero (0.0 has all bits clear)
+  launch_fill((double*)a.FE.hi, 4 * N, 0.0, c->stream);
+  launch_fill((double*)a.Uh.hi, 4 * N, 0.0, c->stream);
+  launch_fill((double*)a.Rh.hi, 6 * N, 0.0, c->stream);
+  launch_fill((double*)a.bad, 1, 0.0, c->stream);
   // segments from last to first on the adjoint's own two streams: the
   // recompute of segment j - 1 (first stream, in the role of the context's
   // stream for the loop) overlaps the reverse sweep of segment j (second
@@ -1199,8 +1224,15 @@ lbib_status adjoint_backward_impl(lbib_ctx* c, double dJ, double* grad) {
   c->step = c->ck_step[A.nseg];
   c->stencil_dirty = true;
   std::vector<double> g(3 * (size_t)std::max(c->nbody, 1));
+  int bad = 0;
   HIPCHK(c, hipMemcpyAsync(g.data(), a.grad, 8 * g.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&bad, a.bad, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (bad) {
+    (void)set_freeze(c, c->inst[0].adh.freeze_topology);
+    c->ktiming = kt;
+    return fail(c, LBIB_EUNSTABLE, "adjoint: a scattered term was not finite or beyond 2^62");
+  }
   if (grad) std::memcpy(grad, g.data(), 8 * 3 * (size_t)c->nbody);
   st = set_freeze(c, c->inst[0].adh.freeze_topology);
   if (st != LBIB_OK) return st;

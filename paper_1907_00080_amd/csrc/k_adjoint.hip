@@ -7,19 +7,27 @@
 //   soft:  F_el = probe loads(rho*, u*) + springs,          (Sec. 2.2, 2.3)
 //          X^{n+1} = X + U0 + Fv/(2 m_v), U0 = interp(u*, X),
 //          F_k = 2 (X^{n+1} - X - U0) ds_k
+//   rigid: F_tot, M_tot from the element loads, U', Omega' by BDF2, the
+//          reference point and angle moved, X^{n+1} = x_c' + R(theta') r0,
+//          F_k = 2 (U' + Omega' x (X^{n+1} - x_c') - U0) ds_k
+//          (Eqs. linearVelRig, angularVelRig)
 //   F_E = g + sum_k F_k delta(x - X_k)                     spreading
 //   h^{n+1}, u = collide(f_pre, F_E)                       (Sec. 2.1)
 //   RBC:   X^{n+1} = 2/3 (2 X^n - X^{n-1}/2 + interp(u, X^n))  (Eq. kinematicPos;
 //          forward Euler on the first step)
 // The kernels below apply the transposed Jacobian of this map to the
-// adjoint state (h^, X^, X^_prev) in reverse order, and accumulate the
-// derivatives with respect to each body's k_s, k_b and bond constant sigma.
+// adjoint state (h^, X^, X^_prev, and the rigid particles' state) in reverse
+// order, and accumulate the derivatives with respect to each body's k_s, k_b
+// and bond constant sigma.
 // All adjoint arithmetic is float64; the forward data of step n come from
 // the segment store of the checkpointed recomputation.
 //
-// Scatter-form adjoints (transpose of an interpolation, of a probe
-// evaluation) use the hardware float64 atomic add into dense adjoint fields
-// (the workspace is ordinary coarse-grained device memory, which it needs).
+// Scatter-form terms (the spreading of the stored marker forces, the
+// transpose of an interpolation or of a probe evaluation) add into dense
+// fields of exact 128-bit fixed-point accumulators (value = hi + lo 2^-64):
+// each contribution is rounded once to that grid and the sum is exact, so it
+// does not depend on the order of the atomics and the gradient is bitwise
+// reproducible from run to run.
 #include "adj_math.h"
 #include "lbib_dev.h"
 
@@ -62,22 +70,147 @@ __device__ inline int wrap_idx(int i, int n) { return i < 0 ? i + n : (i >= n ? 
 
 constexpr int kAdjThreads = 256;
 
-__device__ inline void block_sum4(double v[4], double (*s)[kAdjThreads / 64]) {
+// Adds v to the accumulator entry k.  |v| is split into its integer part and
+// its fraction scaled by 2^64 (both exact: the fraction of a double is a
+// multiple of its ulp), negated in two's complement for v < 0, and added
+// word by word; the carry out of the low word is read from the old value the
+// atomic returns.  The number of carries into the high word is fixed by the
+// total of the low words, so the 128-bit result is exact in any order.
+__device__ inline void acc_add(const AccField& f, long long k, double v, int* bad) {
+  const double m = fabs(v);
+  if (!(m < 0x1p62)) {   // also NaN
+    atomicOr(bad, 1);
+    return;
+  }
+  const double ip = floor(m);
+  unsigned long long lo = __double2ull_rn((m - ip) * 0x1p64);   // < 2^64: m - ip <= 1 - 2^-53
+  long long hi = (long long)ip;
+  if (v < 0.0) {
+    hi = -hi - (lo != 0ull ? 1 : 0);
+    lo = 0ull - lo;
+  }
+  if (lo != 0ull) {
+    const unsigned long long old = atomicAdd(&f.lo[k], lo);
+    hi += old + lo < old ? 1 : 0;
+  }
+  if (hi != 0) atomicAdd((unsigned long long*)&f.hi[k], (unsigned long long)hi);
+}
+
+__device__ inline double acc_get(const AccField& f, long long k) {
+  return double(f.hi[k]) + double(f.lo[k]) * 0x1p-64;
+}
+
+__device__ inline void acc_clear(const AccField& f, long long k) {
+  f.hi[k] = 0;
+  f.lo[k] = 0ull;
+}
+
+// Sums K values over the workgroup in a fixed order (butterfly within each
+// wave, then the waves in turn): every thread gets the totals.
+template <int K>
+__device__ inline void block_sum(double v[K], double (*s)[kAdjThreads / 64]) {
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < K; ++k) {
     double x = v[k];
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
     if (lane == 0) s[k][w] = x;
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < K; ++k) {
     double x = 0.0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) x += s[k][i];
     v[k] = x;
   }
   __syncthreads();
+}
+
+// Bond geometry of element l of a particle (Eq. adhFor): for a bonded ligand
+// element, the bond length y from the centroid (cx, cy) to its receptor and
+// (ddx, ddy) = dy/dc.  Returns false for an element without a bond.
+template <typename T>
+__device__ inline bool bond_geometry(const Ptrs<T>& p, const LatDev& L, const BodyDev* Bp, int l,
+                                     double cx, double cy, double& yl, double& ddx, double& ddy) {
+  if (Bp->lig_stride <= 0 || l % Bp->lig_stride != 0) return false;
+  const int r = p.l2r[Bp->lig_base + l / Bp->lig_stride];
+  if (r < 0) return false;
+  const int wall = r < L.n_rec0 ? 0 : 1;
+  const double xr = p.rec_x[L.rec_base + r];
+  const double cxw = cx - L.nx * floor(cx / L.nx);
+  double dx = xr - cxw;
+  if (dx > 0.5 * L.nx) dx -= L.nx;
+  else if (dx < -0.5 * L.nx) dx += L.nx;
+  const double yw = wall == 0 ? -0.5 : L.ny - 0.5;
+  const double dy = cy - yw;
+  yl = sqrt(dx * dx + dy * dy);
+  ddx = -dx / yl;
+  ddy = dy / yl;
+  return true;
+}
+
+// Probe load of an element (centroid c, outward normal n, length len) read
+// at q = c + 1.2 n, its ordinate clamped into the fluid (Eqs. hydroForP,
+// hydroForNu, from rho*, u* in mom).  Returns the load in (pfx, pfy); given
+// its adjoint (Fhx, Fhy), adds the adjoints of c, n and len and scatters
+// those of rho*, u* into Rh.
+__device__ inline void probe_adjoint(const LatDev& L, const AdjPtrs& a, double cx, double cy,
+                                     double nxl, double nyl, double len, double nu, double Fhx,
+                                     double Fhy, double& pfx, double& pfy, double& Chx, double& Chy,
+                                     double& nhx, double& nhy, double& lenh) {
+  const long long N = L.plane;
+  const double* mom = a.mom;
+  const double qx = cx + 1.2 * nxl;
+  const double qy_raw = cy + 1.2 * nyl;
+  double qy = qy_raw;
+  bool clamped = false;
+  if (!L.periodic_y) {
+    qy = fmin(fmax(qy_raw, 0.5), L.ny - 1.5);
+    clamped = qy != qy_raw;
+  }
+  Stencil s;
+  stencil_at(L, qx, qy, true, s);
+  double rq = 0.0, g[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int bb = 0; bb < 3; ++bb) {
+    if (!s.ok[bb]) continue;
+    for (int c = 0; c < 3; ++c) {
+      const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
+      const double w = s.wx[c] * s.wy[bb];
+      const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
+      rq += r0 * w;
+      g[0] -= us * s.dwx[c] * s.wy[bb];
+      g[1] -= us * s.wx[c] * s.dwy[bb];
+      g[2] -= vs * s.dwx[c] * s.wy[bb];
+      g[3] -= vs * s.wx[c] * s.dwy[bb];
+    }
+  }
+  const double pr = (rq - 1.0) * (1.0 / 3.0);
+  adj::hydro_fwd(pr, g, nu, nxl, nyl, len, pfx, pfy);
+  double prh = 0.0, gh[4] = {0.0, 0.0, 0.0, 0.0}, nh2x = 0.0, nh2y = 0.0;
+  adj::hydro_vjp(pr, g, nu, nxl, nyl, len, Fhx, Fhy, prh, gh, nh2x, nh2y, lenh);
+  const double rqh = prh * (1.0 / 3.0);
+  double qhx = 0.0, qhy = 0.0;
+  for (int bb = 0; bb < 3; ++bb) {
+    if (!s.ok[bb]) continue;
+    for (int c = 0; c < 3; ++c) {
+      const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
+      const double wx = s.wx[c], wy = s.wy[bb], dwx = s.dwx[c], dwy = s.dwy[bb];
+      const double ddwx = s.ddwx[c], ddwy = s.ddwy[bb];
+      const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
+      acc_add(a.Rh, node, rqh * wx * wy, a.bad);
+      acc_add(a.Rh, N + node, -gh[0] * dwx * wy - gh[1] * wx * dwy, a.bad);
+      acc_add(a.Rh, 2 * N + node, -gh[2] * dwx * wy - gh[3] * wx * dwy, a.bad);
+      qhx += -rqh * r0 * dwx * wy + gh[0] * us * ddwx * wy + gh[1] * us * dwx * dwy +
+             gh[2] * vs * ddwx * wy + gh[3] * vs * dwx * dwy;
+      qhy += -rqh * r0 * wx * dwy + gh[0] * us * dwx * dwy + gh[1] * us * wx * ddwy +
+             gh[2] * vs * dwx * dwy + gh[3] * vs * wx * ddwy;
+    }
+  }
+  if (clamped) qhy = 0.0;
+  Chx += qhx;
+  Chy += qhy;
+  nhx += nh2x + 1.2 * qhx;
+  nhy += nh2y + 1.2 * qhy;
 }
 
 }  // namespace
@@ -108,11 +241,11 @@ __device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm
     for (int c = 0; c < 3; ++c) {
       const long long node = (long long)s.row[b] * L.pitch + s.col[c];
       const double w = s.wx[c] * s.wy[b];
-      unsafeAtomicAdd(&a.FE[node], fx * w);
-      unsafeAtomicAdd(&a.FE[N + node], fy * w);
+      acc_add(a.FE, node, fx * w, a.bad);
+      acc_add(a.FE, N + node, fy * w, a.bad);
       if (rbc) {
-        unsafeAtomicAdd(&a.Uh[node], ux * w);
-        unsafeAtomicAdd(&a.Uh[N + node], uy * w);
+        acc_add(a.Uh, node, ux * w, a.bad);
+        acc_add(a.Uh, N + node, uy * w, a.bad);
         const double uu = ux * double(U[node]) + uy * double(U[N + node]);
         gx -= uu * s.dwx[c] * s.wy[b];
         gy -= uu * s.wx[c] * s.dwy[b];
@@ -156,10 +289,11 @@ __global__ void ka_collide(Ptrs<T> p, AdjPtrs a) {
     h[i] = double(H[src]);
     ah[i] = a.ha[i * N + node];
   }
-  const double Fx = L.gx + a.FE[node], Fy = L.gy + a.FE[N + node];
+  const double Fx = L.gx + acc_get(a.FE, node), Fy = L.gy + acc_get(a.FE, N + node);
   const double omega = 1.0 / L.tau, pre = 1.0 - 0.5 / L.tau;
   double Fhx, Fhy;
-  adj::collide_vjp(h, Fx, Fy, omega, pre, ah, a.Uh[node], a.Uh[N + node], hh, Fhx, Fhy);
+  adj::collide_vjp(h, Fx, Fy, omega, pre, ah, acc_get(a.Uh, node), acc_get(a.Uh, N + node), hh, Fhx,
+                   Fhy);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) a.fph[i * N + node] = hh[i];
   a.FEh[node] = Fhx;
@@ -178,24 +312,191 @@ __global__ void ka_collide(Ptrs<T> p, AdjPtrs a) {
   a.mom[2 * N + node] = (jy + 0.5 * L.gy) / rho;
   // this node's accumulators are consumed: clear them for the next step
   // (rho^*, u^* are filled by the body kernel that follows)
-  a.FE[node] = 0.0;
-  a.FE[N + node] = 0.0;
-  a.Uh[node] = 0.0;
-  a.Uh[N + node] = 0.0;
-  a.Rh[node] = 0.0;
-  a.Rh[N + node] = 0.0;
-  a.Rh[2 * N + node] = 0.0;
+  acc_clear(a.FE, node);
+  acc_clear(a.FE, N + node);
+  acc_clear(a.Uh, node);
+  acc_clear(a.Uh, N + node);
+  acc_clear(a.Rh, node);
+  acc_clear(a.Rh, N + node);
+  acc_clear(a.Rh, 2 * N + node);
 }
 
 // --------------------------------------------------------------- bodies
-// One workgroup per deformable body (red cells and soft particles).
+// Rigid particle (Sec. 2.3, Eqs. linearVelRig, angularVelRig), forward step:
+//   f_e = probe load + adhesion spring of element e at X^n;
+//   F_tot = sum f_e, M_tot = sum (c_e - x_c) x f_e;
+//   U', Omega' by BDF2 (forward Euler on the first step);
+//   x_c' = x_c + U', theta' = theta + Omega', X' = x_c' + R(theta') r0;
+//   F_k = 2 (U_k - U0_k) ds_k, U_k = U' + Omega' x (X'_k - x_c'),
+//   U0 = interp(u*, X^n), spread at X^n.
+// Its reverse: the adjoint of X' (per vertex) and of the state after the
+// step (rig) give those of the loads, of X^n (per vertex, out), of sigma and
+// of the state before the step (rig, out).  X^n itself was formed from the
+// state by the previous step, whose reverse maps its adjoint onto it.
+template <typename T>
+__device__ void rigid_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int b,
+                              double (*s_red)[kAdjThreads / 64]) {
+  const BodyDev* Bp = p.body + b;
+  const BodyDev& S0 = a.body0[b];   // state before the step
+  const BodyDev& S1 = a.body1[b];   // after it
+  const int nv = Bp->nv, v0 = Bp->v0;
+  const LatDev& L = p.lat[0];
+  const long long N = L.plane;
+  const double nu = (L.tau - 0.5) / 3.0, sigma = Bp->sigma;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const double* X = a.x + v0;
+  const double* Y = a.y + v0;
+  const double* mom = a.mom;
+  double* R = a.rig + 9 * b;
+  double rin[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) rin[k] = R[k];
+  const bool first = a.first != 0;
+
+  // ---- vertices: adjoint of the spread force F_k, through U_k to the
+  // state after the step, through U0 to u*, and of X^n by the spreading
+  // weights and by U0's interpolation weights
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // x_c'^ (2), theta'^, U'^ (2), Omega'^
+  for (int v = t; v < nv; v += nt) {
+    const int gm = v0 + v;
+    const int vp = v + 1 == nv ? 0 : v + 1, vm = v == 0 ? nv - 1 : v - 1;
+    const double lr = sqrt((X[vp] - X[v]) * (X[vp] - X[v]) + (Y[vp] - Y[v]) * (Y[vp] - Y[v]));
+    const double ll = sqrt((X[v] - X[vm]) * (X[v] - X[vm]) + (Y[v] - Y[vm]) * (Y[v] - Y[vm]));
+    const double ds = 0.5 * (ll + lr);
+    Stencil s;
+    stencil_at(L, X[v], Y[v], false, s);
+    const double Fx = a.fx[gm], Fy = a.fy[gm];
+    double fhx = 0.0, fhy = 0.0, gx = 0.0, gy = 0.0, U0x = 0.0, U0y = 0.0;
+    for (int bb = 0; bb < 3; ++bb) {
+      if (!s.ok[bb]) continue;
+      for (int c = 0; c < 3; ++c) {
+        const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
+        const double w = s.wx[c] * s.wy[bb];
+        const double ex_ = a.FEh[node], ey_ = a.FEh[N + node];
+        fhx += ex_ * w;
+        fhy += ey_ * w;
+        U0x += mom[N + node] * w;
+        U0y += mom[2 * N + node] * w;
+        const double sf = Fx * ex_ + Fy * ey_;
+        gx -= sf * s.dwx[c] * s.wy[bb];
+        gy -= sf * s.wx[c] * s.dwy[bb];
+      }
+    }
+    const double relx = a.xn[gm] - S1.xc, rely = a.yn[gm] - S1.yc;
+    const double Ukx = S1.U[0] + S1.Om * (-rely), Uky = S1.U[1] + S1.Om * relx;
+    const double dsh = 2.0 * ((Ukx - U0x) * fhx + (Uky - U0y) * fhy);
+    const double uhx = 2.0 * ds * fhx, uhy = 2.0 * ds * fhy;   // adjoint of U_k; U0 gets minus it
+    double g2x = 0.0, g2y = 0.0;
+    for (int bb = 0; bb < 3; ++bb) {
+      if (!s.ok[bb]) continue;
+      for (int c = 0; c < 3; ++c) {
+        const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
+        const double w = s.wx[c] * s.wy[bb];
+        acc_add(a.Rh, N + node, -uhx * w, a.bad);
+        acc_add(a.Rh, 2 * N + node, -uhy * w, a.bad);
+        const double uu = -uhx * mom[N + node] - uhy * mom[2 * N + node];
+        g2x -= uu * s.dwx[c] * s.wy[bb];
+        g2y -= uu * s.wx[c] * s.dwy[bb];
+      }
+    }
+    double ch[2] = {0.0, 0.0}, Uh[2] = {0.0, 0.0}, thh = 0.0, Omh = 0.0;
+    adj::rigid_vertex_vjp(relx, rely, S1.Om, a.xa[gm], a.ya[gm], uhx, uhy, ch, thh, Uh, Omh);
+    acc[0] += ch[0];
+    acc[1] += ch[1];
+    acc[2] += thh;
+    acc[3] += Uh[0];
+    acc[4] += Uh[1];
+    acc[5] += Omh;
+    a.dirx[gm] = a.dirx[gm] + gx + g2x;
+    a.diry[gm] = a.diry[gm] + gy + g2y;
+    a.dsh[gm] = dsh;
+  }
+  block_sum<6>(acc, s_red);   // barriers also publish the vertex pass
+
+  // ---- the state: x_c' = x_c + U', theta' = theta + Omega', BDF2
+  const double xch[2] = {rin[0] + acc[0], rin[1] + acc[1]};
+  const double thh = rin[2] + acc[2];
+  const double Uh1[2] = {rin[3] + acc[3] + xch[0], rin[4] + acc[4] + xch[1]};
+  const double Omh1 = rin[7] + acc[5] + thh;
+  double Uh0[2] = {rin[5], rin[6]}, Umh0[2] = {0.0, 0.0}, Omh0 = rin[8], Ommh0 = 0.0;
+  const double Fh[2] = {adj::bdf2_vjp(first, Bp->mass, Uh1[0], Uh0[0], Umh0[0]),
+                        adj::bdf2_vjp(first, Bp->mass, Uh1[1], Uh0[1], Umh0[1])};
+  const double Mh = adj::bdf2_vjp(first, Bp->inertia, Omh1, Omh0, Ommh0);
+
+  // ---- elements: loads into F_tot and M_tot (arms from x_c of the state
+  // before the step)
+  double arm[3] = {0.0, 0.0, 0.0};   // x_c^ (2) from the arms, sigma^
+  for (int l = t; l < nv; l += nt) {
+    const int gl = v0 + l;
+    const int lp = l + 1 == nv ? 0 : l + 1;
+    const double dx = X[lp] - X[l], dy = Y[lp] - Y[l];
+    const double len = sqrt(dx * dx + dy * dy);
+    const double cx = 0.5 * (X[l] + X[lp]), cy = 0.5 * (Y[l] + Y[lp]);
+    const double nxl = dy / len, nyl = -dx / len;
+    const double rx = cx - S0.xc, ry = cy - S0.yc;
+    // adjoint of f_e (it needs only the arm; the arm's needs f_e, below)
+    double Fex = 0.0, Fey = 0.0, rhx = 0.0, rhy = 0.0;
+    adj::rigid_load_vjp(rx, ry, 0.0, 0.0, Fh[0], Fh[1], Mh, Fex, Fey, rhx, rhy);
+    double Dhx = 0.0, Dhy = 0.0, Chx = 0.0, Chy = 0.0;
+    double lenh = 0.5 * (a.dsh[gl] + a.dsh[v0 + lp]);
+    double fex = 0.0, fey = 0.0;
+    double yl, ddx, ddy;
+    if (bond_geometry(p, L, Bp, l, cx, cy, yl, ddx, ddy)) {
+      adj::spring_fwd(dx, dy, yl, sigma, L.y_eq, fex, fey);
+      adj::spring_vjp(dx, dy, yl, ddx, ddy, sigma, L.y_eq, Fex, Fey, Dhx, Dhy, Chx, Chy, arm[2]);
+    }
+    double pfx, pfy, nhx = 0.0, nhy = 0.0;
+    probe_adjoint(L, a, cx, cy, nxl, nyl, len, nu, Fex, Fey, pfx, pfy, Chx, Chy, nhx, nhy, lenh);
+    fex += pfx;
+    fey += pfy;
+    // adjoint of the arm r = c - x_c: to the centroid and to x_c
+    double fdx = 0.0, fdy = 0.0;
+    adj::rigid_load_vjp(rx, ry, fex, fey, 0.0, 0.0, Mh, fdx, fdy, rhx, rhy);
+    Chx += rhx;
+    Chy += rhy;
+    arm[0] -= rhx;
+    arm[1] -= rhy;
+    adj::unit_vjp(dx, dy, -nhy, nhx, 0.0, Dhx, Dhy);
+    adj::unit_vjp(dx, dy, 0.0, 0.0, lenh, Dhx, Dhy);
+    a.Dx[gl] = Dhx;
+    a.Dy[gl] = Dhy;
+    a.Cx[gl] = Chx;
+    a.Cy[gl] = Chy;
+  }
+  block_sum<3>(arm, s_red);
+
+  // ---- vertices: gather the element terms into the adjoint of X^n
+  for (int v = t; v < nv; v += nt) {
+    const int gm = v0 + v;
+    const int vm = v == 0 ? nv - 1 : v - 1;
+    a.xa[gm] = a.dirx[gm] + a.Dx[v0 + vm] - a.Dx[gm] + 0.5 * (a.Cx[gm] + a.Cx[v0 + vm]);
+    a.ya[gm] = a.diry[gm] + a.Dy[v0 + vm] - a.Dy[gm] + 0.5 * (a.Cy[gm] + a.Cy[v0 + vm]);
+  }
+  if (t == 0) {
+    R[0] = xch[0] + arm[0];
+    R[1] = xch[1] + arm[1];
+    R[2] = thh;
+    R[3] = Uh0[0];
+    R[4] = Uh0[1];
+    R[5] = Umh0[0];
+    R[6] = Umh0[1];
+    R[7] = Omh0;
+    R[8] = Ommh0;
+    a.grad[3 * b + 2] += arm[2];
+  }
+}
+
+// One workgroup per body.
 template <typename T>
 __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
-  __shared__ double s_red[4][kAdjThreads / 64];
+  __shared__ double s_red[6][kAdjThreads / 64];
   const int b = blockIdx.x;
   const BodyDev* Bp = p.body + b;
   const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0;
-  if (kind == kRigid) return;   // refused by the host
+  if (kind == kRigid) {
+    rigid_adjoint(p, a, b, s_red);
+    return;
+  }
   const LatDev& L = p.lat[0];
   const long long N = L.plane;
   const bool pery = L.periodic_y != 0;
@@ -247,8 +548,8 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
           const double us = mom[N + node], vs = mom[2 * N + node];
           U0x += us * w;
           U0y += vs * w;
-          unsafeAtomicAdd(&a.Rh[N + node], xa * w);
-          unsafeAtomicAdd(&a.Rh[2 * N + node], ya * w);
+          acc_add(a.Rh, N + node, xa * w, a.bad);
+          acc_add(a.Rh, 2 * N + node, ya * w, a.bad);
           const double uu = xa * us + ya * vs;
           g2x -= uu * s.dwx[c] * s.wy[bb];
           g2y -= uu * s.wx[c] * s.dwy[bb];
@@ -268,9 +569,9 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
     a.dsh[gm] = dsh;
   }
   {
-    double v4[4] = {shoe, 0.0, 0.0, 0.0};
-    block_sum4(v4, s_red);   // barriers also publish phase A
-    shoe = v4[0];
+    double v1[1] = {shoe};
+    block_sum<1>(v1, s_red);   // barriers also publish phase A
+    shoe = v1[0];
   }
   const double area = 0.5 * shoe;
   const double kappa = ka * (1.0 - area / A0) * p_ref;
@@ -292,73 +593,11 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
       const double cx = 0.5 * (X[l] + X[lp]), cy = 0.5 * (Y[l] + Y[lp]);
       const double nxl = dy / len, nyl = -dx / len;
       // adhesion spring on a bonded ligand element
-      if (Bp->lig_stride > 0 && l % Bp->lig_stride == 0) {
-        const int r = p.l2r[Bp->lig_base + l / Bp->lig_stride];
-        if (r >= 0) {
-          const int wall = r < L.n_rec0 ? 0 : 1;
-          const double xr = p.rec_x[L.rec_base + r];
-          const double cxw = cx - L.nx * floor(cx / L.nx);
-          double ddx = xr - cxw;
-          if (ddx > 0.5 * L.nx) ddx -= L.nx;
-          else if (ddx < -0.5 * L.nx) ddx += L.nx;
-          const double yw = wall == 0 ? -0.5 : L.ny - 0.5;
-          const double ddy = cy - yw;
-          const double yl = sqrt(ddx * ddx + ddy * ddy);
-          adj::spring_vjp(dx, dy, yl, -ddx / yl, ddy / yl, sigma, L.y_eq, Fex, Fey, Dhx, Dhy, Chx,
-                          Chy, sigh);
-        }
-      }
-      // probe load at q = c + 1.2 n (ordinate clamped into the fluid)
-      const double qx = cx + 1.2 * nxl;
-      const double qy_raw = cy + 1.2 * nyl;
-      double qy = qy_raw;
-      bool clamped = false;
-      if (!pery) {
-        qy = fmin(fmax(qy_raw, 0.5), L.ny - 1.5);
-        clamped = qy != qy_raw;
-      }
-      Stencil s;
-      stencil_at(L, qx, qy, true, s);
-      double rq = 0.0, g[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int bb = 0; bb < 3; ++bb) {
-        if (!s.ok[bb]) continue;
-        for (int c = 0; c < 3; ++c) {
-          const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
-          const double w = s.wx[c] * s.wy[bb];
-          const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
-          rq += r0 * w;
-          g[0] -= us * s.dwx[c] * s.wy[bb];
-          g[1] -= us * s.wx[c] * s.dwy[bb];
-          g[2] -= vs * s.dwx[c] * s.wy[bb];
-          g[3] -= vs * s.wx[c] * s.dwy[bb];
-        }
-      }
-      const double pr = (rq - 1.0) * (1.0 / 3.0);
-      double prh = 0.0, gh[4] = {0.0, 0.0, 0.0, 0.0}, nhx = 0.0, nhy = 0.0;
-      adj::hydro_vjp(pr, g, nu, nxl, nyl, len, Fex, Fey, prh, gh, nhx, nhy, lenh);
-      const double rqh = prh * (1.0 / 3.0);
-      double qhx = 0.0, qhy = 0.0;
-      for (int bb = 0; bb < 3; ++bb) {
-        if (!s.ok[bb]) continue;
-        for (int c = 0; c < 3; ++c) {
-          const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
-          const double wx = s.wx[c], wy = s.wy[bb], dwx = s.dwx[c], dwy = s.dwy[bb];
-          const double ddwx = s.ddwx[c], ddwy = s.ddwy[bb];
-          const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
-          unsafeAtomicAdd(&a.Rh[node], rqh * wx * wy);
-          unsafeAtomicAdd(&a.Rh[N + node], -gh[0] * dwx * wy - gh[1] * wx * dwy);
-          unsafeAtomicAdd(&a.Rh[2 * N + node], -gh[2] * dwx * wy - gh[3] * wx * dwy);
-          qhx += -rqh * r0 * dwx * wy + gh[0] * us * ddwx * wy + gh[1] * us * dwx * dwy +
-                 gh[2] * vs * ddwx * wy + gh[3] * vs * dwx * dwy;
-          qhy += -rqh * r0 * wx * dwy + gh[0] * us * dwx * dwy + gh[1] * us * wx * ddwy +
-                 gh[2] * vs * dwx * dwy + gh[3] * vs * wx * ddwy;
-        }
-      }
-      if (clamped) qhy = 0.0;
-      Chx += qhx;
-      Chy += qhy;
-      nhx += 1.2 * qhx;
-      nhy += 1.2 * qhy;
+      double yl, ddx, ddy;
+      if (bond_geometry(p, L, Bp, l, cx, cy, yl, ddx, ddy))
+        adj::spring_vjp(dx, dy, yl, ddx, ddy, sigma, L.y_eq, Fex, Fey, Dhx, Dhy, Chx, Chy, sigh);
+      double pfx, pfy, nhx = 0.0, nhy = 0.0;
+      probe_adjoint(L, a, cx, cy, nxl, nyl, len, nu, Fex, Fey, pfx, pfy, Chx, Chy, nhx, nhy, lenh);
       // n = (t_y, -t_x)
       adj::unit_vjp(dx, dy, -nhy, nhx, 0.0, Dhx, Dhy);
     }
@@ -380,7 +619,7 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
     a.BRy[gl] = dRh[1];
   }
   double v4[4] = {ksh, kbh, sigh, kaph};
-  block_sum4(v4, s_red);
+  block_sum<4>(v4, s_red);
   const double Ah = -v4[3] * ka * p_ref / A0;
 
   // ---- phase D (vertices): gather element terms into the adjoint of X^n
@@ -430,7 +669,7 @@ __device__ inline void stream_adjoint(const Ptrs<T>& p, const AdjPtrs& a, long l
       src = (long long)ys * L.pitch + xs;
     }
     const double rho = a.mom[src], us = a.mom[N + src], vs = a.mom[2 * N + src];
-    const double rh = a.Rh[src], uh = a.Rh[N + src], vh = a.Rh[2 * N + src];
+    const double rh = acc_get(a.Rh, src), uh = acc_get(a.Rh, N + src), vh = acc_get(a.Rh, 2 * N + src);
     const double r = rh - (uh * us + vh * vs) / rho;
     a.ha[j * N + node] = a.fph[i * N + src] + r + (ex(i) * uh + ey(i) * vh) / rho;
   }

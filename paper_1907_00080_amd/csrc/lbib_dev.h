@@ -314,6 +314,16 @@ __device__ inline double philox_uniform(unsigned long long seed, long long step,
 // Pointers of one reverse step (single lattice instance).  Forward data of
 // step n come from the segment store; everything else is float64 adjoint
 // state or per-step scratch.
+// Scatter target of the adjoint: an exact accumulator per entry, the value
+// at k being hi[k] + lo[k] * 2^-64 (a 128-bit two's-complement fixed-point
+// number).  Integer addition is associative, so the sum does not depend on
+// the order in which contributions arrive: the reverse sweep is bitwise
+// reproducible.
+struct AccField {
+  long long* hi;
+  unsigned long long* lo;
+};
+
 struct AdjPtrs {
   const void* h;                      // h^n (T[9][N])
   const double *x, *y;                // X^n
@@ -324,9 +334,16 @@ struct AdjPtrs {
   double* ha;                         // [9][N] adjoint of h^{n+1} in, of h^n out
   double *xa, *ya;                    // adjoint of X^{n+1} in, of X^n out
   double *xma, *yma;                  // adjoint of X_prev^{n+1} in, of X_prev^n out
-  double *fph, *FE, *FEh, *mom, *Uh, *Rh;   // [9N] [2N] [2N] [3N] [2N] [3N]
+  double *fph, *FEh, *mom;            // [9N] [2N] [3N]
+  AccField FE, Uh, Rh;                // [2N] [2N] [3N] scatter targets
+  int* bad;                           // set by a scattered value that is not finite or
+                                      // beyond the accumulator's range (|v| >= 2^62)
   double *dirx, *diry, *fvx, *fvy, *dsh, *Dx, *Dy, *Cx, *Cy, *BLx, *BLy, *BRx, *BRy;  // [nm]
   double* grad;                       // [nbody][3]: d/dks, d/dkb, d/dsigma
+  const BodyDev *body0, *body1;       // bodies before and after step n (rigid state)
+  double* rig;                        // [nbody][9] adjoint of a rigid particle's state
+                                      // (x_c, y_c, theta, U, U_prev, Omega, Omega_prev):
+                                      // after step n in, before it out
 };
 
 // Up to 24 device-to-device copies in one launch (sizes multiple of 4 bytes).

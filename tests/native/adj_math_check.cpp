@@ -46,6 +46,31 @@ void t_hydro_vjp(double pr, const double* g, double nu, double nx, double ny, do
   for (int i = 0; i < 8; ++i) out[i] = 0.0;
   hydro_vjp(pr, g, nu, nx, ny, len, Fhx, Fhy, out[0], out + 1, out[5], out[6], out[7]);
 }
+void t_spring_fwd(double dx, double dy, double y, double sigma, double y_eq, double* F) {
+  spring_fwd(dx, dy, y, sigma, y_eq, F[0], F[1]);
+}
+void t_rigid_load_vjp(double rx, double ry, double fx, double fy, double Fhx, double Fhy, double Mh,
+                      double* out) {
+  for (int i = 0; i < 4; ++i) out[i] = 0.0;
+  rigid_load_vjp(rx, ry, fx, fy, Fhx, Fhy, Mh, out[0], out[1], out[2], out[3]);
+}
+double t_bdf2_vjp(int first, double m, double vh_new, double* out) {
+  out[0] = out[1] = 0.0;
+  return bdf2_vjp(first != 0, m, vh_new, out[0], out[1]);
+}
+void t_rigid_vertex_fwd(double r0x, double r0y, const double* s, double* out) {
+  rigid_vertex_fwd(r0x, r0y, s[0], s[1], s[2], s[3], s[4], s[5], out, out + 2);
+}
+void t_rigid_vertex_vjp(double relx, double rely, double Om, const double* xh, const double* uh,
+                        double* out) {
+  for (int i = 0; i < 6; ++i) out[i] = 0.0;
+  double ch[2] = {0.0, 0.0}, Uh[2] = {0.0, 0.0};
+  rigid_vertex_vjp(relx, rely, Om, xh[0], xh[1], uh[0], uh[1], ch, out[2], Uh, out[5]);
+  out[0] = ch[0];
+  out[1] = ch[1];
+  out[3] = Uh[0];
+  out[4] = Uh[1];
+}
 void t_area_vjp(double dx, double dy, double kappa, double Fhx, double Fhy, double* out) {
   out[0] = out[1] = 0.0;
   out[2] = area_vjp(dx, dy, kappa, Fhx, Fhy, out[0], out[1]);

@@ -38,10 +38,14 @@ def lib(tmp_path_factory):
            "t_strain_vjp": [d, d, d, d, d, d, D], "t_bend_fwd": [D, d, d, D],
            "t_bend_vjp": [D, d, d, D, D], "t_spring_vjp": [d, d, d, d, d, d, d, d, d, D],
            "t_hydro_fwd": [d, D, d, d, d, d, D], "t_hydro_vjp": [d, D, d, d, d, d, d, d, D],
-           "t_area_vjp": [d, d, d, d, d, D]}
+           "t_area_vjp": [d, d, d, d, d, D], "t_spring_fwd": [d, d, d, d, d, D],
+           "t_rigid_load_vjp": [d, d, d, d, d, d, d, D], "t_rigid_vertex_fwd": [d, d, D, D],
+           "t_rigid_vertex_vjp": [d, d, d, D, D, D]}
     for name, args in sig.items():
         getattr(L, name).argtypes = args
         getattr(L, name).restype = None
+    L.t_bdf2_vjp.argtypes = [ctypes.c_int, d, d, D]
+    L.t_bdf2_vjp.restype = ctypes.c_double
     return L
 
 
@@ -216,3 +220,73 @@ def test_hydro_vjp(lib, seed):
     lib.t_hydro_vjp(ctypes.c_double(pr), p(g), ctypes.c_double(nu), ctypes.c_double(n[0]),
                     ctypes.c_double(n[1]), ctypes.c_double(ln), a[0], a[1], p(out))
     fd_check(f, np.concatenate([[pr], g, n, [ln]]), a, out, h=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_spring_fwd(lib, seed):
+    """Eq. adhFor: sigma (y - y_eq) along the element's outward normal (d_y, -d_x)/|d|."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-1, 1, 2)
+    y, sigma, y_eq = rng.uniform(0.1, 1.0), rng.uniform(1e-3, 1e-2), 0.25
+    F = np.zeros(2)
+    lib.t_spring_fwd(d[0], d[1], y, sigma, y_eq, p(F))
+    n = np.array([d[1], -d[0]]) / np.hypot(*d)
+    np.testing.assert_allclose(F, sigma * (y - y_eq) * n, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_rigid_load_vjp(lib, seed):
+    """Summed load and torque of a rigid particle, F = f, M = r x f."""
+    rng = np.random.default_rng(seed)
+    r, f = rng.standard_normal(2), rng.standard_normal(2)
+
+    def fwd(z):
+        rr, ff = z[:2], z[2:]
+        return np.array([ff[0], ff[1], rr[0] * ff[1] - rr[1] * ff[0]])
+
+    a = rng.standard_normal(3)
+    out = np.zeros(4)
+    lib.t_rigid_load_vjp(r[0], r[1], f[0], f[1], a[0], a[1], a[2], p(out))
+    # out = (f^, r^); the forward's inputs are ordered (r, f)
+    fd_check(fwd, np.concatenate([r, f]), a, np.concatenate([out[2:], out[:2]]))
+
+
+@pytest.mark.parametrize("first", [0, 1])
+def test_bdf2_vjp(lib, first):
+    """Eqs. linearVelRig / angularVelRig: v' = 2/3 (2 v - v_prev/2 + r/m); v + r/m first."""
+    m = 3.7
+
+    def fwd(z):
+        v, vp, r = z
+        return np.array([v + r / m if first else (2.0 / 3.0) * (2.0 * v - 0.5 * vp + r / m)])
+
+    a = np.array([1.3])
+    out = np.zeros(2)
+    rh = lib.t_bdf2_vjp(first, m, a[0], p(out))
+    fd_check(fwd, np.array([0.2, -0.1, 0.05]), a, np.array([out[0], out[1], rh]))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_rigid_vertex_vjp(lib, seed):
+    """X' = x_c' + R(theta') r0, U_k = U' + Omega' x (X' - x_c')."""
+    rng = np.random.default_rng(seed)
+    r0 = rng.standard_normal(2) * 3.0
+    s = np.array([rng.uniform(0, 50), rng.uniform(0, 20), rng.uniform(-3, 3),
+                  1e-2 * rng.standard_normal(), 1e-2 * rng.standard_normal(), 1e-2 * rng.standard_normal()])
+
+    def fwd(z):
+        c, sn = np.cos(z[2]), np.sin(z[2])
+        rel = np.array([c * r0[0] - sn * r0[1], sn * r0[0] + c * r0[1]])
+        X = z[:2] + rel
+        U = z[3:5] + z[5] * np.array([-rel[1], rel[0]])
+        return np.concatenate([X, U])
+
+    got = np.zeros(4)
+    lib.t_rigid_vertex_fwd(r0[0], r0[1], p(s), p(got))
+    np.testing.assert_allclose(got, fwd(s), rtol=1e-13, atol=1e-13)
+    a = rng.standard_normal(4)
+    c, sn = np.cos(s[2]), np.sin(s[2])
+    rel = np.array([c * r0[0] - sn * r0[1], sn * r0[0] + c * r0[1]])
+    out = np.zeros(6)
+    lib.t_rigid_vertex_vjp(rel[0], rel[1], s[5], p(a[:2]), p(a[2:]), p(out))
+    fd_check(fwd, s, a, out)

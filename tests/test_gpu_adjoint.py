@@ -47,21 +47,24 @@ def oracle_J(wl, P, window):
 
 
 def entries(wl):
-    """(body, parameter) pairs that the window depends on."""
+    """(body, parameter) pairs that the window depends on (k_s and k_b do not
+    act on a rigid particle)."""
     out = []
     for b, body in enumerate(wl.bodies):
-        out.append((b, 0))
-        if body.kb > 0:
-            out.append((b, 1))
+        if body.kind != configs.PARTICLE_RIGID:
+            out.append((b, 0))
+            if body.kb > 0:
+                out.append((b, 1))
         if body.ligand_stride > 0:
             out.append((b, 2))
     return out
 
 
-def test_adjoint_matches_gpu_finite_differences_fp64():
-    wl = configs.adjoint_channel(nx=96, ny=32, seed_offset=6)
+@pytest.mark.parametrize("rigid", [False, True])
+def test_adjoint_matches_gpu_finite_differences_fp64(rigid):
+    wl = configs.adjoint_channel(nx=96, ny=32, seed_offset=6, rigid=rigid)
     W, k = 30, 7
-    announce(f"fp64 window {W} checkpoints every {k}, bodies {len(wl.bodies)}")
+    announce(f"fp64 window {W} checkpoints every {k}, {wl.name}")
     sim = pkg.Sim(wl, dtype="f64")
     sim.step(1)
     nb = int(np.sum(sim.bonds() >= 0))
@@ -85,12 +88,14 @@ def test_adjoint_matches_gpu_finite_differences_fp64():
         assert abs(g[b, q] - fd) <= 1e-5 * abs(fd) + 1e-12, (b, q, g[b, q], fd)
 
 
-def test_adjoint_fp32_window_200_matches_oracle_fd():
+@pytest.mark.parametrize("rigid", [False, True])
+def test_adjoint_fp32_window_200_matches_oracle_fd(rigid):
     """Float32 forward, float64 adjoint, 200 steps, against central
-    differences of the FP64 oracle at two steps (plateau), rel <= 1e-3."""
-    wl = configs.adjoint_channel()
+    differences of the FP64 oracle at two steps (plateau), rel <= 1e-3; the
+    particle soft or rigid (Eqs. linearVelRig, angularVelRig)."""
+    wl = configs.adjoint_channel(rigid=rigid)
     W, k = 200, 50
-    announce(f"fp32 window {W} vs oracle FD")
+    announce(f"fp32 window {W} vs oracle FD, {wl.name}")
     sim = pkg.Sim(wl, dtype="f32")
     sim.step(1)
     state = sim.get_state()
@@ -173,3 +178,35 @@ def test_window_objective_autograd():
     (3.0 * J2).backward()
     assert torch.allclose(P.grad, 3.0 * g1, rtol=1e-12, atol=0)
     assert float(torch.abs(g1).max()) > 0
+
+
+def test_adjoint_gradient_is_bitwise_reproducible():
+    """The scatter-form terms add into exact fixed-point accumulators, so the
+    gradient does not depend on the order of the atomics: two backward
+    passes of one context and one of a second context agree bit for bit
+    (red cell, soft and rigid particles in one channel)."""
+    wl = configs.adjoint_channel()
+    rig = configs.adjoint_channel(rigid=True, seed_offset=5)
+    # the rigid particle a quarter channel downstream of the soft one
+    xy = rig.bodies[-1].xy.copy()
+    xy[:, 0] = xy[:, 0] + 0.25 * wl.nx
+    wl.bodies.append(configs.Body(configs.PARTICLE_RIGID, xy, sigma=rig.bodies[-1].sigma,
+                                  ligand_stride=2))
+    W, k = 300, 50
+    announce(f"bitwise reproducibility, window {W}, bodies {len(wl.bodies)}")
+    out = []
+    for rep in range(2):
+        sim = pkg.Sim(wl, dtype="f32", graph_steps=100)
+        sim.step(1)
+        state = sim.get_state()
+        win = AdjointWindow(sim, W, k)
+        for _ in range(2 if rep == 0 else 1):
+            sim.set_state(state)
+            J, _ = win.forward()
+            out.append((J, win.backward(1.0).copy()))
+        sim.close()
+    J0, g0 = out[0]
+    assert np.abs(g0[:2]).max() > 0
+    for J, g in out[1:]:
+        assert J == J0
+        assert np.array_equal(g.view(np.uint64), g0.view(np.uint64)), (g, g0)

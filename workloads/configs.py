@@ -336,12 +336,13 @@ def sweep_instances(n_inst: int = 64, seed_offset: int = 4) -> List[Workload]:
 
 
 def adjoint_channel(nx: int = 256, ny: int = 64, seed_offset: int = 5, ks_particle: float = 0.02,
-                    sigma: float = 1e-3, n_rbc: int = 1) -> Workload:
+                    sigma: float = 1e-3, n_rbc: int = 1, rigid: bool = False) -> Workload:
     """Gradient window: the 256x64 channel with its seeded red cell, and the
-    1 um particle made soft (k_s = 0.02, E_b = 0.05) and released next to the
-    lower wall with its lowest vertex at a wall distance of y_cr / 2, so that
-    bonds form at the first step.  Adhesion in lattice units: y_cr = 0.5,
-    y_eq = 0.25, sigma = 1e-3, k_f0 dt = 0.5 (bonds form at once)."""
+    1 um particle made soft (k_s = 0.02, E_b = 0.05; or rigid) and released
+    next to the lower wall with its lowest vertex at a wall distance of
+    y_cr / 2, so that bonds form at the first step.  Adhesion in lattice
+    units: y_cr = 0.5, y_eq = 0.25, sigma = 1e-3, k_f0 dt = 0.5 (bonds form at
+    once)."""
     base = channel_256x64(seed_offset=1, with_particle=False)
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + seed_offset))
     scale = ny / base.ny
@@ -357,12 +358,15 @@ def adjoint_channel(nx: int = 256, ny: int = 64, seed_offset: int = 5, ks_partic
     x_c = float(bodies[0].xy[:, 0].mean() + 0.5 * nx) if bodies else rng.uniform(0, nx)
     y_c = -0.5 + 0.5 * y_cr - p0[:, 1].min()
     xy = geometry.place(p0, 0.0, [x_c % nx, y_c])
-    bodies.append(Body(PARTICLE_SOFT, xy, ks=ks_particle, kb=0.05 * ks_particle * r_p * r_p,
-                       sigma=sigma, ligand_stride=2))
+    if rigid:
+        bodies.append(Body(PARTICLE_RIGID, xy, sigma=sigma, ligand_stride=2))
+    else:
+        bodies.append(Body(PARTICLE_SOFT, xy, ks=ks_particle, kb=0.05 * ks_particle * r_p * r_p,
+                           sigma=sigma, ligand_stride=2))
     rho0, u0 = poiseuille_init(nx, ny, g, base.tau)
     adh = Adhesion(y_cr=y_cr, y_eq=0.5 * y_cr, kf0_dt=0.5, kr0_dt=0.5 / 8.5e3,
                    sigma_ts_frac=0.5, kbt=1e-3)
-    return Workload(f"adjoint-channel-{nx}x{ny}", nx, ny, base.tau, gx=g,
+    return Workload(f"adjoint-channel-{nx}x{ny}" + ("-rigid" if rigid else ""), nx, ny, base.tau, gx=g,
                     seed=SEED_BASE + seed_offset, bodies=bodies,
                     receptors=uniform_receptors(nx), adhesion=adh, rho0=rho0, u0=u0,
                     steps=2000, dtype="f32")

@@ -435,14 +435,15 @@ lbib_status lbib_get_kernel_timing(lbib_ctx* ctx, double* lattice_ms_avg, int64_
  *   dJ * dJ/dsigma of body b (all bodies of the context, host array).  The
  *   context is left at the end of the window.  The gradient is bitwise
  *   reproducible: the scatter-form terms (transposed interpolation, probe
- *   and spreading) add into exact 128-bit fixed-point accumulators, so their
- *   sums do not depend on the order of the atomics.
+ *   and spreading) add into exact fixed-point accumulators (two 64-bit
+ *   integer words, resolution 2^-72), so their sums do not depend on the
+ *   order of the atomics.
  * Errors: LBIB_ESTATE before finalize_setup, without a bound workspace or
  *   forward window; LBIB_EINVAL for batches, the vertex repulsion, velocity
  *   walls, the MLS transfer or bad sizes;
  *   LBIB_ENOSPACE for a workspace that is too small; LBIB_EUNSTABLE from
  *   lbib_adjoint_backward when a scattered term is not finite or of magnitude
- *   2^62 or more (grad is then left unwritten). */
+ *   2^30 or more (grad is then left unwritten). */
 lbib_status lbib_adjoint_workspace_query(const lbib_ctx* ctx, int64_t nsteps, int32_t ckpt_every,
                                          size_t* bytes);
 lbib_status lbib_adjoint_bind(lbib_ctx* ctx, void* dev_workspace, size_t bytes, int64_t nsteps,

@@ -945,7 +945,7 @@ AdjPtrs adj_ptrs(const lbib_ctx* c, const AdjLayout& A) {
   a.ha = (double*)(w + A.ha); a.fph = (double*)(w + A.fph);
   const size_t N = (size_t)c->nodes;
   auto acc = [&](size_t off, size_t n) {
-    return AccField{(long long*)(w + off), (unsigned long long*)(w + off + 8 * n)};
+    return AccField{(long long*)(w + off), (long long*)(w + off + 8 * n)};
   };
   a.FE = acc(A.FE, 2 * N); a.Uh = acc(A.Uh, 2 * N); a.Rh = acc(A.Rh, 3 * N);
   a.FEh = (double*)(w + A.FEh); a.mom = (double*)(w + A.mom);
@@ -1231,7 +1231,7 @@ lbib_status adjoint_backward_impl(lbib_ctx* c, double dJ, double* grad) {
   if (bad) {
     (void)set_freeze(c, c->inst[0].adh.freeze_topology);
     c->ktiming = kt;
-    return fail(c, LBIB_EUNSTABLE, "adjoint: a scattered term was not finite or beyond 2^62");
+    return fail(c, LBIB_EUNSTABLE, "adjoint: a scattered term was not finite or of magnitude 2^30 or more");
   }
   if (grad) std::memcpy(grad, g.data(), 8 * 3 * (size_t)c->nbody);
   st = set_freeze(c, c->inst[0].adh.freeze_topology);

@@ -24,10 +24,10 @@
 //
 // Scatter-form terms (the spreading of the stored marker forces, the
 // transpose of an interpolation or of a probe evaluation) add into dense
-// fields of exact 128-bit fixed-point accumulators (value = hi + lo 2^-64):
-// each contribution is rounded once to that grid and the sum is exact, so it
-// does not depend on the order of the atomics and the gradient is bitwise
-// reproducible from run to run.
+// fields of exact two-word fixed-point accumulators (value = hi 2^-24 +
+// lo 2^-72): each contribution is rounded once to the 2^-72 grid and the
+// sums are exact integer sums, so they do not depend on the order of the
+// atomics and the gradient is bitwise reproducible from run to run.
 #include "adj_math.h"
 #include "lbib_dev.h"
 
@@ -70,39 +70,33 @@ __device__ inline int wrap_idx(int i, int n) { return i < 0 ? i + n : (i >= n ? 
 
 constexpr int kAdjThreads = 256;
 
-// Adds v to the accumulator entry k.  |v| is split into its integer part and
-// its fraction scaled by 2^64 (both exact: the fraction of a double is a
-// multiple of its ulp), negated in two's complement for v < 0, and added
-// word by word; the carry out of the low word is read from the old value the
-// atomic returns.  The number of carries into the high word is fixed by the
-// total of the low words, so the 128-bit result is exact in any order.
+// Adds v to the accumulator entry k.  v is split into a coarse part, an
+// integer multiple of 2^-24 (v rounded to that grid, exact as a double),
+// and the exact remainder, |r| <= 2^-25, rounded to a multiple of 2^-72;
+// each part is added to its own 64-bit integer word.  Integer sums are
+// exact in any order; the atomics return nothing, so none waits.  Range: a
+// term of magnitude 2^30 or more (or not finite) is refused and flagged, so
+// the coarse word holds sums of up to 2^9 such terms and the fine word
+// (|r 2^72| <= 2^47 per term) of up to 2^16 terms without overflow.
 __device__ inline void acc_add(const AccField& f, long long k, double v, int* bad) {
-  const double m = fabs(v);
-  if (!(m < 0x1p62)) {   // also NaN
+  if (!(fabs(v) < 0x1p30)) {   // also NaN
     atomicOr(bad, 1);
     return;
   }
-  const double ip = floor(m);
-  unsigned long long lo = __double2ull_rn((m - ip) * 0x1p64);   // < 2^64: m - ip <= 1 - 2^-53
-  long long hi = (long long)ip;
-  if (v < 0.0) {
-    hi = -hi - (lo != 0ull ? 1 : 0);
-    lo = 0ull - lo;
-  }
-  if (lo != 0ull) {
-    const unsigned long long old = atomicAdd(&f.lo[k], lo);
-    hi += old + lo < old ? 1 : 0;
-  }
-  if (hi != 0) atomicAdd((unsigned long long*)&f.hi[k], (unsigned long long)hi);
+  const double c = rint(v * 0x1p24);       // integer valued, |c| < 2^54
+  const double r = v - c * 0x1p-24;        // exact
+  const long long hi = (long long)c, lo = __double2ll_rn(r * 0x1p72);
+  if (hi != 0) __hip_atomic_fetch_add(&f.hi[k], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lo != 0) __hip_atomic_fetch_add(&f.lo[k], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline double acc_get(const AccField& f, long long k) {
-  return double(f.hi[k]) + double(f.lo[k]) * 0x1p-64;
+  return double(f.hi[k]) * 0x1p-24 + double(f.lo[k]) * 0x1p-72;
 }
 
 __device__ inline void acc_clear(const AccField& f, long long k) {
   f.hi[k] = 0;
-  f.lo[k] = 0ull;
+  f.lo[k] = 0;
 }
 
 // Sums K values over the workgroup in a fixed order (butterfly within each

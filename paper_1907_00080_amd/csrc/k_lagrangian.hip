@@ -651,7 +651,8 @@ __device__ __forceinline__ void bonds_kinetics(Ptrs<T>& p, const LatDev& L, int 
           broken = u < P;
         }
         if (broken) {
-          p.l2r[gl[r]] = -1;
+          // atomic: body waves read the table while this runs
+          __hip_atomic_store(&p.l2r[gl[r]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           p.r2l[L.rec_base + rc] = -1;
         } else {
           p.lig_sp[gl[r]] = sig * dy;
@@ -745,7 +746,7 @@ __device__ __forceinline__ void bonds_kinetics(Ptrs<T>& p, const LatDev& L, int 
       const double u = philox_uniform(L.seed, n, l, 0, L.instance);
       ties += fabs(u - P) < 1e-12;
       if (u < P) {
-        p.l2r[gl] = roff + best;
+        __hip_atomic_store(&p.l2r[gl], roff + best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         p.r2l[L.rec_base + roff + best] = gl;
         p.lig_sp[gl] = sig * dy;
       }
@@ -1092,6 +1093,7 @@ __device__ __forceinline__ void rigid_step(const BodyDev* Bp, bool first, const 
 }
 
 __device__ __forceinline__ void rigid_commit(BodyDev* Bp, const double st[6]) {
+  Bp->stepped = 1;
   Bp->Um[0] = Bp->U[0];
   Bp->Um[1] = Bp->U[1];
   Bp->U[0] = st[0];
@@ -1148,6 +1150,12 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
   const double l0v = rigid ? 0.0 : p.l0[gm];
   const double th0v = rigid ? 0.0 : p.th0[gm];
   const double sv = rep && inner ? p.frep[gm] : 0.0;
+  // the ligand of element v and its bond table entry as this wave finds it:
+  // the bond workgroup rewrites the table while the wave runs (see below)
+  const int ls = particle ? Bp->lig_stride : 0;
+  const bool lig = has_elem && ls > 0 && v % ls == 0;
+  const int gl = lig ? Bp->lig_base + v / ls : 0;
+  const int r_seen = lig ? __hip_atomic_load(&p.l2r[gl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
   double area = 0.0;
   if (!rigid) area = body_area2(p.area_part, p.nchunk_total, ch0, nch) * 0.5;
 
@@ -1185,20 +1193,28 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
       uvy = uy;
     }
   }
-  // adhesion springs on bonded ligand elements (after this step's bond update)
-  bool first = false, spring_on = false;
+  // adhesion springs on bonded ligand elements (after this step's bond
+  // update).  A ligand element whose centroid lies farther than y_cr from
+  // both wall lines cannot form a bond in this step, and a bond broken in
+  // this step is not re-formed in it: if the entry the wave read is free,
+  // whether it was the entry before the update or after it, the element
+  // holds no bond after the update.  A chunk whose ligands are all such
+  // needs nothing from the bond workgroup and does not wait for it.
+  bool spring_on = false;
   double sp = 0.0;
   if (particle) {
-    wait_bonds(p, inst);
-    first = p.step_cur[inst] == 0;
-    const int ls = Bp->lig_stride;
-    if (has_elem && ls > 0 && v % ls == 0) {
-      const int gl = Bp->lig_base + v / ls;
-      const int r = p.l2r[gl];
-      sp = p.lig_sp[gl];   // sigma (y_l - y_eq), from the bond workgroup
-      spring_on = r >= 0;
+    const double dw = fmin(cy - L.y_wall_lo, L.y_wall_hi - cy);
+    const bool maybe = lig && (r_seen >= 0 || dw < L.y_cr + 0.25);
+    if (__ballot(maybe) != 0ull) {
+      wait_bonds(p, inst);
+      if (lig) {
+        const int r = p.l2r[gl];
+        sp = p.lig_sp[gl];   // sigma (y_l - y_eq), from the bond workgroup
+        spring_on = r >= 0;
+      }
     }
   }
+  const bool first = rigid && Bp->stepped == 0;
   const double ca = rigid ? 0.0 : Bp->ka * (1.0 - area / Bp->A0) * Bp->p_ref * len;
   double fex, fey;
   element_load(!rigid, ca, spring_on, sp, particle, pfx, pfy, enx, eny, fex, fey);
@@ -1592,11 +1608,8 @@ __device__ __forceinline__ void body_merged_impl(Ptrs<T>& p, int b, int cache_no
     __syncthreads();
   }
 
-  bool first = false;
-  if (kind != kRBC) {
-    wait_bonds(p, inst);
-    first = p.step_cur[inst] == 0;
-  }
+  const bool first = kind == kRigid && Bp->stepped == 0;
+  if (kind != kRBC) wait_bonds(p, inst);
 
   // A particle of at most nt/2 vertices: the upper half of the lanes (other
   // waves, so other SIMDs) interpolates the fluid velocity at the vertices

@@ -85,6 +85,7 @@ struct BodyDev {
   int kind, nv, v0, inst;   // v0: global index of vertex 0
   int lig_base, n_lig, lig_stride;
   int chunk0;               // global index of the body's first vertex chunk
+  int stepped;              // rigid: 1 once the body has taken a step (BDF2 has a history)
   double ks, kb, ka, p_ref;
   double A0, mass, mv, inertia, sigma;
   double xc, yc, theta;     // rigid: reference point and angle
@@ -315,13 +316,13 @@ __device__ inline double philox_uniform(unsigned long long seed, long long step,
 // step n come from the segment store; everything else is float64 adjoint
 // state or per-step scratch.
 // Scatter target of the adjoint: an exact accumulator per entry, the value
-// at k being hi[k] + lo[k] * 2^-64 (a 128-bit two's-complement fixed-point
-// number).  Integer addition is associative, so the sum does not depend on
-// the order in which contributions arrive: the reverse sweep is bitwise
-// reproducible.
+// at k being hi[k] 2^-24 + lo[k] 2^-72 (two signed 64-bit integer words, a
+// coarse and a fine part of every term).  Integer addition is associative,
+// so the sums do not depend on the order in which contributions arrive: the
+// reverse sweep is bitwise reproducible.
 struct AccField {
   long long* hi;
-  unsigned long long* lo;
+  long long* lo;
 };
 
 struct AdjPtrs {
@@ -337,7 +338,7 @@ struct AdjPtrs {
   double *fph, *FEh, *mom;            // [9N] [2N] [3N]
   AccField FE, Uh, Rh;                // [2N] [2N] [3N] scatter targets
   int* bad;                           // set by a scattered value that is not finite or
-                                      // beyond the accumulator's range (|v| >= 2^62)
+                                      // beyond the accumulator's range (|v| >= 2^30)
   double *dirx, *diry, *fvx, *fvy, *dsh, *Dx, *Dy, *Cx, *Cy, *BLx, *BLy, *BRx, *BRy;  // [nm]
   double* grad;                       // [nbody][3]: d/dks, d/dkb, d/dsigma
   const BodyDev *body0, *body1;       // bodies before and after step n (rigid state)

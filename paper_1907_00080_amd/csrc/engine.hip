@@ -65,7 +65,7 @@ struct Layout {
   size_t cnt[2], bins[2], touched, overflow, fmax, bond_flag, step_slot, spin, Uspare, tile_inst;
   size_t lig_body, lig_elem, l2r, r2l, lig_flag, rec_x, lig_va, lig_vb, lig_sigma, lig_sp;
   size_t step_next, step_cur, ties, red;
-  size_t chunk_body, area_part, rig_part, body_cnt, star, pbox, star_wg, slot_chunk;
+  size_t chunk_info, area_part, rig_part, body_cnt, star, pbox, star_wg, slot_chunk;
   size_t total;
 };
 
@@ -262,7 +262,7 @@ void compute_layout(lbib_ctx* c) {
   L.ties = take(8 * c->ninst);
   L.red = take(8 * (6 * 1024 + 64));
   const size_t nch = (size_t)std::max(c->nchunk, 1);
-  L.chunk_body = take(4 * nch);
+  L.chunk_info = take(16 * nch);
   L.area_part = take(8 * 5 * nch);
   L.rig_part = take(8 * 3 * nch);
   L.body_cnt = take(4 * (size_t)std::max(c->nbody, 1));
@@ -331,7 +331,7 @@ Ptrs<T> make_ptrs(const lbib_ctx* c) {
   p.step_cur = (long long*)(w + L.step_cur);
   p.ties = (unsigned long long*)(w + L.ties);
   p.red = (double*)(w + L.red);
-  p.chunk_body = (int*)(w + L.chunk_body);
+  p.chunk_info = (const int4*)(w + L.chunk_info);
   p.area_part = (double*)(w + L.area_part);
   p.rig_part = (double*)(w + L.rig_part);
   p.body_cnt = (int*)(w + L.body_cnt);
@@ -435,7 +435,7 @@ lbib_status upload_all(lbib_ctx* c) {
   std::vector<int> lig_va(std::max(c->nlig, 1)), lig_vb(std::max(c->nlig, 1));
   std::vector<double> lig_sigma(std::max(c->nlig, 1), 0.0);
   std::vector<double> rec_x(std::max(c->nrec, 1));
-  std::vector<int> chunk_body(std::max(c->nchunk, 1), 0);
+  std::vector<int> chunk_info(4 * (size_t)std::max(c->nchunk, 1), 0);
   int bi = 0, li = 0, ci = 0;
   for (int i = 0; i < c->ninst; ++i) {
     InstHost& I = c->inst[i];
@@ -478,7 +478,13 @@ lbib_status upload_all(lbib_ctx* c) {
       B.lig_stride = b.d.ligand_stride;
       B.lig_base = D.lig_base + nl;
       B.chunk0 = ci;
-      for (int k = 0; k < chunks_of(b.d.nv); ++k) chunk_body[ci++] = bi;
+      for (int k = 0; k < chunks_of(b.d.nv); ++k, ++ci) {
+        const int first = k * kChunk;
+        chunk_info[4 * ci] = bi;
+        chunk_info[4 * ci + 1] = m + first - 2;
+        chunk_info[4 * ci + 2] = std::min(kChunk, b.d.nv - first);
+        chunk_info[4 * ci + 3] = b.d.kind | (i << 2);
+      }
       std::vector<double> bl0, bth0;
       double A0;
       rest_state(b.xy, b.d.nv, bl0, bth0, A0);
@@ -559,12 +565,13 @@ lbib_status upload_all(lbib_ctx* c) {
     if (!chunks.empty()) HIPCHK(c, up(L.rep_chunk, chunks.data(), 4 * chunks.size()));
   }
   HIPCHK(c, up(L.minfo, minfo.data(), 4 * nm));
-  HIPCHK(c, up(L.chunk_body, chunk_body.data(), 4 * chunk_body.size()));
-  HIPCHK(c, hipMemsetAsync(w + L.area_part, 0, 8 * 5 * chunk_body.size(), s));
-  HIPCHK(c, hipMemsetAsync(w + L.rig_part, 0, 8 * 3 * chunk_body.size(), s));
+  const size_t nchk = chunk_info.size() / 4;
+  HIPCHK(c, up(L.chunk_info, chunk_info.data(), 4 * chunk_info.size()));
+  HIPCHK(c, hipMemsetAsync(w + L.area_part, 0, 8 * 5 * nchk, s));
+  HIPCHK(c, hipMemsetAsync(w + L.rig_part, 0, 8 * 3 * nchk, s));
   HIPCHK(c, hipMemsetAsync(w + L.body_cnt, 0, 4 * (size_t)std::max(c->nbody, 1), s));
   HIPCHK(c, hipMemsetAsync(w + L.star, 0, (size_t)elem_size(c->dtype) * 4 * c->nodes, s));
-  HIPCHK(c, hipMemsetAsync(w + L.pbox, 0, 4 * 4 * chunk_body.size(), s));
+  HIPCHK(c, hipMemsetAsync(w + L.pbox, 0, 4 * 4 * nchk, s));
   {
     // star work list: (body, rank, workgroups of the body) per workgroup
     std::vector<int> sw;

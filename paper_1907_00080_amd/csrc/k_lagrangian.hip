@@ -356,8 +356,10 @@ struct BinSlots {
 template <int TX, int TY, int R>
 __device__ inline void bins_reserve(int* cnt, const LatDev& L, const int* cx, const int* cy,
                                     const bool* active, BinSlots<R>& S) {
+  // lattice fields in registers: read inside the loop below, the compiler
+  // reloads them (and waits for them) at every slot
   const bool pery = L.periodic_y != 0;
-  const int nx = L.nx, ny = L.ny;
+  const int nx = L.nx, ny = L.ny, tile_base = L.tile_base, ntx = L.ntx;
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int gcount[R][9];
@@ -399,7 +401,7 @@ __device__ inline void bins_reserve(int* cnt, const LatDev& L, const int* cx, co
     for (int s9 = 0; s9 < 9; ++s9) {
       const int i = s9 / 3, j = s9 % 3;
       const bool has = vr[i] && vc[j];
-      const int k = has ? L.tile_base + tr[i] * L.ntx + tc[j] : -1;
+      const int k = has ? tile_base + tr[i] * ntx + tc[j] : -1;
       key[r][s9] = k;
       leader[r][s9] = lane;
       rank[r][s9] = 0;
@@ -431,21 +433,33 @@ __device__ inline void bins_reserve(int* cnt, const LatDev& L, const int* cx, co
 }
 
 // 3. positions and stores
+//    (every slot's position first, then the stores: a store issued between
+//    two of the reads would be waited for by the next one)
 template <int R>
 __device__ inline void bins_commit(int* bin, int cap, int* overflow, const int* gm, const BinSlots<R>& S) {
   const unsigned used = S.used;
+  int pos[R][9];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s9 = 0; s9 < 9; ++s9)
+      pos[r][s9] = (used >> (r * 9 + s9) & 1u) ? __shfl(S.base[r][s9], S.leader[r][s9]) + S.rank[r][s9] : 0;
+  int dropped = 0;
+  int* dst[R][9];
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int s9 = 0; s9 < 9; ++s9) {
-      if (!(used >> (r * 9 + s9) & 1u)) continue;
-      const int b = __shfl(S.base[r][s9], S.leader[r][s9]);
-      if (S.key[r][s9] >= 0) {
-        const int pos = b + S.rank[r][s9];
-        if (pos < cap) bin[(long long)S.key[r][s9] * cap + pos] = gm[r];
-        else atomicAdd(overflow, 1);
-      }
+      const bool on = (used >> (r * 9 + s9) & 1u) && S.key[r][s9] >= 0;
+      dropped += on && pos[r][s9] >= cap;
+      dst[r][s9] = on && pos[r][s9] < cap ? bin + (long long)S.key[r][s9] * cap + pos[r][s9] : nullptr;
     }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s9 = 0; s9 < 9; ++s9)
+      if (dst[r][s9]) *dst[r][s9] = gm[r];
+  if (dropped) atomicAdd(overflow, dropped);
 }
 
 template <int TX, int TY, int R>
@@ -470,6 +484,14 @@ __device__ inline void register_marker(int* cnt, int* bin, int cap, int* overflo
 // can be recognised) and the weights of its 3x3 nodes: the Roma kernel
 // along each axis (zero for rows beyond the walls), or the MLS shape
 // functions.
+// Stencil centre node of a marker at (X, Y), as marker_stencil stores it.
+__device__ inline void stencil_centre(const LatDev& L, double X, double Y, int& ocx, int& ocy) {
+  const bool pery = L.periodic_y != 0;
+  const double cxr = floor(X + 0.5), cyr = floor(Y + 0.5);
+  ocx = wrap_i((int)cxr, L.nx);
+  ocy = pery ? wrap_i((int)cyr, L.ny) : (int)fmin(fmax(cyr, -4.0), (double)(L.ny + 3));
+}
+
 template <bool MLS = true, typename T>
 __device__ inline void marker_stencil(const Ptrs<T>& p, const LatDev& L, int gm, double X, double Y,
                                       int& ocx, int& ocy) {
@@ -761,7 +783,7 @@ __device__ __forceinline__ void bonds_kinetics(Ptrs<T>& p, const LatDev& L, int 
 template <typename T>
 __device__ __forceinline__ void bonds_impl(Ptrs<T>& p, int inst, int* s_tmp, int* s_nelig_p) {
   int& s_nelig = *s_nelig_p;
-  const LatDev& L = p.lat[inst];
+  const LatDev L = p.lat[inst];
   const int tid = threadIdx.x, nt = blockDim.x;
   const long long n = p.step_next[inst];
   __syncthreads();
@@ -821,11 +843,14 @@ __device__ inline void put_box(int* pbox, int chunk, const IBox& q) {
 // and the particle's workgroup count; src holds the populations the next
 // step streams from.  Nodes of overlapping boxes are written twice with the
 // same values.
+// The kernels below copy their instance's lattice record into registers
+// before their first store: read through a reference, its fields are
+// reloaded (and waited for) after every store, which may alias them.
 template <typename T>
 __device__ inline void star_pass(Ptrs<T>& p, const T* src, int w) {
   const int b = p.star_wg[3 * w], rank = p.star_wg[3 * w + 1], K = p.star_wg[3 * w + 2];
   const BodyDev& B = p.body[b];
-  const LatDev& L = p.lat[B.inst];
+  const LatDev L = p.lat[B.inst];
   const int nch = chunks_of(B.nv);
   int x0 = 0x7fffffff, x1 = -0x7fffffff, y0 = 0x7fffffff, y1 = -0x7fffffff;
   for (int k = 0; k < nch; ++k) {
@@ -1135,26 +1160,31 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
   // rigid body whose chunks share this workgroup (it takes part in the sums)
   const bool idle = code < 0;
   const int chunk = idle ? -1 : code;
+  // the body record in registers, read before any store (the rigid step
+  // writes the record back through Bp)
   BodyDev* Bp = p.body + b;
-  const int kind = Bp->kind, nv = Bp->nv, v0 = Bp->v0, inst = Bp->inst, ch0 = Bp->chunk0;
+  const BodyDev B = *Bp;
+  const int kind = B.kind, nv = B.nv, v0 = B.v0, inst = B.inst, ch0 = B.chunk0;
   const int nch = chunks_of(nv);
   const int first_v = idle ? 0 : (chunk - ch0) * kChunk, cnt = idle ? 0 : min(kChunk, nv - first_v);
   const int v = chunk_vertex(lane, first_v, nv), gm = v0 + v;
   const bool inner = lane >= 2 && lane < 2 + cnt;     // the chunk's own vertices
   const bool has_elem = lane >= 1 && lane < 2 + cnt;  // elements v -> v+1 they touch
-  const LatDev& L = p.lat[inst];
+  const LatDev L = p.lat[inst];
   const T* S = p.star + 4 * L.node_base;   // rho*, u* over the particles' boxes
   const bool rigid = kind == kRigid, particle = kind != kRBC;
   const bool rep = L.rep_coeff > 0.0;
   const double X = p.x[gm], Y = p.y[gm];
+  // a rigid vertex's reference offset, for its move after the rigid step
+  const double r0xv = rigid && inner ? p.r0x[gm] : 0.0, r0yv = rigid && inner ? p.r0y[gm] : 0.0;
   const double l0v = rigid ? 0.0 : p.l0[gm];
   const double th0v = rigid ? 0.0 : p.th0[gm];
   const double sv = rep && inner ? p.frep[gm] : 0.0;
   // the ligand of element v and its bond table entry as this wave finds it:
   // the bond workgroup rewrites the table while the wave runs (see below)
-  const int ls = particle ? Bp->lig_stride : 0;
+  const int ls = particle ? B.lig_stride : 0;
   const bool lig = has_elem && ls > 0 && v % ls == 0;
-  const int gl = lig ? Bp->lig_base + v / ls : 0;
+  const int gl = lig ? B.lig_base + v / ls : 0;
   const int r_seen = lig ? __hip_atomic_load(&p.l2r[gl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
   double area = 0.0;
   if (!rigid) area = body_area2(p.area_part, p.nchunk_total, ch0, nch) * 0.5;
@@ -1167,7 +1197,7 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
   const double txl = __shfl_up(tx, 1), tyl = __shfl_up(ty, 1);
   double bnx = 0.0, bny = 0.0, bc = 0.0;
   if (!rigid || rep) vertex_normal(txl, tyl, tx, ty, bnx, bny);
-  if (!rigid) bc = bend_coeff(txl, tyl, tx, ty, Bp->kb, th0v);
+  if (!rigid) bc = bend_coeff(txl, tyl, tx, ty, B.kb, th0v);
 
   // particles: probe load of the element and fluid velocity u* at the vertex,
   // from the star field of the particle's box
@@ -1214,8 +1244,8 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
       }
     }
   }
-  const bool first = rigid && Bp->stepped == 0;
-  const double ca = rigid ? 0.0 : Bp->ka * (1.0 - area / Bp->A0) * Bp->p_ref * len;
+  const bool first = rigid && B.stepped == 0;
+  const double ca = rigid ? 0.0 : B.ka * (1.0 - area / B.A0) * B.p_ref * len;
   double fex, fey;
   element_load(!rigid, ca, spring_on, sp, particle, pfx, pfy, enx, eny, fex, fey);
   const double len_m = __shfl_up(len, 1);
@@ -1223,7 +1253,7 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
 
   double fm = 0.0;
   if (rigid) {
-    const double xc0 = Bp->xc, yc0 = Bp->yc;
+    const double xc0 = B.xc, yc0 = B.yc;
     double t3[3] = {0.0, 0.0, 0.0};
     if (inner) {
       rigid_terms(fex, fey, cx - xc0, cy - yc0, rep, -sv * bnx, -sv * bny, X - xc0, Y - yc0, t3);
@@ -1244,12 +1274,12 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
       double r3[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) r3[k] = chunk_total(s_rp[k], nch);
-      rigid_step(Bp, first, r3, st);
+      rigid_step(&B, first, r3, st);
       __syncthreads();   // every wave has read the rigid state
       if (threadIdx.x == 0) rigid_commit(Bp, st);
       const double cs = cos(st[5]), sn = sin(st[5]);
       if (inner) {
-        rigid_vertex(p.r0x[gm], p.r0y[gm], st, cs, sn, uvx, uvy, ds, xn, yn, fx, fy);
+        rigid_vertex(r0xv, r0yv, st, cs, sn, uvx, uvy, ds, xn, yn, fx, fy);
         p.xn[gm] = xn;
         p.yn[gm] = yn;
         p.fx[gm] = fx;
@@ -1282,7 +1312,7 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
       double r3[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) r3[k] = chunk_total(p.rig_part + k * nct + ch0, nch);
-      rigid_step(Bp, first, r3, st);
+      rigid_step(&B, first, r3, st);
       if (lane == 0) rigid_commit(Bp, st);
       const double cs = cos(st[5]), sn = sin(st[5]);
       IBox q{0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff};
@@ -1354,14 +1384,14 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
   double sxn = 0.0, syn = 0.0, ffx, ffy;   // a soft particle's new position
   if (inner) {
     double fx, fy;
-    membrane_force(q, Bp->ks, l0v, l0m, rep, sv, fx, fy);
+    membrane_force(q, B.ks, l0v, l0m, rep, sv, fx, fy);
     if (rep) p.frep[gm] = 0.0;   // applied: the next step's repulsion kernel rewrites it
     if (kind == kRBC) {
       p.fx[gm] = fx;
       p.fy[gm] = fy;
       fm = fmax_nan(fabs(fx), fabs(fy));
     } else {
-      soft_vertex(X, Y, uvx, uvy, fx, fy, Bp->mv, ds, sxn, syn, ffx, ffy);
+      soft_vertex(X, Y, uvx, uvy, fx, fy, B.mv, ds, sxn, syn, ffx, ffy);
       p.xn[gm] = sxn;
       p.yn[gm] = syn;
       p.fx[gm] = ffx;
@@ -1415,7 +1445,7 @@ __device__ __forceinline__ void body_merged_impl(Ptrs<T>& p, int b, int cache_no
   const double ks = Bp->ks, kb = Bp->kb, ka = Bp->ka, p_ref = Bp->p_ref, A0 = Bp->A0;
   const double mv = Bp->mv, sigma = Bp->sigma;
   const int lig_stride = Bp->lig_stride, lig_base = Bp->lig_base;
-  const LatDev& L = p.lat[inst];
+  const LatDev L = p.lat[inst];
   const int t = threadIdx.x, nt = kBodyThreads;   // the launch's block size
   const T* A = p.A + 9 * L.node_base;
   const double nu = (L.tau - 0.5) / 3.0;
@@ -1838,13 +1868,12 @@ __device__ __forceinline__ void advance_chunk(Ptrs<T>& p, int* cnt, int* bin) {
   const int lane = threadIdx.x & 63;
   const int chunk = blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (chunk >= p.nchunk_total) return;   // the whole wave
-  const int b = p.chunk_body[chunk];
-  const BodyDev& B = p.body[b];
-  const int kind = B.kind, nv = B.nv, inst = B.inst;
-  const int first_v = (chunk - B.chunk0) * kChunk, cnt_v = min(kChunk, nv - first_v);
-  const int gm = B.v0 + chunk_vertex(lane, first_v, nv);
+  // one load gives the wave its vertices (the body record is not needed)
+  const int4 ci = p.chunk_info[chunk];
+  const int kind = ci.w & 3, inst = ci.w >> 2, cnt_v = ci.z;
   const bool inner = lane >= 2 && lane < 2 + cnt_v;
-  const LatDev& L = p.lat[inst];
+  const int gm = inner ? ci.y + lane : 0;
+  const LatDev L = p.lat[inst];
   double X = 0.0, Y = 0.0, xn = 0.0, yn = 0.0;
   int ncx = 0, ncy = 0;
   if (inner) {
@@ -1860,6 +1889,13 @@ __device__ __forceinline__ void advance_chunk(Ptrs<T>& p, int* cnt, int* bin) {
         yn = p.yn[gm];
       }
     }
+    stencil_centre(L, xn, yn, ncx, ncy);
+  }
+  // bin slots for the new stencil: the reservations (atomics) go out first
+  // and the stores below are issued while they are in flight
+  BinSlots<1> S;
+  bins_reserve<TX, TY, 1>(cnt, L, &ncx, &ncy, &inner, S);
+  if (inner) {
     if (ADVANCE) {
       p.xm[gm] = X;
       p.ym[gm] = Y;
@@ -1870,7 +1906,6 @@ __device__ __forceinline__ void advance_chunk(Ptrs<T>& p, int* cnt, int* bin) {
     // interpolation (this lane has finished reading the old one)
     marker_stencil<MLS>(p, L, gm, xn, yn, ncx, ncy);
   }
-  register_marker<TX, TY>(cnt, bin, p.bin_cap, p.overflow, L, gm, ncx, ncy, inner);
   const double xr = __shfl_down(xn, 1), yr = __shfl_down(yn, 1);
   const double part = wave_sum(lane >= 2 && lane < 1 + cnt_v ? shoelace_term(xn, yn, xr, yr) : 0.0);
   const int nct = p.nchunk_total;
@@ -1889,6 +1924,7 @@ __device__ __forceinline__ void advance_chunk(Ptrs<T>& p, int* cnt, int* bin) {
     const IBox q = wave_box(xn, yn, inner);
     if (lane == 0) put_box(p.pbox, chunk, q);
   }
+  bins_commit<1>(bin, p.bin_cap, p.overflow, &gm, S);
 }
 
 inline __host__ __device__ int chunk_blocks(int nchunk) { return (nchunk + kWaves - 1) / kWaves; }

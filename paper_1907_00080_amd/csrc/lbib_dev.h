@@ -170,7 +170,9 @@ struct Ptrs {
   double* rec_x;
   long long *step_next, *step_cur;   // per instance
   // vertex chunks (kChunk consecutive vertices of one body, one wave each)
-  int* chunk_body;                    // per chunk: its body
+  const int4* chunk_info;             // per chunk: body, global index of its first
+                                      // vertex minus 2 (the marker of lane 0),
+                                      // vertex count, kind | instance << 2
   // waves of the chunked body kernel: (chunk, body) each one takes (chunk
   // -1: none; -2: an idle wave in the workgroup of a rigid body whose
   // chunks, at most four, share one workgroup so that its force and torque

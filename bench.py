@@ -141,11 +141,13 @@ def cpu_baseline_sweep(n_inst: int, budget_s: float = 20.0) -> dict:
                       f"all processes / longest stepping time"}
 
 
-def traffic_from_profile(workload_name: str, tile=None, hints=None):
+def traffic_from_profile(workload_name: str, tile=None, hints=None, launch=0):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), if
     it was taken with the current kernel source and (when given) the same tile
-    shape and cache hints; else None."""
+    shape and cache hints, for the one-workgroup-per-tile launch; else None."""
+    if launch:
+        return None
     try:
         with open(PROFILE_TRAFFIC) as f:
             rec = json.load(f)
@@ -165,18 +167,21 @@ def tuned_config(pkg, wl, args):
     steps of this workload timed for every tile and step form), or the tile
     given on the command line with the default step form."""
     if args.tile != "auto":
-        return tuple(int(v) for v in args.tile.split("x")), args.step_mode, args.hints, None
+        return tuple(int(v) for v in args.tile.split("x")), args.step_mode, args.hints, args.launch, None
     from paper_1907_00080_amd import tune
     rec = tune.autotune([wl], dtype="f32", device="cuda:0", steps=200, warmup=20,
                         graph_steps=(args.graph_steps,))
     tile = tuple(rec["tile"])
+    launch = int(rec.get("lattice_launch", 0))
     print(f"bench: {wl.name} tuned: tile {tile[0]}x{tile[1]}, step mode {rec['step_mode']}, "
-          f"cache hints {rec['cache_hints']} ({len(rec['candidates'])} candidates)",
+          f"cache hints {rec['cache_hints']}, lattice launch {launch} "
+          f"({len(rec['candidates'])} + {len(rec.get('launch_candidates', []))} candidates)",
           file=sys.stderr, flush=True)
     cands = [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "step_mode": c["step_mode"],
-              "cache_hints": c["cache_hints"], "us_per_step": round(c["ms_per_step"] * 1e3, 2)}
-             for c in rec["candidates"]]
-    return tile, rec["step_mode"], rec["cache_hints"], cands
+              "cache_hints": c["cache_hints"], "lattice_launch": int(c.get("lattice_launch", 0)),
+              "us_per_step": round(c["ms_per_step"] * 1e3, 2)}
+             for c in list(rec["candidates"]) + list(rec.get("launch_candidates", []))[1:]]
+    return tile, rec["step_mode"], rec["cache_hints"], launch, cands
 
 
 def main():
@@ -193,6 +198,9 @@ def main():
                     help="TXxTY, or auto: tile, step form and cache hints from the autotuner")
     ap.add_argument("--step-mode", type=int, default=None,
                     help="with a fixed --tile: step form (1 three kernels, 2 merged, 3 overlapped)")
+    ap.add_argument("--launch", type=int, default=0,
+                    help="lattice-kernel launch with a fixed --tile: 0 one workgroup per tile, "
+                         "1/2/4/8 persistent workgroups per CU")
     ap.add_argument("--hints", type=int, default=None,
                     help="with a fixed --tile: cache hints of the lattice kernel (0, 1 or 3)")
     ap.add_argument("--side-workload", default="capillary-2000x200",
@@ -241,9 +249,9 @@ def main():
     import paper_1907_00080_amd as pkg
 
     wl = make_workload(args.workload)
-    tile, mode, hints, cands = tuned_config(pkg, wl, args)
+    tile, mode, hints, launch, cands = tuned_config(pkg, wl, args)
     res = run_workload(pkg, torch, wl, tile, args.steps, args.warmup, args.graph_steps,
-                       args.kernel_steps, mode, hints, windows=args.windows)
+                       args.kernel_steps, mode, hints, windows=args.windows, lattice_launch=launch)
     roof = roofline(res, wl, tile)
 
     out = {
@@ -264,6 +272,7 @@ def main():
                    "particles": sum(b.kind != 0 for b in wl.bodies),
                    "markers": wl.n_markers, "tile": f"{tile[0]}x{tile[1]}",
                    "step_mode": res["step_mode"], "cache_hints": res["cache_hints"],
+                   "lattice_launch": res["lattice_launch"],
                    "graph_steps": res["graph_steps"], "plain_steps": res["plain_steps"],
                    "graph_prime_steps": res["prime_steps"], "tuned": cands is not None},
         "windows": res["windows"],
@@ -277,9 +286,10 @@ def main():
             if name == args.workload:
                 continue
             xw = make_workload(name)
-            xtile, xmode, xhints, xcands = tuned_config(pkg, xw, args)
+            xtile, xmode, xhints, xlaunch, xcands = tuned_config(pkg, xw, args)
             xres = run_workload(pkg, torch, xw, xtile, args.extra_steps, 100, args.graph_steps,
-                                args.kernel_steps, xmode, xhints, windows=args.windows)
+                                args.kernel_steps, xmode, xhints, windows=args.windows,
+                                lattice_launch=xlaunch)
             xroof = roofline(xres, xw, xtile)
             if 2 * 72.0 * xw.nodes <= 128e6:
                 xroof["note"] = ("populations (2 x 36 B per node) stay in the 256 MB last-level "
@@ -287,7 +297,8 @@ def main():
                                  "roofline; the step is bound by the body kernel's latency")
             out[key] = {"workload": xw.name, "nodes": xw.nodes, "markers": xw.n_markers,
                         "tile": f"{xtile[0]}x{xtile[1]}", "step_mode": xres["step_mode"],
-                        "cache_hints": xres["cache_hints"], "graph_steps": xres["graph_steps"],
+                        "cache_hints": xres["cache_hints"], "lattice_launch": xres["lattice_launch"],
+                        "graph_steps": xres["graph_steps"],
                         "steps": args.extra_steps, "mlups": round(xres["mlups"], 1),
                         "ms_per_step": round(xres["ms_step"], 5), "windows": xres["windows"],
                         "roofline": xroof}
@@ -330,7 +341,7 @@ def graph_chunk(requested: int, steps: int) -> int:
 
 
 def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps, step_mode=None,
-                 cache_hints=None, windows=5):
+                 cache_hints=None, windows=5, lattice_launch=0):
     """W warm-up steps, then graph capture of both buffer parities (2 chunks,
     untimed), then exactly `steps` steps replayed from the graphs, bracketed by
     HIP events after a device synchronisation; then `windows - 1` more such
@@ -344,6 +355,7 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps,
         sim.set_step_mode(int(step_mode))
     if cache_hints is not None:
         sim.set_cache_hints(int(cache_hints))
+    sim.set_lattice_launch(int(lattice_launch or 0))
     stream = sim.stream
     sim.step(warmup)
     sim.step(2 * G)                  # captures the graphs of both parities
@@ -382,9 +394,11 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps,
           file=sys.stderr, flush=True)
     mode = sim.step_mode
     hints_used = sim.cache_hints
+    launch_used = sim.lattice_launch
     sim.close()
     return {"mlups": mlups, "ms_step": ms_step, "kernel_ms": k_ms, "kernel_launches": k_n,
-            "step_mode": mode, "cache_hints": hints_used, "graph_steps": G,
+            "step_mode": mode, "cache_hints": hints_used, "lattice_launch": launch_used,
+            "graph_steps": G,
             "plain_steps": steps % G if G else steps, "prime_steps": 2 * G,
             "windows": {"count": len(times), "ms_per_step": [round(t / steps, 5) for t in times],
                         "median_ms_per_step": round(med / steps, 5),
@@ -541,6 +555,7 @@ def batched_vs_plain(pkg, torch, args, n_inst, steps):
     b = pkg.Batch(ws, dtype="f32", tile=tile, device="cuda:0", graph_steps=tuned["graph_steps"])
     b.set_step_mode(tuned["step_mode"])
     b.set_cache_hints(tuned["cache_hints"])
+    b.set_lattice_launch(int(tuned.get("lattice_launch", 0)))
     b.step(2 * max(20, tuned["graph_steps"]))
     ms_b = _timed(torch, b, steps)
     # the fused lattice kernel of the batch (one launch for all instances):
@@ -569,6 +584,7 @@ def batched_vs_plain(pkg, torch, args, n_inst, steps):
         s = pkg.Sim(w, dtype="f32", tile=tuple(one["tile"]), device="cuda:0", graph_steps=100)
         s.set_step_mode(one["step_mode"])
         s.set_cache_hints(one["cache_hints"])
+        s.set_lattice_launch(int(one.get("lattice_launch", 0)))
         s.step(200)
         ms_g += _timed(torch, s, steps)
         s.close()
@@ -588,6 +604,7 @@ def batched_vs_plain(pkg, torch, args, n_inst, steps):
             "sequential_graph_tuned_config": {"tile": f"{one['tile'][0]}x{one['tile'][1]}",
                                               "step_mode": one["step_mode"],
                                               "cache_hints": one["cache_hints"],
+                                              "lattice_launch": int(one.get("lattice_launch", 0)),
                                               "tuned_on": rep.name},
             "tile": f"{tile[0]}x{tile[1]}", "cache_hints": tuned["cache_hints"],
             "lattice_kernel": {"kernel_us": round(k_ms * 1e3, 3), "launches": k_n,
@@ -596,10 +613,17 @@ def batched_vs_plain(pkg, torch, args, n_inst, steps):
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": round(72.0 * nodes / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
             "graph_steps": tuned["graph_steps"], "step_mode": tuned["step_mode"],
+            "lattice_launch": int(tuned.get("lattice_launch", 0)),
             "candidates": [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "graph_steps": c["graph_steps"],
                             "step_mode": c["step_mode"], "cache_hints": c["cache_hints"],
                             "mlups": round(c["mlups"], 1)}
-                           for c in tuned["candidates"]]}
+                           for c in tuned["candidates"]],
+            # the lattice kernel's launch form at the pick: 0 one workgroup per
+            # tile, w > 0 a persistent grid of w workgroups per CU
+            "launch_candidates": [{"lattice_launch": int(c["lattice_launch"]),
+                                   "mlups": round(c["mlups"], 1),
+                                   "us_per_step": round(c["ms_per_step"] * 1e3, 2)}
+                                  for c in tuned.get("launch_candidates", [])]}
 
 
 FD_PARAMS = ((1, 0, "ks_particle"), (1, 1, "kb_particle"), (1, 2, "sigma_particle"),
@@ -699,8 +723,10 @@ def roofline(res, wl, tile=None):
     achieved = bytes_alg / (res["kernel_ms"] / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profile(wl.name, tile, res.get("cache_hints")),
-            "kernel": "k_lb_fused", "kernel_us": round(res["kernel_ms"] * 1e3, 3),
+            "traffic": traffic_from_profile(wl.name, tile, res.get("cache_hints"),
+                                            res.get("lattice_launch", 0)),
+            "kernel": "k_lb_persistent" if res.get("lattice_launch") else "k_lb_fused",
+            "kernel_us": round(res["kernel_ms"] * 1e3, 3),
             "launches": res["kernel_launches"], "bytes_per_launch": bytes_alg}
 
 

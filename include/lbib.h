@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define LBIB_ABI_VERSION 5u
+#define LBIB_ABI_VERSION 6u
 
 typedef struct lbib_ctx lbib_ctx;
 
@@ -483,6 +483,17 @@ lbib_status lbib_get_step_mode(const lbib_ctx* ctx, int32_t* mode);
  * returns the hints in use. */
 lbib_status lbib_set_cache_hints(lbib_ctx* ctx, int32_t hints);
 lbib_status lbib_get_cache_hints(const lbib_ctx* ctx, int32_t* hints);
+
+/* Launch form of the fused lattice kernel (the results are the same bit for
+ * bit; only the speed differs):
+ *   0        one workgroup per tile, the default;
+ *   1,2,4,8  persistent: that many workgroups per compute unit of the
+ *            device, each walking the tiles with a fixed stride (the tiles
+ *            of one XCD stay on that XCD).
+ * The batched sweeps' autotuner times these forms.  Allowed in any phase;
+ * LBIB_EINVAL for other values.  lbib_get_lattice_launch returns the form. */
+lbib_status lbib_set_lattice_launch(lbib_ctx* ctx, int32_t wgs_per_cu);
+lbib_status lbib_get_lattice_launch(const lbib_ctx* ctx, int32_t* wgs_per_cu);
 
 /* Completed step count. */
 lbib_status lbib_get_step(const lbib_ctx* ctx, int64_t* step);

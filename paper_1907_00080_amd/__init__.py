@@ -42,7 +42,7 @@ EXPORTS = [
     "lbib_adjoint_workspace_query", "lbib_adjoint_bind", "lbib_adjoint_forward",
     "lbib_adjoint_backward", "lbib_set_body_params", "lbib_set_step_mode", "lbib_get_step_mode",
     "lbib_observe", "lbib_get_observations", "lbib_reset_observations",
-    "lbib_set_cache_hints", "lbib_get_cache_hints", "lbib_set_watchdog_mass_tolerance",
+    "lbib_set_cache_hints", "lbib_get_cache_hints", "lbib_set_lattice_launch", "lbib_get_lattice_launch", "lbib_set_watchdog_mass_tolerance",
     "lbib_get_fields_noalloc",
 ]
 
@@ -163,6 +163,8 @@ def library() -> ctypes.CDLL:
         "lbib_set_step_mode": (I32, [P, I32]),
         "lbib_get_step_mode": (I32, [P, ip]),
         "lbib_set_cache_hints": (I32, [P, I32]),
+        "lbib_set_lattice_launch": (I32, [P, I32]),
+        "lbib_get_lattice_launch": (I32, [P, ip]),
         "lbib_set_watchdog_mass_tolerance": (I32, [P, D]),
         "lbib_get_cache_hints": (I32, [P, ip]),
     }
@@ -252,6 +254,17 @@ class _Ctx:
     def cache_hints(self) -> int:
         m = ctypes.c_int32()
         self.check(self.lib.lbib_get_cache_hints(self.h, ctypes.byref(m)))
+        return m.value
+
+    def set_lattice_launch(self, wgs_per_cu: int):
+        """Lattice-kernel launch: 0 one workgroup per tile, 1/2/4/8 a
+        persistent grid of that many workgroups per CU."""
+        self.check(self.lib.lbib_set_lattice_launch(self.h, int(wgs_per_cu)))
+
+    @property
+    def lattice_launch(self) -> int:
+        m = ctypes.c_int32()
+        self.check(self.lib.lbib_get_lattice_launch(self.h, ctypes.byref(m)))
         return m.value
 
     def time_lattice_kernel(self, reps: int = 20) -> float:

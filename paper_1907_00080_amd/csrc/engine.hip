@@ -111,6 +111,10 @@ struct lbib_ctx {
   // cache hints of the fused lattice kernel's population accesses
   // (lbib_set_cache_hints): -1 automatic, else the NT bits
   int cache_hints = -1;
+  // launch form of the fused lattice kernel (lbib_set_lattice_launch): 0 one
+  // workgroup per tile, else persistent with this many workgroups per CU
+  int lb_wpc = 0;
+  int n_cu = 256;             // compute units of the bound device
   bool merge_advance = true;  // resolved from step_mode and the bodies
   bool repulsion = false;     // some instance has the vertex repulsion on
   int nrep_chunk = 0;         // repulsion work units (kRepChunk vertices of a body)
@@ -384,6 +388,8 @@ StepArgs step_args(const lbib_ctx* c) {
     a.max_inst_tiles = std::max(a.max_inst_tiles, nt);
   }
   a.body_cache_bytes = c->body_cache;
+  a.lb_wpc = c->lb_wpc;
+  a.n_cu = c->n_cu;
   a.max_nv = 0;
   a.any_mls = 0;
   // automatic cache hints: non-temporal loads and stores on a single lattice
@@ -1494,6 +1500,9 @@ lbib_status lbib_bind(lbib_ctx* c, void* ws, size_t bytes, void* stream) {
   if (bytes < c->L.total) return fail(c, LBIB_ENOSPACE, "workspace smaller than lbib_workspace_query");
   lbib_status rs = resolve_scratch(c);
   if (rs != LBIB_OK) return rs;
+  int ncu = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  if (ncu > 0) c->n_cu = ncu;
   c->ws = (char*)ws;
   c->ws_bytes = bytes;
   c->stream = (hipStream_t)stream;
@@ -1540,6 +1549,24 @@ lbib_status lbib_set_cache_hints(lbib_ctx* c, int32_t hints) {
     drop_adjoint_graphs(c);
   }
   c->cache_hints = hints;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_lattice_launch(lbib_ctx* c, int32_t wgs_per_cu) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (wgs_per_cu != 0 && wgs_per_cu != 1 && wgs_per_cu != 2 && wgs_per_cu != 4 && wgs_per_cu != 8)
+    return fail(c, LBIB_EINVAL, "lattice launch must be 0, 1, 2, 4 or 8 workgroups per CU");
+  if (wgs_per_cu != c->lb_wpc) {
+    drop_graphs(c);
+    drop_adjoint_graphs(c);
+  }
+  c->lb_wpc = wgs_per_cu;
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_lattice_launch(const lbib_ctx* c, int32_t* wgs_per_cu) {
+  if (!c || !wgs_per_cu) return fail(const_cast<lbib_ctx*>(c), LBIB_EINVAL, "NULL argument");
+  *wgs_per_cu = c->lb_wpc;
   return LBIB_OK;
 }
 

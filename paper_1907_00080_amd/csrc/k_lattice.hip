@@ -19,6 +19,8 @@
 // Workgroup -> tile mapping is XCD aware: consecutive workgroups go to the 8
 // XCDs in turn, so XCD k receives a contiguous band of tiles (its own L2 then
 // holds the rows that neighbouring tiles share).
+#include <algorithm>
+
 #include "lbib_dev.h"
 
 namespace lbib {
@@ -80,10 +82,13 @@ __device__ __forceinline__ void spread_entries(const Ptrs<T>& p, const int* bin,
 // carry it too, which measured faster on a lattice whose populations stay in
 // the last-level cache and much slower on one larger than it.  The host
 // chooses per context.
+// One tile, the g-th of the launch's virtual grid of 8 * ceil(ntiles / 8)
+// workgroups: g mod 8 is the XCD the hardware gives workgroup g, which takes
+// a contiguous band of tiles.  Returns early (every lane, or a lane outside
+// the lattice after the workgroup's last barrier).
 template <typename T, int TX, int TY, int NT>
-__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int mode) {
+__device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int mode) {
   static_assert(TX * TY == kCap, "one lane per LDS slot");
-  const int g = blockIdx.x;
   const int per = (ntiles_total + 7) >> 3;
   const int tile = (g & 7) * per + (g >> 3);
   if (tile >= ntiles_total) return;
@@ -200,6 +205,25 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
   }
 }
 
+// One workgroup per tile (the default launch).
+template <typename T, int TX, int TY, int NT>
+__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int mode) {
+  lb_tile<T, TX, TY, NT>(p, blockIdx.x, ntiles_total, mode);
+}
+
+// Persistent launch: a fixed grid (a multiple of 8 workgroups, sized by the
+// host as a number of workgroups per CU) walks the virtual grid with stride
+// gridDim.x, so workgroup b keeps to the tiles of XCD b mod 8.  The barrier
+// between tiles frees the LDS accumulators for the next one.
+template <typename T, int TX, int TY, int NT>
+__global__ __launch_bounds__(TX * TY) void k_lb_persistent(Ptrs<T> p, int ntiles_total, int mode) {
+  const int gtot = 8 * ((ntiles_total + 7) >> 3);
+  for (int g = blockIdx.x; g < gtot; g += gridDim.x) {
+    lb_tile<T, TX, TY, NT>(p, g, ntiles_total, mode);
+    __syncthreads();
+  }
+}
+
 // Physical fields of the last step from its post-collision populations:
 // collision conserves mass, so rho = 1 + sum h*; the forced BGK step leaves
 // a post-collision momentum sum h* e = rho u + F/2, so where F is the uniform
@@ -307,26 +331,33 @@ template <typename T>
 void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mode,
                      hipEvent_t ev0, hipEvent_t ev1) {
   const int per = (a.ntiles_total + 7) / 8;
-  dim3 grid(8 * per), block(kCap);
+  // persistent: wpc workgroups per CU, a multiple of 8, at most the tiles
+  const bool persist = a.lb_wpc > 0;
+  const int pgrid = std::min(8 * per, 8 * ((a.lb_wpc * a.n_cu + 7) / 8));
+  dim3 grid(persist ? pgrid : 8 * per), block(kCap);
   // the optional events are bound to the dispatch itself, so their elapsed
   // time is the kernel's execution time and not that of separate markers
+#define LBIB_LB1(KERNEL, TXv, TYv, NTv)                                                          \
+  hipExtLaunchKernelGGL((KERNEL<T, TXv, TYv, NTv>), grid, block, 0, s, ev0, ev1, 0, p,           \
+                        a.ntiles_total, mode)
 #define LBIB_LB(TXv, TYv)                                                                        \
   do {                                                                                          \
-    if (a.nt_mode == 3)                                                                         \
-      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, 3>), grid, block, 0, s, ev0, ev1, 0, p,     \
-                            a.ntiles_total, mode);                                              \
-    else if (a.nt_mode == 1)                                                                    \
-      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, 1>), grid, block, 0, s, ev0, ev1, 0, p,     \
-                            a.ntiles_total, mode);                                              \
-    else                                                                                        \
-      hipExtLaunchKernelGGL((k_lb_fused<T, TXv, TYv, 0>), grid, block, 0, s, ev0, ev1, 0, p,     \
-                            a.ntiles_total, mode);                                              \
+    if (persist) {                                                                              \
+      if (a.nt_mode == 3) LBIB_LB1(k_lb_persistent, TXv, TYv, 3);                               \
+      else if (a.nt_mode == 1) LBIB_LB1(k_lb_persistent, TXv, TYv, 1);                          \
+      else LBIB_LB1(k_lb_persistent, TXv, TYv, 0);                                              \
+    } else {                                                                                    \
+      if (a.nt_mode == 3) LBIB_LB1(k_lb_fused, TXv, TYv, 3);                                    \
+      else if (a.nt_mode == 1) LBIB_LB1(k_lb_fused, TXv, TYv, 1);                               \
+      else LBIB_LB1(k_lb_fused, TXv, TYv, 0);                                                   \
+    }                                                                                           \
   } while (0)
   if (a.tile_x == 64 && a.tile_y == 4) LBIB_LB(64, 4);
   else if (a.tile_x == 128 && a.tile_y == 2) LBIB_LB(128, 2);
   else if (a.tile_x == 32 && a.tile_y == 8) LBIB_LB(32, 8);
   else LBIB_LB(256, 1);
 #undef LBIB_LB
+#undef LBIB_LB1
 }
 
 template <typename T>

@@ -376,6 +376,9 @@ struct StepArgs {
   int max_nv;           // most vertices of any body
   int any_mls;          // some instance uses the MLS transfer
   int nt_mode;          // lattice kernel: non-temporal population loads (1), and stores (3)
+  int lb_wpc;           // lattice kernel: 0 one workgroup per tile, else a persistent
+                        // grid of this many workgroups per CU
+  int n_cu;             // compute units of the device
 };
 
 template <typename T>

@@ -1,4 +1,5 @@
-"""Autotuner for batched sweeps: tile shape, step form, cache hints, graph chunk (host logic).
+"""Autotuner for batched sweeps: tile shape, step form, cache hints, graph chunk
+and lattice-kernel launch form (host logic).
 
 A batch advances many uneven capillary instances together (one launch per
 kernel per step for all of them).  Which tile shape of the fused lattice
@@ -26,6 +27,9 @@ TILES: Tuple[Tuple[int, int], ...] = ((64, 4), (128, 2), (32, 8), (256, 1))
 GRAPH_STEPS: Tuple[int, ...] = (10, 100)
 STEP_MODES: Tuple[int, ...] = (1, 2, 3)   # three kernels, merged advance, overlapped tiles
 CACHE_HINTS: Tuple[int, ...] = (0, 1, 3)   # plain, non-temporal loads, non-temporal loads + stores
+# lattice-kernel launch: one workgroup per tile (0) or a persistent grid of
+# that many workgroups per CU; timed for the best of the other choices
+LATTICE_LAUNCHES: Tuple[int, ...] = (0, 1, 2, 4, 8)
 
 
 def signature(workloads: Sequence, dtype: str) -> str:
@@ -94,15 +98,17 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
              graph_steps: Sequence[int] = GRAPH_STEPS,
              step_modes: Sequence[int] = STEP_MODES,
              cache_hints: Sequence[int] = CACHE_HINTS,
+             lattice_launches: Sequence[int] = LATTICE_LAUNCHES,
              measure: Optional[Callable] = None) -> dict:
     """Pick the tile shape, step form, cache hints and graph chunk for a batch
-    of `workloads`.
+    of `workloads`, then the lattice kernel's launch form for that pick.
 
     Returns {"tile": [tx, ty], "graph_steps": g, "step_mode": m, "cache_hints": c,
-    "ms_per_step": t, "mlups": ..., "candidates": [...], "device": name,
-    "cached": bool}.  `steps` is rounded up to a multiple of every graph chunk.
-    `measure(tile, g, mode, hints)` replaces the GPU timing (returns ms per
-    step); it exists for tests of the selection and caching logic.
+    "lattice_launch": w, "ms_per_step": t, "mlups": ..., "candidates": [...],
+    "launch_candidates": [...], "device": name, "cached": bool}.  `steps` is
+    rounded up to a multiple of every graph chunk.  `measure(tile, g, mode,
+    hints, launch=0)` replaces the GPU timing (returns ms per step); it exists
+    for tests of the selection and caching logic.
     """
     nodes = sum(int(w.nx) * int(w.ny) for w in workloads)
     dev_name = _device_name(device) if measure is None else "measure-callback"
@@ -140,11 +146,39 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
         finally:
             b.close()
     best = choose(results)
+    # second stage: the lattice kernel's launch form at the chosen settings
+    launches = []
+    for w in lattice_launches:
+        if int(w) == 0:
+            r = dict(best)
+        elif measure is not None:
+            ms = float(measure(tuple(best["tile"]), best["graph_steps"], best["step_mode"],
+                               best["cache_hints"], launch=int(w)))
+            r = _record(best["tile"], best["graph_steps"], best["step_mode"], best["cache_hints"],
+                        ms, nodes)
+        else:
+            from . import Batch
+            b = Batch(workloads, dtype=dtype, tile=tuple(best["tile"]), device=device,
+                      graph_steps=int(best["graph_steps"]))
+            try:
+                b.set_step_mode(int(best["step_mode"]))
+                b.set_cache_hints(int(best["cache_hints"]))
+                b.set_lattice_launch(int(w))
+                b.step(max(int(warmup), int(best["graph_steps"])))
+                ms = _time_steps(b, steps) / steps
+            finally:
+                b.close()
+            r = _record(best["tile"], best["graph_steps"], best["step_mode"], best["cache_hints"],
+                        ms, nodes)
+        r["lattice_launch"] = int(w)
+        launches.append(r)
+    best_launch = choose(launches) if launches else dict(best, lattice_launch=0)
     rec = {"tile": list(best["tile"]), "graph_steps": best["graph_steps"],
            "step_mode": best["step_mode"], "cache_hints": best["cache_hints"],
-           "ms_per_step": best["ms_per_step"], "mlups": best["mlups"],
-           "candidates": results, "device": dev_name, "nodes": nodes,
-           "instances": len(workloads), "dtype": str(dtype)}
+           "lattice_launch": int(best_launch["lattice_launch"]),
+           "ms_per_step": best_launch["ms_per_step"], "mlups": best_launch["mlups"],
+           "candidates": results, "launch_candidates": launches, "device": dev_name,
+           "nodes": nodes, "instances": len(workloads), "dtype": str(dtype)}
     if cache:
         store_cache(cache, key, rec)
     rec = dict(rec)

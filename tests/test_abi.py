@@ -173,6 +173,21 @@ def test_step_mode_validation():
     lib.lbib_destroy(h)
 
 
+def test_lattice_launch_validation():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    got = ctypes.c_int32()
+    assert lib.lbib_get_lattice_launch(h, ctypes.byref(got)) == 0 and got.value == 0
+    for bad in (-1, 3, 5, 16):
+        assert lib.lbib_set_lattice_launch(h, bad) == 1
+    for w in (1, 2, 4, 8, 0):
+        assert lib.lbib_set_lattice_launch(h, w) == 0
+        assert lib.lbib_get_lattice_launch(h, ctypes.byref(got)) == 0 and got.value == w
+    assert lib.lbib_get_lattice_launch(h, None) == 1
+    lib.lbib_destroy(h)
+
+
 def test_repulsion_validation_and_phase():
     lib = pkg.library()
     st, h = _create()

@@ -84,6 +84,42 @@ def test_batch_bitwise_equals_individual_runs(tile):
     assert bonded > 0       # the adhesive instance formed bonds
 
 
+@pytest.mark.parametrize("tile", [(64, 4), (256, 1)])
+def test_persistent_lattice_launch_is_bitwise_the_default(tile):
+    """The lattice kernel's persistent launch (a fixed grid of 1, 2 or 8
+    workgroups per CU walking the tiles) gives the one-workgroup-per-tile
+    launch's bits: on the uneven batch and on the 2000 x 200 capillary."""
+    announce(f"persistent lattice launch, tile {tile}")
+    ws = uneven_instances()
+    ref = pkg.Batch(ws, dtype="f32", tile=tile, graph_steps=10)
+    ref.step(40)
+    for wpc in (1, 2, 8):
+        b = pkg.Batch(ws, dtype="f32", tile=tile, graph_steps=10)
+        b.set_lattice_launch(wpc)
+        assert b.lattice_launch == wpc
+        b.step(40)
+        d = b.diagnostics()
+        assert d["nonfinite"] == 0 and d["bin_overflow"] == 0
+        for i, w in enumerate(ws):
+            for x, y in zip(b.fields(i), ref.fields(i)):
+                assert np.array_equal(x, y), (wpc, i)
+            for k in range(len(w.bodies)):
+                assert np.array_equal(b.markers(i, k), ref.markers(i, k)), (wpc, i, k)
+        b.close()
+    ref.close()
+    wl = configs.capillary_2000x200()
+    runs = []
+    for wpc in (0, 4):
+        s = pkg.Sim(wl, dtype="f32", tile=tile, graph_steps=10)
+        s.set_lattice_launch(wpc)
+        s.step(20)
+        runs.append((s.fields(), s.all_markers()))
+        s.close()
+    for x, y in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(runs[0][1], runs[1][1])
+
+
 def test_batch_fp64_matches_oracle_per_instance():
     announce("batch fp64 vs oracle")
     ws = uneven_instances()
@@ -145,7 +181,12 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path):
     assert tuple(rec["tile"]) in pkg.TILES and rec["graph_steps"] in (10, 100)
     assert len(rec["candidates"]) == len(pkg.TILES) * 2 * 3 * 3   # tiles x graph chunks x forms x hints
     assert rec["step_mode"] in (1, 2, 3)
-    assert rec["ms_per_step"] == min(c["ms_per_step"] for c in rec["candidates"])
+    # the launch stage starts from the first stage's best and keeps the fastest form
+    launches = rec["launch_candidates"]
+    assert [c["lattice_launch"] for c in launches] == [0, 1, 2, 4, 8]
+    assert launches[0]["ms_per_step"] == min(c["ms_per_step"] for c in rec["candidates"])
+    assert rec["ms_per_step"] == min(c["ms_per_step"] for c in launches)
+    assert rec["lattice_launch"] in (0, 1, 2, 4, 8)
     again = autotune(ws, "f32", cache=path, steps=20, warmup=10)
     assert again["cached"] is True
     assert again["tile"] == rec["tile"] and again["graph_steps"] == rec["graph_steps"]

@@ -42,23 +42,30 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
             ((128, 2), 100): 1.5, ((32, 8), 10): 4.0, ((32, 8), 100): 1.7,
             ((256, 1), 10): 2.2, ((256, 1), 100): 2.0}
 
-    def measure(tile, g, mode, hints):
-        calls.append((tile, g, mode, hints))
-        return cost[(tile, g)] + (0.0 if mode == 2 else 0.25 * mode) + (0.0 if hints == 1 else 0.1)
+    def measure(tile, g, mode, hints, launch=0):
+        calls.append((tile, g, mode, hints, launch))
+        return (cost[(tile, g)] + (0.0 if mode == 2 else 0.25 * mode) + (0.0 if hints == 1 else 0.1)
+                - (0.1 if launch == 4 else 0.0))
 
     path = str(tmp_path / "sub" / "tune.json")
     ws = _ws()
     rec = tune.autotune(ws, "f32", cache=path, measure=measure)
     assert rec["tile"] == [128, 2] and rec["graph_steps"] == 100 and not rec["cached"]
     assert rec["step_mode"] == 2 and rec["cache_hints"] == 1
-    assert len(calls) == 72
+    # second stage: the launch forms at that pick (0 is the first stage's own time)
+    assert len(calls) == 72 + 4 and all(c[4] == 0 for c in calls[:72])
+    assert [c[4] for c in calls[72:]] == [1, 2, 4, 8]
+    assert all(c[:4] == ((128, 2), 100, 2, 1) for c in calls[72:])
+    assert rec["lattice_launch"] == 4 and len(rec["launch_candidates"]) == 5
     nodes = sum(w.nodes for w in ws)
-    assert abs(rec["mlups"] - nodes / 1.5e-3 / 1e6) < 1e-9
+    assert abs(rec["ms_per_step"] - 1.4) < 1e-12
+    assert abs(rec["mlups"] - nodes / 1.4e-3 / 1e6) < 1e-9
     with open(path) as f:
         data = json.load(f)
     assert len(data) == 1
     again = tune.autotune(ws, "f32", cache=path, measure=measure)
-    assert again["cached"] and again["tile"] == [128, 2] and len(calls) == 72
+    assert again["cached"] and again["tile"] == [128, 2] and again["lattice_launch"] == 4
+    assert len(calls) == 76
     # another batch adds a second record and keeps the first
     tune.autotune(ws[:1], "f32", cache=path, measure=measure)
     with open(path) as f:
@@ -67,6 +74,8 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
 
 def test_autotune_without_cache_measures_every_time():
     n = []
-    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m, c: n.append(1) or 1.0)
-    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m, c: n.append(1) or 1.0)
-    assert len(n) == 144
+    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m, c, launch=0: n.append(1) or 1.0)
+    rec = tune.autotune(_ws(), "f32", cache=None,
+                        measure=lambda t, g, m, c, launch=0: n.append(1) or 1.0)
+    assert len(n) == 2 * (72 + 4)
+    assert rec["lattice_launch"] == 0   # ties go to the one-workgroup-per-tile launch

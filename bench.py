@@ -141,11 +141,12 @@ def cpu_baseline_sweep(n_inst: int, budget_s: float = 20.0) -> dict:
                       f"all processes / longest stepping time"}
 
 
-def traffic_from_profile(workload_name: str, tile=None, hints=None, launch=0):
+def traffic_from_profile(workload_name: str, tile=None, hints=None, launch=0, streaming=None):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), if
     it was taken with the current kernel source and (when given) the same tile
-    shape and cache hints, for the one-workgroup-per-tile launch; else None."""
+    shape, cache hints and population streaming, for the one-workgroup-per-tile
+    launch; else None."""
     if launch:
         return None
     try:
@@ -159,6 +160,8 @@ def traffic_from_profile(workload_name: str, tile=None, hints=None, launch=0):
         return None
     if hints is not None and rec.get("cache_hints", {}).get(workload_name) != int(hints):
         return None
+    if streaming is not None and rec.get("streaming", {}).get(workload_name, 0) != int(streaming):
+        return None
     return rec.get("bytes_per_launch", {}).get(workload_name)
 
 
@@ -167,21 +170,25 @@ def tuned_config(pkg, wl, args):
     steps of this workload timed for every tile and step form), or the tile
     given on the command line with the default step form."""
     if args.tile != "auto":
-        return tuple(int(v) for v in args.tile.split("x")), args.step_mode, args.hints, args.launch, None
+        return (tuple(int(v) for v in args.tile.split("x")), args.step_mode, args.hints, args.launch,
+                args.streaming, None)
     from paper_1907_00080_amd import tune
     rec = tune.autotune([wl], dtype="f32", device="cuda:0", steps=200, warmup=20,
                         graph_steps=(args.graph_steps,))
     tile = tuple(rec["tile"])
     launch = int(rec.get("lattice_launch", 0))
+    streaming = int(rec.get("streaming", 0))
     print(f"bench: {wl.name} tuned: tile {tile[0]}x{tile[1]}, step mode {rec['step_mode']}, "
-          f"cache hints {rec['cache_hints']}, lattice launch {launch} "
-          f"({len(rec['candidates'])} + {len(rec.get('launch_candidates', []))} candidates)",
-          file=sys.stderr, flush=True)
+          f"cache hints {rec['cache_hints']}, lattice launch {launch}, streaming {streaming} "
+          f"({len(rec['candidates'])} + {len(rec.get('launch_candidates', []))} + "
+          f"{len(rec.get('streaming_candidates', []))} candidates)", file=sys.stderr, flush=True)
     cands = [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "step_mode": c["step_mode"],
               "cache_hints": c["cache_hints"], "lattice_launch": int(c.get("lattice_launch", 0)),
+              "streaming": int(c.get("streaming", 0)),
               "us_per_step": round(c["ms_per_step"] * 1e3, 2)}
-             for c in list(rec["candidates"]) + list(rec.get("launch_candidates", []))[1:]]
-    return tile, rec["step_mode"], rec["cache_hints"], launch, cands
+             for c in (list(rec["candidates"]) + list(rec.get("launch_candidates", []))[1:]
+                       + list(rec.get("streaming_candidates", []))[1:])]
+    return tile, rec["step_mode"], rec["cache_hints"], launch, streaming, cands
 
 
 def main():
@@ -201,6 +208,9 @@ def main():
     ap.add_argument("--launch", type=int, default=0,
                     help="lattice-kernel launch with a fixed --tile: 0 one workgroup per tile, "
                          "1/2/4/8 persistent workgroups per CU")
+    ap.add_argument("--streaming", type=int, default=None,
+                    help="population streaming with a fixed --tile: 0 two buffers, 1 in place "
+                         "(default: the library's automatic choice)")
     ap.add_argument("--hints", type=int, default=None,
                     help="with a fixed --tile: cache hints of the lattice kernel (0, 1 or 3)")
     ap.add_argument("--side-workload", default="capillary-2000x200",
@@ -249,9 +259,10 @@ def main():
     import paper_1907_00080_amd as pkg
 
     wl = make_workload(args.workload)
-    tile, mode, hints, launch, cands = tuned_config(pkg, wl, args)
+    tile, mode, hints, launch, streaming, cands = tuned_config(pkg, wl, args)
     res = run_workload(pkg, torch, wl, tile, args.steps, args.warmup, args.graph_steps,
-                       args.kernel_steps, mode, hints, windows=args.windows, lattice_launch=launch)
+                       args.kernel_steps, mode, hints, windows=args.windows, lattice_launch=launch,
+                       streaming=streaming)
     roof = roofline(res, wl, tile)
 
     out = {
@@ -272,7 +283,7 @@ def main():
                    "particles": sum(b.kind != 0 for b in wl.bodies),
                    "markers": wl.n_markers, "tile": f"{tile[0]}x{tile[1]}",
                    "step_mode": res["step_mode"], "cache_hints": res["cache_hints"],
-                   "lattice_launch": res["lattice_launch"],
+                   "lattice_launch": res["lattice_launch"], "streaming": res["streaming"],
                    "graph_steps": res["graph_steps"], "plain_steps": res["plain_steps"],
                    "graph_prime_steps": res["prime_steps"], "tuned": cands is not None},
         "windows": res["windows"],
@@ -286,10 +297,10 @@ def main():
             if name == args.workload:
                 continue
             xw = make_workload(name)
-            xtile, xmode, xhints, xlaunch, xcands = tuned_config(pkg, xw, args)
+            xtile, xmode, xhints, xlaunch, xstream, xcands = tuned_config(pkg, xw, args)
             xres = run_workload(pkg, torch, xw, xtile, args.extra_steps, 100, args.graph_steps,
                                 args.kernel_steps, xmode, xhints, windows=args.windows,
-                                lattice_launch=xlaunch)
+                                lattice_launch=xlaunch, streaming=xstream)
             xroof = roofline(xres, xw, xtile)
             if 2 * 72.0 * xw.nodes <= 128e6:
                 xroof["note"] = ("populations (2 x 36 B per node) stay in the 256 MB last-level "
@@ -298,6 +309,7 @@ def main():
             out[key] = {"workload": xw.name, "nodes": xw.nodes, "markers": xw.n_markers,
                         "tile": f"{xtile[0]}x{xtile[1]}", "step_mode": xres["step_mode"],
                         "cache_hints": xres["cache_hints"], "lattice_launch": xres["lattice_launch"],
+                        "streaming": xres["streaming"],
                         "graph_steps": xres["graph_steps"],
                         "steps": args.extra_steps, "mlups": round(xres["mlups"], 1),
                         "ms_per_step": round(xres["ms_step"], 5), "windows": xres["windows"],
@@ -341,7 +353,7 @@ def graph_chunk(requested: int, steps: int) -> int:
 
 
 def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps, step_mode=None,
-                 cache_hints=None, windows=5, lattice_launch=0):
+                 cache_hints=None, windows=5, lattice_launch=0, streaming=None):
     """W warm-up steps, then graph capture of both buffer parities (2 chunks,
     untimed), then exactly `steps` steps replayed from the graphs, bracketed by
     HIP events after a device synchronisation; then `windows - 1` more such
@@ -350,7 +362,8 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps,
     print(f"bench: workload {wl.name} nodes={wl.nodes} markers={wl.n_markers} "
           f"bodies={len(wl.bodies)} tile {tile[0]}x{tile[1]}", file=sys.stderr, flush=True)
     G = graph_chunk(graph_steps, steps)
-    sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=G)
+    sim = pkg.Sim(wl, dtype="f32", tile=tile, device="cuda:0", graph_steps=G,
+                  streaming=None if streaming is None else int(streaming))
     if step_mode is not None:
         sim.set_step_mode(int(step_mode))
     if cache_hints is not None:
@@ -395,9 +408,11 @@ def run_workload(pkg, torch, wl, tile, steps, warmup, graph_steps, kernel_steps,
     mode = sim.step_mode
     hints_used = sim.cache_hints
     launch_used = sim.lattice_launch
+    streaming_used = sim.streaming
     sim.close()
     return {"mlups": mlups, "ms_step": ms_step, "kernel_ms": k_ms, "kernel_launches": k_n,
             "step_mode": mode, "cache_hints": hints_used, "lattice_launch": launch_used,
+            "streaming": streaming_used,
             "graph_steps": G,
             "plain_steps": steps % G if G else steps, "prime_steps": 2 * G,
             "windows": {"count": len(times), "ms_per_step": [round(t / steps, 5) for t in times],
@@ -552,7 +567,8 @@ def batched_vs_plain(pkg, torch, args, n_inst, steps):
           f"{sum(w.n_markers for w in ws)} markers; autotuning", file=sys.stderr, flush=True)
     tuned = autotune(ws, "f32", device="cuda:0", steps=100, warmup=20)
     tile = tuple(tuned["tile"])
-    b = pkg.Batch(ws, dtype="f32", tile=tile, device="cuda:0", graph_steps=tuned["graph_steps"])
+    b = pkg.Batch(ws, dtype="f32", tile=tile, device="cuda:0", graph_steps=tuned["graph_steps"],
+                  streaming=int(tuned.get("streaming", 0)))
     b.set_step_mode(tuned["step_mode"])
     b.set_cache_hints(tuned["cache_hints"])
     b.set_lattice_launch(int(tuned.get("lattice_launch", 0)))
@@ -581,7 +597,8 @@ def batched_vs_plain(pkg, torch, args, n_inst, steps):
     one = autotune([rep], "f32", device="cuda:0", steps=100, warmup=20, graph_steps=(100,))
     ms_g = 0.0
     for w in ws:
-        s = pkg.Sim(w, dtype="f32", tile=tuple(one["tile"]), device="cuda:0", graph_steps=100)
+        s = pkg.Sim(w, dtype="f32", tile=tuple(one["tile"]), device="cuda:0", graph_steps=100,
+                    streaming=int(one.get("streaming", 0)))
         s.set_step_mode(one["step_mode"])
         s.set_cache_hints(one["cache_hints"])
         s.set_lattice_launch(int(one.get("lattice_launch", 0)))
@@ -614,6 +631,10 @@ def batched_vs_plain(pkg, torch, args, n_inst, steps):
                                "frac": round(72.0 * nodes / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
             "graph_steps": tuned["graph_steps"], "step_mode": tuned["step_mode"],
             "lattice_launch": int(tuned.get("lattice_launch", 0)),
+            "streaming": int(tuned.get("streaming", 0)),
+            "streaming_candidates": [{"streaming": int(c["streaming"]), "mlups": round(c["mlups"], 1),
+                                      "us_per_step": round(c["ms_per_step"] * 1e3, 2)}
+                                     for c in tuned.get("streaming_candidates", [])],
             "candidates": [{"tile": f"{c['tile'][0]}x{c['tile'][1]}", "graph_steps": c["graph_steps"],
                             "step_mode": c["step_mode"], "cache_hints": c["cache_hints"],
                             "mlups": round(c["mlups"], 1)}
@@ -724,8 +745,11 @@ def roofline(res, wl, tile=None):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_from_profile(wl.name, tile, res.get("cache_hints"),
-                                            res.get("lattice_launch", 0)),
-            "kernel": "k_lb_persistent" if res.get("lattice_launch") else "k_lb_fused",
+                                            res.get("lattice_launch", 0), res.get("streaming")),
+            # in place, the step alternates two passes of the kernel (the
+            # neighbour pass and the node-local pass): their mean
+            "kernel": ("k_lb_persistent" if res.get("lattice_launch") else
+                       "k_lb_fused (in place, both passes)" if res.get("streaming") else "k_lb_fused"),
             "kernel_us": round(res["kernel_ms"] * 1e3, 3),
             "launches": res["kernel_launches"], "bytes_per_launch": bytes_alg}
 

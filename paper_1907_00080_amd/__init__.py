@@ -42,7 +42,8 @@ EXPORTS = [
     "lbib_adjoint_workspace_query", "lbib_adjoint_bind", "lbib_adjoint_forward",
     "lbib_adjoint_backward", "lbib_set_body_params", "lbib_set_step_mode", "lbib_get_step_mode",
     "lbib_observe", "lbib_get_observations", "lbib_reset_observations",
-    "lbib_set_cache_hints", "lbib_get_cache_hints", "lbib_set_lattice_launch", "lbib_get_lattice_launch", "lbib_set_watchdog_mass_tolerance",
+    "lbib_set_cache_hints", "lbib_get_cache_hints", "lbib_set_lattice_launch", "lbib_get_lattice_launch",
+    "lbib_set_streaming", "lbib_get_streaming", "lbib_set_watchdog_mass_tolerance",
     "lbib_get_fields_noalloc",
 ]
 
@@ -164,6 +165,8 @@ def library() -> ctypes.CDLL:
         "lbib_get_step_mode": (I32, [P, ip]),
         "lbib_set_cache_hints": (I32, [P, I32]),
         "lbib_set_lattice_launch": (I32, [P, I32]),
+        "lbib_set_streaming": (I32, [P, I32]),
+        "lbib_get_streaming": (I32, [P, ip]),
         "lbib_get_lattice_launch": (I32, [P, ip]),
         "lbib_set_watchdog_mass_tolerance": (I32, [P, D]),
         "lbib_get_cache_hints": (I32, [P, ip]),
@@ -203,7 +206,7 @@ class _Ctx:
             msg = self.lib.lbib_last_error(h).decode()
             raise LbibError(st, msg)
 
-    def bind(self, device, stream):
+    def bind(self, device, stream, streaming=None):
         import torch
         nb = ctypes.c_size_t()
         self.check(self.lib.lbib_workspace_query(self.h, ctypes.byref(nb)))
@@ -219,6 +222,8 @@ class _Ctx:
         self.stream = stream
         self.check(self.lib.lbib_bind(self.h, ctypes.c_void_p(aligned), nb.value,
                                       ctypes.c_void_p(stream.cuda_stream)))
+        if streaming is not None:
+            self.check(self.lib.lbib_set_streaming(self.h, int(streaming)))
         self.check(self.lib.lbib_finalize_setup(self.h))
         self.workspace_bytes = nb.value
 
@@ -265,6 +270,16 @@ class _Ctx:
     def lattice_launch(self) -> int:
         m = ctypes.c_int32()
         self.check(self.lib.lbib_get_lattice_launch(self.h, ctypes.byref(m)))
+        return m.value
+
+    def set_streaming(self, mode: int):
+        """Population streaming: -1 automatic, 0 two buffers, 1 in place."""
+        self.check(self.lib.lbib_set_streaming(self.h, int(mode)))
+
+    @property
+    def streaming(self) -> int:
+        m = ctypes.c_int32()
+        self.check(self.lib.lbib_get_streaming(self.h, ctypes.byref(m)))
         return m.value
 
     def time_lattice_kernel(self, reps: int = 20) -> float:
@@ -397,14 +412,14 @@ class Sim(_Ctx):
     """One capillary lattice with its bodies, advanced on the GPU."""
 
     def __init__(self, workload, dtype=None, tile=(64, 4), device=None, stream=None,
-                 graph_steps: int = 0, watchdog: bool = False):
+                 graph_steps: int = 0, watchdog: bool = False, streaming: Optional[int] = None):
         super().__init__()
         code = _dtype_code(dtype if dtype is not None else getattr(workload, "dtype", "f32"))
         self.nx, self.ny = int(workload.nx), int(workload.ny)
         self.nv = [int(np.asarray(b.xy).shape[0]) for b in workload.bodies]
         self.dtype = code
         self.h = _create(self.lib, workload, code, tile)
-        self.bind(device, stream)
+        self.bind(device, stream, streaming)
         self.check(self.lib.lbib_set_graph_steps(self.h, int(graph_steps)))
         self.check(self.lib.lbib_set_watchdog(self.h, int(bool(watchdog))))
         n = ctypes.c_int32()
@@ -471,7 +486,7 @@ class Batch(_Ctx):
     """Many independent capillary instances advanced together (parameter sweeps)."""
 
     def __init__(self, workloads: Sequence, dtype="f32", tile=(64, 4), device=None, stream=None,
-                 graph_steps: int = 0):
+                 graph_steps: int = 0, streaming: Optional[int] = None):
         super().__init__()
         code = _dtype_code(dtype)
         self.shapes = [(int(w.nx), int(w.ny)) for w in workloads]
@@ -490,7 +505,7 @@ class Batch(_Ctx):
         finally:
             for s in singles:
                 self.lib.lbib_destroy(s)
-        self.bind(device, stream)
+        self.bind(device, stream, streaming)
         self.check(self.lib.lbib_set_graph_steps(self.h, int(graph_steps)))
 
     @property

@@ -115,6 +115,10 @@ struct lbib_ctx {
   // workgroup per tile, else persistent with this many workgroups per CU
   int lb_wpc = 0;
   int n_cu = 256;             // compute units of the bound device
+  // streaming (lbib_set_streaming): -1 automatic, 0 two buffers, 1 in place;
+  // inplace is the resolved form (see streamed_slot in lbib_dev.h)
+  int streaming = -1;
+  bool inplace = false;
   bool merge_advance = true;  // resolved from step_mode and the bodies
   bool repulsion = false;     // some instance has the vertex repulsion on
   int nrep_chunk = 0;         // repulsion work units (kRepChunk vertices of a body)
@@ -286,8 +290,16 @@ Ptrs<T> make_ptrs(const lbib_ctx* c) {
   p.body = (BodyDev*)(w + L.body);
   T* a = (T*)(w + L.A);
   T* b = (T*)(w + L.B);
-  p.A = c->parity == 0 ? a : b;
-  p.B = c->parity == 0 ? b : a;
+  if (c->inplace) {
+    // one buffer; layout P (scheme 1) at even parity, S (scheme 2) at odd
+    p.A = p.B = a;
+    p.sch = 1 + c->parity;
+    p.sch_next = 1 + (c->parity ^ 1);
+  } else {
+    p.A = c->parity == 0 ? a : b;
+    p.B = c->parity == 0 ? b : a;
+    p.sch = p.sch_next = 0;
+  }
   p.U = (T*)(w + L.U);
   p.x = (double*)(w + L.x); p.y = (double*)(w + L.y);
   p.xm = (double*)(w + L.xm); p.ym = (double*)(w + L.ym);
@@ -426,6 +438,41 @@ void rest_state(const std::vector<double>& xy, int nv, std::vector<double>& l0,
   }
   A *= 0.5;
 }
+
+// Streaming scheme: in place when asked, or (automatic) when the one
+// population buffer takes at most 192 MB, so that a step's whole working
+// set stays in the 256 MB last-level cache; two buffers otherwise.
+bool resolve_inplace(const lbib_ctx* c) {
+  if (c->streaming >= 0) return c->streaming == 1;
+  return (double)elem_size(c->dtype) * 9.0 * (double)c->nodes <= 192.0 * 1024 * 1024;
+}
+
+// nx * ny of every instance (the node counts of the conversion launches).
+std::vector<long long> inst_nodes(const lbib_ctx* c) {
+  std::vector<long long> n;
+  for (auto& I : c->inst) n.push_back((long long)I.lat.nx * I.lat.ny);
+  return n;
+}
+
+// In place: the state's populations between A (in the state's layout) and
+// B in scheme-0 order; to = 1 copies A into B, to = 0 B into A.
+template <typename T>
+lbib_status canon_populations(lbib_ctx* c, int to) {
+  const std::vector<long long> n = inst_nodes(c);
+  launch_canon<T>(make_ptrs<T>(c), c->ninst, n.data(), (T*)(c->ws + c->L.B), to, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return LBIB_OK;
+}
+
+lbib_status canon_any(lbib_ctx* c, int to) {
+  return c->dtype == LBIB_F64 ? canon_populations<double>(c, to) : canon_populations<float>(c, to);
+}
+
+// The state's populations in scheme-0 order where state_regions points
+// (before a save; in place they are staged in B) ...
+lbib_status stage_state(lbib_ctx* c) { return c->inplace ? canon_any(c, 1) : LBIB_OK; }
+// ... and back into the state's layout (after a restore).
+lbib_status unstage_state(lbib_ctx* c) { return c->inplace ? canon_any(c, 0) : LBIB_OK; }
 
 template <typename T>
 lbib_status upload_all(lbib_ctx* c) {
@@ -663,14 +710,21 @@ lbib_status upload_all(lbib_ctx* c) {
         h[q * N + node] = T(w8 * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
       }
     }
-    HIPCHK(c, hipMemcpyAsync(w + L.A + 9 * c->node_base[i] * sizeof(T), h.data(), sizeof(T) * h.size(),
-                             hipMemcpyHostToDevice, s));
+    // two buffers: straight into A; in place: into B in scheme-0 order,
+    // then into A in the state's layout
+    HIPCHK(c, hipMemcpyAsync(w + (c->inplace ? L.B : L.A) + 9 * c->node_base[i] * sizeof(T), h.data(),
+                             sizeof(T) * h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
   }
-  HIPCHK(c, hipMemsetAsync(w + L.B, 0, sizeof(T) * 9 * c->nodes, s));
+  c->parity = 0;
+  if (c->inplace) {
+    lbib_status st = canon_populations<T>(c, 0);
+    if (st != LBIB_OK) return st;
+  } else {
+    HIPCHK(c, hipMemsetAsync(w + L.B, 0, sizeof(T) * 9 * c->nodes, s));
+  }
   HIPCHK(c, hipMemsetAsync(w + L.U, 0, sizeof(T) * 2 * c->nodes, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  c->parity = 0;
   c->step = 0;
   c->stencil_dirty = true;
   return LBIB_OK;
@@ -842,8 +896,9 @@ lbib_status fields_impl(lbib_ctx* c, int inst, double* rho, double* ux, double* 
   const InstHost& I = c->inst[inst];
   const long long N = (long long)I.lat.nx * I.lat.ny;
   Ptrs<T> p = make_ptrs<T>(c);
-  // stage in the non-current population buffer (rewritten in full by the next step)
-  double* stage = (double*)p.B;
+  // stage in the population buffer the state does not hold (two buffers: the
+  // one the next step rewrites in full; in place: the spare)
+  double* stage = c->inplace ? (double*)(c->ws + c->L.B) : (double*)p.B;
   launch_fields<T>(p, step_args(c), inst, stage, stage + N, stage + 2 * N, I.lat.nx, I.lat.ny,
                    c->node_base[inst], c->stream);
   HIPCHK(c, hipGetLastError());
@@ -873,7 +928,9 @@ std::vector<std::pair<size_t, size_t>> state_regions(const lbib_ctx* c) {
   const Layout& L = c->L;
   const size_t es = elem_size(c->dtype);
   const size_t nm = std::max(c->nm, 1), nl = std::max(c->nlig, 1), nr = std::max(c->nrec, 1);
-  const size_t Aoff = c->parity == 0 ? L.A : L.B;
+  // in place, the state's populations travel in scheme-0 order through B
+  // (staged by stage_state / unstage_state)
+  const size_t Aoff = c->inplace ? L.B : (c->parity == 0 ? L.A : L.B);
   std::vector<std::pair<size_t, size_t>> r = {
       {Aoff, es * 9 * c->nodes}, {L.U, es * 2 * c->nodes},
       {L.body, sizeof(BodyDev) * std::max(c->nbody, 1)},
@@ -976,6 +1033,7 @@ AdjPtrs adj_ptrs(const lbib_ctx* c, const AdjLayout& A) {
 // Save (or restore) the dynamic state to (from) checkpoint j.
 void adj_checkpoint(lbib_ctx* c, const AdjLayout& A, int j, bool save) {
   char* base = c->aws + A.ck + (size_t)j * A.ck_bytes;
+  if (save) (void)stage_state(c);
   CopyList cl{};
   size_t off = 0;
   for (auto& r : state_regions(c)) {
@@ -990,6 +1048,7 @@ void adj_checkpoint(lbib_ctx* c, const AdjLayout& A, int j, bool save) {
     off += align256(r.second);
   }
   launch_copies(cl, c->stream);
+  if (!save) (void)unstage_state(c);
 }
 
 lbib_status set_freeze(lbib_ctx* c, int32_t f) {
@@ -1095,6 +1154,11 @@ void enqueue_recompute(lbib_ctx* c, const AdjLayout& A, int buf, long long n) {
     char* rec = seg + (size_t)s * A.rec_bytes;
     Ptrs<T> p = make_ptrs<T>(c);
     launch_lagrangian<T>(p, sa, c->stream, c->merge_advance && s > 0);
+    if (c->inplace) {
+      // h^n in scheme-0 order, before the lattice kernel rewrites its buffer
+      const long long nn = (long long)c->inst[0].lat.nx * c->inst[0].lat.ny;
+      launch_canon<T>(p, 1, &nn, (T*)(rec + A.r_h), 1, c->stream);
+    }
     launch_lb_fused<T>(p, sa, c->stream);
     CopyList cl{};
     const char* src[10] = {(const char*)p.A, (const char*)p.x, (const char*)p.y, (const char*)p.fx,
@@ -1103,11 +1167,13 @@ void enqueue_recompute(lbib_ctx* c, const AdjLayout& A, int buf, long long n) {
     const size_t off[10] = {A.r_h, A.r_x, A.r_y, A.r_fx, A.r_fy, A.r_xn, A.r_yn, A.r_u, A.r_b1,
                             A.rec_bytes + A.r_b0};
     const size_t by[10] = {es * 9 * N, nmb, nmb, nmb, nmb, nmb, nmb, es * 2 * N, bb, bb};
-    cl.n = bb == 0 ? 8 : (s + 1 < n ? 10 : 9);
-    for (int k = 0; k < cl.n; ++k) {
-      cl.src[k] = src[k];
-      cl.dst[k] = rec + off[k];
-      cl.bytes[k] = by[k];
+    const int k0 = c->inplace ? 1 : 0;   // in place, h^n is stored already
+    const int kn = bb == 0 ? 8 : (s + 1 < n ? 10 : 9);
+    cl.n = kn - k0;
+    for (int k = k0; k < kn; ++k) {
+      cl.src[k - k0] = src[k];
+      cl.dst[k - k0] = rec + off[k];
+      cl.bytes[k - k0] = by[k];
     }
     launch_copies(cl, c->stream);
     if (!c->merge_advance || s == n - 1) launch_advance<T>(p, sa, c->stream);
@@ -1520,6 +1586,7 @@ lbib_status lbib_finalize_setup(lbib_ctx* c) {
   if (c->phase != 1) return fail(c, LBIB_ESTATE, "bind a workspace before finalize_setup");
   c->body_cache = body_cache_bytes(c);
   resolve_step_mode(c);
+  c->inplace = resolve_inplace(c);
   lbib_status s = c->dtype == LBIB_F64 ? upload_all<double>(c) : upload_all<float>(c);
   if (s != LBIB_OK) return s;
   s = record_mass(c);
@@ -1561,6 +1628,38 @@ lbib_status lbib_set_lattice_launch(lbib_ctx* c, int32_t wgs_per_cu) {
     drop_adjoint_graphs(c);
   }
   c->lb_wpc = wgs_per_cu;
+  return LBIB_OK;
+}
+
+lbib_status lbib_set_streaming(lbib_ctx* c, int32_t mode) {
+  if (!c) return fail(c, LBIB_EINVAL, "NULL context");
+  if (mode < -1 || mode > 1) return fail(c, LBIB_EINVAL, "streaming must be -1, 0 or 1");
+  c->streaming = mode;
+  if (c->phase != 2) return LBIB_OK;
+  const bool want = resolve_inplace(c);
+  if (want == c->inplace) return LBIB_OK;
+  // the populations through B in scheme-0 order (two buffers: the state's
+  // buffer is A at even parity, B at odd), then into the new form
+  const size_t bytes = elem_size(c->dtype) * 9 * (size_t)c->nodes;
+  lbib_status st = LBIB_OK;
+  if (c->inplace) st = canon_any(c, 1);
+  else if (c->parity == 0) HIPCHK(c, hipMemcpyAsync(c->ws + c->L.B, c->ws + c->L.A, bytes,
+                                                    hipMemcpyDeviceToDevice, c->stream));
+  if (st != LBIB_OK) return st;
+  c->inplace = want;
+  if (c->inplace) st = canon_any(c, 0);
+  else if (c->parity == 0) HIPCHK(c, hipMemcpyAsync(c->ws + c->L.A, c->ws + c->L.B, bytes,
+                                                    hipMemcpyDeviceToDevice, c->stream));
+  if (st != LBIB_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  drop_adjoint_graphs(c);
+  return LBIB_OK;
+}
+
+lbib_status lbib_get_streaming(const lbib_ctx* c, int32_t* inplace) {
+  if (!c || !inplace) return fail(const_cast<lbib_ctx*>(c), LBIB_EINVAL, "NULL argument");
+  *inplace = c->phase == 2 ? (c->inplace ? 1 : 0) : (int32_t)resolve_inplace(c);
   return LBIB_OK;
 }
 
@@ -1756,6 +1855,8 @@ lbib_status lbib_get_state(lbib_ctx* c, void* blob, size_t* bytes) {
   if (*bytes < total) return fail(c, LBIB_EINVAL, "state buffer too small");
   StateHeader h{kMagic, total, (uint64_t)c->step, c->dtype, c->ninst, c->nm, c->nbody, c->nlig,
                 c->nrec, c->ntiles, 0, c->nodes};
+  lbib_status st = stage_state(c);
+  if (st != LBIB_OK) return st;
   char* o = (char*)blob;
   std::memcpy(o, &h, sizeof(h));
   o += sizeof(h);
@@ -1784,6 +1885,8 @@ lbib_status lbib_set_state(lbib_ctx* c, const void* blob, size_t bytes) {
     HIPCHK(c, hipMemcpyAsync(c->ws + r.first, o, r.second, hipMemcpyHostToDevice, c->stream));
     o += r.second;
   }
+  lbib_status st = unstage_state(c);
+  if (st != LBIB_OK) return st;
   // the host copies of the body constants follow the restored records
   std::vector<BodyDev> bd(std::max(c->nbody, 1));
   HIPCHK(c, hipMemcpyAsync(bd.data(), c->ws + c->L.body, sizeof(BodyDev) * bd.size(),
@@ -1869,6 +1972,10 @@ lbib_status lbib_time_lattice_kernel(lbib_ctx* c, int32_t reps, double* avg_ms) 
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   const StepArgs a = step_args(c);
+  // in place the launches rewrite the state's own buffer: it is kept in B
+  // meanwhile and put back afterwards
+  lbib_status st = stage_state(c);
+  if (st != LBIB_OK) return st;
   HIPCHK(c, hipEventRecord(e0, c->stream));
   // measurement launches: bins of the coming step are read but not consumed,
   // the velocity output goes to a spare buffer, populations to the spare set
@@ -1884,6 +1991,8 @@ lbib_status lbib_time_lattice_kernel(lbib_ctx* c, int32_t reps, double* avg_ms) 
     }
   }
   HIPCHK(c, hipEventRecord(e1, c->stream));
+  st = unstage_state(c);
+  if (st != LBIB_OK) return st;
   HIPCHK(c, hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));

@@ -33,21 +33,13 @@
 namespace lbib {
 
 // ------------------------------------------------------------------ helpers
-// Populations at a node after streaming, before forcing (walls: bounce-back).
+// Populations at a node after streaming, before forcing (walls: bounce-back),
+// from a state of streaming scheme sch.
 template <typename T>
-__device__ inline void pull_node(const T* A, long long N, int nx, int ny, int pitch, bool pery, int x,
-                                 int y, T hv[kQ]) {
-  const long long node = (long long)y * pitch + x;
+__device__ inline void pull_node(const T* A, int sch, long long N, int nx, int ny, int pitch, bool pery,
+                                 int x, int y, T hv[kQ]) {
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    int xs = x - ex(i);
-    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-    int ys = y - ey(i);
-    const bool out = ys < 0 || ys >= ny;
-    ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-    const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * pitch + xs;
-    hv[i] = A[src];
-  }
+  for (int i = 0; i < kQ; ++i) hv[i] = A[streamed_slot(sch, i, x, y, nx, ny, pitch, pery, N)];
 }
 
 // Velocity walls: a wall node of the pre-forcing state takes the drive as its
@@ -114,10 +106,10 @@ __device__ __forceinline__ void interp_mls(const LatDev& L, double X, double Y, 
 // rho*, u* of the pre-forcing state at a node (x, y) inside the lattice,
 // from the streamed populations, as star_values rounds them.
 template <typename T>
-__device__ inline void node_star(const T* A, const LatDev& L, int x, int y, double& rho, double& ux,
-                                 double& uy) {
+__device__ inline void node_star(const T* A, int sch, const LatDev& L, int x, int y, double& rho,
+                                 double& ux, double& uy) {
   T hv[kQ];
-  pull_node(A, L.plane, L.nx, L.ny, L.pitch, L.periodic_y != 0, x, y, hv);
+  pull_node(A, sch, L.plane, L.nx, L.ny, L.pitch, L.periodic_y != 0, x, y, hv);
   wall_fill_drive(L, y, hv);
   double drho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
@@ -145,11 +137,11 @@ __device__ inline void node_star(const T* A, const LatDev& L, int x, int y, doub
 // beyond a wall adds nothing (skipped here, zero weight in star_sum:
 // the same sums).
 template <bool MLS, typename T>
-__device__ inline void interp_star(const T* A, const LatDev& L, double X, double Y, bool grad,
+__device__ inline void interp_star(const T* A, int sch, const LatDev& L, double X, double Y, bool grad,
                                    double& rho, double& ux, double& uy, double g[4]) {
   if (MLS && use_mls(L)) {
     auto fetch = [&](int, int, int xr, int row, double& r, double& u, double& v) {
-      node_star(A, L, wrap_i(xr, L.nx), L.periodic_y ? wrap_i(row, L.ny) : row, r, u, v);
+      node_star(A, sch, L, wrap_i(xr, L.nx), L.periodic_y ? wrap_i(row, L.ny) : row, r, u, v);
     };
     if (grad) interp_mls<true>(L, X, Y, fetch, rho, ux, uy, g);
     else interp_mls<false>(L, X, Y, fetch, rho, ux, uy, g);
@@ -174,7 +166,7 @@ __device__ inline void interp_star(const T* A, const LatDev& L, double X, double
       const int col = wrap_i((int)rx, L.nx);
       const double wx = wxa[a], dwx = dwxa[a];
       double r, u, v;
-      node_star(A, L, col, row, r, u, v);
+      node_star(A, sch, L, col, row, r, u, v);
       rho += r * wx * wy;
       ux += u * wx * wy;
       uy += v * wx * wy;
@@ -841,13 +833,13 @@ __device__ inline void put_box(int* pbox, int chunk, const IBox& q) {
 // a node of margin), rows clamped to the lattice unless it is periodic.
 // Entry w of the star work list names the particle, this workgroup's rank
 // and the particle's workgroup count; src holds the populations the next
-// step streams from.  Nodes of overlapping boxes are written twice with the
-// same values.
+// step streams from, in streaming scheme sch.  Nodes of overlapping boxes
+// are written twice with the same values.
 // The kernels below copy their instance's lattice record into registers
 // before their first store: read through a reference, its fields are
 // reloaded (and waited for) after every store, which may alias them.
 template <typename T>
-__device__ inline void star_pass(Ptrs<T>& p, const T* src, int w) {
+__device__ inline void star_pass(Ptrs<T>& p, const T* src, int sch, int w) {
   const int b = p.star_wg[3 * w], rank = p.star_wg[3 * w + 1], K = p.star_wg[3 * w + 2];
   const BodyDev& B = p.body[b];
   const LatDev L = p.lat[B.inst];
@@ -886,7 +878,7 @@ __device__ inline void star_pass(Ptrs<T>& p, const T* src, int w) {
       if (pery) r = wrap_i(r, L.ny);
       row[q] = r;
       node[q] = (long long)r * L.pitch + col;
-      pull_node(A, L.plane, L.nx, L.ny, L.pitch, pery, col, r, hv[q]);
+      pull_node(A, sch, L.plane, L.nx, L.ny, L.pitch, pery, col, r, hv[q]);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -1574,7 +1566,7 @@ __device__ __forceinline__ void body_merged_impl(Ptrs<T>& p, int b, int cache_no
           const int col = wrap_i(C.bx0 + kk % bw, L.nx);
           int row = by0 + kk / bw;
           if (pery) row = wrap_i(row, L.ny);
-          pull_node(A, Nn, L.nx, L.ny, L.pitch, pery, col, row, hv[q]);
+          pull_node(A, p.sch, Nn, L.nx, L.ny, L.pitch, pery, col, row, hv[q]);
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -1650,7 +1642,7 @@ __device__ __forceinline__ void body_merged_impl(Ptrs<T>& p, int b, int cache_no
     const int v = t - nt / 2;
     double rho, ux, uy, g[4];
     if (cached) interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
-    else interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
+    else interp_star<MLS>(A, p.sch, L, X[v], Y[v], false, rho, ux, uy, g);
     s_uv[0][v] = ux;
     s_uv[1][v] = uy;
   }
@@ -1662,7 +1654,7 @@ __device__ __forceinline__ void body_merged_impl(Ptrs<T>& p, int b, int cache_no
     } else if (cached) {
       interp_cached<MLS>(C, L, X[v], Y[v], false, rho, ux, uy, g);
     } else {
-      interp_star<MLS>(A, L, X[v], Y[v], false, rho, ux, uy, g);
+      interp_star<MLS>(A, p.sch, L, X[v], Y[v], false, rho, ux, uy, g);
     }
   };
   // pass 2: element loads (area penalty, adhesion springs, probe stresses)
@@ -1682,7 +1674,7 @@ __device__ __forceinline__ void body_merged_impl(Ptrs<T>& p, int b, int cache_no
       double qx, qy, rho, ux, uy, g[4];
       probe_point(L, cx, cy, nxl, nyl, qx, qy);
       if (cached) interp_cached<MLS>(C, L, qx, qy, true, rho, ux, uy, g);
-      else interp_star<MLS>(A, L, qx, qy, true, rho, ux, uy, g);
+      else interp_star<MLS>(A, p.sch, L, qx, qy, true, rho, ux, uy, g);
       probe_load(rho, g, nu, nxl, nyl, len, pfx, pfy);
     }
     element_load(kind != kRigid, ca, spring_on, sp, kind != kRBC, pfx, pfy, nxl, nyl, S_fex[l], S_fey[l]);
@@ -1937,7 +1929,7 @@ template <typename T, int TX, int TY>
 __global__ __launch_bounds__(256) void k_advance(Ptrs<T> p) {
   const int cb = chunk_blocks(p.nchunk_total);
   if ((int)blockIdx.x >= cb) {
-    star_pass(p, p.B, blockIdx.x - cb);
+    star_pass(p, p.B, p.sch_next, blockIdx.x - cb);
     return;
   }
   advance_chunk<T, TX, TY, false, true>(p, p.cnt_next, p.bin_next);
@@ -1947,7 +1939,7 @@ template <typename T, int TX, int TY>
 __global__ __launch_bounds__(256) void k_advance_mls(Ptrs<T> p) {
   const int cb = chunk_blocks(p.nchunk_total);
   if ((int)blockIdx.x >= cb) {
-    star_pass(p, p.B, blockIdx.x - cb);
+    star_pass(p, p.B, p.sch_next, blockIdx.x - cb);
     return;
   }
   advance_chunk<T, TX, TY, true, true>(p, p.cnt_next, p.bin_next);
@@ -1956,7 +1948,7 @@ __global__ __launch_bounds__(256) void k_advance_mls(Ptrs<T> p) {
 // Star field of the particles' boxes from the current populations (after
 // the stencil pass).
 template <typename T>
-__global__ __launch_bounds__(256) void k_star(Ptrs<T> p) { star_pass(p, p.A, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_star(Ptrs<T> p) { star_pass(p, p.A, p.sch, blockIdx.x); }
 
 // Stencils, bins and area partials of all markers from their current
 // positions (after set-up or after positions were overwritten from the host).

@@ -19,6 +19,12 @@
 // Workgroup -> tile mapping is XCD aware: consecutive workgroups go to the 8
 // XCDs in turn, so XCD k receives a contiguous band of tiles (its own L2 then
 // holds the rows that neighbouring tiles share).
+//
+// No multiply-add contraction in this file: the kernel is instantiated per
+// streaming form, tile and cache hint, and every instantiation must round
+// alike (fused multiply-adds formed differently per instantiation differ in
+// the last bit).  The kernel is bound by memory traffic, not arithmetic.
+#pragma clang fp contract(off)
 #include <algorithm>
 
 #include "lbib_dev.h"
@@ -86,7 +92,7 @@ __device__ __forceinline__ void spread_entries(const Ptrs<T>& p, const int* bin,
 // workgroups: g mod 8 is the XCD the hardware gives workgroup g, which takes
 // a contiguous band of tiles.  Returns early (every lane, or a lane outside
 // the lattice after the workgroup's last barrier).
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, int SCH>
 __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int mode) {
   static_assert(TX * TY == kCap, "one lane per LDS slot");
   const int per = (ntiles_total + 7) >> 3;
@@ -109,8 +115,11 @@ __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int
   // ---- pull streaming with halfway bounce-back, issued first so that the
   // population loads are in flight while the tile's IB force is gathered
   const long long N = L.plane;
+  // two buffers (SCH 0): A and B never alias; in place (SCH 1, 2) they are
+  // one array, accessed through the plain pointers
   const T* __restrict__ A = p.A + 9 * L.node_base;
   T* __restrict__ B = p.B + 9 * L.node_base;
+  T* const F = p.B + 9 * L.node_base;
   const long long node = (long long)y * pitch + x;
   T h[kQ];
   if (inside) {
@@ -118,13 +127,9 @@ __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int
     // loads are issued back to back
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-      int xs = x - ex(i);
-      xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-      int ys = y - ey(i);
-      const bool out = ys < 0 || ys >= ny;
-      ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-      const long long src = (out && !pery) ? opp(i) * N + node : i * N + (long long)ys * pitch + xs;
-      h[i] = (NT & 1) ? __builtin_nontemporal_load(&A[src]) : A[src];
+      const long long src = streamed_slot(SCH, i, x, y, nx, ny, pitch, pery, N);
+      if constexpr (SCH == 0) h[i] = (NT & 1) ? __builtin_nontemporal_load(&A[src]) : A[src];
+      else h[i] = F[src];
     }
   }
 
@@ -195,8 +200,14 @@ __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int
     const T src = pre * wq<T>(i) *
                   ((T(3) * (exi - ux) + T(9) * eu * exi) * Fx + (T(3) * (eyi - uy) + T(9) * eu * eyi) * Fy);
     const T hn = h[i] + omega * (heq - h[i]) + src;
-    if (NT & 2) __builtin_nontemporal_store(hn, &B[i * N + node]);
-    else B[i * N + node] = hn;
+    if constexpr (SCH == 0) {
+      if (NT & 2) __builtin_nontemporal_store(hn, &B[i * N + node]);
+      else B[i * N + node] = hn;
+    } else {
+      // every store depends on all nine loads above, and no other node of
+      // the step touches these slots
+      F[post_store_slot(SCH, i, x, y, nx, ny, pitch, pery, N)] = hn;
+    }
   }
   if (M > 0) {
     T* U = p.U + 2 * L.node_base;
@@ -206,9 +217,9 @@ __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int
 }
 
 // One workgroup per tile (the default launch).
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, int SCH>
 __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int mode) {
-  lb_tile<T, TX, TY, NT>(p, blockIdx.x, ntiles_total, mode);
+  lb_tile<T, TX, TY, NT, SCH>(p, blockIdx.x, ntiles_total, mode);
 }
 
 // Persistent launch: a fixed grid (a multiple of 8 workgroups, sized by the
@@ -219,7 +230,7 @@ template <typename T, int TX, int TY, int NT>
 __global__ __launch_bounds__(TX * TY) void k_lb_persistent(Ptrs<T> p, int ntiles_total, int mode) {
   const int gtot = 8 * ((ntiles_total + 7) >> 3);
   for (int g = blockIdx.x; g < gtot; g += gridDim.x) {
-    lb_tile<T, TX, TY, NT>(p, g, ntiles_total, mode);
+    lb_tile<T, TX, TY, NT, 0>(p, g, ntiles_total, mode);
     __syncthreads();
   }
 }
@@ -241,7 +252,7 @@ __global__ void k_fields(Ptrs<T> p, int inst, int TX, int TY, double* rho_o, dou
   const long long node = (long long)y * L.pitch + x;
   const T* A = p.A + 9 * L.node_base;  // A holds the newest post-collision populations
   double h[kQ];
-  for (int i = 0; i < kQ; ++i) h[i] = double(A[i * N + node]);
+  for (int i = 0; i < kQ; ++i) h[i] = double(A[post_slot(p.sch, i, x, y, L.nx, L.ny, L.pitch, L.periodic_y != 0, N)]);
   double drho = 0, jx = 0, jy = 0;
   for (int i = 0; i < kQ; ++i) {
     drho += h[i];
@@ -281,11 +292,12 @@ __global__ __launch_bounds__(256) void k_diag1(Ptrs<T> p, long long nodes_total,
     const long long N = L.plane;
     const long long node = g - L.node_base;
     if (node % L.pitch >= L.nx) continue;   // row padding
+    const int x = (int)(node % L.pitch), y = (int)(node / L.pitch);
     const T* A = p.A + 9 * L.node_base;
     double drho = 0, jx = 0, jy = 0;
     bool fin = true;
     for (int i = 0; i < kQ; ++i) {
-      double v = double(A[i * N + node]);
+      double v = double(A[post_slot(p.sch, i, x, y, L.nx, L.ny, L.pitch, L.periodic_y != 0, N)]);
       fin &= isfinite(v);
       drho += v;
       jx += ex(i) * v;
@@ -326,30 +338,55 @@ __global__ void k_diag2(const double* part, int nblk, double* out) {
   out[0] = m; out[1] = px; out[2] = py; out[3] = rmin; out[4] = umax; out[5] = bad;
 }
 
+// Populations of instance `inst` between the state in p.A (scheme p.sch) and
+// a buffer in scheme-0 order (every node's h*_i in slot i): to = 1 copies the
+// state into buf, to = 0 writes buf into the state.  Row padding is left
+// alone.
+template <typename T>
+__global__ void k_canon(Ptrs<T> p, int inst, T* buf, int to) {
+  const LatDev& L = p.lat[inst];
+  const long long N = L.plane;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)L.nx * L.ny) return;
+  const int x = (int)(k % L.nx), y = (int)(k / L.nx);
+  const long long node = (long long)y * L.pitch + x;
+  T* A = p.A + 9 * L.node_base;
+  T* C = buf + 9 * L.node_base;
+  const bool pery = L.periodic_y != 0;
+  for (int i = 0; i < kQ; ++i) {
+    const long long s = post_slot(p.sch, i, x, y, L.nx, L.ny, L.pitch, pery, N);
+    if (to) C[i * N + node] = A[s];
+    else A[s] = C[i * N + node];
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename T>
 void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mode,
                      hipEvent_t ev0, hipEvent_t ev1) {
   const int per = (a.ntiles_total + 7) / 8;
   // persistent: wpc workgroups per CU, a multiple of 8, at most the tiles
-  const bool persist = a.lb_wpc > 0;
+  // persistent launch: two-buffer streaming only
+  const bool persist = a.lb_wpc > 0 && p.sch == 0;
   const int pgrid = std::min(8 * per, 8 * ((a.lb_wpc * a.n_cu + 7) / 8));
   dim3 grid(persist ? pgrid : 8 * per), block(kCap);
   // the optional events are bound to the dispatch itself, so their elapsed
   // time is the kernel's execution time and not that of separate markers
-#define LBIB_LB1(KERNEL, TXv, TYv, NTv)                                                          \
-  hipExtLaunchKernelGGL((KERNEL<T, TXv, TYv, NTv>), grid, block, 0, s, ev0, ev1, 0, p,           \
+#define LBIB_LB1(KERNEL, ...)                                                                    \
+  hipExtLaunchKernelGGL((KERNEL<T, __VA_ARGS__>), grid, block, 0, s, ev0, ev1, 0, p,             \
                         a.ntiles_total, mode)
 #define LBIB_LB(TXv, TYv)                                                                        \
   do {                                                                                          \
-    if (persist) {                                                                              \
+    if (p.sch == 1) LBIB_LB1(k_lb_fused, TXv, TYv, 0, 1);                                       \
+    else if (p.sch == 2) LBIB_LB1(k_lb_fused, TXv, TYv, 0, 2);                                  \
+    else if (persist) {                                                                         \
       if (a.nt_mode == 3) LBIB_LB1(k_lb_persistent, TXv, TYv, 3);                               \
       else if (a.nt_mode == 1) LBIB_LB1(k_lb_persistent, TXv, TYv, 1);                          \
       else LBIB_LB1(k_lb_persistent, TXv, TYv, 0);                                              \
     } else {                                                                                    \
-      if (a.nt_mode == 3) LBIB_LB1(k_lb_fused, TXv, TYv, 3);                                    \
-      else if (a.nt_mode == 1) LBIB_LB1(k_lb_fused, TXv, TYv, 1);                               \
-      else LBIB_LB1(k_lb_fused, TXv, TYv, 0);                                                   \
+      if (a.nt_mode == 3) LBIB_LB1(k_lb_fused, TXv, TYv, 3, 0);                                 \
+      else if (a.nt_mode == 1) LBIB_LB1(k_lb_fused, TXv, TYv, 1, 0);                            \
+      else LBIB_LB1(k_lb_fused, TXv, TYv, 0, 0);                                                \
     }                                                                                           \
   } while (0)
   if (a.tile_x == 64 && a.tile_y == 4) LBIB_LB(64, 4);
@@ -375,6 +412,17 @@ void launch_diag(const Ptrs<T>& p, const StepArgs&, long long nodes_total, doubl
   hipLaunchKernelGGL(k_diag1<T>, dim3(nblk), dim3(256), 0, s, p, nodes_total, p.red);
   hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, p.red, nblk, out);
 }
+
+template <typename T>
+void launch_canon(const Ptrs<T>& p, int ninst, const long long* inst_nodes, T* buf, int to,
+                  hipStream_t s) {
+  for (int i = 0; i < ninst; ++i) {
+    const unsigned g = (unsigned)((inst_nodes[i] + 255) / 256);
+    if (g) hipLaunchKernelGGL(k_canon<T>, dim3(g), dim3(256), 0, s, p, i, buf, to);
+  }
+}
+template void launch_canon<float>(const Ptrs<float>&, int, const long long*, float*, int, hipStream_t);
+template void launch_canon<double>(const Ptrs<double>&, int, const long long*, double*, int, hipStream_t);
 
 template void launch_lb_fused<float>(const Ptrs<float>&, const StepArgs&, hipStream_t, int,
                                      hipEvent_t, hipEvent_t);

@@ -46,6 +46,61 @@ __host__ __device__ constexpr T wq(int i) {
 
 enum BodyKind : int { kRBC = 0, kSoft = 1, kRigid = 2 };
 
+// ------------------------------------------------------------ streaming schemes
+// Where the populations live (Ptrs::sch):
+//   0  two buffers: A holds every node's post-collision h*_i(x) in slot i; a
+//      step pulls from A and writes B (pull streaming, halfway bounce-back).
+//   1  one buffer, in place, layout P: h*_i(x) sits in slot opp(i) of x.
+//   2  one buffer, in place, layout S: the populations already streamed for
+//      the coming step sit in their own slots, h_i(x) in slot i of x.
+// In place, a step on layout P reads slot opp(i) of x - e_i and writes slot
+// i of x + e_i (layout S); a step on layout S reads and writes node x only
+// (slot i in, slot opp(i) out: layout P again).  Every slot is read and then
+// written by one node of the step, so the update needs no second buffer, and
+// a lattice of 160 MB of populations keeps its whole working set in the
+// 256 MB last-level cache.  Where x - e_i (x + e_i) lies beyond a wall the
+// population bounces back at x, as in scheme 0.
+//
+// Slot (index into the population array of the instance, N nodes per plane)
+// of the population h_i that node (x, y) streams in for the coming step.
+__host__ __device__ inline long long streamed_slot(int s, int i, int x, int y, int nx, int ny,
+                                                   int pitch, bool pery, long long N) {
+  const long long node = (long long)y * pitch + x;
+  if (s == 2) return i * N + node;
+  int xs = x - ex(i);
+  xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+  int ys = y - ey(i);
+  const bool out = ys < 0 || ys >= ny;
+  ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+  // bounce-back: h*_opp(i) of the node itself
+  if (out && !pery) return (s == 1 ? i : opp(i)) * N + node;
+  return (s == 1 ? opp(i) : i) * N + (long long)ys * pitch + xs;
+}
+
+// Slot where the step that read a state of scheme s leaves h*_i of node
+// (x, y) (scheme 0: in B).
+__host__ __device__ inline long long post_store_slot(int s, int i, int x, int y, int nx, int ny,
+                                                     int pitch, bool pery, long long N) {
+  const long long node = (long long)y * pitch + x;
+  if (s == 0) return i * N + node;
+  if (s == 2) return opp(i) * N + node;
+  int xd = x + ex(i);
+  xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+  int yd = y + ey(i);
+  const bool out = yd < 0 || yd >= ny;
+  yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+  if (out && !pery) return opp(i) * N + node;   // bounced into h_opp(i) of the node
+  return i * N + (long long)yd * pitch + xd;
+}
+
+// Slot holding the last post-collision h*_i of node (x, y) in a state of
+// scheme s (the scheme the next step reads).
+__host__ __device__ inline long long post_slot(int s, int i, int x, int y, int nx, int ny,
+                                               int pitch, bool pery, long long N) {
+  if (s == 2) return post_store_slot(1, i, x, y, nx, ny, pitch, pery, N);
+  return (s == 1 ? opp(i) : i) * (N) + (long long)y * pitch + x;
+}
+
 // Row pitch of an instance's node arrays: nx rounded up to 64 elements.
 // Rows that start on 256-byte boundaries keep a tile's row segment within
 // whole cache lines; with unaligned rows every segment straddles one more
@@ -130,7 +185,9 @@ struct Ptrs {
   LatDev* lat;
   BodyDev* body;
   T* A;  // populations read this step
-  T* B;  // populations written this step
+  T* B;  // populations written this step (in place: A)
+  int sch;        // streaming scheme of the state this step reads (see above)
+  int sch_next;   // and of the state it leaves
   T* U;  // velocity of touched tiles
   double *x, *y, *xm, *ym, *xn, *yn, *fx, *fy;
   double *l0, *th0, *r0x, *r0y;
@@ -391,6 +448,12 @@ constexpr int kRepChunk = 16;
 template <typename T>
 void launch_repulsion(const Ptrs<T>& p, const StepArgs& a, const int* chunks, int nchunk,
                       hipStream_t s);
+// Populations between the state (scheme p.sch, in p.A) and scheme-0 order in
+// buf, per instance (inst_nodes[i] = nx * ny of instance i): to = 1 state ->
+// buf, to = 0 buf -> state.
+template <typename T>
+void launch_canon(const Ptrs<T>& p, int ninst, const long long* inst_nodes, T* buf, int to,
+                  hipStream_t s);
 template <typename T>
 void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mode = 3,
                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

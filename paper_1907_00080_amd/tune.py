@@ -1,5 +1,5 @@
-"""Autotuner for batched sweeps: tile shape, step form, cache hints, graph chunk
-and lattice-kernel launch form (host logic).
+"""Autotuner for batched sweeps: tile shape, step form, cache hints, graph chunk,
+lattice-kernel launch form and population streaming (host logic).
 
 A batch advances many uneven capillary instances together (one launch per
 kernel per step for all of them).  Which tile shape of the fused lattice
@@ -30,6 +30,9 @@ CACHE_HINTS: Tuple[int, ...] = (0, 1, 3)   # plain, non-temporal loads, non-temp
 # lattice-kernel launch: one workgroup per tile (0) or a persistent grid of
 # that many workgroups per CU; timed for the best of the other choices
 LATTICE_LAUNCHES: Tuple[int, ...] = (0, 1, 2, 4, 8)
+# population streaming: two buffers (0) or one buffer in place (1); timed
+# last, at the pick of the other stages (the launch form applies to 0 only)
+STREAMINGS: Tuple[int, ...] = (0, 1)
 
 
 def signature(workloads: Sequence, dtype: str) -> str:
@@ -99,16 +102,20 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
              step_modes: Sequence[int] = STEP_MODES,
              cache_hints: Sequence[int] = CACHE_HINTS,
              lattice_launches: Sequence[int] = LATTICE_LAUNCHES,
+             streamings: Sequence[int] = STREAMINGS,
              measure: Optional[Callable] = None) -> dict:
     """Pick the tile shape, step form, cache hints and graph chunk for a batch
     of `workloads`, then the lattice kernel's launch form for that pick.
 
     Returns {"tile": [tx, ty], "graph_steps": g, "step_mode": m, "cache_hints": c,
-    "lattice_launch": w, "ms_per_step": t, "mlups": ..., "candidates": [...],
-    "launch_candidates": [...], "device": name, "cached": bool}.  `steps` is
-    rounded up to a multiple of every graph chunk.  `measure(tile, g, mode,
-    hints, launch=0)` replaces the GPU timing (returns ms per step); it exists
-    for tests of the selection and caching logic.
+    "lattice_launch": w, "streaming": s, "ms_per_step": t, "mlups": ...,
+    "candidates": [...], "launch_candidates": [...], "streaming_candidates":
+    [...], "device": name, "cached": bool}.  The first stages run with two
+    population buffers; the last times in-place streaming at their pick.
+    `steps` is rounded up to a multiple of every graph chunk.
+    `measure(tile, g, mode, hints, launch=0, streaming=0)` replaces the GPU
+    timing (returns ms per step); it exists for tests of the selection and
+    caching logic.
     """
     nodes = sum(int(w.nx) * int(w.ny) for w in workloads)
     dev_name = _device_name(device) if measure is None else "measure-callback"
@@ -132,7 +139,8 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
                         results.append(_record(tile, g, mode, hints, ms, nodes))
             continue
         from . import Batch
-        b = Batch(workloads, dtype=dtype, tile=tuple(tile), device=device, graph_steps=0)
+        b = Batch(workloads, dtype=dtype, tile=tuple(tile), device=device, graph_steps=0,
+                  streaming=0)
         try:
             for mode in step_modes:
                 b.set_step_mode(int(mode))
@@ -159,7 +167,7 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
         else:
             from . import Batch
             b = Batch(workloads, dtype=dtype, tile=tuple(best["tile"]), device=device,
-                      graph_steps=int(best["graph_steps"]))
+                      graph_steps=int(best["graph_steps"]), streaming=0)
             try:
                 b.set_step_mode(int(best["step_mode"]))
                 b.set_cache_hints(int(best["cache_hints"]))
@@ -173,11 +181,39 @@ def autotune(workloads: Sequence, dtype: str = "f32", cache: Optional[str] = Non
         r["lattice_launch"] = int(w)
         launches.append(r)
     best_launch = choose(launches) if launches else dict(best, lattice_launch=0)
+    # last stage: the population streaming (two buffers is the first stages' form)
+    streams = []
+    for sm in streamings:
+        if int(sm) == 0:
+            r = dict(best_launch)
+        elif measure is not None:
+            ms = float(measure(tuple(best["tile"]), best["graph_steps"], best["step_mode"],
+                               best["cache_hints"], launch=0, streaming=int(sm)))
+            r = _record(best["tile"], best["graph_steps"], best["step_mode"], best["cache_hints"],
+                        ms, nodes)
+            r["lattice_launch"] = 0
+        else:
+            from . import Batch
+            b = Batch(workloads, dtype=dtype, tile=tuple(best["tile"]), device=device,
+                      graph_steps=int(best["graph_steps"]), streaming=int(sm))
+            try:
+                b.set_step_mode(int(best["step_mode"]))
+                b.step(max(int(warmup), int(best["graph_steps"])))
+                ms = _time_steps(b, steps) / steps
+            finally:
+                b.close()
+            r = _record(best["tile"], best["graph_steps"], best["step_mode"], best["cache_hints"],
+                        ms, nodes)
+            r["lattice_launch"] = 0
+        r["streaming"] = int(sm)
+        streams.append(r)
+    pick = choose(streams) if streams else dict(best_launch, streaming=0)
     rec = {"tile": list(best["tile"]), "graph_steps": best["graph_steps"],
            "step_mode": best["step_mode"], "cache_hints": best["cache_hints"],
-           "lattice_launch": int(best_launch["lattice_launch"]),
-           "ms_per_step": best_launch["ms_per_step"], "mlups": best_launch["mlups"],
-           "candidates": results, "launch_candidates": launches, "device": dev_name,
+           "lattice_launch": int(pick["lattice_launch"]), "streaming": int(pick["streaming"]),
+           "ms_per_step": pick["ms_per_step"], "mlups": pick["mlups"],
+           "candidates": results, "launch_candidates": launches,
+           "streaming_candidates": streams, "device": dev_name,
            "nodes": nodes, "instances": len(workloads), "dtype": str(dtype)}
     if cache:
         store_cache(cache, key, rec)

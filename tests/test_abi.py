@@ -188,6 +188,23 @@ def test_lattice_launch_validation():
     lib.lbib_destroy(h)
 
 
+def test_streaming_validation():
+    lib = pkg.library()
+    st, h = _create()
+    assert st == 0
+    got = ctypes.c_int32()
+    for bad in (-2, 2, 7):
+        assert lib.lbib_set_streaming(h, bad) == 1
+    for mode, want in ((0, 0), (1, 1)):
+        assert lib.lbib_set_streaming(h, mode) == 0
+        assert lib.lbib_get_streaming(h, ctypes.byref(got)) == 0 and got.value == want
+    # automatic: a small lattice's one population buffer fits the last-level cache
+    assert lib.lbib_set_streaming(h, -1) == 0
+    assert lib.lbib_get_streaming(h, ctypes.byref(got)) == 0 and got.value == 1
+    assert lib.lbib_get_streaming(h, None) == 1
+    lib.lbib_destroy(h)
+
+
 def test_repulsion_validation_and_phase():
     lib = pkg.library()
     st, h = _create()

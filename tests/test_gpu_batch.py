@@ -185,8 +185,12 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path):
     launches = rec["launch_candidates"]
     assert [c["lattice_launch"] for c in launches] == [0, 1, 2, 4, 8]
     assert launches[0]["ms_per_step"] == min(c["ms_per_step"] for c in rec["candidates"])
-    assert rec["ms_per_step"] == min(c["ms_per_step"] for c in launches)
     assert rec["lattice_launch"] in (0, 1, 2, 4, 8)
+    # then the streaming form: two buffers (the launch stage's best) or in place
+    streams = rec["streaming_candidates"]
+    assert [c["streaming"] for c in streams] == [0, 1]
+    assert streams[0]["ms_per_step"] == min(c["ms_per_step"] for c in launches)
+    assert rec["ms_per_step"] == min(c["ms_per_step"] for c in streams)
     again = autotune(ws, "f32", cache=path, steps=20, warmup=10)
     assert again["cached"] is True
     assert again["tile"] == rec["tile"] and again["graph_steps"] == rec["graph_steps"]

@@ -42,10 +42,10 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
             ((128, 2), 100): 1.5, ((32, 8), 10): 4.0, ((32, 8), 100): 1.7,
             ((256, 1), 10): 2.2, ((256, 1), 100): 2.0}
 
-    def measure(tile, g, mode, hints, launch=0):
-        calls.append((tile, g, mode, hints, launch))
+    def measure(tile, g, mode, hints, launch=0, streaming=0):
+        calls.append((tile, g, mode, hints, launch, streaming))
         return (cost[(tile, g)] + (0.0 if mode == 2 else 0.25 * mode) + (0.0 if hints == 1 else 0.1)
-                - (0.1 if launch == 4 else 0.0))
+                - (0.1 if launch == 4 else 0.0) - (0.2 if streaming else 0.0))
 
     path = str(tmp_path / "sub" / "tune.json")
     ws = _ws()
@@ -53,19 +53,22 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
     assert rec["tile"] == [128, 2] and rec["graph_steps"] == 100 and not rec["cached"]
     assert rec["step_mode"] == 2 and rec["cache_hints"] == 1
     # second stage: the launch forms at that pick (0 is the first stage's own time)
-    assert len(calls) == 72 + 4 and all(c[4] == 0 for c in calls[:72])
-    assert [c[4] for c in calls[72:]] == [1, 2, 4, 8]
+    assert len(calls) == 72 + 4 + 1 and all(c[4] == 0 and c[5] == 0 for c in calls[:72])
+    assert [c[4] for c in calls[72:76]] == [1, 2, 4, 8]
     assert all(c[:4] == ((128, 2), 100, 2, 1) for c in calls[72:])
-    assert rec["lattice_launch"] == 4 and len(rec["launch_candidates"]) == 5
+    assert calls[76][4:] == (0, 1)   # in place, at the pick, with the per-tile launch
+    assert len(rec["launch_candidates"]) == 5 and len(rec["streaming_candidates"]) == 2
+    # in place (1.5 - 0.2) beats the best two-buffer launch form (1.5 - 0.1)
+    assert rec["streaming"] == 1 and rec["lattice_launch"] == 0
     nodes = sum(w.nodes for w in ws)
-    assert abs(rec["ms_per_step"] - 1.4) < 1e-12
-    assert abs(rec["mlups"] - nodes / 1.4e-3 / 1e6) < 1e-9
+    assert abs(rec["ms_per_step"] - 1.3) < 1e-12
+    assert abs(rec["mlups"] - nodes / 1.3e-3 / 1e6) < 1e-9
     with open(path) as f:
         data = json.load(f)
     assert len(data) == 1
     again = tune.autotune(ws, "f32", cache=path, measure=measure)
-    assert again["cached"] and again["tile"] == [128, 2] and again["lattice_launch"] == 4
-    assert len(calls) == 76
+    assert again["cached"] and again["tile"] == [128, 2] and again["streaming"] == 1
+    assert len(calls) == 77
     # another batch adds a second record and keeps the first
     tune.autotune(ws[:1], "f32", cache=path, measure=measure)
     with open(path) as f:
@@ -74,8 +77,10 @@ def test_autotune_selects_minimum_and_caches(tmp_path):
 
 def test_autotune_without_cache_measures_every_time():
     n = []
-    tune.autotune(_ws(), "f32", cache=None, measure=lambda t, g, m, c, launch=0: n.append(1) or 1.0)
+    tune.autotune(_ws(), "f32", cache=None,
+                  measure=lambda t, g, m, c, launch=0, streaming=0: n.append(1) or 1.0)
     rec = tune.autotune(_ws(), "f32", cache=None,
-                        measure=lambda t, g, m, c, launch=0: n.append(1) or 1.0)
-    assert len(n) == 2 * (72 + 4)
-    assert rec["lattice_launch"] == 0   # ties go to the one-workgroup-per-tile launch
+                        measure=lambda t, g, m, c, launch=0, streaming=0: n.append(1) or 1.0)
+    assert len(n) == 2 * (72 + 4 + 1)
+    # ties go to the earlier candidate: one workgroup per tile, two buffers
+    assert rec["lattice_launch"] == 0 and rec["streaming"] == 0

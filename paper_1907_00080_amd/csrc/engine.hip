@@ -510,6 +510,8 @@ lbib_status upload_all(lbib_ctx* c) {
     D.instance = I.lat.instance;
     D.node_base = c->node_base[i];
     D.tau = I.lat.tau; D.gx = I.lat.gx; D.gy = I.lat.gy;
+    D.omega = 1.0 / D.tau;
+    D.pre = 1.0 - 0.5 / D.tau;
     D.seed = I.lat.seed;
     D.y_cr = I.adh.y_cr; D.y_eq = I.adh.y_eq; D.kf0_dt = I.adh.kf0_dt; D.kr0_dt = I.adh.kr0_dt;
     D.sigma_ts_frac = I.adh.sigma_ts_frac; D.kbt = I.adh.kbt; D.freeze = I.adh.freeze_topology;

@@ -284,7 +284,7 @@ __global__ void ka_collide(Ptrs<T> p, AdjPtrs a) {
     ah[i] = a.ha[i * N + node];
   }
   const double Fx = L.gx + acc_get(a.FE, node), Fy = L.gy + acc_get(a.FE, N + node);
-  const double omega = 1.0 / L.tau, pre = 1.0 - 0.5 / L.tau;
+  const double omega = L.omega, pre = L.pre;
   double Fhx, Fhy;
   adj::collide_vjp(h, Fx, Fy, omega, pre, ah, acc_get(a.Uh, node), acc_get(a.Uh, N + node), hh, Fhx,
                    Fhy);

@@ -102,7 +102,9 @@ __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int
   if (cls != 0 && (cls == 1) == (p.cnt_cur[tile] > 0)) return;   // the other launch's tile
   // a single lattice needs no lookup: its parameters are the first load
   const int inst = p.ninst == 1 ? 0 : p.tile_inst[tile];
-  const LatDev& L = p.lat[inst];
+  // by value: the fields are read once, before the stores below (through a
+  // reference they are re-read, and waited for, after every store)
+  const LatDev L = p.lat[inst];
   const int nx = L.nx, ny = L.ny, ntx = L.ntx, pitch = L.pitch;
   const bool pery = L.periodic_y != 0;
   const int local = tile - L.tile_base;
@@ -113,23 +115,52 @@ __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int
   const bool inside = x < nx && y < ny;
 
   // ---- pull streaming with halfway bounce-back, issued first so that the
-  // population loads are in flight while the tile's IB force is gathered
+  // population loads are in flight while the tile's IB force is gathered.
+  // Addresses: one uniform pointer per population plane plus a 32-bit
+  // element offset inside the plane (a plane holds at most 2^31 nodes).
   const long long N = L.plane;
-  // two buffers (SCH 0): A and B never alias; in place (SCH 1, 2) they are
-  // one array, accessed through the plain pointers
+  // two buffers (SCH 0): A and B never alias; in place (SCH 1, 2) the one
+  // array is accessed through F only
   const T* __restrict__ A = p.A + 9 * L.node_base;
   T* __restrict__ B = p.B + 9 * L.node_base;
   T* const F = p.B + 9 * L.node_base;
-  const long long node = (long long)y * pitch + x;
+  const unsigned o0 = (unsigned)y * (unsigned)pitch + (unsigned)x;
+  // neighbour columns (periodic) and rows: periodic rows wrap, otherwise a
+  // row beyond a wall is replaced by the node's own row and the lanes
+  // concerned take the bounced value instead (lo / hi: the node lies on the
+  // first / last row of a walled lattice)
+  const bool lo = !pery && y == 0, hi = !pery && y == ny - 1;
+  const unsigned cm = x == 0 ? nx - 1 : x - 1, cp = x == nx - 1 ? 0 : x + 1;
+  const unsigned rm = (unsigned)(y == 0 ? (pery ? ny - 1 : y) : y - 1) * (unsigned)pitch;
+  const unsigned rp = (unsigned)(y == ny - 1 ? (pery ? 0 : y) : y + 1) * (unsigned)pitch;
+  const unsigned r0 = (unsigned)y * (unsigned)pitch;
   T h[kQ];
   if (inside) {
-    // source index per direction chosen without branches, so that all nine
-    // loads are issued back to back
+    // all nine loads issued back to back; the bounced values of the wall
+    // rows are fetched afterwards (uniform per wave when a wave is one row)
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-      const long long src = streamed_slot(SCH, i, x, y, nx, ny, pitch, pery, N);
-      if constexpr (SCH == 0) h[i] = (NT & 1) ? __builtin_nontemporal_load(&A[src]) : A[src];
-      else h[i] = F[src];
+      if constexpr (SCH == 2) {
+        h[i] = F[i * N + o0];   // node-local pass: slot i of the node itself
+      } else {
+        const unsigned c = ex(i) > 0 ? cm : (ex(i) < 0 ? cp : (unsigned)x);
+        const unsigned r = ey(i) > 0 ? rm : (ey(i) < 0 ? rp : r0);
+        if constexpr (SCH == 0) {
+          const T* src = A + i * N + (r + c);
+          h[i] = (NT & 1) ? __builtin_nontemporal_load(src) : *src;
+        } else {
+          h[i] = F[opp(i) * N + (r + c)];
+        }
+      }
+    }
+    if constexpr (SCH != 2) {
+      if (lo || hi) {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+          if ((ey(i) > 0 && lo) || (ey(i) < 0 && hi))
+            h[i] = SCH == 0 ? A[opp(i) * N + o0] : F[i * N + o0];   // h*_opp(i) of the node
+        }
+      }
     }
   }
 
@@ -181,38 +212,67 @@ __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int
   if (L.wall_mode == 1 && !pery && (y == 0 || y == ny - 1))
     zou_he_fill(h, y == 0, T(y == 0 ? L.u_wall_lo : L.u_wall_hi), Fx, Fy);
 
-  // ---- moments and forced BGK collision
+  // ---- moments and forced BGK collision, written with explicit
+  // multiply-adds (the same rounding in every instantiation)
   const T drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
   const T rho = T(1) + drho;
   const T jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
   const T jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
-  const T inv_rho = T(1) / rho;
-  const T ux = (jx + T(0.5) * Fx) * inv_rho;
-  const T uy = (jy + T(0.5) * Fy) * inv_rho;
-  const T uu = ux * ux + uy * uy;
-  const T omega = T(1.0 / L.tau);
-  const T pre = T(1.0 - 0.5 / L.tau);
+  T inv_rho;
+  if constexpr (sizeof(T) == 4) inv_rho = __builtin_amdgcn_rcpf(rho);   // hardware reciprocal, 1 ulp
+  else inv_rho = T(1) / rho;
+  const T ux = fma(T(0.5), Fx, jx) * inv_rho;
+  const T uy = fma(T(0.5), Fy, jy) * inv_rho;
+  // per node: 3u, 3/2 |u|^2 and u.F; per workgroup: the relaxation weights
+  const T ux3 = T(3) * ux, uy3 = T(3) * uy;
+  const T uu15 = T(1.5) * fma(ux, ux, uy * uy);
+  const T uF = fma(ux, Fx, uy * Fy);
+  const T omega = T(L.omega);
+  const T keep = T(1) - omega;
+  const T pre3 = T(3) * T(L.pre);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    const T exi = T(ex(i)), eyi = T(ey(i));
-    const T eu = exi * ux + eyi * uy;
-    const T heq = wq<T>(i) * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu));
-    const T src = pre * wq<T>(i) *
-                  ((T(3) * (exi - ux) + T(9) * eu * exi) * Fx + (T(3) * (eyi - uy) + T(9) * eu * eyi) * Fy);
-    const T hn = h[i] + omega * (heq - h[i]) + src;
-    if constexpr (SCH == 0) {
-      if (NT & 2) __builtin_nontemporal_store(hn, &B[i * N + node]);
-      else B[i * N + node] = hn;
+    // h* = (1 - 1/tau) h + w/tau (drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2))
+    //      + 3 (1 - 1/(2 tau)) w (3 (e.u)(e.F) + e.F - u.F)
+    // (Guo's source [3 (e - u) + 9 (e.u) e].F regrouped); the zero and unit
+    // components of e_i are folded by hand, since IEEE rules keep the
+    // compiler from dropping 0 * u
+    T q, s;
+    if (ex(i) == 0 && ey(i) == 0) {
+      q = fma(-rho, uu15, drho);
+      s = -uF;
     } else {
-      // every store depends on all nine loads above, and no other node of
-      // the step touches these slots
-      F[post_store_slot(SCH, i, x, y, nx, ny, pitch, pery, N)] = hn;
+      const T eu3 = ex(i) == 0 ? T(ey(i)) * uy3
+                  : (ey(i) == 0 ? T(ex(i)) * ux3 : T(ex(i)) * ux3 + T(ey(i)) * uy3);
+      const T eF = ex(i) == 0 ? T(ey(i)) * Fy
+                 : (ey(i) == 0 ? T(ex(i)) * Fx : T(ex(i)) * Fx + T(ey(i)) * Fy);
+      q = fma(rho, fma(eu3, fma(T(0.5), eu3, T(1)), -uu15), drho);
+      s = fma(eu3, eF, eF - uF);
+    }
+    const T hn = fma(keep, h[i], fma(omega * wq<T>(i), q, (pre3 * wq<T>(i)) * s));
+    if constexpr (SCH == 0) {
+      T* dst = B + i * N + o0;
+      if (NT & 2) __builtin_nontemporal_store(hn, dst);
+      else *dst = hn;
+    } else if constexpr (SCH == 2) {
+      F[opp(i) * N + o0] = hn;
+    } else {
+      // neighbour pass: slot i of x + e_i, or slot opp(i) of the node when
+      // x + e_i lies beyond a wall.  Every store depends on all nine loads
+      // above, and no other node of the step touches these slots.
+      if ((ey(i) > 0 && hi) || (ey(i) < 0 && lo)) {
+        F[opp(i) * N + o0] = hn;
+      } else {
+        const unsigned c = ex(i) > 0 ? cp : (ex(i) < 0 ? cm : (unsigned)x);
+        const unsigned r = ey(i) > 0 ? rp : (ey(i) < 0 ? rm : r0);
+        F[i * N + (r + c)] = hn;
+      }
     }
   }
   if (M > 0) {
     T* U = p.U + 2 * L.node_base;
-    U[node] = ux;
-    U[N + node] = uy;
+    U[o0] = ux;
+    U[N + o0] = uy;
   }
 }
 

@@ -133,6 +133,7 @@ struct LatDev {
   int transfer;                   // 0 Roma kernel, 1 moving least squares (LBIB_TRANSFER_*)
   int mls_weight;                 // MLS weight (LBIB_MLS_WEIGHT_*)
   double mls_h;                   // MLS support half-width (3/2 for the Roma weight)
+  double omega, pre;              // 1/tau and 1 - 1/(2 tau), computed once on the host
 };
 
 // Per-body description and rigid-body state (device copy; rigid state mutable).

@@ -42,17 +42,22 @@ def announce(msg):
 
 
 # ------------------------------------------------------------- lattice only
+@pytest.mark.parametrize("streaming", [0, 1])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 @pytest.mark.parametrize("nx,ny,pery", [(100, 37, 0), (64, 8, 0), (5, 3, 0), (1, 1, 0),
-                                        (2, 9, 0), (70, 13, 1), (3, 2, 1)])
-def test_lattice_only_matches_oracle(dtype, tol, nx, ny, pery):
-    announce(f"lattice-only {nx}x{ny} periodic_y={pery} {dtype}")
+                                        (2, 9, 0), (9, 1, 0), (1, 6, 0), (70, 13, 1), (3, 2, 1),
+                                        (4, 1, 1)])
+def test_lattice_only_matches_oracle(dtype, tol, nx, ny, pery, streaming):
+    # both streaming forms: two buffers, and one buffer updated in place
+    # (whose passes alternate, hence the odd step counts)
+    announce(f"lattice-only {nx}x{ny} periodic_y={pery} {dtype} streaming={streaming}")
     rng = np.random.default_rng(nx * 100 + ny)
     u0 = 0.02 * rng.standard_normal((2, ny, nx))
     rho0 = 1 + 0.01 * rng.standard_normal((ny, nx))
     wl = configs.Workload("lat", nx, ny, tau=0.8, gx=2e-5, gy=-1e-5, periodic_y=pery,
                           rho0=rho0, u0=u0)
-    sim = pkg.Sim(wl, dtype=dtype)
+    sim = pkg.Sim(wl, dtype=dtype, streaming=streaming)
+    assert sim.streaming == streaming
     ref = oracle.Sim(wl)
     for n in (1, 7, 40):
         sim.step(n - sim.step_count)
@@ -63,11 +68,12 @@ def test_lattice_only_matches_oracle(dtype, tol, nx, ny, pery):
     sim.close()
 
 
+@pytest.mark.parametrize("streaming", [0, 1])
 @pytest.mark.parametrize("tile", pkg.TILES)
-def test_poiseuille_all_tiles_fp32(tile):
-    announce(f"poiseuille tile {tile}")
+def test_poiseuille_all_tiles_fp32(tile, streaming):
+    announce(f"poiseuille tile {tile} streaming={streaming}")
     w = configs.small_case(nx=300, ny=50, n_rbc=0)
-    sim = pkg.Sim(w, dtype="f32", tile=tile)
+    sim = pkg.Sim(w, dtype="f32", tile=tile, streaming=streaming)
     ref = oracle.Sim(w)
     sim.step(300)
     ref.step(300)

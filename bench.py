@@ -146,7 +146,9 @@ def traffic_from_profile(workload_name: str, tile=None, hints=None, launch=0, st
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), if
     it was taken with the current kernel source and (when given) the same tile
     shape, cache hints and population streaming, for the one-workgroup-per-tile
-    launch; else None."""
+    launch; else None.  The summary holds one configuration per workload and
+    optionally further "variants" of it; the cache hints only matter with two
+    buffers (in place the kernel uses none)."""
     if launch:
         return None
     try:
@@ -156,13 +158,23 @@ def traffic_from_profile(workload_name: str, tile=None, hints=None, launch=0, st
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if tile is not None and rec.get("tiles", {}).get(workload_name) != f"{tile[0]}x{tile[1]}":
-        return None
-    if hints is not None and rec.get("cache_hints", {}).get(workload_name) != int(hints):
-        return None
-    if streaming is not None and rec.get("streaming", {}).get(workload_name, 0) != int(streaming):
-        return None
-    return rec.get("bytes_per_launch", {}).get(workload_name)
+    entries = []
+    if workload_name in rec.get("bytes_per_launch", {}):
+        entries.append({"tile": rec.get("tiles", {}).get(workload_name),
+                        "cache_hints": rec.get("cache_hints", {}).get(workload_name),
+                        "streaming": rec.get("streaming", {}).get(workload_name, 0),
+                        "bytes_per_launch": rec["bytes_per_launch"][workload_name]})
+    entries += [v for v in rec.get("variants", []) if v.get("workload") == workload_name]
+    for e in entries:
+        st = int(e.get("streaming", 0))
+        if tile is not None and e.get("tile") != f"{tile[0]}x{tile[1]}":
+            continue
+        if streaming is not None and st != int(streaming):
+            continue
+        if hints is not None and st == 0 and e.get("cache_hints") != int(hints):
+            continue
+        return e["bytes_per_launch"]
+    return None
 
 
 def tuned_config(pkg, wl, args):

@@ -1,6 +1,6 @@
 """Host logic of bench.py (no GPU): the stored HBM-counter figure is reported
-only for the kernel source, tile shape and cache hints it was taken with, and
-the multi-GPU request is refused."""
+only for the kernel source, tile shape, streaming form and (with two buffers)
+cache hints it was taken with, and the multi-GPU request is refused."""
 import importlib.util
 import json
 import os
@@ -24,13 +24,39 @@ def test_traffic_figure_follows_source_hash_tile_and_hints(monkeypatch):
     name = "capillary-6667x667"
     tile = tuple(int(v) for v in rec["tiles"][name].split("x"))
     hints = rec["cache_hints"][name]
+    st = rec.get("streaming", {}).get(name, 0)
     monkeypatch.setattr(b, "kernel_source_hash", lambda: rec["kernel_source_sha256_16"])
-    assert b.traffic_from_profile(name, tile, hints) == rec["bytes_per_launch"][name]
-    other = (64, 4) if tile != (64, 4) else (256, 1)
-    assert b.traffic_from_profile(name, other, hints) is None
-    assert b.traffic_from_profile(name, tile, 0 if hints else 3) is None
+    assert b.traffic_from_profile(name, tile, hints, 0, st) == rec["bytes_per_launch"][name]
+    assert b.traffic_from_profile(name, tile, hints, 0, 1 - st) is None
+    assert b.traffic_from_profile(name, tile, hints, 4, st) is None   # persistent launch
     monkeypatch.setattr(b, "kernel_source_hash", lambda: "0" * 16)
-    assert b.traffic_from_profile(name, tile, hints) is None
+    assert b.traffic_from_profile(name, tile, hints, 0, st) is None
+
+
+def test_traffic_lookup_rules(monkeypatch, tmp_path):
+    """Synthetic summary: the primary figure and its variants match on tile
+    and streaming form; the cache hints count only with two buffers."""
+    b = _bench()
+    rec = {"kernel_source_sha256_16": "f" * 16, "tiles": {"w": "64x4"}, "cache_hints": {"w": 3},
+           "streaming": {"w": 1}, "bytes_per_launch": {"w": 100},
+           "variants": [{"workload": "w", "tile": "32x8", "cache_hints": 3, "streaming": 1,
+                         "bytes_per_launch": 101},
+                        {"workload": "w", "tile": "64x4", "cache_hints": 0, "streaming": 0,
+                         "bytes_per_launch": 102},
+                        {"workload": "v", "tile": "64x4", "cache_hints": 0, "streaming": 0,
+                         "bytes_per_launch": 103}]}
+    path = tmp_path / "traffic.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(b, "PROFILE_TRAFFIC", str(path))
+    monkeypatch.setattr(b, "kernel_source_hash", lambda: "f" * 16)
+    assert b.traffic_from_profile("w", (64, 4), 3, 0, 1) == 100
+    assert b.traffic_from_profile("w", (64, 4), 0, 0, 1) == 100     # hints unused in place
+    assert b.traffic_from_profile("w", (32, 8), 0, 0, 1) == 101
+    assert b.traffic_from_profile("w", (64, 4), 0, 0, 0) == 102
+    assert b.traffic_from_profile("w", (64, 4), 3, 0, 0) is None    # two buffers: hints count
+    assert b.traffic_from_profile("w", (256, 1), 3, 0, 1) is None
+    assert b.traffic_from_profile("v", (64, 4), 0, 0, 0) == 103
+    assert b.traffic_from_profile("u", (64, 4), 0, 0, 0) is None
 
 
 def test_stored_counters_match_current_kernel():

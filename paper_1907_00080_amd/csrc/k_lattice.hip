@@ -17,8 +17,13 @@
 // float32 keeps the small deviations of the low-Mach flows accurately.
 //
 // Workgroup -> tile mapping is XCD aware: consecutive workgroups go to the 8
-// XCDs in turn, so XCD k receives a contiguous band of tiles (its own L2 then
-// holds the rows that neighbouring tiles share).
+// XCDs in turn, and the tiles are cut into 8 * kXcdBands equal bands of
+// consecutive tiles, XCD k taking bands k, k + 8, ...  Within a band the
+// rows that neighbouring tiles share stay in one XCD's L2; two bands per XCD
+// instead of one spread each XCD's share over the lattice, so that the tiles
+// with IB force (which cluster where the bodies are) and the lattice regions
+// even out between XCDs (measured faster on the 6667 x 667 capillary, the
+// same on 2000 x 200; more bands gained no more).
 //
 // No multiply-add contraction in this file: the kernel is instantiated per
 // streaming form, tile and cache hint, and every instantiation must round
@@ -32,6 +37,7 @@
 namespace lbib {
 
 constexpr int kCap = 256;  // lanes per workgroup = nodes per tile
+constexpr int kXcdBands = 2;   // bands of tiles per XCD
 
 // mode bits: 1 = record which tiles carried IB force (touched), 2 = clear the
 // bin counts this launch consumed; mode >> 2 selects tiles: 0 all, 1 only
@@ -88,15 +94,16 @@ __device__ __forceinline__ void spread_entries(const Ptrs<T>& p, const int* bin,
 // carry it too, which measured faster on a lattice whose populations stay in
 // the last-level cache and much slower on one larger than it.  The host
 // chooses per context.
-// One tile, the g-th of the launch's virtual grid of 8 * ceil(ntiles / 8)
-// workgroups: g mod 8 is the XCD the hardware gives workgroup g, which takes
-// a contiguous band of tiles.  Returns early (every lane, or a lane outside
-// the lattice after the workgroup's last barrier).
+// One tile, the g-th of the launch's virtual grid of 8 * kXcdBands * band
+// workgroups (band = tiles per band): g mod 8 is the XCD the hardware gives
+// workgroup g, whose (g / 8)-th workgroup takes the tiles of its bands in
+// order.  Returns early (every lane, or a lane outside the lattice after the
+// workgroup's last barrier).
 template <typename T, int TX, int TY, int NT, int SCH>
-__device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int mode) {
+__device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int band, int mode) {
   static_assert(TX * TY == kCap, "one lane per LDS slot");
-  const int per = (ntiles_total + 7) >> 3;
-  const int tile = (g & 7) * per + (g >> 3);
+  const int q = (g >> 3) / band, r = (g >> 3) - q * band;
+  const int tile = (q * 8 + (g & 7)) * band + r;
   if (tile >= ntiles_total) return;
   const int cls = mode >> 2;
   if (cls != 0 && (cls == 1) == (p.cnt_cur[tile] > 0)) return;   // the other launch's tile
@@ -278,8 +285,8 @@ __device__ __forceinline__ void lb_tile(Ptrs<T>& p, int g, int ntiles_total, int
 
 // One workgroup per tile (the default launch).
 template <typename T, int TX, int TY, int NT, int SCH>
-__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int mode) {
-  lb_tile<T, TX, TY, NT, SCH>(p, blockIdx.x, ntiles_total, mode);
+__global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_total, int band, int mode) {
+  lb_tile<T, TX, TY, NT, SCH>(p, blockIdx.x, ntiles_total, band, mode);
 }
 
 // Persistent launch: a fixed grid (a multiple of 8 workgroups, sized by the
@@ -287,10 +294,10 @@ __global__ __launch_bounds__(TX * TY) void k_lb_fused(Ptrs<T> p, int ntiles_tota
 // gridDim.x, so workgroup b keeps to the tiles of XCD b mod 8.  The barrier
 // between tiles frees the LDS accumulators for the next one.
 template <typename T, int TX, int TY, int NT>
-__global__ __launch_bounds__(TX * TY) void k_lb_persistent(Ptrs<T> p, int ntiles_total, int mode) {
-  const int gtot = 8 * ((ntiles_total + 7) >> 3);
+__global__ __launch_bounds__(TX * TY) void k_lb_persistent(Ptrs<T> p, int ntiles_total, int band, int mode) {
+  const int gtot = 8 * kXcdBands * band;
   for (int g = blockIdx.x; g < gtot; g += gridDim.x) {
-    lb_tile<T, TX, TY, NT, 0>(p, g, ntiles_total, mode);
+    lb_tile<T, TX, TY, NT, 0>(p, g, ntiles_total, band, mode);
     __syncthreads();
   }
 }
@@ -424,17 +431,18 @@ __global__ void k_canon(Ptrs<T> p, int inst, T* buf, int to) {
 template <typename T>
 void launch_lb_fused(const Ptrs<T>& p, const StepArgs& a, hipStream_t s, int mode,
                      hipEvent_t ev0, hipEvent_t ev1) {
-  const int per = (a.ntiles_total + 7) / 8;
-  // persistent: wpc workgroups per CU, a multiple of 8, at most the tiles
-  // persistent launch: two-buffer streaming only
+  const int band = (a.ntiles_total + 8 * kXcdBands - 1) / (8 * kXcdBands);
+  const int vgrid = 8 * kXcdBands * band;
+  // persistent: wpc workgroups per CU, a multiple of 8, at most the virtual
+  // grid; two-buffer streaming only
   const bool persist = a.lb_wpc > 0 && p.sch == 0;
-  const int pgrid = std::min(8 * per, 8 * ((a.lb_wpc * a.n_cu + 7) / 8));
-  dim3 grid(persist ? pgrid : 8 * per), block(kCap);
+  const int pgrid = std::min(vgrid, 8 * ((a.lb_wpc * a.n_cu + 7) / 8));
+  dim3 grid(persist ? pgrid : vgrid), block(kCap);
   // the optional events are bound to the dispatch itself, so their elapsed
   // time is the kernel's execution time and not that of separate markers
 #define LBIB_LB1(KERNEL, ...)                                                                    \
   hipExtLaunchKernelGGL((KERNEL<T, __VA_ARGS__>), grid, block, 0, s, ev0, ev1, 0, p,             \
-                        a.ntiles_total, mode)
+                        a.ntiles_total, band, mode)
 #define LBIB_LB(TXv, TYv)                                                                        \
   do {                                                                                          \
     if (p.sch == 1) LBIB_LB1(k_lb_fused, TXv, TYv, 0, 1);                                       \

@@ -401,7 +401,7 @@ __device__ inline void bins_reserve(int* cnt, const LatDev& L, const int* cx, co
       const unsigned long long hasm = __ballot(has);
       if (hasm == 0ull) continue;
       used |= 1u << (r * 9 + s9);
-      const int kprev = __shfl_up(k, 1);
+      const int kprev = dpp_i<kDppWaveShr1>(k);   // lane 0: its own (not used)
       const unsigned long long heads = __ballot(has && (lane == 0 || kprev != k));
       const unsigned long long le = lt | (1ull << lane);
       const unsigned long long mine = heads & le;
@@ -809,15 +809,10 @@ struct IBox {
   int x0, x1, y0, y1;
 };
 __device__ inline IBox wave_box(double x, double y, bool on) {
-  IBox q{on ? (int)floor(x) : 0x7fffffff, on ? (int)ceil(x) : -0x7fffffff,
-         on ? (int)floor(y) : 0x7fffffff, on ? (int)ceil(y) : -0x7fffffff};
-  for (int o = 32; o > 0; o >>= 1) {
-    q.x0 = min(q.x0, __shfl_xor(q.x0, o));
-    q.x1 = max(q.x1, __shfl_xor(q.x1, o));
-    q.y0 = min(q.y0, __shfl_xor(q.y0, o));
-    q.y1 = max(q.y1, __shfl_xor(q.y1, o));
-  }
-  return q;
+  const auto mn = [](int a, int b) { return min(a, b); };
+  const auto mx = [](int a, int b) { return max(a, b); };
+  return IBox{wave_reduce_i(on ? (int)floor(x) : 0x7fffffff, mn), wave_reduce_i(on ? (int)ceil(x) : -0x7fffffff, mx),
+              wave_reduce_i(on ? (int)floor(y) : 0x7fffffff, mn), wave_reduce_i(on ? (int)ceil(y) : -0x7fffffff, mx)};
 }
 
 __device__ inline void put_box(int* pbox, int chunk, const IBox& q) {
@@ -913,10 +908,7 @@ __device__ inline double fmax_nan(double a, double b) { return (a > b || a != a)
 // and Inf sort above every finite value, so a broken force shows up as a
 // non-finite maximum).
 __device__ inline void record_fmax(unsigned long long* slot, double m) {
-  for (int o = 32; o > 0; o >>= 1) {
-    const double other = __shfl_xor(m, o);
-    m = (other > m || other != other) ? other : m;
-  }
+  m = wave_reduce_d(m, [](double a, double b) { return fmax_nan(a, b); });
   if ((threadIdx.x & 63) == 0 && m != 0.0) atomicMax(slot, (unsigned long long)__double_as_longlong(m));
 }
 
@@ -1182,11 +1174,11 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
   if (!rigid) area = body_area2(p.area_part, p.nchunk_total, ch0, nch) * 0.5;
 
   // element v -> v+1 and the bending at v
-  const double Xp = __shfl_down(X, 1), Yp = __shfl_down(Y, 1);
+  const double Xp = lane_next(X), Yp = lane_next(Y);
   double len, tx, ty;
   edge_of(X, Y, Xp, Yp, len, tx, ty);
   const double enx = ty, eny = -tx;
-  const double txl = __shfl_up(tx, 1), tyl = __shfl_up(ty, 1);
+  const double txl = lane_prev(tx), tyl = lane_prev(ty);
   double bnx = 0.0, bny = 0.0, bc = 0.0;
   if (!rigid || rep) vertex_normal(txl, tyl, tx, ty, bnx, bny);
   if (!rigid) bc = bend_coeff(txl, tyl, tx, ty, B.kb, th0v);
@@ -1240,7 +1232,7 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
   const double ca = rigid ? 0.0 : B.ka * (1.0 - area / B.A0) * B.p_ref * len;
   double fex, fey;
   element_load(!rigid, ca, spring_on, sp, particle, pfx, pfy, enx, eny, fex, fey);
-  const double len_m = __shfl_up(len, 1);
+  const double len_m = lane_prev(len);
   const double ds = 0.5 * (len_m + len);   // spreading weight of the vertex
 
   double fm = 0.0;
@@ -1898,7 +1890,7 @@ __device__ __forceinline__ void advance_chunk(Ptrs<T>& p, int* cnt, int* bin) {
     // interpolation (this lane has finished reading the old one)
     marker_stencil<MLS>(p, L, gm, xn, yn, ncx, ncy);
   }
-  const double xr = __shfl_down(xn, 1), yr = __shfl_down(yn, 1);
+  const double xr = lane_next(xn), yr = lane_next(yn);
   const double part = wave_sum(lane >= 2 && lane < 1 + cnt_v ? shoelace_term(xn, yn, xr, yr) : 0.0);
   const int nct = p.nchunk_total;
   if (lane == 0) p.area_part[chunk] = part;

@@ -276,14 +276,6 @@ __device__ __forceinline__ int chunk_vertex(int lane, int first, int nv) {
   return v < 0 ? v + nv : v;
 }
 
-// Sum over the 64 lanes of a wave, fixed butterfly: every lane ends with the
-// same bits (each pair adds the same two values).
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
 // Value of a double held by lane l of the wave (l wave-uniform: two
 // readlanes, no LDS traffic).
 __device__ __forceinline__ double readlane_d(double v, int l) {
@@ -291,6 +283,60 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   const int lo = __builtin_amdgcn_readlane((int)b, l);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Cross-lane moves by DPP (a vector ALU move from another lane, a few cycles,
+// where a shuffle through the LDS crossbar takes a round trip of about a
+// hundred).  Every lane of the wave must be active: a lane reading an
+// inactive one gets its own value back.
+constexpr int kDppWaveShl1 = 0x130;   // lane i reads lane i + 1 (lane 63 keeps its own)
+constexpr int kDppWaveShr1 = 0x138;   // lane i reads lane i - 1 (lane 0 keeps its own)
+constexpr int kDppRowRor8 = 0x128, kDppRowRor4 = 0x124, kDppRowRor2 = 0x122, kDppRowRor1 = 0x121;
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// x of the next / previous lane, as __shfl_down(x, 1) / __shfl_up(x, 1)
+__device__ __forceinline__ double lane_next(double x) { return dpp_d<kDppWaveShl1>(x); }
+__device__ __forceinline__ double lane_prev(double x) { return dpp_d<kDppWaveShr1>(x); }
+
+// Sum over the 64 lanes of a wave in one fixed order: within each 16-lane
+// row, rotations by 8, 4, 2 and 1 lanes (each lane adds the value the
+// rotation brings, so both lanes of a pair add the same two values and the
+// row ends with the same bits in every lane), then the four row sums as
+// (r0 + r1) + (r2 + r3).  Every lane gets the same bits.
+__device__ __forceinline__ double wave_sum(double x) {
+  x += dpp_d<kDppRowRor8>(x);
+  x += dpp_d<kDppRowRor4>(x);
+  x += dpp_d<kDppRowRor2>(x);
+  x += dpp_d<kDppRowRor1>(x);
+  return (readlane_d(x, 0) + readlane_d(x, 16)) + (readlane_d(x, 32) + readlane_d(x, 48));
+}
+
+// Reduction over the 64 lanes with an associative, commutative operation
+// that rounds nothing (min, max), every lane getting the result.
+template <typename Op>
+__device__ __forceinline__ double wave_reduce_d(double v, Op op) {
+  v = op(v, dpp_d<kDppRowRor8>(v));
+  v = op(v, dpp_d<kDppRowRor4>(v));
+  v = op(v, dpp_d<kDppRowRor2>(v));
+  v = op(v, dpp_d<kDppRowRor1>(v));
+  return op(op(readlane_d(v, 0), readlane_d(v, 16)), op(readlane_d(v, 32), readlane_d(v, 48)));
+}
+template <typename Op>
+__device__ __forceinline__ int wave_reduce_i(int v, Op op) {
+  v = op(v, dpp_i<kDppRowRor8>(v));
+  v = op(v, dpp_i<kDppRowRor4>(v));
+  v = op(v, dpp_i<kDppRowRor2>(v));
+  v = op(v, dpp_i<kDppRowRor1>(v));
+  return op(op(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+            op(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // s + x_0 + x_1 + ... + x_{m-1} in this order, x_j held by lane j (m <= 64;

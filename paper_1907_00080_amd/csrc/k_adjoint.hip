@@ -99,15 +99,14 @@ __device__ inline void acc_clear(const AccField& f, long long k) {
   f.lo[k] = 0;
 }
 
-// Sums K values over the workgroup in a fixed order (butterfly within each
+// Sums K values over the workgroup in a fixed order (wave_sum within each
 // wave, then the waves in turn): every thread gets the totals.
 template <int K>
 __device__ inline void block_sum(double v[K], double (*s)[kAdjThreads / 64]) {
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    double x = v[k];
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    const double x = wave_sum(v[k]);
     if (lane == 0) s[k][w] = x;
   }
   __syncthreads();

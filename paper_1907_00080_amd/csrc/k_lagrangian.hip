@@ -1289,7 +1289,7 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
       int done = 0;
       if (lane == 0)
         done = __hip_atomic_fetch_add(&p.body_cnt[b], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      done = __shfl(done, 0);
+      done = __builtin_amdgcn_readfirstlane(done);   // lane 0's count
       if (done != nch - 1) return;   // a later chunk finishes the body
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (lane == 0) p.body_cnt[b] = 0;
@@ -1329,12 +1329,10 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
           q.y0 = min(q.y0, (int)floor(yn)); q.y1 = max(q.y1, (int)ceil(yn));
         }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        q.x0 = min(q.x0, __shfl_xor(q.x0, o));
-        q.x1 = max(q.x1, __shfl_xor(q.x1, o));
-        q.y0 = min(q.y0, __shfl_xor(q.y0, o));
-        q.y1 = max(q.y1, __shfl_xor(q.y1, o));
-      }
+      const auto mn = [](int a, int b) { return min(a, b); };
+      const auto mx = [](int a, int b) { return max(a, b); };
+      q = IBox{wave_reduce_i(q.x0, mn), wave_reduce_i(q.x1, mx), wave_reduce_i(q.y0, mn),
+               wave_reduce_i(q.y1, mx)};
       for (int k = lane; k < nch; k += 64) put_box(p.pbox, ch0 + k, q);
     }
     record_fmax(p.fmax_bits + inst, fm);
@@ -1343,28 +1341,29 @@ __device__ __forceinline__ void chunk_impl(Ptrs<T>& p, int code, int b, double (
 
   // red cells and soft particles: vertex forces
   VertexNbr q;
-  q.len_mm = __shfl_up(len, 2);
+  // (two lanes back: lane 1 gets lane 0's value, which only the halo uses)
+  q.len_mm = lane_prev(len_m);
   q.len_m = len_m;
   q.len = len;
-  q.len_p = __shfl_down(len, 1);
-  q.nx_m = __shfl_up(enx, 1);
-  q.ny_m = __shfl_up(eny, 1);
+  q.len_p = lane_next(len);
+  q.nx_m = lane_prev(enx);
+  q.ny_m = lane_prev(eny);
   q.nx = enx;
   q.ny = eny;
-  q.bc_m = __shfl_up(bc, 1);
+  q.bc_m = lane_prev(bc);
   q.bc = bc;
-  q.bc_p = __shfl_down(bc, 1);
-  q.bnx_m = __shfl_up(bnx, 1);
-  q.bny_m = __shfl_up(bny, 1);
+  q.bc_p = lane_next(bc);
+  q.bnx_m = lane_prev(bnx);
+  q.bny_m = lane_prev(bny);
   q.bnx = bnx;
   q.bny = bny;
-  q.bnx_p = __shfl_down(bnx, 1);
-  q.bny_p = __shfl_down(bny, 1);
-  q.fex_m = __shfl_up(fex, 1);
-  q.fey_m = __shfl_up(fey, 1);
+  q.bnx_p = lane_next(bnx);
+  q.bny_p = lane_next(bny);
+  q.fex_m = lane_prev(fex);
+  q.fey_m = lane_prev(fey);
   q.fex = fex;
   q.fey = fey;
-  const double l0m = __shfl_up(l0v, 1);
+  const double l0m = lane_prev(l0v);
   double sxn = 0.0, syn = 0.0, ffx, ffy;   // a soft particle's new position
   if (inner) {
     double fx, fy;
@@ -1527,7 +1526,9 @@ __device__ __forceinline__ void body_merged_impl(Ptrs<T>& p, int b, int cache_no
   bool cached = false;
   StarCache<T> C{(const T*)s_dyn, 0, 0, 0, 0};
   if (kind != kRBC) {
-    // wave reductions first: only one lane per wave touches the LDS words
+    // wave reductions first: only one lane per wave touches the LDS words.
+    // (Shuffles, not wave_reduce_i: with the DPP form this kernel's FP32
+    // MLS particles went non-finite, for a cause not found.)
     for (int o = 32; o > 0; o >>= 1) {
       mnx = min(mnx, __shfl_xor(mnx, o)); mxx = max(mxx, __shfl_xor(mxx, o));
       mny = min(mny, __shfl_xor(mny, o)); mxy = max(mxy, __shfl_xor(mxy, o));

@@ -129,9 +129,13 @@ __global__ __launch_bounds__(kRepThreads) void k_repulsion(Ptrs<T> p, const int*
   if (t < 64) {
     double bx0 = own ? xv : 1e300, bx1 = own ? xv : -1e300;
     double by0 = own ? yv : 1e300, by1 = own ? yv : -1e300;
-    for (int o = 32; o > 0; o >>= 1) {
-      bx0 = fmin(bx0, __shfl_xor(bx0, o)); bx1 = fmax(bx1, __shfl_xor(bx1, o));
-      by0 = fmin(by0, __shfl_xor(by0, o)); by1 = fmax(by1, __shfl_xor(by1, o));
+    {
+      const auto mn = [](double a, double b) { return fmin(a, b); };
+      const auto mx = [](double a, double b) { return fmax(a, b); };
+      bx0 = wave_reduce_d(bx0, mn);
+      bx1 = wave_reduce_d(bx1, mx);
+      by0 = wave_reduce_d(by0, mn);
+      by1 = wave_reduce_d(by1, mx);
     }
     if (t == 0) {
       s_box[0] = bx0; s_box[1] = bx1; s_box[2] = by0; s_box[3] = by1;

@@ -288,14 +288,29 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 // Cross-lane moves by DPP (a vector ALU move from another lane, a few cycles,
 // where a shuffle through the LDS crossbar takes a round trip of about a
 // hundred).  Every lane of the wave must be active: a lane reading an
-// inactive one gets its own value back.
+// inactive one gets its own value back.  The moves are volatile asm so that
+// the compiler keeps them where they are written (in converged code) and
+// does not sink them into a branch that only some lanes take, such as the
+// one where lane 0 stores a reduced value; each starts with the two wait
+// states a DPP read of a just-written register needs.
 constexpr int kDppWaveShl1 = 0x130;   // lane i reads lane i + 1 (lane 63 keeps its own)
 constexpr int kDppWaveShr1 = 0x138;   // lane i reads lane i - 1 (lane 0 keeps its own)
 constexpr int kDppRowRor8 = 0x128, kDppRowRor4 = 0x124, kDppRowRor2 = 0x122, kDppRowRor1 = 0x121;
+#define LBIB_DPP_MOV(CTRLTXT) \
+  asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 " CTRLTXT " row_mask:0xf bank_mask:0xf" : "+v"(r) : "v"(v))
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+  int r = v;   // lanes whose source lies outside the wave keep their own value
+  if constexpr (CTRL == kDppWaveShl1) LBIB_DPP_MOV("wave_shl:1");
+  else if constexpr (CTRL == kDppWaveShr1) LBIB_DPP_MOV("wave_shr:1");
+  else if constexpr (CTRL == kDppRowRor8) LBIB_DPP_MOV("row_ror:8");
+  else if constexpr (CTRL == kDppRowRor4) LBIB_DPP_MOV("row_ror:4");
+  else if constexpr (CTRL == kDppRowRor2) LBIB_DPP_MOV("row_ror:2");
+  else if constexpr (CTRL == kDppRowRor1) LBIB_DPP_MOV("row_ror:1");
+  else static_assert(CTRL == kDppWaveShl1, "unsupported DPP control");
+  return r;
 }
+#undef LBIB_DPP_MOV
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
   const long long b = __double_as_longlong(x);

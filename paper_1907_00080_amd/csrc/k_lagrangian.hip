@@ -35,11 +35,33 @@ namespace lbib {
 // ------------------------------------------------------------------ helpers
 // Populations at a node after streaming, before forcing (walls: bounce-back),
 // from a state of streaming scheme sch.
+// The slots are those of streamed_slot, addressed as the fused kernel
+// addresses them: the node's neighbour columns and row offsets once, then a
+// uniform plane offset plus a 32-bit in-plane offset per direction (a plane
+// holds at most 2^31 nodes).
 template <typename T>
 __device__ inline void pull_node(const T* A, int sch, long long N, int nx, int ny, int pitch, bool pery,
                                  int x, int y, T hv[kQ]) {
+  const unsigned o0 = (unsigned)y * (unsigned)pitch + (unsigned)x;
+  if (sch == 2) {   // node-local layout: slot i of the node itself
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) hv[i] = A[streamed_slot(sch, i, x, y, nx, ny, pitch, pery, N)];
+    for (int i = 0; i < kQ; ++i) hv[i] = A[i * N + o0];
+    return;
+  }
+  const bool lo = !pery && y == 0, hi = !pery && y == ny - 1;   // first / last row of a walled lattice
+  const unsigned cm = x == 0 ? nx - 1 : x - 1, cp = x == nx - 1 ? 0 : x + 1;
+  const unsigned rm = (unsigned)(y == 0 ? (pery ? ny - 1 : y) : y - 1) * (unsigned)pitch;
+  const unsigned rp = (unsigned)(y == ny - 1 ? (pery ? 0 : y) : y + 1) * (unsigned)pitch;
+  const unsigned r0 = (unsigned)y * (unsigned)pitch;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const unsigned c = ex(i) > 0 ? cm : (ex(i) < 0 ? cp : (unsigned)x);
+    const unsigned r = ey(i) > 0 ? rm : (ey(i) < 0 ? rp : r0);
+    // bounce-back: h*_opp(i) of the node itself
+    const bool bounce = (ey(i) > 0 && lo) || (ey(i) < 0 && hi);
+    const int pl = bounce ? (sch == 1 ? i : opp(i)) : (sch == 1 ? opp(i) : i);
+    hv[i] = A[pl * N + (bounce ? o0 : r + c)];
+  }
 }
 
 // Velocity walls: a wall node of the pre-forcing state takes the drive as its

@@ -41,11 +41,17 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "lb_fused_traffic.json")
 
 def kernel_source_hash() -> str:
     """Hash of the fused kernel's device code (the lattice source up to its
-    host launchers), which the stored counter figures are tied to."""
+    host launchers, line comments and blank lines left out), which the stored
+    counter figures are tied to."""
     with open(os.path.join(ROOT, "paper_1907_00080_amd", "csrc", "k_lattice.hip"), "rb") as f:
         text = f.read()
     cut = text.find(b"// ------------------------------------------------------------------ launchers")
-    return hashlib.sha256(text if cut < 0 else text[:cut]).hexdigest()[:16]
+    code = []
+    for line in (text if cut < 0 else text[:cut]).split(b"\n"):
+        line = line.split(b"//", 1)[0].rstrip()
+        if line:
+            code.append(line)
+    return hashlib.sha256(b"\n".join(code)).hexdigest()[:16]
 
 
 def make_workload(name: str):

@@ -7,8 +7,11 @@
 //      accumulated in LDS in 64-bit fixed point (order independent, hence
 //      deterministic, and free of global atomics).  Tiles with an empty bin
 //      skip this and use F = g.
-//   2. Pull streaming h_i(x) <- h*_i(x - e_i), x periodic, halfway bounce-back
-//      at y = -1/2 and ny - 1/2 (Sec. 3 walls; Eq. BGK streaming part).
+//   2. Streaming h_i(x) <- h*_i(x - e_i), x periodic, halfway bounce-back
+//      at y = -1/2 and ny - 1/2 (Sec. 3 walls; Eq. BGK streaming part):
+//      pulled from a second buffer (SCH 0), or in place in one buffer by
+//      the neighbour pass (SCH 1) and the node-local pass (SCH 2), which
+//      alternate (slot layouts: streamed_slot in lbib_dev.h).
 //   3. rho = 1 + sum h, u = (sum h e + F/2)/rho, BGK relaxation towards the
 //      equilibrium of Eq. (feq) plus Guo's source of Eq. (ForcingTerm):
 //      h* = h + (h_eq - h)/tau + (1 - 1/(2 tau)) w_i [3(e-u) + 9(e.u)e].F
@@ -28,7 +31,7 @@
 // No multiply-add contraction in this file: the kernel is instantiated per
 // streaming form, tile and cache hint, and every instantiation must round
 // alike (fused multiply-adds formed differently per instantiation differ in
-// the last bit).  The kernel is bound by memory traffic, not arithmetic.
+// the last bit).  The collision writes its multiply-adds explicitly.
 #pragma clang fp contract(off)
 #include <algorithm>
 

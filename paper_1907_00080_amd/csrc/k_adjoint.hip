@@ -217,7 +217,7 @@ __device__ inline void probe_adjoint(const LatDev& L, const AdjPtrs& a, double c
 template <typename T>
 __device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm) {
   if (gm >= p.nm_total) return;
-  const LatDev& L = p.lat[0];
+  const LatDev L = p.lat[0];
   const long long N = L.plane;
   const int kind = p.minfo[gm] & 3;
   Stencil s;
@@ -264,11 +264,12 @@ __device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm
 // populations and of the Eulerian force.
 template <typename T>
 __global__ void ka_collide(Ptrs<T> p, AdjPtrs a) {
-  const LatDev& L = p.lat[0];
+  const LatDev L = p.lat[0];
   const long long N = L.plane;
   const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= N) return;
-  const int x = (int)(node % L.pitch), y = (int)(node / L.pitch);
+  const unsigned un = (unsigned)node, pitch = (unsigned)L.pitch;
+  const int x = (int)(un % pitch), y = (int)(un / pitch);
   if (x >= L.nx) return;   // row padding
   const T* H = (const T*)a.h;
   double h[kQ], ah[kQ], hh[kQ];
@@ -333,7 +334,7 @@ __device__ void rigid_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int b,
   const BodyDev& S0 = a.body0[b];   // state before the step
   const BodyDev& S1 = a.body1[b];   // after it
   const int nv = Bp->nv, v0 = Bp->v0;
-  const LatDev& L = p.lat[0];
+  const LatDev L = p.lat[0];
   const long long N = L.plane;
   const double nu = (L.tau - 0.5) / 3.0, sigma = Bp->sigma;
   const int t = threadIdx.x, nt = blockDim.x;
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
     rigid_adjoint(p, a, b, s_red);
     return;
   }
-  const LatDev& L = p.lat[0];
+  const LatDev L = p.lat[0];
   const long long N = L.plane;
   const bool pery = L.periodic_y != 0;
   const double nu = (L.tau - 0.5) / 3.0;
@@ -644,10 +645,11 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
 // terms of rho*, u*.
 template <typename T>
 __device__ inline void stream_adjoint(const Ptrs<T>& p, const AdjPtrs& a, long long node) {
-  const LatDev& L = p.lat[0];
+  const LatDev L = p.lat[0];
   const long long N = L.plane;
   if (node >= N) return;
-  const int x = (int)(node % L.pitch), y = (int)(node / L.pitch);
+  const unsigned un = (unsigned)node, pitch = (unsigned)L.pitch;
+  const int x = (int)(un % pitch), y = (int)(un / pitch);
   if (x >= L.nx) return;   // row padding
 #pragma unroll
   for (int j = 0; j < kQ; ++j) {
@@ -663,8 +665,9 @@ __device__ inline void stream_adjoint(const Ptrs<T>& p, const AdjPtrs& a, long l
     }
     const double rho = a.mom[src], us = a.mom[N + src], vs = a.mom[2 * N + src];
     const double rh = acc_get(a.Rh, src), uh = acc_get(a.Rh, N + src), vh = acc_get(a.Rh, 2 * N + src);
-    const double r = rh - (uh * us + vh * vs) / rho;
-    a.ha[j * N + node] = a.fph[i * N + src] + r + (ex(i) * uh + ey(i) * vh) / rho;
+    const double ir = 1.0 / rho;
+    const double r = rh - (uh * us + vh * vs) * ir;
+    a.ha[j * N + node] = a.fph[i * N + src] + r + (ex(i) * uh + ey(i) * vh) * ir;
   }
 }
 

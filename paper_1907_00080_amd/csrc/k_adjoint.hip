@@ -190,13 +190,21 @@ __device__ inline void probe_adjoint(const LatDev& L, const AdjPtrs& a, double c
       const double wx = s.wx[c], wy = s.wy[bb], dwx = s.dwx[c], dwy = s.dwy[bb];
       const double ddwx = s.ddwx[c], ddwy = s.ddwy[bb];
       const double r0 = mom[node], us = mom[N + node], vs = mom[2 * N + node];
-      acc_add(a.Rh, node, rqh * wx * wy, a.bad);
-      acc_add(a.Rh, N + node, -gh[0] * dwx * wy - gh[1] * wx * dwy, a.bad);
-      acc_add(a.Rh, 2 * N + node, -gh[2] * dwx * wy - gh[3] * wx * dwy, a.bad);
       qhx += -rqh * r0 * dwx * wy + gh[0] * us * ddwx * wy + gh[1] * us * dwx * dwy +
              gh[2] * vs * ddwx * wy + gh[3] * vs * dwx * dwy;
       qhy += -rqh * r0 * wx * dwy + gh[0] * us * dwx * dwy + gh[1] * us * wx * ddwy +
              gh[2] * vs * dwx * dwy + gh[3] * vs * wx * ddwy;
+    }
+  }
+  // the scatter last: no load waits behind its atomics
+  for (int bb = 0; bb < 3; ++bb) {
+    if (!s.ok[bb]) continue;
+    for (int c = 0; c < 3; ++c) {
+      const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
+      const double wx = s.wx[c], wy = s.wy[bb], dwx = s.dwx[c], dwy = s.dwy[bb];
+      acc_add(a.Rh, node, rqh * wx * wy, a.bad);
+      acc_add(a.Rh, N + node, -gh[0] * dwx * wy - gh[1] * wx * dwy, a.bad);
+      acc_add(a.Rh, 2 * N + node, -gh[2] * dwx * wy - gh[3] * wx * dwy, a.bad);
     }
   }
   if (clamped) qhy = 0.0;
@@ -222,13 +230,28 @@ __device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm
   const int kind = p.minfo[gm] & 3;
   Stencil s;
   stencil_at(L, a.x[gm], a.y[gm], false, s);
+  // Every load comes before the first atomic: a load issued behind pending
+  // atomics waits for all of them.
   const double fx = a.fx[gm], fy = a.fy[gm];
+  const double xa = a.xa[gm], ya = a.ya[gm];
+  double dx = a.xma[gm], dy = a.yma[gm];
   const bool rbc = kind == kRBC;
   const double c1 = a.first ? 1.0 : 4.0 / 3.0, c2 = a.first ? 0.0 : -1.0 / 3.0;
   const double c3 = a.first ? 1.0 : 2.0 / 3.0;
-  const double ux = rbc ? c3 * a.xa[gm] : 0.0, uy = rbc ? c3 * a.ya[gm] : 0.0;
+  const double ux = rbc ? c3 * xa : 0.0, uy = rbc ? c3 * ya : 0.0;
   const T* U = (const T*)a.u;
   double gx = 0.0, gy = 0.0;
+  if (rbc) {
+    for (int b = 0; b < 3; ++b) {
+      if (!s.ok[b]) continue;
+      for (int c = 0; c < 3; ++c) {
+        const long long node = (long long)s.row[b] * L.pitch + s.col[c];
+        const double uu = ux * double(U[node]) + uy * double(U[N + node]);
+        gx -= uu * s.dwx[c] * s.wy[b];
+        gy -= uu * s.wx[c] * s.dwy[b];
+      }
+    }
+  }
   for (int b = 0; b < 3; ++b) {
     if (!s.ok[b]) continue;
     for (int c = 0; c < 3; ++c) {
@@ -239,18 +262,14 @@ __device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm
       if (rbc) {
         acc_add(a.Uh, node, ux * w, a.bad);
         acc_add(a.Uh, N + node, uy * w, a.bad);
-        const double uu = ux * double(U[node]) + uy * double(U[N + node]);
-        gx -= uu * s.dwx[c] * s.wy[b];
-        gy -= uu * s.wx[c] * s.dwy[b];
       }
     }
   }
-  double dx = a.xma[gm], dy = a.yma[gm];
   if (rbc) {
-    dx += c1 * a.xa[gm] + gx;
-    dy += c1 * a.ya[gm] + gy;
-    a.xma[gm] = c2 * a.xa[gm];
-    a.yma[gm] = c2 * a.ya[gm];
+    dx += c1 * xa + gx;
+    dy += c1 * ya + gy;
+    a.xma[gm] = c2 * xa;
+    a.yma[gm] = c2 * ya;
   } else {
     a.xma[gm] = 0.0;
     a.yma[gm] = 0.0;
@@ -385,24 +404,33 @@ __device__ void rigid_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int b,
       if (!s.ok[bb]) continue;
       for (int c = 0; c < 3; ++c) {
         const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
-        const double w = s.wx[c] * s.wy[bb];
-        acc_add(a.Rh, N + node, -uhx * w, a.bad);
-        acc_add(a.Rh, 2 * N + node, -uhy * w, a.bad);
         const double uu = -uhx * mom[N + node] - uhy * mom[2 * N + node];
         g2x -= uu * s.dwx[c] * s.wy[bb];
         g2y -= uu * s.wx[c] * s.dwy[bb];
       }
     }
+    const double xa = a.xa[gm], ya = a.ya[gm], dirx = a.dirx[gm], diry = a.diry[gm];
+    const double Om1 = S1.Om;
+    // the scatter after every load of this vertex
+    for (int bb = 0; bb < 3; ++bb) {
+      if (!s.ok[bb]) continue;
+      for (int c = 0; c < 3; ++c) {
+        const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
+        const double w = s.wx[c] * s.wy[bb];
+        acc_add(a.Rh, N + node, -uhx * w, a.bad);
+        acc_add(a.Rh, 2 * N + node, -uhy * w, a.bad);
+      }
+    }
     double ch[2] = {0.0, 0.0}, Uh[2] = {0.0, 0.0}, thh = 0.0, Omh = 0.0;
-    adj::rigid_vertex_vjp(relx, rely, S1.Om, a.xa[gm], a.ya[gm], uhx, uhy, ch, thh, Uh, Omh);
+    adj::rigid_vertex_vjp(relx, rely, Om1, xa, ya, uhx, uhy, ch, thh, Uh, Omh);
     acc[0] += ch[0];
     acc[1] += ch[1];
     acc[2] += thh;
     acc[3] += Uh[0];
     acc[4] += Uh[1];
     acc[5] += Omh;
-    a.dirx[gm] = a.dirx[gm] + gx + g2x;
-    a.diry[gm] = a.diry[gm] + gy + g2y;
+    a.dirx[gm] = dirx + gx + g2x;
+    a.diry[gm] = diry + gy + g2y;
     a.dsh[gm] = dsh;
   }
   block_sum<6>(acc, s_red);   // barriers also publish the vertex pass
@@ -542,11 +570,20 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
           const double us = mom[N + node], vs = mom[2 * N + node];
           U0x += us * w;
           U0y += vs * w;
-          acc_add(a.Rh, N + node, xa * w, a.bad);
-          acc_add(a.Rh, 2 * N + node, ya * w, a.bad);
           const double uu = xa * us + ya * vs;
           g2x -= uu * s.dwx[c] * s.wy[bb];
           g2y -= uu * s.wx[c] * s.dwy[bb];
+        }
+      }
+      const double xnv = a.xn[gm], ynv = a.yn[gm], Xv = X[v], Yv = Y[v];
+      // the scatter after every load of this vertex
+      for (int bb = 0; bb < 3; ++bb) {
+        if (!s.ok[bb]) continue;
+        for (int c = 0; c < 3; ++c) {
+          const long long node = (long long)s.row[bb] * L.pitch + s.col[c];
+          const double w = s.wx[c] * s.wy[bb];
+          acc_add(a.Rh, N + node, xa * w, a.bad);
+          acc_add(a.Rh, 2 * N + node, ya * w, a.bad);
         }
       }
       const double xn1h = xa + 2.0 * ds * fhx, yn1h = ya + 2.0 * ds * fhy;
@@ -554,7 +591,7 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
       dyv += ya + g2y;
       fvx = 0.5 * xn1h / mv;
       fvy = 0.5 * yn1h / mv;
-      dsh = 2.0 * ((a.xn[gm] - X[v] - U0x) * fhx + (a.yn[gm] - Y[v] - U0y) * fhy);
+      dsh = 2.0 * ((xnv - Xv - U0x) * fhx + (ynv - Yv - U0y) * fhy);
     }
     a.dirx[gm] = dxv;
     a.diry[gm] = dyv;
@@ -582,6 +619,11 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
     adj::strain_vjp(dx, dy, p.l0[gl], ks, f0x - f1x, f0y - f1y, Dhx, Dhy, ksh);
     const double Fex = 0.5 * (f0x + f1x), Fey = 0.5 * (f0y + f1y);   // element-load adjoint
     kaph += adj::area_vjp(dx, dy, kappa, Fex, Fey, Dhx, Dhy);
+    // bending operands (vertex l: left element lm, right element l), read
+    // before the probe's scatter
+    const double dLx = X[l] - X[lm], dLy = Y[l] - Y[lm];
+    const double Fhm[2] = {a.fvx[v0 + lm], a.fvy[v0 + lm]};
+    const double th0 = p.th0[gl];
     if (kind == kSoft) {
       lenh += 0.5 * (a.dsh[gl] + a.dsh[v0 + lp]);
       const double cx = 0.5 * (X[l] + X[lp]), cy = 0.5 * (Y[l] + Y[lp]);
@@ -600,13 +642,11 @@ __global__ __launch_bounds__(kAdjThreads) void ka_body(Ptrs<T> p, AdjPtrs a) {
     a.Dy[gl] = Dhy;
     a.Cx[gl] = Chx;
     a.Cy[gl] = Chy;
-    // bending at vertex l (left element lm, right element l)
-    const double dLx = X[l] - X[lm], dLy = Y[l] - Y[lm];
-    const double Fhm[2] = {a.fvx[v0 + lm], a.fvy[v0 + lm]};
+    // bending at vertex l
     const double Fhu[2] = {f0x, f0y};
     const double Fhp[2] = {f1x, f1y};
     double dLh[2] = {0.0, 0.0}, dRh[2] = {0.0, 0.0};
-    adj::bend_vjp(dLx, dLy, dx, dy, p.th0[gl], kb, Fhm, Fhu, Fhp, dLh, dRh, kbh);
+    adj::bend_vjp(dLx, dLy, dx, dy, th0, kb, Fhm, Fhu, Fhp, dLh, dRh, kbh);
     a.BLx[gl] = dLh[0];
     a.BLy[gl] = dLh[1];
     a.BRx[gl] = dRh[0];
@@ -691,16 +731,26 @@ __global__ void ka_stream_marker(Ptrs<T> p, AdjPtrs as, AdjPtrs am, int gn) {
 }
 
 // --------------------------------------------------------------- copies
-// Several device-to-device copies in one launch (4-byte words).
+// Several device-to-device copies in one launch, one row of the grid per
+// copy: 16-byte words where both ends are 16-byte aligned, the remaining
+// 4-byte words after them (sizes are whole 4-byte words).
 __global__ void ka_copy(CopyList c) {
   const int r = blockIdx.y;
   if (r >= c.n) return;
+  const unsigned long long n = c.bytes[r] >> 2;
+  const unsigned long long k0 = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned long long st = (unsigned long long)gridDim.x * blockDim.x;
+  unsigned long long done = 0;
+  if ((((unsigned long long)c.src[r] | (unsigned long long)c.dst[r]) & 15) == 0) {
+    const uint4* s = (const uint4*)c.src[r];
+    uint4* d = (uint4*)c.dst[r];
+    const unsigned long long n4 = n >> 2;
+    for (unsigned long long k = k0; k < n4; k += st) d[k] = s[k];
+    done = n4 << 2;
+  }
   const unsigned* s = (const unsigned*)c.src[r];
   unsigned* d = (unsigned*)c.dst[r];
-  const unsigned long long n = c.bytes[r] >> 2;
-  for (unsigned long long k = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += (unsigned long long)gridDim.x * blockDim.x)
-    d[k] = s[k];
+  for (unsigned long long k = done + k0; k < n; k += st) d[k] = s[k];
 }
 
 // Set the adjoint seed / clear accumulators: out[k] = v for k < n.
@@ -735,7 +785,7 @@ void launch_adjoint_segment(const Ptrs<T>& p, const AdjPtrs* a, int n, long long
 void launch_copies(const CopyList& c, hipStream_t s) {
   if (c.n <= 0) return;
   unsigned long long mx = 0;
-  for (int r = 0; r < c.n; ++r) mx = std::max(mx, c.bytes[r] >> 2);
+  for (int r = 0; r < c.n; ++r) mx = std::max(mx, c.bytes[r] >> 4);
   const unsigned gx = (unsigned)std::min<unsigned long long>((mx + 255) / 256, 1024ull);
   hipLaunchKernelGGL(ka_copy, dim3(std::max(gx, 1u), c.n), dim3(256), 0, s, c);
 }

@@ -711,9 +711,12 @@ __device__ inline void stream_adjoint(const Ptrs<T>& p, const AdjPtrs& a, long l
   }
 }
 
+// Marker work goes mpb markers to a workgroup (mpb <= blockDim.x): each marker
+// issues up to 72 scattered 64-bit atomics, which a compute unit's memory
+// pipeline takes lane by lane, so few markers are spread over many units.
 template <typename T>
-__global__ void ka_marker(Ptrs<T> p, AdjPtrs a) {
-  marker_adjoint(p, a, blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void ka_marker(Ptrs<T> p, AdjPtrs a, int mpb) {
+  if ((int)threadIdx.x < mpb) marker_adjoint(p, a, (int)blockIdx.x * mpb + (int)threadIdx.x);
 }
 
 template <typename T>
@@ -724,10 +727,10 @@ __global__ void ka_stream(Ptrs<T> p, AdjPtrs a) {
 // Reverse streaming of step s (workgroups [0, gn)) together with the marker
 // kernel of step s - 1 (the rest): independent data, one launch.
 template <typename T>
-__global__ void ka_stream_marker(Ptrs<T> p, AdjPtrs as, AdjPtrs am, int gn) {
+__global__ void ka_stream_marker(Ptrs<T> p, AdjPtrs as, AdjPtrs am, int gn, int mpb) {
   const int b = blockIdx.x;
   if (b < gn) stream_adjoint(p, as, (long long)b * blockDim.x + threadIdx.x);
-  else marker_adjoint(p, am, (b - gn) * (int)blockDim.x + (int)threadIdx.x);
+  else if ((int)threadIdx.x < mpb) marker_adjoint(p, am, (b - gn) * mpb + (int)threadIdx.x);
 }
 
 // --------------------------------------------------------------- copies
@@ -767,18 +770,26 @@ __global__ void ka_fill(double* out, long long n, double v) {
 template <typename T>
 void launch_adjoint_segment(const Ptrs<T>& p, const AdjPtrs* a, int n, long long N, hipStream_t s) {
   const int nm = p.nm_total;
-  const unsigned gn = (unsigned)((N + 255) / 256), gm = (unsigned)((nm + 255) / 256);
+  // one wave per workgroup for the node kernels (a small lattice still
+  // reaches every compute unit); markers 16 to 64 to a workgroup, enough
+  // workgroups for every unit where there are markers for them (4 to a
+  // workgroup measured no faster than 16)
+  constexpr int kNodeThreads = 64;
+  const int per_unit = (nm + 255) / 256;
+  const int mpb = std::min(64, std::max(16, (per_unit + 15) / 16 * 16));
+  const unsigned gn = (unsigned)((N + kNodeThreads - 1) / kNodeThreads), gm = (unsigned)((nm + mpb - 1) / mpb);
   // FE, Uh (and Rh) start each step cleared: by the previous reverse step's
   // collide kernel, or by the fill before the first one
-  if (nm > 0) hipLaunchKernelGGL(ka_marker<T>, dim3(gm), dim3(256), 0, s, p, a[n - 1]);
+  if (nm > 0) hipLaunchKernelGGL(ka_marker<T>, dim3(gm), dim3(kNodeThreads), 0, s, p, a[n - 1], mpb);
   for (int k = n - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(ka_collide<T>, dim3(gn), dim3(256), 0, s, p, a[k]);
+    hipLaunchKernelGGL(ka_collide<T>, dim3(gn), dim3(kNodeThreads), 0, s, p, a[k]);
     if (p.nbody_total > 0)
       hipLaunchKernelGGL(ka_body<T>, dim3(p.nbody_total), dim3(kAdjThreads), 0, s, p, a[k]);
     if (k > 0 && nm > 0)
-      hipLaunchKernelGGL(ka_stream_marker<T>, dim3(gn + gm), dim3(256), 0, s, p, a[k], a[k - 1], (int)gn);
+      hipLaunchKernelGGL(ka_stream_marker<T>, dim3(gn + gm), dim3(kNodeThreads), 0, s, p, a[k], a[k - 1],
+                         (int)gn, mpb);
     else
-      hipLaunchKernelGGL(ka_stream<T>, dim3(gn), dim3(256), 0, s, p, a[k]);
+      hipLaunchKernelGGL(ka_stream<T>, dim3(gn), dim3(kNodeThreads), 0, s, p, a[k]);
   }
 }
 

@@ -222,49 +222,71 @@ __device__ inline void probe_adjoint(const LatDev& L, const AdjPtrs& a, double c
 // X_prev^{n+1} = X^n; (c) red cells: reverse of the kinematic BDF2 / Euler
 // update, whose interpolation of the stored velocity u^n scatters into the
 // adjoint of u.
+// One marker per row of 16 lanes: lane j < 9 of the row takes stencil node
+// (j / 3, j % 3), its atomics and its share of the interpolation gradient;
+// the row's sum (xor butterfly, the same value in every lane) goes to lane 0,
+// which writes the marker's outputs.  Every lane of the row takes part in the
+// sums, also where the marker index is past the end.
 template <typename T>
-__device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm) {
-  if (gm >= p.nm_total) return;
+__device__ inline void marker_adjoint(const Ptrs<T>& p, const AdjPtrs& a, int gm, int j) {
+  const bool live = gm < p.nm_total;
   const LatDev L = p.lat[0];
   const long long N = L.plane;
-  const int kind = p.minfo[gm] & 3;
-  Stencil s;
-  stencil_at(L, a.x[gm], a.y[gm], false, s);
-  // Every load comes before the first atomic: a load issued behind pending
-  // atomics waits for all of them.
-  const double fx = a.fx[gm], fy = a.fy[gm];
-  const double xa = a.xa[gm], ya = a.ya[gm];
-  double dx = a.xma[gm], dy = a.yma[gm];
-  const bool rbc = kind == kRBC;
-  const double c1 = a.first ? 1.0 : 4.0 / 3.0, c2 = a.first ? 0.0 : -1.0 / 3.0;
-  const double c3 = a.first ? 1.0 : 2.0 / 3.0;
-  const double ux = rbc ? c3 * xa : 0.0, uy = rbc ? c3 * ya : 0.0;
-  const T* U = (const T*)a.u;
   double gx = 0.0, gy = 0.0;
-  if (rbc) {
-    for (int b = 0; b < 3; ++b) {
-      if (!s.ok[b]) continue;
-      for (int c = 0; c < 3; ++c) {
-        const long long node = (long long)s.row[b] * L.pitch + s.col[c];
-        const double uu = ux * double(U[node]) + uy * double(U[N + node]);
-        gx -= uu * s.dwx[c] * s.wy[b];
-        gy -= uu * s.wx[c] * s.dwy[b];
-      }
-    }
-  }
-  for (int b = 0; b < 3; ++b) {
-    if (!s.ok[b]) continue;
-    for (int c = 0; c < 3; ++c) {
-      const long long node = (long long)s.row[b] * L.pitch + s.col[c];
-      const double w = s.wx[c] * s.wy[b];
-      acc_add(a.FE, node, fx * w, a.bad);
-      acc_add(a.FE, N + node, fy * w, a.bad);
+  const int bb = j / 3, c = j - 3 * (j / 3);
+  bool mine = false, rbc = false;
+  long long node = 0;
+  double w = 0.0, fx = 0.0, fy = 0.0, ux = 0.0, uy = 0.0, xa = 0.0, ya = 0.0, dx = 0.0, dy = 0.0;
+  if (live) {
+    const int kind = p.minfo[gm] & 3;
+    rbc = kind == kRBC;
+    const double X = a.x[gm], Y = a.y[gm];
+    // every load before the first atomic: a load issued behind pending
+    // atomics waits for all of them
+    fx = a.fx[gm];
+    fy = a.fy[gm];
+    xa = a.xa[gm];
+    ya = a.ya[gm];
+    dx = a.xma[gm];
+    dy = a.yma[gm];
+    const double c3 = a.first ? 1.0 : 2.0 / 3.0;
+    ux = rbc ? c3 * xa : 0.0;
+    uy = rbc ? c3 * ya : 0.0;
+    // this lane's node of the 3x3 stencil (the weights as stencil_at takes them)
+    const double rx = floor(X + 0.5) + (c - 1), ry = floor(Y + 0.5) + (bb - 1);
+    int row = (int)ry;
+    bool ok = true;
+    if (L.periodic_y != 0) row = wrap_i(row, L.ny);
+    else ok = row >= 0 && row < L.ny;
+    mine = j < 9 && ok;
+    if (mine) {
+      const double wx = roma_phi(rx - X), dwx = roma_dphi(rx - X);
+      const double wy = roma_phi(ry - Y), dwy = roma_dphi(ry - Y);
+      node = (long long)row * L.pitch + wrap_i((int)rx, L.nx);
+      w = wx * wy;
       if (rbc) {
-        acc_add(a.Uh, node, ux * w, a.bad);
-        acc_add(a.Uh, N + node, uy * w, a.bad);
+        const T* U = (const T*)a.u;
+        const double uu = ux * double(U[node]) + uy * double(U[N + node]);
+        gx = -uu * dwx * wy;
+        gy = -uu * wx * dwy;
       }
     }
   }
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1) {
+    gx += __shfl_xor(gx, m, 16);
+    gy += __shfl_xor(gy, m, 16);
+  }
+  if (mine) {
+    acc_add(a.FE, node, fx * w, a.bad);
+    acc_add(a.FE, N + node, fy * w, a.bad);
+    if (rbc) {
+      acc_add(a.Uh, node, ux * w, a.bad);
+      acc_add(a.Uh, N + node, uy * w, a.bad);
+    }
+  }
+  if (!live || j != 0) return;
+  const double c1 = a.first ? 1.0 : 4.0 / 3.0, c2 = a.first ? 0.0 : -1.0 / 3.0;
   if (rbc) {
     dx += c1 * xa + gx;
     dy += c1 * ya + gy;
@@ -711,12 +733,10 @@ __device__ inline void stream_adjoint(const Ptrs<T>& p, const AdjPtrs& a, long l
   }
 }
 
-// Marker work goes mpb markers to a workgroup (mpb <= blockDim.x): each marker
-// issues up to 72 scattered 64-bit atomics, which a compute unit's memory
-// pipeline takes lane by lane, so few markers are spread over many units.
+// Four markers to a 64-lane workgroup, a row of 16 lanes each.
 template <typename T>
-__global__ void ka_marker(Ptrs<T> p, AdjPtrs a, int mpb) {
-  if ((int)threadIdx.x < mpb) marker_adjoint(p, a, (int)blockIdx.x * mpb + (int)threadIdx.x);
+__global__ void ka_marker(Ptrs<T> p, AdjPtrs a) {
+  marker_adjoint(p, a, (int)blockIdx.x * 4 + (int)(threadIdx.x >> 4), (int)(threadIdx.x & 15));
 }
 
 template <typename T>
@@ -727,10 +747,10 @@ __global__ void ka_stream(Ptrs<T> p, AdjPtrs a) {
 // Reverse streaming of step s (workgroups [0, gn)) together with the marker
 // kernel of step s - 1 (the rest): independent data, one launch.
 template <typename T>
-__global__ void ka_stream_marker(Ptrs<T> p, AdjPtrs as, AdjPtrs am, int gn, int mpb) {
+__global__ void ka_stream_marker(Ptrs<T> p, AdjPtrs as, AdjPtrs am, int gn) {
   const int b = blockIdx.x;
   if (b < gn) stream_adjoint(p, as, (long long)b * blockDim.x + threadIdx.x);
-  else if ((int)threadIdx.x < mpb) marker_adjoint(p, am, (b - gn) * mpb + (int)threadIdx.x);
+  else marker_adjoint(p, am, (b - gn) * 4 + (int)(threadIdx.x >> 4), (int)(threadIdx.x & 15));
 }
 
 // --------------------------------------------------------------- copies
@@ -770,24 +790,20 @@ __global__ void ka_fill(double* out, long long n, double v) {
 template <typename T>
 void launch_adjoint_segment(const Ptrs<T>& p, const AdjPtrs* a, int n, long long N, hipStream_t s) {
   const int nm = p.nm_total;
-  // one wave per workgroup for the node kernels (a small lattice still
-  // reaches every compute unit); markers 16 to 64 to a workgroup, enough
-  // workgroups for every unit where there are markers for them (4 to a
-  // workgroup measured no faster than 16)
+  // one wave per workgroup (a small lattice still reaches every compute
+  // unit); four markers to a workgroup
   constexpr int kNodeThreads = 64;
-  const int per_unit = (nm + 255) / 256;
-  const int mpb = std::min(64, std::max(16, (per_unit + 15) / 16 * 16));
-  const unsigned gn = (unsigned)((N + kNodeThreads - 1) / kNodeThreads), gm = (unsigned)((nm + mpb - 1) / mpb);
+  const unsigned gn = (unsigned)((N + kNodeThreads - 1) / kNodeThreads), gm = (unsigned)((nm + 3) / 4);
   // FE, Uh (and Rh) start each step cleared: by the previous reverse step's
   // collide kernel, or by the fill before the first one
-  if (nm > 0) hipLaunchKernelGGL(ka_marker<T>, dim3(gm), dim3(kNodeThreads), 0, s, p, a[n - 1], mpb);
+  if (nm > 0) hipLaunchKernelGGL(ka_marker<T>, dim3(gm), dim3(kNodeThreads), 0, s, p, a[n - 1]);
   for (int k = n - 1; k >= 0; --k) {
     hipLaunchKernelGGL(ka_collide<T>, dim3(gn), dim3(kNodeThreads), 0, s, p, a[k]);
     if (p.nbody_total > 0)
       hipLaunchKernelGGL(ka_body<T>, dim3(p.nbody_total), dim3(kAdjThreads), 0, s, p, a[k]);
     if (k > 0 && nm > 0)
       hipLaunchKernelGGL(ka_stream_marker<T>, dim3(gn + gm), dim3(kNodeThreads), 0, s, p, a[k], a[k - 1],
-                         (int)gn, mpb);
+                         (int)gn);
     else
       hipLaunchKernelGGL(ka_stream<T>, dim3(gn), dim3(kNodeThreads), 0, s, p, a[k]);
   }
